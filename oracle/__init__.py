@@ -1,0 +1,333 @@
+"""FP64 CPU oracle for the nonlinear reconstruction (arXiv:1611.09638).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by ``__graft_entry__.smoke()``
+and by the benchmark's ``cpu_baseline`` leg.  The product path (the HIP library
+and its Python binding) never imports or calls anything here, and this package
+imports nothing from the product package.
+
+Thin numpy wrappers over ``librecon_oracle.so`` (plain C, see
+``recon_oracle.c`` and ``recon_oracle_adjoint.c``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SOURCES = ["recon_oracle.c", "recon_oracle_adjoint.c"]
+_LIB_PATH = os.path.join(_HERE, "librecon_oracle.so")
+
+ORC_E = {0: "ok", -1: "E_ARG", -2: "E_INPUT", -3: "E_NOT_PD", -4: "E_NO_CONVERGENCE", -5: "E_NO_TAPE", -7: "E_NOMEM"}
+
+MAX_STEPS = 256
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, no FMA contraction)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    if not force and os.path.exists(_LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs)
+        if os.path.getmtime(_LIB_PATH) >= newest:
+            return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class OrcConfig(ctypes.Structure):
+    _fields_ = [
+        ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
+        ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
+        ("max_halvings", ctypes.c_int), ("record_tape", ctypes.c_int), ("solver", ctypes.c_int),
+        ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
+        ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
+        ("a_min", ctypes.c_double),
+    ]
+
+
+class OrcStats(ctypes.Structure):
+    _fields_ = [
+        ("outer_steps", ctypes.c_int), ("vcycles_total", ctypes.c_int),
+        ("vcycles", ctypes.c_int * MAX_STEPS),
+        ("alpha", ctypes.c_double * MAX_STEPS), ("rms_sigma", ctypes.c_double * MAX_STEPS),
+        ("kappa", ctypes.c_double * MAX_STEPS), ("rel_residual", ctypes.c_double * MAX_STEPS),
+        ("min_det", ctypes.c_double), ("min_lambda0", ctypes.c_double), ("max_delta_r", ctypes.c_double),
+    ]
+
+    def to_dict(self):
+        k = self.outer_steps
+        return dict(outer_steps=k, vcycles_total=self.vcycles_total,
+                    vcycles=list(self.vcycles[:k]), alpha=list(self.alpha[:k]),
+                    rms_sigma=list(self.rms_sigma[:k + 1]), kappa=list(self.kappa[:k + 1]),
+                    rel_residual=list(self.rel_residual[:k]), min_det=self.min_det,
+                    min_lambda0=self.min_lambda0, max_delta_r=self.max_delta_r)
+
+
+@dataclass
+class Config:
+    """Solver knobs (defaults: xi_m = 1/10 and v_m = 10 from App. A/B; the rest
+    are the readings of the multigrid and step control)."""
+    max_outer: int = 10
+    n_pre: int = 2
+    n_post: int = 2
+    coarse_n: int = 8
+    coarse_sweeps: int = 64
+    max_vcycles: int = 100
+    max_halvings: int = 30
+    record_tape: int = 0
+    solver: int = 0  # 0: V-cycle-preconditioned CG, 1: plain V-cycle iteration
+    tol: float = 1e-10
+    outer_tol: float = 0.0
+    xi_m: float = 0.1
+    v_m: float = 10.0
+    smooth_center: float = 0.5
+    s_max: float = 1.0
+    a_min: float = 1e-3
+
+    def c(self) -> OrcConfig:
+        return OrcConfig(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__("oracle error %d (%s)" % (code, ORC_E.get(code, "?")))
+        self.code = code
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        d, i, dbl, ll = _dp, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+        fp = ctypes.POINTER(ctypes.c_float)
+        sig = {
+            "orc_cic_particles": (i, [fp, ll, i, dbl, d]),
+            "orc_normalize": (i, [d, i, d]),
+            "orc_meshmass": (None, [d, d, i, d]),
+            "orc_smooth": (None, [d, i, dbl, d]),
+            "orc_source_terms": (dbl, [d, d, i, dbl, dbl, d]),
+            "orc_source": (None, [d, d, i, dbl, dbl, dbl, d]),
+            "orc_apply": (None, [d, d, i, dbl, dbl, d]),
+            "orc_residual": (None, [d, d, d, i, dbl, dbl, d]),
+            "orc_rbgs_sweep": (None, [d, d, d, i, dbl, dbl, i]),
+            "orc_rbgs_half": (None, [d, d, d, i, dbl, dbl, i]),
+            "orc_vcycle": (i, [d, d, i, ctypes.POINTER(OrcConfig), d]),
+            "orc_restrict": (None, [d, i, d]),
+            "orc_prolong_add": (None, [d, d, i]),
+            "orc_num_levels": (i, [i, i]),
+            "orc_mg_solve": (i, [d, d, i, ctypes.POINTER(OrcConfig), d, d]),
+            "orc_is_pd": (i, [d, i]),
+            "orc_max_shift": (dbl, [d, i]),
+            "orc_choose_step": (i, [d, d, i, ctypes.POINTER(OrcConfig), d]),
+            "orc_delta_r": (None, [d, i, d]),
+            "orc_solve": (i, [d, i, dbl, ctypes.POINTER(OrcConfig), d, d, ctypes.POINTER(OrcStats)]),
+            "orc_lambda_min": (dbl, [d]),
+            "orc_det3": (dbl, [d]),
+            "orc_triad_at": (None, [d, i, i, i, i, d]),
+            "orc_tape_steps": (i, []),
+            "orc_tape_clear": (None, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cic_particles(pos: np.ndarray, n: int, box: float) -> np.ndarray:
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    rho = np.empty((n, n, n))
+    rc = lib().orc_cic_particles(pos.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), pos.shape[0], n, box, _p(rho))
+    if rc:
+        raise OracleError(rc)
+    return rho
+
+
+def normalize(rho) -> np.ndarray:
+    rho = _f64(rho)
+    m = np.empty_like(rho)
+    rc = lib().orc_normalize(_p(rho), rho.shape[0], _p(m))
+    if rc:
+        raise OracleError(rc)
+    return m
+
+
+def meshmass(phi, m) -> np.ndarray:
+    phi, m = _f64(phi), _f64(m)
+    M = np.empty_like(m)
+    lib().orc_meshmass(_p(phi), _p(m), m.shape[0], _p(M))
+    return M
+
+
+def smooth(f, c0: float = 0.5) -> np.ndarray:
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib().orc_smooth(_p(f), f.shape[0], c0, _p(out))
+    return out
+
+
+def source_terms(phi, M, xi_m=0.1, v_m=10.0):
+    phi, M = _f64(phi), _f64(M)
+    t = np.empty_like(M)
+    rb = lib().orc_source_terms(_p(phi), _p(M), M.shape[0], xi_m, v_m, _p(t))
+    return t, rb
+
+
+def source(phi, M, xi_m=0.1, v_m=10.0, c0=0.5) -> np.ndarray:
+    phi, M = _f64(phi), _f64(M)
+    b = np.empty_like(M)
+    lib().orc_source(_p(phi), _p(M), M.shape[0], xi_m, v_m, c0, _p(b))
+    return b
+
+
+def apply(u, a, scale=1.0, a_min=1e-3) -> np.ndarray:
+    u, a = _f64(u), _f64(a)
+    out = np.empty_like(u)
+    lib().orc_apply(_p(u), _p(a), u.shape[0], scale, a_min, _p(out))
+    return out
+
+
+def residual(u, a, b, scale=1.0, a_min=1e-3) -> np.ndarray:
+    u, a, b = _f64(u), _f64(a), _f64(b)
+    r = np.empty_like(u)
+    lib().orc_residual(_p(u), _p(a), _p(b), u.shape[0], scale, a_min, _p(r))
+    return r
+
+
+def rbgs_sweep(u, a, b, scale=1.0, a_min=1e-3, first=0) -> np.ndarray:
+    u = _f64(u).copy()
+    a, b = _f64(a), _f64(b)
+    lib().orc_rbgs_sweep(_p(u), _p(a), _p(b), u.shape[0], scale, a_min, first)
+    return u
+
+
+def rbgs_half(u, a, b, colour, scale=1.0, a_min=1e-3) -> np.ndarray:
+    u = _f64(u).copy()
+    a, b = _f64(a), _f64(b)
+    lib().orc_rbgs_half(_p(u), _p(a), _p(b), u.shape[0], scale, a_min, colour)
+    return u
+
+
+def vcycle(a, r, cfg: Config | None = None) -> np.ndarray:
+    cfg = cfg or Config()
+    a, r = _f64(a), _f64(r)
+    z = np.empty_like(r)
+    c = cfg.c()
+    rc = lib().orc_vcycle(_p(a), _p(r), r.shape[0], ctypes.byref(c), _p(z))
+    if rc:
+        raise OracleError(rc)
+    return z
+
+
+def restrict(f) -> np.ndarray:
+    f = _f64(f)
+    n = f.shape[0]
+    c = np.empty((n // 2,) * 3)
+    lib().orc_restrict(_p(f), n, _p(c))
+    return c
+
+
+def prolong_add(u, e) -> np.ndarray:
+    u = _f64(u).copy()
+    e = _f64(e)
+    lib().orc_prolong_add(_p(u), _p(e), u.shape[0])
+    return u
+
+
+def mg_solve(a, b, cfg: Config | None = None):
+    cfg = cfg or Config()
+    a, b = _f64(a), _f64(b)
+    u = np.empty_like(b)
+    rel = ctypes.c_double(0.0)
+    c = cfg.c()
+    rc = lib().orc_mg_solve(_p(a), _p(b), b.shape[0], ctypes.byref(c), _p(u), ctypes.byref(rel))
+    if rc < 0:
+        raise OracleError(rc)
+    return u, rc, rel.value
+
+
+def is_pd(phi) -> bool:
+    phi = _f64(phi)
+    return bool(lib().orc_is_pd(_p(phi), phi.shape[0]))
+
+
+def max_shift(f) -> float:
+    f = _f64(f)
+    return lib().orc_max_shift(_p(f), f.shape[0])
+
+
+def choose_step(phi, dphi, cfg: Config | None = None):
+    cfg = cfg or Config()
+    phi, dphi = _f64(phi), _f64(dphi)
+    alpha = ctypes.c_double(0.0)
+    c = cfg.c()
+    j = lib().orc_choose_step(_p(phi), _p(dphi), phi.shape[0], ctypes.byref(c), ctypes.byref(alpha))
+    return j, (alpha.value if j >= 0 else None)
+
+
+def delta_r(phi) -> np.ndarray:
+    phi = _f64(phi)
+    d = np.empty_like(phi)
+    lib().orc_delta_r(_p(phi), phi.shape[0], _p(d))
+    return d
+
+
+def lambda_min(e) -> float:
+    e = np.ascontiguousarray(e, dtype=np.float64).reshape(9)
+    return lib().orc_lambda_min(_p(e))
+
+
+def triad_at(phi, i, j, k) -> np.ndarray:
+    phi = _f64(phi)
+    e = np.empty(9)
+    lib().orc_triad_at(_p(phi), phi.shape[0], i, j, k, _p(e))
+    return e.reshape(3, 3)
+
+
+def det3(e) -> float:
+    e = np.ascontiguousarray(e, dtype=np.float64).reshape(9)
+    return lib().orc_det3(_p(e))
+
+
+def num_levels(n: int, coarse_n: int = 8) -> int:
+    return lib().orc_num_levels(n, coarse_n)
+
+
+def solve(rho, box: float, cfg: Config | None = None, raise_on_error: bool = True):
+    """Full forward reconstruction.  Returns (phi [length^2], delta_r, stats dict)."""
+    cfg = cfg or Config()
+    rho = _f64(rho)
+    n = rho.shape[0]
+    phi = np.empty_like(rho)
+    dr = np.empty_like(rho)
+    st = OrcStats()
+    c = cfg.c()
+    rc = lib().orc_solve(_p(rho), n, box, ctypes.byref(c), _p(phi), _p(dr), ctypes.byref(st))
+    if rc and raise_on_error:
+        raise OracleError(rc)
+    out = st.to_dict()
+    out["status"] = rc
+    return phi, dr, out

@@ -1,0 +1,902 @@
+/*
+ * FP64 CPU oracle for the nonlinear reconstruction of Zhu, Yu, Pen, Chen & Yu,
+ * "Nonlinear reconstruction" (arXiv:1611.09638).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is loaded by the test suite, by the
+ * smoke check and by the benchmark's CPU-baseline leg, and by nothing else.
+ * It shares no source, header or generated table with the HIP library; the
+ * two meet only through the seeded inputs the tests hand to both.
+ *
+ * It is written to be read against the paper: plain loops over the periodic
+ * lattice, FP64 throughout, no blocking or fusion, sums taken plane by plane
+ * in a fixed order.  OpenMP only splits the outer loop of element-wise work.
+ *
+ * Method (Sec. II and App. A):
+ *   mapping   x = xi + grad phi                         (Eq. mapping)
+ *   triad     e = dx/dxi = I + Hess phi, sqrt g = det e (App. A)
+ *   deviation Sigma = rho_bar - rho sqrt g              (App. A, after Eq. elliptic_diff)
+ *   solve     div(rho sqrt g grad phidot) = S(Sigma + C + E), with x ~ xi
+ *                                                       (Eq. elliptic, App. A)
+ *   increment dphi = S phidot; phi = sum of increments  (App. A, Sec. II)
+ *   output    delta_r = -laplacian phi                  (Eq. rec)
+ *
+ * Readings of points the paper leaves open (all shared with the HIP path by
+ * specification, not by code):
+ *   - grid: vertex centred, periodic, grid units; value j sits at position j.
+ *   - rho sqrt g on the current mesh: M_n = det(e_n) * CIC-interpolant of the
+ *     normalised density at x_n = n + D_c phi (central differences).
+ *   - Hessian: compact second differences; H_ab uses the 4-point cross stencil.
+ *   - rho_bar = mean of M; C = 4 max(0, xi_m/lambda_0 - 1)^2;
+ *     E = -2 [sqrt g > v_m] |Sigma|.
+ *   - S f = c0 f + (1 - c0)/6 * (sum of the six nearest neighbours), c0 = 1/2.
+ *   - operator (x ~ xi): flux form sum_faces c_f (u_nb - u_n) with face
+ *     coefficient c_f = max(a_min, (M_n + M_nb)/2), scaled by 4^-l on level l.
+ *   - multigrid: symmetric V(n_pre, n_post) cycles with red-black
+ *     Gauss-Seidel (red = i+j+k even; pre-smoothing red then black,
+ *     post-smoothing black then red), 27-point full-weighting restriction of
+ *     residual and coefficient, trilinear prolongation (= 8 R^T), coarsest
+ *     grid relaxed from zero on a zero-mean right-hand side by a palindromic
+ *     red/black sequence.  The V-cycle preconditions conjugate gradients
+ *     (default) or is iterated on its own; stop when ||b - A u||_2 <=
+ *     tol ||b||_2; u made mean-free at the end.
+ *   - step: alpha = 2^-j, first j with I + Hess(phi + alpha dphi) positive
+ *     definite at every node (Sylvester) and max |alpha D_c dphi| <= s_max.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_INPUT (-2)
+#define ORC_E_NOT_PD (-3)
+#define ORC_E_NO_CONVERGENCE (-4)
+#define ORC_E_NO_TAPE (-5)
+#define ORC_E_NOMEM (-7)
+
+#define ORC_MAX_STEPS 256
+
+typedef struct {
+    int max_outer;
+    int n_pre, n_post;
+    int coarse_n;
+    int coarse_sweeps;
+    int max_vcycles;
+    int max_halvings;
+    int record_tape;
+    int solver;
+    double tol;
+    double outer_tol;
+    double xi_m, v_m;
+    double smooth_center;
+    double s_max;
+    double a_min;
+} orc_config;
+
+typedef struct {
+    int outer_steps;
+    int vcycles_total;
+    int vcycles[ORC_MAX_STEPS];
+    double alpha[ORC_MAX_STEPS];
+    double rms_sigma[ORC_MAX_STEPS];
+    double kappa[ORC_MAX_STEPS];
+    double rel_residual[ORC_MAX_STEPS];
+    double min_det, min_lambda0, max_delta_r;
+} orc_stats;
+
+/* ------------------------------------------------------------------ lattice */
+
+static inline int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+static inline long at(int n, int i, int j, int k)
+{
+    return ((long)wrap(i, n) * n + wrap(j, n)) * n + wrap(k, n);
+}
+
+static long cube(int n) { return (long)n * n * n; }
+
+/* Sum of a field, plane by plane, planes added in order (fixed order). */
+static double field_sum(const double *f, int n)
+{
+    double *plane = (double *)malloc(sizeof(double) * n);
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (long q = 0; q < (long)n * n; ++q) s += f[(long)i * n * n + q];
+        plane[i] = s;
+    }
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += plane[i];
+    free(plane);
+    return s;
+}
+
+static double field_dot(const double *f, const double *g, int n)
+{
+    double *plane = (double *)malloc(sizeof(double) * n);
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (long q = 0; q < (long)n * n; ++q) {
+            long p = (long)i * n * n + q;
+            s += f[p] * g[p];
+        }
+        plane[i] = s;
+    }
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += plane[i];
+    free(plane);
+    return s;
+}
+
+static double field_mean(const double *f, int n) { return field_sum(f, n) / (double)cube(n); }
+
+/* ------------------------------------------------------ 3x3 symmetric algebra */
+
+static double det3(const double e[3][3])
+{
+    return e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1])
+         - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0])
+         + e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+}
+
+/* Smallest eigenvalue of a symmetric 3x3 matrix by cyclic Jacobi rotations
+ * (the textbook iteration; converges to working precision in a few sweeps). */
+static double lambda_min_jacobi(const double e_in[3][3])
+{
+    double a[3][3];
+    memcpy(a, e_in, sizeof(a));
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        double diag = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off <= 1e-34 * diag || off == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int r = 0; r < 3; ++r) { /* columns p, q */
+                    double arp = a[r][p], arq = a[r][q];
+                    a[r][p] = c * arp - s * arq;
+                    a[r][q] = s * arp + c * arq;
+                }
+                for (int r = 0; r < 3; ++r) { /* rows p, q */
+                    double apr = a[p][r], aqr = a[q][r];
+                    a[p][r] = c * apr - s * aqr;
+                    a[q][r] = s * apr + c * aqr;
+                }
+            }
+    }
+    double l = a[0][0];
+    if (a[1][1] < l) l = a[1][1];
+    if (a[2][2] < l) l = a[2][2];
+    return l;
+}
+
+double orc_lambda_min(const double *e9) { return lambda_min_jacobi((const double(*)[3])e9); }
+double orc_det3(const double *e9) { return det3((const double(*)[3])e9); }
+
+/* Compact Hessian of phi at node (i,j,k): second differences on the diagonal,
+ * four-point cross differences off it. */
+static void hessian(const double *phi, int n, int i, int j, int k, double H[3][3])
+{
+    int d[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    double c = phi[at(n, i, j, k)];
+    for (int a = 0; a < 3; ++a) {
+        double p = phi[at(n, i + d[a][0], j + d[a][1], k + d[a][2])];
+        double m = phi[at(n, i - d[a][0], j - d[a][1], k - d[a][2])];
+        H[a][a] = p - 2.0 * c + m;
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b) {
+            int pi = d[a][0] + d[b][0], pj = d[a][1] + d[b][1], pk = d[a][2] + d[b][2];
+            int qi = d[a][0] - d[b][0], qj = d[a][1] - d[b][1], qk = d[a][2] - d[b][2];
+            double pp = phi[at(n, i + pi, j + pj, k + pk)];
+            double pm = phi[at(n, i + qi, j + qj, k + qk)];
+            double mp = phi[at(n, i - qi, j - qj, k - qk)];
+            double mm = phi[at(n, i - pi, j - pj, k - pk)];
+            H[a][b] = H[b][a] = 0.25 * (pp - pm - mp + mm);
+        }
+}
+
+static void triad(const double *phi, int n, int i, int j, int k, double e[3][3])
+{
+    hessian(phi, n, i, j, k, e);
+    for (int a = 0; a < 3; ++a) e[a][a] += 1.0;
+}
+
+/* e = I + Hess(phi) at one node, row-major (exposed for the tests). */
+void orc_triad_at(const double *phi, int n, int i, int j, int k, double *e9)
+{
+    double e[3][3];
+    triad(phi, n, i, j, k, e);
+    memcpy(e9, e, sizeof(e));
+}
+
+/* Central-difference gradient of phi: the displacement x - xi at a node. */
+static void displacement(const double *phi, int n, int i, int j, int k, double s[3])
+{
+    s[0] = 0.5 * (phi[at(n, i + 1, j, k)] - phi[at(n, i - 1, j, k)]);
+    s[1] = 0.5 * (phi[at(n, i, j + 1, k)] - phi[at(n, i, j - 1, k)]);
+    s[2] = 0.5 * (phi[at(n, i, j, k + 1)] - phi[at(n, i, j, k - 1)]);
+}
+
+/* ----------------------------------------------------------- input (Sec. III) */
+
+/* Cloud-in-cell assignment of particles (positions in box units) onto the
+ * n^3 vertex-centred grid: each particle gives weight prod_a (1 - |x_a - j_a|)
+ * to the 8 surrounding nodes.  Output is particle count per node. */
+int orc_cic_particles(const float *pos, long long np, int n, double box, double *rho)
+{
+    if (!pos || !rho || n <= 0 || box <= 0) return ORC_E_ARG;
+    memset(rho, 0, sizeof(double) * cube(n));
+    double toc = (double)n / box;
+    for (long long p = 0; p < np; ++p) {
+        double x[3];
+        int f[3];
+        double w1[3];
+        for (int a = 0; a < 3; ++a) {
+            x[a] = (double)pos[3 * p + a] * toc;
+            double fl = floor(x[a]);
+            f[a] = (int)fl;
+            w1[a] = x[a] - fl;
+        }
+        for (int c = 0; c < 8; ++c) {
+            int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+            double w = (o0 ? w1[0] : 1.0 - w1[0]) * (o1 ? w1[1] : 1.0 - w1[1]) * (o2 ? w1[2] : 1.0 - w1[2]);
+            rho[at(n, f[0] + o0, f[1] + o1, f[2] + o2)] += w;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Input conditioning: density must be finite, non-negative with positive
+ * total; the normalised density m = rho / mean(rho) has mean 1 (Sec. III). */
+int orc_normalize(const double *rho, int n, double *m)
+{
+    long N3 = cube(n);
+    for (long p = 0; p < N3; ++p)
+        if (!isfinite(rho[p]) || rho[p] < 0.0) return ORC_E_INPUT;
+    double mean = field_mean(rho, n);
+    if (!(mean > 0.0)) return ORC_E_INPUT;
+    for (long p = 0; p < N3; ++p) m[p] = rho[p] / mean;
+    return ORC_OK;
+}
+
+/* -------------------------------------------- mass on the deformed mesh (App. A) */
+
+/* Trilinear (CIC) interpolant of the grid field m at a point x (grid units). */
+static double cic_interp(const double *m, int n, const double x[3])
+{
+    int f[3];
+    double w1[3];
+    for (int a = 0; a < 3; ++a) {
+        double fl = floor(x[a]);
+        f[a] = (int)fl;
+        w1[a] = x[a] - fl;
+    }
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+        double w = (o0 ? w1[0] : 1.0 - w1[0]) * (o1 ? w1[1] : 1.0 - w1[1]) * (o2 ? w1[2] : 1.0 - w1[2]);
+        s += w * m[at(n, f[0] + o0, f[1] + o1, f[2] + o2)];
+    }
+    return s;
+}
+
+/* M_n = sqrt g_n * rho(x_n): the mass per curvilinear cell, rho sqrt g. */
+void orc_meshmass(const double *phi, const double *m, int n, double *M)
+{
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double s[3], e[3][3], x[3];
+                displacement(phi, n, i, j, k, s);
+                x[0] = i + s[0];
+                x[1] = j + s[1];
+                x[2] = k + s[2];
+                triad(phi, n, i, j, k, e);
+                M[at(n, i, j, k)] = det3(e) * cic_interp(m, n, x);
+            }
+}
+
+/* --------------------------------------------------------- smoothing operator */
+
+void orc_smooth(const double *f, int n, double c0, double *out)
+{
+    double cn = (1.0 - c0) / 6.0;
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double nb = f[at(n, i + 1, j, k)] + f[at(n, i - 1, j, k)] + f[at(n, i, j + 1, k)]
+                          + f[at(n, i, j - 1, k)] + f[at(n, i, j, k + 1)] + f[at(n, i, j, k - 1)];
+                out[at(n, i, j, k)] = c0 * f[at(n, i, j, k)] + cn * nb;
+            }
+}
+
+/* ------------------------------------------------ source of Eq. (elliptic) */
+
+/* t = Sigma + C + E at every node, Sigma = mean(M) - M (App. A).
+ * Returns rho_bar = mean(M). */
+double orc_source_terms(const double *phi, const double *M, int n, double xi_m, double v_m, double *t)
+{
+    double rho_bar = field_mean(M, n);
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double e[3][3];
+                triad(phi, n, i, j, k, e);
+                double g = det3(e);
+                double lam0 = lambda_min_jacobi(e);
+                double sigma = rho_bar - M[at(n, i, j, k)];
+                double r = xi_m / lam0 - 1.0;
+                double C = r > 0.0 ? 4.0 * r * r : 0.0;
+                double E = g > v_m ? -2.0 * fabs(sigma) : 0.0;
+                t[at(n, i, j, k)] = sigma + C + E;
+            }
+    return rho_bar;
+}
+
+/* b = S(Sigma + C + E) with its mean removed (the periodic operator annihilates
+ * constants, so only the mean-free part of the source is solvable). */
+void orc_source(const double *phi, const double *M, int n, double xi_m, double v_m, double c0, double *b)
+{
+    double *t = (double *)malloc(sizeof(double) * cube(n));
+    orc_source_terms(phi, M, n, xi_m, v_m, t);
+    orc_smooth(t, n, c0, b);
+    free(t);
+    double mb = field_mean(b, n);
+    long N3 = cube(n);
+    for (long p = 0; p < N3; ++p) b[p] -= mb;
+}
+
+/* ------------------------------------------ operator div(a grad u) and multigrid */
+
+static inline double face(double an, double anb, double a_min)
+{
+    double c = 0.5 * (an + anb);
+    return c > a_min ? c : a_min;
+}
+
+/* (A u)_n = scale * sum over the six faces of c_f (u_nb - u_n). */
+static double apply_at(const double *u, const double *a, int n, int i, int j, int k, double scale, double a_min)
+{
+    int off[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    double un = u[at(n, i, j, k)], an = a[at(n, i, j, k)];
+    double s = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        long q = at(n, i + off[f][0], j + off[f][1], k + off[f][2]);
+        s += face(an, a[q], a_min) * (u[q] - un);
+    }
+    return scale * s;
+}
+
+void orc_apply(const double *u, const double *a, int n, double scale, double a_min, double *out)
+{
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) out[at(n, i, j, k)] = apply_at(u, a, n, i, j, k, scale, a_min);
+}
+
+void orc_residual(const double *u, const double *a, const double *b, int n, double scale, double a_min, double *r)
+{
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k)
+                r[at(n, i, j, k)] = b[at(n, i, j, k)] - apply_at(u, a, n, i, j, k, scale, a_min);
+}
+
+/* One Gauss-Seidel relaxation at a node: the value of u_n that makes
+ * (A u)_n = b_n with the neighbours held fixed. */
+static double relax_at(const double *u, const double *a, const double *b, int n, int i, int j, int k, double scale,
+                       double a_min)
+{
+    int off[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    double an = a[at(n, i, j, k)];
+    double num = 0.0, den = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        long q = at(n, i + off[f][0], j + off[f][1], k + off[f][2]);
+        double c = face(an, a[q], a_min);
+        num += c * u[q];
+        den += c;
+    }
+    return (num - b[at(n, i, j, k)] / scale) / den;
+}
+
+/* Relax every node of one colour (0 = red, i+j+k even; 1 = black). */
+void orc_rbgs_half(double *u, const double *a, const double *b, int n, double scale, double a_min, int colour)
+{
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k)
+                if (((i + j + k) & 1) == colour) u[at(n, i, j, k)] = relax_at(u, a, b, n, i, j, k, scale, a_min);
+}
+
+/* One red-black Gauss-Seidel sweep: every node of colour `first`, then every
+ * node of the other colour. */
+void orc_rbgs_sweep(double *u, const double *a, const double *b, int n, double scale, double a_min, int first)
+{
+    orc_rbgs_half(u, a, b, n, scale, a_min, first);
+    orc_rbgs_half(u, a, b, n, scale, a_min, 1 - first);
+}
+
+/* 27-point full weighting onto the coarse lattice (coarse node I = fine 2I). */
+void orc_restrict(const double *f, int n, double *c)
+{
+    int nc = n / 2;
+    #pragma omp parallel for
+    for (int I = 0; I < nc; ++I)
+        for (int J = 0; J < nc; ++J)
+            for (int K = 0; K < nc; ++K) {
+                double s = 0.0;
+                for (int di = -1; di <= 1; ++di)
+                    for (int dj = -1; dj <= 1; ++dj)
+                        for (int dk = -1; dk <= 1; ++dk) {
+                            double w = (di ? 0.25 : 0.5) * (dj ? 0.25 : 0.5) * (dk ? 0.25 : 0.5);
+                            s += w * f[at(n, 2 * I + di, 2 * J + dj, 2 * K + dk)];
+                        }
+                c[at(nc, I, J, K)] = s;
+            }
+}
+
+/* u += P e, trilinear interpolation from the coarse lattice (n/2)^3. */
+void orc_prolong_add(double *u, const double *e, int n)
+{
+    int nc = n / 2;
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                int lo[3] = {i / 2, j / 2, k / 2};
+                int odd[3] = {i & 1, j & 1, k & 1};
+                double s = 0.0;
+                for (int c = 0; c < 8; ++c) {
+                    int o[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+                    double w = 1.0;
+                    int skip = 0;
+                    for (int d = 0; d < 3; ++d) {
+                        if (!odd[d]) {
+                            if (o[d]) skip = 1; /* even index: the coarse node itself only */
+                        } else {
+                            w *= 0.5;
+                        }
+                    }
+                    if (skip) continue;
+                    s += w * e[at(nc, lo[0] + o[0], lo[1] + o[1], lo[2] + o[2])];
+                }
+                u[at(n, i, j, k)] += s;
+            }
+}
+
+typedef struct {
+    int levels;
+    int n[32];
+    double *a[32]; /* coefficient per level */
+    double *u[32], *b[32], *r[32];
+    const orc_config *cfg;
+} mg_t;
+
+static double level_scale(int l) { return ldexp(1.0, -2 * l); }
+
+/* Coarsest level: zero-mean right-hand side, then from u = 0 the palindromic
+ * sequence red, black, red, ..., black, red (2 * coarse_sweeps + 1 colour
+ * passes), then the mean of u removed. */
+static void coarse_solve(mg_t *mg, int l)
+{
+    int n = mg->n[l];
+    long N3 = cube(n);
+    double *b = mg->r[l];
+    double mb = field_mean(mg->b[l], n);
+    for (long p = 0; p < N3; ++p) b[p] = mg->b[l][p] - mb;
+    memset(mg->u[l], 0, sizeof(double) * N3);
+    double sc = level_scale(l), amin = mg->cfg->a_min;
+    for (int s = 0; s < mg->cfg->coarse_sweeps; ++s) orc_rbgs_sweep(mg->u[l], mg->a[l], b, n, sc, amin, 0);
+    orc_rbgs_half(mg->u[l], mg->a[l], b, n, sc, amin, 0);
+    double mu = field_mean(mg->u[l], n);
+    for (long p = 0; p < N3; ++p) mg->u[l][p] -= mu;
+}
+
+/* One V-cycle from u = 0 on level l for right-hand side b[l]: n_pre sweeps
+ * red-then-black, residual, full weighting, recursion, trilinear correction,
+ * n_post sweeps black-then-red.  With n_pre == n_post this is a symmetric
+ * operator b -> u (post-smoother = adjoint of the pre-smoother, P = 8 R^T). */
+static void vcycle(mg_t *mg, int l)
+{
+    int n = mg->n[l];
+    memset(mg->u[l], 0, sizeof(double) * cube(n));
+    if (l == mg->levels - 1) {
+        coarse_solve(mg, l);
+        return;
+    }
+    double sc = level_scale(l), amin = mg->cfg->a_min;
+    for (int s = 0; s < mg->cfg->n_pre; ++s) orc_rbgs_sweep(mg->u[l], mg->a[l], mg->b[l], n, sc, amin, 0);
+    orc_residual(mg->u[l], mg->a[l], mg->b[l], n, sc, amin, mg->r[l]);
+    orc_restrict(mg->r[l], n, mg->b[l + 1]);
+    vcycle(mg, l + 1);
+    orc_prolong_add(mg->u[l], mg->u[l + 1], n);
+    for (int s = 0; s < mg->cfg->n_post; ++s) orc_rbgs_sweep(mg->u[l], mg->a[l], mg->b[l], n, sc, amin, 1);
+}
+
+static double norm2(const double *f, int n) { return sqrt(field_dot(f, f, n)); }
+
+int orc_num_levels(int n, int coarse_n)
+{
+    if (n <= 0 || coarse_n < 2 || (coarse_n & 1)) return -1;
+    int L = 1;
+    while (n > coarse_n) {
+        if (n & 1) return -1;
+        n /= 2;
+        ++L;
+    }
+    return n == coarse_n ? L : -1;
+}
+
+static int mg_alloc(mg_t *mg, const double *a0, int n, const orc_config *cfg)
+{
+    memset(mg, 0, sizeof(*mg));
+    mg->cfg = cfg;
+    mg->levels = orc_num_levels(n, cfg->coarse_n);
+    if (mg->levels < 1) return ORC_E_ARG;
+    int nl = n;
+    for (int l = 0; l < mg->levels; ++l, nl /= 2) {
+        mg->n[l] = nl;
+        long N3 = cube(nl);
+        mg->a[l] = (double *)malloc(sizeof(double) * N3);
+        mg->u[l] = (double *)calloc(N3, sizeof(double));
+        mg->b[l] = (double *)malloc(sizeof(double) * N3);
+        mg->r[l] = (double *)malloc(sizeof(double) * N3);
+    }
+    memcpy(mg->a[0], a0, sizeof(double) * cube(n));
+    /* coefficient hierarchy: full weighting of the fine coefficient */
+    for (int l = 1; l < mg->levels; ++l) orc_restrict(mg->a[l - 1], mg->n[l - 1], mg->a[l]);
+    return ORC_OK;
+}
+
+static void mg_free(mg_t *mg)
+{
+    for (int l = 0; l < mg->levels; ++l) {
+        free(mg->a[l]);
+        free(mg->u[l]);
+        free(mg->b[l]);
+        free(mg->r[l]);
+    }
+}
+
+/* z = V-cycle applied to r (fine level). */
+static void precondition(mg_t *mg, const double *r, double *z)
+{
+    long N3 = cube(mg->n[0]);
+    memcpy(mg->b[0], r, sizeof(double) * N3);
+    vcycle(mg, 0);
+    memcpy(z, mg->u[0], sizeof(double) * N3);
+}
+
+/* Apply one V-cycle to a right-hand side (exposed for the tests). */
+int orc_vcycle(const double *a0, const double *r, int n, const orc_config *cfg, double *z)
+{
+    mg_t mg;
+    int rc = mg_alloc(&mg, a0, n, cfg);
+    if (rc) return rc;
+    precondition(&mg, r, z);
+    mg_free(&mg);
+    return ORC_OK;
+}
+
+/* Solve A(a) u = b on mean-free fields from u = 0, to ||b - A u|| <= tol ||b||.
+ * solver 0: conjugate gradients preconditioned by one V-cycle per iteration
+ *           (flexible form: beta = z_new.(r_new - r_old) / z_old.r_old);
+ * solver 1: plain V-cycle iteration u += V(b - A u).
+ * Returns the number of V-cycles (>= 0) or a negative error; *rel receives
+ * the final true relative residual. */
+int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cfg, double *u_out, double *rel)
+{
+    mg_t mg;
+    int rc = mg_alloc(&mg, a0, n, cfg);
+    if (rc) return rc;
+    long N3 = cube(n);
+    double *u = (double *)calloc(N3, sizeof(double));
+    double *r = (double *)malloc(sizeof(double) * N3);
+    double *z = (double *)malloc(sizeof(double) * N3);
+    double *p = (double *)malloc(sizeof(double) * N3);
+    double *q = (double *)malloc(sizeof(double) * N3);
+    double *r_old = (double *)malloc(sizeof(double) * N3);
+
+    int status = ORC_E_NO_CONVERGENCE;
+    double bn = norm2(b0, n);
+    int cycles = 0;
+    if (bn == 0.0) {
+        status = 0;
+    } else if (cfg->solver == 1) {
+        for (cycles = 1; cycles <= cfg->max_vcycles; ++cycles) {
+            orc_residual(u, a0, b0, n, 1.0, cfg->a_min, r);
+            precondition(&mg, r, z);
+            for (long i = 0; i < N3; ++i) u[i] += z[i];
+            orc_residual(u, a0, b0, n, 1.0, cfg->a_min, r);
+            double rn = norm2(r, n);
+            if (!isfinite(rn)) break;
+            if (rn <= cfg->tol * bn) {
+                status = cycles;
+                break;
+            }
+        }
+    } else {
+        memcpy(r, b0, sizeof(double) * N3);
+        precondition(&mg, r, z);
+        cycles = 1;
+        memcpy(p, z, sizeof(double) * N3);
+        double rz = field_dot(r, z, n);
+        while (cycles <= cfg->max_vcycles) {
+            orc_apply(p, a0, n, 1.0, cfg->a_min, q);
+            double pq = field_dot(p, q, n);
+            double alpha = rz / pq;
+            memcpy(r_old, r, sizeof(double) * N3);
+            for (long i = 0; i < N3; ++i) {
+                u[i] += alpha * p[i];
+                r[i] -= alpha * q[i];
+            }
+            double rn = norm2(r, n);
+            if (!isfinite(rn)) break;
+            if (rn <= cfg->tol * bn) {
+                status = cycles;
+                break;
+            }
+            if (cycles == cfg->max_vcycles) break;
+            precondition(&mg, r, z);
+            ++cycles;
+            double rz_new = field_dot(z, r, n);
+            double beta = (rz_new - field_dot(z, r_old, n)) / rz;
+            rz = rz_new;
+            for (long i = 0; i < N3; ++i) p[i] = z[i] + beta * p[i];
+        }
+    }
+    double mu = field_mean(u, n);
+    for (long i = 0; i < N3; ++i) u_out[i] = u[i] - mu;
+    orc_residual(u_out, a0, b0, n, 1.0, cfg->a_min, r);
+    *rel = bn > 0.0 ? norm2(r, n) / bn : 0.0;
+    free(u);
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(r_old);
+    mg_free(&mg);
+    return status;
+}
+
+/* ------------------------------------------------ positive-definite step control */
+
+/* 1 if I + Hess(phi) is positive definite at every node (leading principal
+ * minors e11, e11 e22 - e12^2 and det all positive). */
+int orc_is_pd(const double *phi, int n)
+{
+    int ok = 1;
+    #pragma omp parallel for reduction(&& : ok)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double e[3][3];
+                triad(phi, n, i, j, k, e);
+                double m1 = e[0][0];
+                double m2 = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+                double m3 = det3(e);
+                if (!(m1 > 0.0 && m2 > 0.0 && m3 > 0.0)) ok = 0;
+            }
+    return ok;
+}
+
+double orc_max_shift(const double *f, int n)
+{
+    double mx = 0.0;
+    #pragma omp parallel for reduction(max : mx)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double s[3];
+                displacement(f, n, i, j, k, s);
+                for (int a = 0; a < 3; ++a)
+                    if (fabs(s[a]) > mx) mx = fabs(s[a]);
+            }
+    return mx;
+}
+
+/* First alpha = 2^-j (j = 0..max_halvings) for which phi + alpha dphi keeps the
+ * map positive definite everywhere and no node moves more than s_max cells.
+ * Returns j, or -1 when every trial fails. */
+int orc_choose_step(const double *phi, const double *dphi, int n, const orc_config *cfg, double *alpha_out)
+{
+    long N3 = cube(n);
+    double *trial = (double *)malloc(sizeof(double) * N3);
+    double shift = orc_max_shift(dphi, n);
+    int found = -1;
+    for (int j = 0; j <= cfg->max_halvings; ++j) {
+        double alpha = ldexp(1.0, -j);
+        if (alpha * shift > cfg->s_max) continue;
+        for (long p = 0; p < N3; ++p) trial[p] = phi[p] + alpha * dphi[p];
+        if (orc_is_pd(trial, n)) {
+            found = j;
+            *alpha_out = alpha;
+            break;
+        }
+    }
+    free(trial);
+    return found;
+}
+
+/* -------------------------------------------------------- the outer iteration */
+
+void orc_config_default(orc_config *c)
+{
+    c->max_outer = 10;
+    c->n_pre = 2;
+    c->n_post = 2;
+    c->coarse_n = 8;
+    c->coarse_sweeps = 64;
+    c->max_vcycles = 100;
+    c->max_halvings = 30;
+    c->record_tape = 0;
+    c->solver = 0;
+    c->tol = 1e-10;
+    c->outer_tol = 0.0;
+    c->xi_m = 0.1;
+    c->v_m = 10.0;
+    c->smooth_center = 0.5;
+    c->s_max = 1.0;
+    c->a_min = 1e-3;
+}
+
+/* Reconstructed density delta_r = -(discrete Laplacian of phi), Eq. (rec). */
+void orc_delta_r(const double *phi, int n, double *delta)
+{
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double c = phi[at(n, i, j, k)];
+                double lap = phi[at(n, i + 1, j, k)] + phi[at(n, i - 1, j, k)] + phi[at(n, i, j + 1, k)]
+                           + phi[at(n, i, j - 1, k)] + phi[at(n, i, j, k + 1)] + phi[at(n, i, j, k - 1)] - 6.0 * c;
+                delta[at(n, i, j, k)] = -lap;
+            }
+}
+
+static void invariants(const double *phi, int n, orc_stats *st)
+{
+    double mind = INFINITY, minl = INFINITY, maxd = -INFINITY;
+    #pragma omp parallel for reduction(min : mind, minl) reduction(max : maxd)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                double e[3][3];
+                triad(phi, n, i, j, k, e);
+                double g = det3(e), l = lambda_min_jacobi(e);
+                double d = 3.0 - (e[0][0] + e[1][1] + e[2][2]);
+                if (g < mind) mind = g;
+                if (l < minl) minl = l;
+                if (d > maxd) maxd = d;
+            }
+    st->min_det = mind;
+    st->min_lambda0 = minl;
+    st->max_delta_r = maxd;
+}
+
+/* Tape of the forward iteration: the solution u of every outer step and its
+ * accepted alpha (phi_{i+1} = phi_i + alpha_i S u_i). */
+typedef struct {
+    int n, steps;
+    double *u[ORC_MAX_STEPS];
+    double alpha[ORC_MAX_STEPS];
+    double *m;   /* normalised input density */
+    double mean; /* mean of the raw input density */
+} orc_tape;
+
+static orc_tape g_tape;
+
+void orc_tape_clear(void)
+{
+    for (int s = 0; s < g_tape.steps; ++s) free(g_tape.u[s]);
+    free(g_tape.m);
+    memset(&g_tape, 0, sizeof(g_tape));
+}
+
+/* Full forward reconstruction.  phi_out in (box/n)^2 units (length^2),
+ * delta_out dimensionless.  Either output may be NULL. */
+int orc_solve(const double *rho, int n, double box, const orc_config *cfg, double *phi_out, double *delta_out,
+              orc_stats *st)
+{
+    if (!rho || n <= 0 || box <= 0 || !cfg || cfg->tol <= 0) return ORC_E_ARG;
+    if (orc_num_levels(n, cfg->coarse_n) < 1) return ORC_E_ARG;
+    if (cfg->max_outer > ORC_MAX_STEPS) return ORC_E_ARG;
+    long N3 = cube(n);
+    double *m = (double *)malloc(sizeof(double) * N3);
+    double *phi = (double *)calloc(N3, sizeof(double));
+    double *M = (double *)malloc(sizeof(double) * N3);
+    double *b = (double *)malloc(sizeof(double) * N3);
+    double *u = (double *)malloc(sizeof(double) * N3);
+    double *dphi = (double *)malloc(sizeof(double) * N3);
+    orc_stats local;
+    if (!st) st = &local;
+    memset(st, 0, sizeof(*st));
+    if (cfg->record_tape) orc_tape_clear();
+
+    int status = orc_normalize(rho, n, m);
+    if (status == ORC_OK) {
+        for (int it = 0; it < cfg->max_outer; ++it) {
+            orc_meshmass(phi, m, n, M);
+            double rho_bar = field_mean(M, n);
+            double ss = 0.0;
+            {
+                /* rms of Sigma = rho_bar - M */
+                double *sig = b;
+                for (long p = 0; p < N3; ++p) sig[p] = rho_bar - M[p];
+                ss = field_dot(sig, sig, n);
+            }
+            double rms = sqrt(ss / (double)N3);
+            st->rms_sigma[it] = rms;
+            st->kappa[it] = rho_bar;
+            if (rms <= cfg->outer_tol) break;
+            orc_source(phi, M, n, cfg->xi_m, cfg->v_m, cfg->smooth_center, b);
+            double rel = 0.0;
+            int cyc = orc_mg_solve(M, b, n, cfg, u, &rel);
+            st->rel_residual[it] = rel;
+            if (cyc < 0) {
+                status = cyc;
+                break;
+            }
+            st->vcycles[it] = cyc;
+            st->vcycles_total += cyc;
+            orc_smooth(u, n, cfg->smooth_center, dphi);
+            double alpha = 0.0;
+            if (orc_choose_step(phi, dphi, n, cfg, &alpha) < 0) {
+                status = ORC_E_NOT_PD;
+                break;
+            }
+            for (long p = 0; p < N3; ++p) phi[p] += alpha * dphi[p];
+            st->alpha[it] = alpha;
+            st->outer_steps = it + 1;
+            if (cfg->record_tape) {
+                g_tape.u[it] = (double *)malloc(sizeof(double) * N3);
+                memcpy(g_tape.u[it], u, sizeof(double) * N3);
+                g_tape.alpha[it] = alpha;
+                g_tape.steps = it + 1;
+            }
+        }
+    }
+    if (status == ORC_OK && st->outer_steps == cfg->max_outer) {
+        /* mass deviation left after the last step */
+        orc_meshmass(phi, m, n, M);
+        double rho_bar = field_mean(M, n);
+        for (long p = 0; p < N3; ++p) b[p] = rho_bar - M[p];
+        st->rms_sigma[cfg->max_outer] = sqrt(field_dot(b, b, n) / (double)N3);
+        st->kappa[cfg->max_outer] = rho_bar;
+    }
+    if (status == ORC_OK) {
+        invariants(phi, n, st);
+        if (delta_out) orc_delta_r(phi, n, delta_out);
+        double h = box / n;
+        if (phi_out)
+            for (long p = 0; p < N3; ++p) phi_out[p] = phi[p] * h * h;
+        if (cfg->record_tape) {
+            g_tape.n = n;
+            g_tape.m = m;
+            g_tape.mean = field_mean(rho, n);
+            m = NULL;
+        }
+    } else if (cfg->record_tape) {
+        orc_tape_clear();
+    }
+    free(m);
+    free(phi);
+    free(M);
+    free(b);
+    free(u);
+    free(dphi);
+    return status;
+}
+
+int orc_tape_steps(void) { return g_tape.steps; }

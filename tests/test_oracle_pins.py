@@ -1,0 +1,528 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics
+(closed forms, library routines, invariants, brute force) -- never against
+the oracle itself.  CPU only."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from paper_1611_09638_amd import inputs
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def plane_wave(n, kvec, amp=1.0, phase=0.0):
+    i = np.arange(n)
+    X = np.meshgrid(i, i, i, indexing="ij")
+    arg = sum(2 * np.pi * kvec[a] * X[a] / n for a in range(3)) + phase
+    return amp * np.cos(arg), arg
+
+
+# ------------------------------------------------------------- 3x3 algebra
+
+def test_lambda_min_and_det_match_lapack(orc):
+    """Jacobi lambda_min and det against numpy (LAPACK) on random symmetric matrices."""
+    rng = np.random.default_rng(7)
+    for scale in (1e-3, 0.3, 1.0, 5.0):
+        for _ in range(400):
+            a = rng.normal(size=(3, 3)) * scale
+            e = np.eye(3) + 0.5 * (a + a.T)
+            assert abs(orc.lambda_min(e) - np.linalg.eigvalsh(e)[0]) <= 1e-12 * max(1, abs(e).max())
+            assert abs(orc.det3(e) - np.linalg.det(e)) <= 1e-12 * max(1, abs(e).max() ** 3)
+    # exactly degenerate cases
+    assert orc.lambda_min(np.eye(3)) == 1.0
+    assert abs(orc.lambda_min(np.diag([2.0, 0.05, 0.05])) - 0.05) < 1e-15
+
+
+# --------------------------------------------------------- Hessian / triad
+
+def test_compact_hessian_symbol(orc):
+    """For phi = cos(k.x) the compact second differences have the exact symbols
+    -4 sin^2(k_a/2) (diagonal) and -sin(k_a) sin(k_b) (cross), times cos(k.x)."""
+    n = 16
+    kv = (1, 2, 3)
+    phi, arg = plane_wave(n, kv, amp=0.7)
+    kk = [2 * np.pi * kv[a] / n for a in range(3)]
+    for (i, j, k) in [(0, 0, 0), (3, 5, 7), (15, 1, 9)]:
+        e = orc.triad_at(phi, i, j, k)
+        c = 0.7 * np.cos(arg[i, j, k])
+        H = np.empty((3, 3))
+        for a in range(3):
+            for b in range(3):
+                H[a, b] = -4 * np.sin(kk[a] / 2) ** 2 * c if a == b else -np.sin(kk[a]) * np.sin(kk[b]) * c
+        np.testing.assert_allclose(e, np.eye(3) + H, atol=1e-13)
+
+
+# ------------------------------------------------------------- operators
+
+def test_smoothing_operator_symbol_and_symmetry(orc):
+    n = 16
+    f, arg = plane_wave(n, (1, 0, 5))
+    kk = 2 * np.pi * np.array([1, 0, 5]) / n
+    Sf = orc.smooth(f, 0.5)
+    np.testing.assert_allclose(Sf, (0.5 + np.cos(kk).sum() / 6) * f, atol=1e-13)
+    rng = np.random.default_rng(1)
+    x, y = rng.normal(size=(2, n, n, n))
+    assert abs(np.vdot(orc.smooth(x), y) - np.vdot(x, orc.smooth(y))) < 1e-10
+    assert abs(orc.smooth(x).sum() - x.sum()) < 1e-9  # mean preserving
+
+
+def test_operator_constant_coefficient_is_seven_point_laplacian(orc):
+    n = 16
+    u, arg = plane_wave(n, (2, 1, 7))
+    kk = 2 * np.pi * np.array([2, 1, 7]) / n
+    Au = orc.apply(u, np.ones_like(u), scale=1.0)
+    np.testing.assert_allclose(Au, -(4 * np.sin(kk / 2) ** 2).sum() * u, atol=1e-12)
+    # level scaling 4^-l
+    np.testing.assert_allclose(orc.apply(u, np.ones_like(u), scale=0.25), 0.25 * Au, atol=1e-13)
+
+
+def test_operator_symmetric_conservative_annihilates_constants(orc):
+    n = 12
+    rng = np.random.default_rng(2)
+    a = np.exp(2 * rng.normal(size=(n, n, n)))
+    x, y = rng.normal(size=(2, n, n, n))
+    Ax, Ay = orc.apply(x, a), orc.apply(y, a)
+    assert abs(np.vdot(Ax, y) - np.vdot(x, Ay)) < 1e-10 * np.abs(Ax).sum()
+    assert abs(Ax.sum()) < 1e-10 * np.abs(Ax).sum()  # flux form telescopes
+    np.testing.assert_allclose(orc.apply(np.full((n, n, n), 3.0), a), 0.0, atol=1e-12)
+    # negative semi-definite
+    assert np.vdot(x, Ax) < 0
+
+
+def test_operator_1d_coefficient_flux_form(orc):
+    """Coefficient varying along one axis only: the operator on a field varying
+    along that axis is the textbook 1-D flux difference with face values
+    max(a_min, mean of the two nodes)."""
+    n = 16
+    rng = np.random.default_rng(3)
+    a1 = np.exp(rng.normal(size=n))
+    a1[3] = 1e-6  # exercises the floor
+    u1 = rng.normal(size=n)
+    a = np.broadcast_to(a1[None, None, :], (n, n, n)).copy()
+    u = np.broadcast_to(u1[None, None, :], (n, n, n)).copy()
+    Au = orc.apply(u, a, a_min=1e-3)
+    expect = np.empty(n)
+    for k in range(n):
+        kp, km = (k + 1) % n, (k - 1) % n
+        cp = max(1e-3, 0.5 * (a1[k] + a1[kp]))
+        cm = max(1e-3, 0.5 * (a1[k] + a1[km]))
+        expect[k] = cp * (u1[kp] - u1[k]) + cm * (u1[km] - u1[k])
+    np.testing.assert_allclose(Au[5, 7, :], expect, atol=1e-13)
+
+
+def test_gauss_seidel_zeroes_residual_of_relaxed_colour(orc):
+    """After relaxing one colour the residual vanishes on that colour (brute
+    force against the operator); the other colour is untouched."""
+    n = 8
+    rng = np.random.default_rng(4)
+    a = np.exp(rng.normal(size=(n, n, n)))
+    u, b = rng.normal(size=(2, n, n, n))
+    i = np.arange(n)
+    col = (i[:, None, None] + i[None, :, None] + i[None, None, :]) % 2
+    for colour in (0, 1):
+        for scale in (1.0, 1.0 / 16):
+            v = orc.rbgs_half(u, a, b, colour, scale=scale)
+            r = orc.residual(v, a, b, scale=scale)
+            assert np.abs(r[col == colour]).max() < 1e-11
+            np.testing.assert_array_equal(v[col != colour], u[col != colour])
+    v = orc.rbgs_sweep(u, a, b, first=0)
+    w = orc.rbgs_half(orc.rbgs_half(u, a, b, 0), a, b, 1)
+    np.testing.assert_array_equal(v, w)
+    v = orc.rbgs_sweep(u, a, b, first=1)
+    w = orc.rbgs_half(orc.rbgs_half(u, a, b, 1), a, b, 0)
+    np.testing.assert_array_equal(v, w)
+
+
+def test_restriction_symbol_and_prolongation_adjoint(orc):
+    n = 16
+    f, arg = plane_wave(n, (1, 3, 2))
+    kk = 2 * np.pi * np.array([1, 3, 2]) / n
+    Rf = orc.restrict(f)
+    np.testing.assert_allclose(Rf, np.prod(0.5 + 0.5 * np.cos(kk)) * f[::2, ::2, ::2], atol=1e-13)
+    np.testing.assert_allclose(orc.restrict(np.full((n, n, n), 2.5)), 2.5, atol=1e-14)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(n, n, n))
+    y = rng.normal(size=(n // 2,) * 3)
+    Py = orc.prolong_add(np.zeros((n, n, n)), y)
+    assert abs(np.vdot(orc.restrict(x), y) * 8 - np.vdot(x, Py)) < 1e-10  # P = 8 R^T
+    np.testing.assert_array_equal(Py[::2, ::2, ::2], y)  # injection at coincident nodes
+    np.testing.assert_allclose(orc.prolong_add(np.zeros((n, n, n)), np.full((n // 2,) * 3, 1.5)), 1.5, atol=1e-15)
+
+
+# ------------------------------------------------------------- multigrid
+
+def fft_poisson(b):
+    n = b.shape[0]
+    k = 2 * np.pi * np.fft.fftfreq(n)
+    lam = -(4 * np.sin(k[:, None, None] / 2) ** 2 + 4 * np.sin(k[None, :, None] / 2) ** 2
+            + 4 * np.sin(k[None, None, :] / 2) ** 2)
+    lam[0, 0, 0] = 1.0
+    bh = np.fft.fftn(b)
+    bh[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(bh / lam))
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_multigrid_equals_fft_poisson(orc, solver):
+    """M == 1 turns the operator into the 7-point Laplacian: the solve must
+    equal the FFT Poisson solution (textbook)."""
+    n = 32
+    rng = np.random.default_rng(6)
+    b = rng.normal(size=(n, n, n))
+    b -= b.mean()
+    u, cyc, relres = orc.mg_solve(np.ones_like(b), b, orc.Config(solver=solver, tol=1e-12))
+    assert rel(u, fft_poisson(b)) < 1e-9
+    assert relres <= 1e-12
+
+
+def test_vcycle_contraction_on_poisson(orc):
+    """Textbook V(2,2) RB-GS on the 3-D Poisson problem contracts by ~0.1 per cycle."""
+    n = 32
+    rng = np.random.default_rng(8)
+    b = rng.normal(size=(n, n, n))
+    b -= b.mean()
+    a = np.ones_like(b)
+    cfg = orc.Config()
+    u = np.zeros_like(b)
+    norms = []
+    for _ in range(5):
+        r = orc.residual(u, a, b)
+        norms.append(np.linalg.norm(r))
+        u = u + orc.vcycle(a, r, cfg)
+    rates = [norms[i + 1] / norms[i] for i in range(len(norms) - 1)]
+    assert max(rates) < 0.25, rates
+
+
+def test_vcycle_is_symmetric(orc):
+    """One V-cycle is a symmetric linear map on mean-free fields (needed for CG)."""
+    n = 16
+    rng = np.random.default_rng(9)
+    a = np.exp(1.5 * rng.normal(size=(n, n, n)))
+    x, y = rng.normal(size=(2, n, n, n))
+    x -= x.mean()
+    y -= y.mean()
+    Vx, Vy = orc.vcycle(a, x), orc.vcycle(a, y)
+    assert abs(np.vdot(Vx, y) - np.vdot(x, Vy)) < 1e-11 * abs(np.vdot(Vx, y))
+
+
+def test_num_levels(orc):
+    assert orc.num_levels(32, 8) == 3
+    assert orc.num_levels(512, 8) == 7
+    assert orc.num_levels(8, 2) == 3
+    assert orc.num_levels(24, 8) == -1
+    assert orc.num_levels(12, 8) == -1
+
+
+# ----------------------------------------------------- outer iteration pins
+
+def test_uniform_density_gives_zero_potential(orc):
+    """Uniform density is already isobaric: phi == 0 and delta_r == 0 exactly."""
+    for val in (1.0, 7.25):
+        phi, dr, st = orc.solve(np.full((16, 16, 16), val), 100.0)
+        assert np.all(phi == 0.0) and np.all(dr == 0.0)
+        assert st["outer_steps"] == 0
+
+
+def cic_matrix(x, n):
+    """Sparse matrix W with (W rho)_p = trilinear interpolant of rho at x_p
+    (x: (3, n, n, n) in grid units, periodic), built from the definition."""
+    N3 = n ** 3
+    rows, cols, vals = [], [], []
+    fl = np.floor(x).astype(int)
+    w1 = x - fl
+    p = np.arange(N3)
+    for c in range(8):
+        o = ((c >> 2) & 1, (c >> 1) & 1, c & 1)
+        w = np.ones(N3)
+        idx = []
+        for a in range(3):
+            w = w * (w1[a].ravel() if o[a] else 1 - w1[a].ravel())
+            idx.append((fl[a].ravel() + o[a]) % n)
+        rows.append(p)
+        cols.append((idx[0] * n + idx[1]) * n + idx[2])
+        vals.append(w)
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N3, N3))
+
+
+def analytic_phi(n):
+    """Three low Fourier modes, max shift ~0.2 cell, lambda_0 >= 0.5."""
+    i = np.arange(n)
+    X, Y, Z = np.meshgrid(i, i, i, indexing="ij")
+    t = 2 * np.pi / n
+    phi = (0.45 * np.cos(t * X + 0.3) + 0.35 * np.sin(t * (Y + Z) + 1.1)
+           + 0.3 * np.cos(t * (X - 2 * Z) + 0.7)) * (n / 16) ** 2 * 0.5
+    return phi - phi.mean()
+
+
+def grad_hess_numpy(phi):
+    """Central-difference displacement and compact Hessian written with np.roll."""
+    def sh(f, d):
+        return np.roll(f, (-d[0], -d[1], -d[2]), axis=(0, 1, 2))
+    e = np.eye(3, dtype=int)
+    s = np.stack([0.5 * (sh(phi, e[a]) - sh(phi, -e[a])) for a in range(3)])
+    H = np.empty((3, 3) + phi.shape)
+    for a in range(3):
+        H[a, a] = sh(phi, e[a]) - 2 * phi + sh(phi, -e[a])
+        for b in range(a + 1, 3):
+            H[a, b] = H[b, a] = 0.25 * (sh(phi, e[a] + e[b]) - sh(phi, e[a] - e[b])
+                                        - sh(phi, -e[a] + e[b]) + sh(phi, -e[a] - e[b]))
+    return s, H
+
+
+def test_exact_discrete_fixed_point_recovered(orc):
+    """A potential phi_true is pushed through the determinant: rho is solved
+    (sparse LU) so that det(I + Hess phi_true) * CIC(rho)(x(phi_true)) == 1 at
+    every node.  The oracle must (a) report M == 1 for phi_true and (b) recover
+    phi_true from rho by its own iteration."""
+    n = 16
+    phi_t = analytic_phi(n)
+    s, H = grad_hess_numpy(phi_t)
+    i = np.arange(n, dtype=float)
+    x = np.stack(np.meshgrid(i, i, i, indexing="ij")) + s
+    assert np.abs(s).max() < 0.35
+    g = np.linalg.det(np.moveaxis(np.eye(3)[:, :, None, None, None] + H, (0, 1), (-2, -1)))
+    lam = np.linalg.eigvalsh(np.moveaxis(np.eye(3)[:, :, None, None, None] + H, (0, 1), (-2, -1)))[..., 0]
+    assert lam.min() > 0.4
+    W = cic_matrix(x, n)
+    rho = spla.spsolve(W.tocsc(), (1.0 / g).ravel()).reshape(n, n, n)
+    assert rho.min() > 0
+    # (a) the oracle's deformed-mesh mass at phi_true is exactly uniform
+    M = orc.meshmass(phi_t, rho)
+    np.testing.assert_allclose(M, 1.0, atol=1e-12)
+    rho /= rho.mean()
+    # (b) iteration from phi = 0 converges to phi_true.  With the default
+    # smoothing (c0 = 1/2, whose symbol vanishes at the (pi,pi,pi) corner) the
+    # near-Nyquist modes excited by the first steps contract only slowly; with
+    # c0 = 1 (no smoothing) or 3/4 the fixed point is reached to round-off.
+    box = float(n)  # grid units
+    for c0, steps, bound in ((1.0, 40, 1e-11), (0.75, 60, 1e-11), (0.5, 40, 1e-6)):
+        cfg = orc.Config(max_outer=steps, outer_tol=1e-14, tol=1e-13, smooth_center=c0)
+        phi, dr, st = orc.solve(rho, box, cfg)
+        assert rel(phi, phi_t) < bound, (c0, rel(phi, phi_t))
+        if c0 > 0.5:
+            assert st["rms_sigma"][st["outer_steps"]] <= 1e-13
+
+
+def solve_1d(orc, rho1, axis, n, **kw):
+    shape = [1, 1, 1]
+    shape[axis] = n
+    rho = np.broadcast_to(rho1.reshape(shape), (n, n, n)).copy()
+    cfg = orc.Config(max_outer=kw.get("max_outer", 60), outer_tol=kw.get("outer_tol", 1e-13), tol=1e-12,
+                     smooth_center=kw.get("c0", 0.5))
+    phi, dr, st = orc.solve(rho, float(n), cfg)
+    return phi, dr, st
+
+
+def density_1d(x, n):
+    """Smooth positive 1-D density on [0, n), values in about [0.5, 2]."""
+    t = 2 * np.pi * x / n
+    return np.exp(0.45 * np.sin(t) + 0.2 * np.cos(2 * t + 0.4))
+
+
+def test_one_dimensional_quantile_map(orc):
+    """Plane-parallel density (limiters inactive): the continuum solution is the
+    quantile map F(x(xi)) = xi + c (F = cumulative mass, mean shift zero), and
+    delta_r = 1 - 1/rho(x(xi)) < 1.  The discrete solution must approach it
+    at second order."""
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+
+    errs = []
+    for n in (16, 32, 64):
+        xs = np.arange(n, dtype=float)
+        rho1 = density_1d(xs, n)
+        phi, dr, st = solve_1d(orc, rho1, 0, n, max_outer=30, outer_tol=1e-11, c0=0.75)
+        s = 0.5 * (np.roll(phi[:, 0, 0], -1) - np.roll(phi[:, 0, 0], 1))  # displacement
+        # continuum map (normalised so mean density is 1 over the period)
+        tot = quad(lambda y: density_1d(y, n), 0, n, limit=200)[0]
+
+        def F(y):
+            return quad(lambda z: density_1d(z, n) * n / tot, 0, y, limit=200)[0]
+
+        def x_of(xi, c):
+            return brentq(lambda y: F(y) - (xi + c), xi + c - 3 * n, xi + c + 3 * n)
+
+        # choose c so that the mean displacement vanishes
+        def mean_shift(c):
+            return np.mean([x_of(xi, c) - xi for xi in xs])
+
+        c = brentq(mean_shift, -n / 2, n / 2)
+        s_true = np.array([x_of(xi, c) - xi for xi in xs])
+        errs.append(np.abs(s - s_true).max() / n)  # in units of the period
+        assert dr.max() < 1.0
+        # every plane of the 3-D grid carries the same 1-D solution
+        assert np.abs(phi - phi[:, :1, :1]).max() < 1e-9 * np.abs(phi).max()
+    assert errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3, errs
+
+
+def test_separable_density_gives_additive_potential(orc):
+    """rho = rho1(x) rho2(y) rho3(z): the discrete fixed point is exactly
+    phi = phi1 + phi2 + phi3 with each phi_a the solution for rho_a alone
+    (cross differences vanish; trilinear interpolation of a product factors)."""
+    n = 16
+    xs = np.arange(n, dtype=float)
+    r = [density_1d(xs, n), density_1d((xs * 2 + 3) % n, n), density_1d(n - 1 - xs, n) ** 0.7]
+    parts = [solve_1d(orc, r[a], a, n, c0=0.75)[0] for a in range(3)]
+    rho = r[0][:, None, None] * r[1][None, :, None] * r[2][None, None, :]
+    phi, dr, st = orc.solve(rho, float(n), orc.Config(max_outer=80, outer_tol=1e-13, tol=1e-12,
+                                                      smooth_center=0.75))
+    assert rel(phi, parts[0] + parts[1] + parts[2]) < 1e-9
+
+
+def test_linear_regime_delta_r_equals_input_contrast(orc):
+    """rho = 1 + eps delta: delta_r = eps delta + O(eps^2) with no discretisation
+    error at first order (det(I + H) = 1 + laplacian phi + O(phi^2))."""
+    n = 16
+    i = np.arange(n)
+    X, Y, Z = np.meshgrid(i, i, i, indexing="ij")
+    t = 2 * np.pi / n
+    delta = np.cos(t * X) + 0.5 * np.sin(t * (Y - Z) + 0.3) + 0.3 * np.cos(2 * t * Z + 1.0)
+    errs = []
+    for eps in (1e-3, 1e-4):
+        rho = 1 + eps * delta
+        phi, dr, st = orc.solve(rho, float(n), orc.Config(max_outer=60, outer_tol=eps * 1e-9, tol=1e-12,
+                                                          smooth_center=0.75))
+        errs.append(rel(dr / eps, delta - delta.mean()))
+    assert errs[0] < 5e-3
+    assert 7 < errs[0] / errs[1] < 13, errs
+
+
+def test_equivariance_under_lattice_symmetries(orc):
+    n = 16
+    rho = inputs.lognormal_density(n, 125.0, 1.0, 11)
+    cfg = orc.Config(max_outer=4)
+    phi, dr, st = orc.solve(rho, 125.0, cfg)
+    # even shift: the colouring is unchanged
+    phs, _, st2 = orc.solve(np.roll(rho, (2, 4, -6), axis=(0, 1, 2)), 125.0, cfg)
+    assert st2["alpha"] == st["alpha"]
+    assert rel(phs, np.roll(phi, (2, 4, -6), axis=(0, 1, 2))) < 1e-11
+    # axis permutation
+    php, _, st3 = orc.solve(np.transpose(rho, (2, 0, 1)), 125.0, cfg)
+    assert st3["alpha"] == st["alpha"]
+    assert rel(php, np.transpose(phi, (2, 0, 1))) < 1e-11
+    # odd shift swaps the colours: equal to the solve tolerance
+    pho, _, st4 = orc.solve(np.roll(rho, 1, axis=2), 125.0, cfg)
+    assert st4["alpha"] == st["alpha"]
+    assert rel(pho, np.roll(phi, 1, axis=2)) < 1e-6
+
+
+# ------------------------------------------------------------------ input
+
+def test_cic_particles_brute_force(orc):
+    n, box = 8, 16.0
+    rng = np.random.default_rng(12)
+    pos = (rng.random((200, 3)) * box).astype(np.float32)
+    rho = orc.cic_particles(pos, n, box)
+    ref = np.zeros((n, n, n))
+    for p in pos.astype(np.float64) * n / box:
+        for di in range(-1, 3):
+            for dj in range(-1, 3):
+                for dk in range(-1, 3):
+                    node = np.floor(p) + np.array([di, dj, dk])
+                    w = np.prod(np.maximum(0.0, 1 - np.abs(p - node)))
+                    if w > 0:
+                        ref[tuple(node.astype(int) % n)] += w
+    np.testing.assert_allclose(rho, ref, atol=1e-12)
+    assert abs(rho.sum() - 200) < 1e-10
+    one = orc.cic_particles(np.array([[2 * box / n, 3 * box / n, 5 * box / n]], np.float32), n, box)
+    assert one[2, 3, 5] == 1.0 and one.sum() == 1.0
+
+
+def test_input_errors(orc):
+    n = 8
+    good = np.ones((n, n, n))
+    for bad_val in (-1.0, np.nan, np.inf):
+        bad = good.copy()
+        bad[1, 2, 3] = bad_val
+        with pytest.raises(orc.OracleError) as e:
+            orc.solve(bad, 10.0, orc.Config(coarse_n=2))
+        assert e.value.code == -2
+    with pytest.raises(orc.OracleError) as e:
+        orc.solve(np.zeros((n, n, n)), 10.0, orc.Config(coarse_n=2))
+    assert e.value.code == -2
+    with pytest.raises(orc.OracleError) as e:
+        orc.solve(np.ones((12, 12, 12)), 10.0)  # 12 does not reach 8 by halving
+    assert e.value.code == -1
+
+
+def test_step_and_convergence_errors(orc):
+    rho = inputs.lognormal_density(16, 125.0, 2.0, 3)
+    with pytest.raises(orc.OracleError) as e:
+        orc.solve(rho, 125.0, orc.Config(max_halvings=0))
+    assert e.value.code == -3
+    with pytest.raises(orc.OracleError) as e:
+        orc.solve(rho, 125.0, orc.Config(max_vcycles=1, tol=1e-14))
+    assert e.value.code == -4
+
+
+# ---------------------------------------------- per-step invariants (8^3 dense)
+
+def dense_operator(orc, a):
+    n = a.shape[0]
+    N3 = n ** 3
+    A = np.empty((N3, N3))
+    for p in range(N3):
+        e = np.zeros(N3)
+        e[p] = 1.0
+        A[:, p] = orc.apply(e.reshape(n, n, n), a).ravel()
+    return A
+
+
+def test_each_linearised_step_matches_dense_solve(orc):
+    """8^3 grid: at every outer step the multigrid solution equals the dense
+    solve of the bordered system [A 1; 1^T 0] (numpy.linalg.solve); each step
+    conserves mass (sum b = 0, sum A u = 0) and keeps det > 0 with the map
+    positive definite.  Driving the steps here from the oracle's parts must
+    reproduce the oracle's own outer loop."""
+    n = 8
+    rho = inputs.lognormal_density(n, 40.0, 1.0, 21)
+    cfg = orc.Config(coarse_n=2, max_outer=5, tol=1e-12)
+    m = orc.normalize(rho)
+    phi = np.zeros_like(m)
+    for step in range(cfg.max_outer):
+        M = orc.meshmass(phi, m)
+        b = orc.source(phi, M, cfg.xi_m, cfg.v_m, cfg.smooth_center)
+        assert abs(b.sum()) < 1e-13 * np.abs(b).sum()
+        u, cyc, relres = orc.mg_solve(M, b, cfg)
+        A = dense_operator(orc, M)
+        Bd = np.zeros((n ** 3 + 1, n ** 3 + 1))
+        Bd[:-1, :-1] = A
+        Bd[:-1, -1] = 1.0
+        Bd[-1, :-1] = 1.0
+        sol = np.linalg.solve(Bd, np.concatenate([b.ravel(), [0.0]]))
+        assert rel(u.ravel(), sol[:-1]) < 1e-9
+        Au = orc.apply(u, M)
+        assert abs(Au.sum()) < 1e-12 * np.abs(Au).sum()
+        dphi = orc.smooth(u, cfg.smooth_center)
+        j, alpha = orc.choose_step(phi, dphi, cfg)
+        assert j >= 0
+        phi = phi + alpha * dphi
+        assert orc.is_pd(phi)
+        for (i, jj, k) in [(0, 0, 0), (1, 2, 3), (7, 7, 7)]:
+            assert np.linalg.det(orc.triad_at(phi, i, jj, k)) > 0
+    phi_o, dr_o, st = orc.solve(rho, float(n), cfg)
+    assert rel(phi_o, phi) < 1e-12
+
+
+def test_zeldovich_invariants(orc):
+    """Zel'dovich input (32^3, rms 0.8 cell): every step is PD, delta_r < 3
+    (it equals 3 - tr e), curvilinear grid lines stay monotone (no overlap),
+    and the deformed-mesh mass stays within 1e-2 of the input mass."""
+    n, box = 32, 250.0
+    pos = inputs.zeldovich_particles(n, box, 0.8, 1)
+    rho = orc.cic_particles(pos, n, box)
+    phi, dr, st = orc.solve(rho, box)
+    assert st["outer_steps"] == 10
+    assert st["rms_sigma"][10] < 0.05 * st["rms_sigma"][0]
+    g = phi / (box / n) ** 2
+    assert orc.is_pd(g)
+    assert st["min_det"] > 0 and st["min_lambda0"] > 0
+    assert dr.max() < 3.0 and abs(dr.max() - st["max_delta_r"]) < 1e-12
+    for a in range(3):
+        s = 0.5 * (np.roll(g, -1, axis=a) - np.roll(g, 1, axis=a))
+        dx = 1.0 + np.roll(s, -1, axis=a) - s  # x^a_{n+e_a} - x^a_n
+        assert dx.min() > 0
+    assert all(abs(k - 1) < 1e-2 for k in st["kappa"][:10])
