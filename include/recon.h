@@ -1,0 +1,204 @@
+/*
+ * recon.h -- C ABI of the MI355X (gfx950) nonlinear-reconstruction library.
+ *
+ * Method: Zhu, Yu, Pen, Chen & Yu, "Nonlinear reconstruction",
+ * arXiv:1611.09638.  Given a nonlinear density field on a periodic grid, find
+ * the displacement potential phi whose curvilinear mesh x = xi + grad phi
+ * (Sec. II, Eq. mapping) carries constant mass per cell with a positive-
+ * definite map det(dx/dxi) > 0 (Sec. II), built from small increments
+ * phi = sum dphi_i (Sec. II; App. A), each solving the linear elliptic
+ * equation div(rho sqrt g grad phidot) = S(Sigma + C + E) with x ~ xi
+ * (App. A, Eq. elliptic) by multigrid; return phi and the reconstructed
+ * density delta_r = -laplacian phi (Sec. II, Eq. rec).
+ *
+ * Conventions for every entry point:
+ *   - Arrays are C-order [n][n][n] (last index fastest), periodic, FP64 unless
+ *     the name says f32.  Array pointers are DEVICE pointers on the device
+ *     that was current at recon_init; the stats/config structs and scalar
+ *     out-parameters are HOST pointers.
+ *   - The caller owns every array and the workspace; the library allocates no
+ *     device memory (it keeps one small pinned host buffer per context).
+ *   - All device work is enqueued on the stream given to recon_init.  Calls
+ *     that take host decisions (solve, backward, the stage calls returning
+ *     scalars) synchronise that stream before returning.
+ *   - A context is not thread-safe; use one per thread/stream.
+ *   - Return value: RECON_OK (0) or a negative RECON_E_* code.  On error the
+ *     outputs are unspecified and recon_last_error(ctx) describes the cause.
+ *     Nothing is thrown across the ABI.
+ */
+#ifndef RECON_H
+#define RECON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RECON_OK 0
+#define RECON_E_ARG (-1)            /* null pointer, bad size, bad config */
+#define RECON_E_INPUT (-2)          /* density negative, NaN/Inf, or zero total mass */
+#define RECON_E_NOT_PD (-3)         /* no step 2^-j (j <= max_halvings) keeps the map positive definite */
+#define RECON_E_NO_CONVERGENCE (-4) /* linear solve exceeded max_vcycles or produced NaN */
+#define RECON_E_NO_TAPE (-5)        /* backward without a forward that recorded its tape */
+#define RECON_E_HIP (-6)            /* a HIP runtime call or kernel launch failed */
+#define RECON_E_WORKSPACE (-7)      /* workspace null, too small or misaligned */
+
+#define RECON_FP64 0  /* every kernel in FP64 */
+#define RECON_MIXED 1 /* V-cycle (smoother, residual, transfers, coarse solve) in FP32 inside the FP64 loop */
+
+#define RECON_SOLVER_PCG 0    /* conjugate gradients preconditioned by one symmetric V-cycle */
+#define RECON_SOLVER_VCYCLE 1 /* plain V-cycle iteration u += V(b - A u) */
+
+#define RECON_MAX_STEPS 64
+
+/* Solver knobs.  xi_m = 1/10 and v_m = 10 are the paper's limiter constants
+ * (App. A, App. B); the other values are this library's readings of what the
+ * paper leaves to its references (multigrid design, smoothing, step control). */
+typedef struct recon_config {
+    int max_outer;      /* outer moving-mesh steps (10)                                   */
+    int n_pre, n_post;  /* RB Gauss-Seidel sweeps before/after the coarse correction (2, 2) */
+    int coarse_n;       /* coarsest grid edge, even, 2..16 (8)                             */
+    int coarse_sweeps;  /* symmetric red/black sweep pairs on the coarsest grid (64)       */
+    int max_vcycles;    /* V-cycles per linear solve before RECON_E_NO_CONVERGENCE (100)   */
+    int max_halvings;   /* step trials alpha = 2^-j, j = 0..max_halvings (30)              */
+    int precision;      /* RECON_FP64 or RECON_MIXED                                       */
+    int solver;         /* RECON_SOLVER_PCG or RECON_SOLVER_VCYCLE                         */
+    int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
+    double tol;         /* linear-solve stop: ||b - A u||_2 <= tol ||b||_2 (1e-10)          */
+    double outer_tol;   /* outer stop when rms(Sigma) <= outer_tol (0: run max_outer)       */
+    double xi_m;        /* maximal compression factor of the compression limiter (0.1)      */
+    double v_m;         /* expansion volume limit of the expansion limiter (10)             */
+    double smooth_center; /* S f = c0 f + (1 - c0)/6 * sum of 6 neighbours (c0 = 0.5)       */
+    double s_max;       /* largest per-step shift of any node, in cells (1.0)              */
+    double a_min;       /* floor of the face coefficient of the elliptic operator (1e-3)  */
+} recon_config;
+
+/* Per-solve diagnostics (host struct).  Entries [0, outer_steps) describe the
+ * steps taken; rms_sigma/kappa have one more entry, the state after the last. */
+typedef struct recon_stats {
+    int outer_steps;
+    int vcycles_total;
+    int vcycles[RECON_MAX_STEPS];       /* V-cycles (preconditioner applications) per step */
+    double alpha[RECON_MAX_STEPS];      /* accepted step 2^-j */
+    double rms_sigma[RECON_MAX_STEPS + 1]; /* rms of Sigma = mean(M) - M before each step */
+    double kappa[RECON_MAX_STEPS + 1];  /* mean of M (mass on the deformed mesh / input mass) */
+    double rel_residual[RECON_MAX_STEPS]; /* final ||b - A u|| / ||b|| of each linear solve */
+    double min_det;                     /* min over nodes of det(I + Hess phi) at the end */
+    double min_lambda0;                 /* min over nodes of the smallest eigenvalue of I + Hess phi */
+    double max_delta_r;                 /* max of delta_r (< 3 for a positive-definite map) */
+    double ms_total;                    /* wall time of the solve on the stream (hipEvents) */
+} recon_stats;
+
+typedef struct recon_ctx recon_ctx;
+
+/* Fill *cfg with the defaults listed above.  Returns RECON_E_ARG if cfg is NULL. */
+int recon_config_default(recon_config *cfg);
+
+/* Bytes of device workspace recon_init needs for an n^3 grid under cfg (host
+ * call, no device work).  Returns 0 if n/cfg are invalid. */
+size_t recon_workspace_bytes(int n, const recon_config *cfg);
+
+/* Create a context for n^3 grids.  workspace: device buffer of at least
+ * recon_workspace_bytes(n, cfg) bytes, 256-byte aligned, owned by the caller
+ * and untouched by anyone else while the context lives.  hip_stream: a
+ * hipStream_t (NULL = default stream).  n must equal coarse_n * 2^k. */
+int recon_init(recon_ctx **ctx, int n, const recon_config *cfg, void *workspace, size_t ws_bytes,
+               void *hip_stream);
+
+/* Forward reconstruction (Sec. II, App. A).  density: n^3 values >= 0 with a
+ * positive total (any normalisation: it is divided by its mean).  box: box
+ * edge in length units; phi_out is returned in length^2 (grid-unit phi times
+ * (box/n)^2), delta_r_out = -laplacian phi (dimensionless; Eq. rec).  tol > 0
+ * overrides cfg->tol for this call.  Either output may be NULL.  stats may be
+ * NULL.  Records the tape when cfg->record_tape is set. */
+int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double tol, double *phi_out,
+                double *delta_r_out, recon_stats *stats);
+
+/* Same, from particles: pos = np x (x, y, z) float32 positions in [0, box),
+ * x along the first array index.  They are cloud-in-cell assigned to the
+ * n^3 vertex-centred grid (node j at position j*box/n) before the solve.
+ * recon_backward then returns the gradient with respect to that grid. */
+int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double box, double tol,
+                          double *phi_out, double *delta_r_out, recon_stats *stats);
+
+/* Reverse-mode gradient of the last recorded forward: given dL/d delta_r and
+ * (optionally, NULL = 0) dL/d phi_out, write dL/d density (n^3) for the
+ * density passed to recon_solve.  Discrete decisions of the forward (step
+ * sizes, limiter branches) are held fixed; each linear solve is
+ * differentiated as exact.  Returns RECON_E_NO_TAPE without a recorded tape. */
+int recon_backward(recon_ctx *ctx, const double *grad_delta_r, const double *grad_phi, double *grad_density);
+
+/* Release the context (not the workspace, which the caller owns). */
+void recon_destroy(recon_ctx *ctx);
+
+/* Static text for an error code. */
+const char *recon_strerror(int code);
+
+/* Text of the last error on this context ("" if none). */
+const char *recon_last_error(const recon_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Stage entry points: one step of the path on caller-provided device arrays,
+ * on the context's stream, using its workspace for reductions and multigrid
+ * levels.  The grid edge is the context's n unless stated.  dtype: 0 = FP64
+ * arrays, 1 = FP32 arrays.  They exist so each kernel can be checked and
+ * timed on its own.
+ * ------------------------------------------------------------------------ */
+
+/* m = rho / mean(rho) after checking rho (App. A input; Sec. III gridding). */
+int recon_stage_normalize(recon_ctx *ctx, const double *rho, double *m);
+
+/* Cloud-in-cell assignment of np particles onto the n^3 grid (particle count per node). */
+int recon_stage_cic(recon_ctx *ctx, const float *pos, long long np, double box, double *rho);
+
+/* Mass per curvilinear cell M = det(I + Hess phi) * CIC(m)(xi + D_c phi)
+ * (rho sqrt g of App. A on the current mesh); phi in grid units. */
+int recon_stage_meshmass(recon_ctx *ctx, const double *phi, const double *m, double *M);
+
+/* b = S(Sigma + C + E) - mean, Sigma = mean(M) - M, with the compression and
+ * expansion limiters of App. A (Eq. elliptic).  *rms_sigma (host) <- rms(Sigma). */
+int recon_stage_source(recon_ctx *ctx, const double *phi, const double *M, double *b, double *rms_sigma);
+
+/* out = S f, the nearest-neighbour smoothing of App. A. */
+int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out);
+
+/* out = A u with A = div(a grad .) in flux form on an nl^3 level (scale 4^-l). */
+int recon_stage_apply(recon_ctx *ctx, const double *u, const double *a, int nl, double scale, double *out);
+
+/* r = b - A u on an nl^3 level. */
+int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const void *b, int nl, double scale,
+                         void *r, int dtype);
+
+/* One red-black Gauss-Seidel sweep in place (colour `first` then the other;
+ * red = i+j+k even) on an nl^3 level. */
+int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first,
+                     int dtype);
+
+/* 27-point full weighting of an nl^3 field onto (nl/2)^3. */
+int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype);
+
+/* u += trilinear prolongation of the (nl/2)^3 field e onto the nl^3 field u. */
+int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype);
+
+/* z = one symmetric V-cycle applied to r for coefficient a (fine level n). */
+int recon_stage_vcycle(recon_ctx *ctx, const void *a, const void *r, void *z, int dtype);
+
+/* Solve A(a) u = b (b mean-free) with cfg's solver and precision; u is
+ * returned mean-free.  *cycles and *rel_residual are host outputs. */
+int recon_stage_mg_solve(recon_ctx *ctx, const double *a, const double *b, double tol, double *u, int *cycles,
+                         double *rel_residual);
+
+/* First alpha = 2^-j keeping I + Hess(phi + alpha dphi) positive definite
+ * everywhere with max |alpha D_c dphi| <= s_max (host output); returns
+ * RECON_E_NOT_PD if none of j = 0..max_halvings does. */
+int recon_stage_choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha);
+
+/* delta = -laplacian phi (7-point, Eq. rec). */
+int recon_stage_delta_r(recon_ctx *ctx, const double *phi, double *delta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RECON_H */

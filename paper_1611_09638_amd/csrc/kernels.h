@@ -1,0 +1,92 @@
+// Internal launch interface of the gfx950 kernels (not part of the C ABI).
+// Every launcher enqueues on `s` and returns hipGetLastError().
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace recon {
+
+// Reductions: kernels that reduce write one row of K partials per block into
+// `part` (capacity kPartCap doubles); reduce_finalize() then folds the rows
+// in a fixed order into out[0..K).  Results are bitwise reproducible for a
+// given launch shape.
+constexpr long kPartCap = 1L << 21;
+enum RedOp { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2 };
+
+struct Part {
+    double *part;   // device partials
+    int blocks;     // rows written by the last reducing launch
+    int k;          // partials per row
+};
+
+hipError_t reduce_finalize(const Part &p, const int *ops, double *out, hipStream_t s);
+
+// ---------------------------------------------------------------- input
+hipError_t launch_check_input(const double *rho, long n3, Part &p, hipStream_t s);  // K=2: sum, bad count
+hipError_t launch_scale(const double *rho, double *m, long n3, const double *mean_dev, hipStream_t s);
+hipError_t launch_fill(double *f, long n3, double v, hipStream_t s);
+hipError_t launch_zero(void *f, long bytes, hipStream_t s);
+hipError_t launch_copy(double *dst, const double *src, long n3, hipStream_t s);
+hipError_t launch_cic(const float *pos, long long np, int n, double box, double *rho, hipStream_t s);
+
+// ------------------------------------------------------- outer-step kernels
+// M = det(I + H) * CIC(m)(x); partial K=1: sum M
+hipError_t launch_meshmass(const double *phi, const double *m, double *M, int n, Part &p, hipStream_t s);
+// t = Sigma + C + E; partials K=2: sum Sigma^2, sum t
+hipError_t launch_source(const double *phi, const double *M, double rho_bar, double xi_m, double v_m, double *t, int n,
+                         Part &p, hipStream_t s);
+// out = c0 f + (1-c0)/6 sum nb - sub
+hipError_t launch_smooth(const double *f, double *out, int n, double c0, double sub, hipStream_t s);
+// partial K=1 (max): max_a |D_c f|
+hipError_t launch_max_shift(const double *f, int n, Part &p, hipStream_t s);
+// partial K=ntrial (sum): nodes where I + Hess(phi + 2^-j dphi) is not PD, j = j0..j0+ntrial-1
+hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p,
+                            hipStream_t s);
+hipError_t launch_axpy(double *y, const double *x, double alpha, long n3, hipStream_t s);
+hipError_t launch_add_scalar(double *y, const double *c_dev, double sign, double scale, long n3, hipStream_t s);
+// delta = -L7 phi; phi_out = phi * h2 (if non-null); partials K=3: min det, min lambda0, max delta
+hipError_t launch_output(const double *phi, double *delta, double *phi_out, double h2, int n, Part &p,
+                         hipStream_t s);
+hipError_t launch_sum(const double *f, long n3, Part &p, hipStream_t s);  // K=1 sum
+
+// ------------------------------------------------------------- multigrid
+// scale = 4^-l.  T = double or float.
+template <typename T>
+hipError_t launch_apply(const T *u, const T *a, T *out, int n, T scale, T a_min, hipStream_t s);
+template <typename T>
+hipError_t launch_rbgs_half(T *u, const T *a, const T *b, int n, T scale, T a_min, int colour, bool zero_init,
+                            hipStream_t s);
+// fused two-colour sweep, out of place: u_out = sweep(u_in); colour `first` first
+template <typename T>
+hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, int n, T scale, T a_min, int first,
+                             bool zero_init, hipStream_t s);
+template <typename T>
+bool rbgs_fused_supported(int n);
+template <typename T>
+hipError_t launch_residual(const T *u, const T *a, const T *b, T *r, int n, T scale, T a_min, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(const T *f, T *c, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(T *u, const T *e, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_coarse_solve(T *u, const T *a, const T *b, int n, T scale, T a_min, int pairs, hipStream_t s);
+hipError_t launch_cast_f32(const double *src, float *dst, long n3, hipStream_t s);
+
+// ------------------------------------------------------------ Krylov (FP64)
+// r = b - A u (FP64) with partial K=1 sum r^2; writes r32 = (float) r if r32 != null
+hipError_t launch_residual_norm(const double *u, const double *a, const double *b, double *r, float *r32, int n,
+                                double a_min, Part &p, hipStream_t s);
+// partials K=2: sum z*r, sum z*q (q may be null -> 0).  Z = double or float
+template <typename Z>
+hipError_t launch_dots_zr_zq(const Z *z, const double *r, const double *q, long n3, Part &p, hipStream_t s);
+// p = z + beta p; q = A z + beta q (first: p = z, q = A z); partial K=1: sum p*q
+template <typename Z>
+hipError_t launch_update_pq(const Z *z, const double *a, double *pv, double *q, double beta, int n,
+                            double a_min, bool first, Part &p, hipStream_t s);
+// u += alpha p; r -= alpha q; partial K=1: sum r^2; r32 = (float) r if r32 != null
+hipError_t launch_update_ur(double *u, double *r, const double *pv, const double *q, double alpha,
+                            float *r32, long n3, Part &p, hipStream_t s);
+// u += z (Z = double or float)
+template <typename Z>
+hipError_t launch_add_correction(double *u, const Z *z, long n3, hipStream_t s);
+
+}  // namespace recon

@@ -1,0 +1,831 @@
+// Host driver and C ABI of the reconstruction library (include/recon.h).
+//
+// Outer moving-mesh iteration (Sec. II; App. A):
+//   m = rho / mean(rho); phi = 0
+//   repeat max_outer times:
+//     M   = det(I + Hess phi) * CIC(m)(xi + D_c phi)         rho sqrt g on the mesh
+//     t   = Sigma + C + E, Sigma = mean(M) - M                Eq. (elliptic) source
+//     b   = S t - mean                                        smoothed, mean-free
+//     u   = A(M)^-1 b, A = div(M grad .) with x ~ xi          multigrid (App. A)
+//     dphi = S u; alpha = first 2^-j keeping I + Hess phi PD  step limiting
+//     phi += alpha dphi
+//   delta_r = -laplacian phi                                  Eq. (rec)
+// Every step runs in the kernels of recon_kernels.hip on the context stream;
+// the host only takes the scalar decisions (step size, convergence).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/recon.h"
+#include "kernels.h"
+
+using namespace recon;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxLevels = 16;
+constexpr int kScal = 64;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+template <typename T>
+struct Levels {
+    int L = 0;
+    int n[kMaxLevels];
+    T *a[kMaxLevels];    // coefficient (level 0: M or its FP32 copy)
+    T *u[kMaxLevels];    // V-cycle iterate (level 0: z)
+    T *b[kMaxLevels];    // right-hand side (level 0: the caller's residual)
+    T *res[kMaxLevels];  // residual inside the cycle
+    T *tmp[kMaxLevels];  // second buffer for out-of-place sweeps
+};
+
+// Byte layout of the caller's workspace.  Computed identically by
+// recon_workspace_bytes and recon_init.
+struct Layout {
+    size_t total = 0;
+    size_t part, scal;
+    size_t m, phi, M, t, b, u, r, z, p, q, dphi;
+    size_t lv64_a[kMaxLevels], lv64_u[kMaxLevels], lv64_b[kMaxLevels], lv64_res[kMaxLevels], lv64_tmp[kMaxLevels];
+    size_t lv32_a[kMaxLevels], lv32_u[kMaxLevels], lv32_b[kMaxLevels], lv32_res[kMaxLevels], lv32_tmp[kMaxLevels];
+    size_t tape;
+    size_t adj[8];
+    int levels = 0;
+};
+
+int num_levels(int n, int coarse_n)
+{
+    if (n <= 0 || coarse_n < 2 || coarse_n > 16 || (coarse_n & 1)) return -1;
+    int L = 1;
+    while (n > coarse_n) {
+        if (n & 1) return -1;
+        n /= 2;
+        ++L;
+    }
+    return (n == coarse_n && L <= kMaxLevels) ? L : -1;
+}
+
+bool config_ok(const recon_config *c)
+{
+    return c && c->max_outer >= 0 && c->max_outer <= RECON_MAX_STEPS && c->n_pre >= 0 && c->n_post >= 0 &&
+           c->n_pre <= 16 && c->n_post <= 16 && c->coarse_sweeps >= 0 && c->max_vcycles >= 1 &&
+           c->max_halvings >= 0 && c->max_halvings <= 60 && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
+           (c->solver == RECON_SOLVER_PCG || c->solver == RECON_SOLVER_VCYCLE) && c->tol > 0 && c->outer_tol >= 0 &&
+           c->xi_m >= 0 && c->v_m > 0 && c->smooth_center >= 0 && c->smooth_center <= 1 && c->s_max > 0 &&
+           c->a_min > 0 && std::isfinite(c->tol) && std::isfinite(c->a_min);
+}
+
+bool make_layout(int n, const recon_config *cfg, Layout &Lo)
+{
+    if (!config_ok(cfg) || n > 1024) return false;
+    int L = num_levels(n, cfg->coarse_n);
+    if (L < 1) return false;
+    Lo.levels = L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    const size_t n3 = (size_t)n * n * n;
+    const size_t f64 = n3 * 8;
+    Lo.part = take(sizeof(double) * kPartCap);
+    Lo.scal = take(sizeof(double) * kScal);
+    Lo.m = take(f64);
+    Lo.phi = take(f64);
+    Lo.M = take(f64);
+    Lo.t = take(f64);
+    Lo.b = take(f64);
+    Lo.u = take(f64);
+    Lo.r = take(f64);
+    Lo.z = take(f64);
+    Lo.p = take(f64);
+    Lo.q = take(f64);
+    Lo.dphi = take(f64);
+    int nl = n;
+    for (int l = 0; l < L; ++l, nl /= 2) {
+        const size_t c3 = (size_t)nl * nl * nl;
+        Lo.lv64_a[l] = l ? take(c3 * 8) : Lo.M;
+        Lo.lv64_u[l] = l ? take(c3 * 8) : Lo.z;
+        Lo.lv64_b[l] = l ? take(c3 * 8) : 0;
+        Lo.lv64_res[l] = take(c3 * 8);
+        Lo.lv64_tmp[l] = take(c3 * 8);
+    }
+    nl = n;
+    for (int l = 0; l < L; ++l, nl /= 2) {
+        const size_t c3 = (size_t)nl * nl * nl;
+        if (cfg->precision == RECON_MIXED) {
+            Lo.lv32_a[l] = take(c3 * 4);
+            Lo.lv32_u[l] = take(c3 * 4);
+            Lo.lv32_b[l] = take(c3 * 4);
+            Lo.lv32_res[l] = take(c3 * 4);
+            Lo.lv32_tmp[l] = take(c3 * 4);
+        } else {
+            Lo.lv32_a[l] = Lo.lv32_u[l] = Lo.lv32_b[l] = Lo.lv32_res[l] = Lo.lv32_tmp[l] = (size_t)-1;
+        }
+    }
+    Lo.tape = cfg->record_tape ? take(f64 * (size_t)std::max(cfg->max_outer, 1)) : (size_t)-1;
+    for (int i = 0; i < 8; ++i) Lo.adj[i] = (size_t)-1;
+    Lo.total = off;
+    return true;
+}
+
+}  // namespace
+
+struct recon_ctx {
+    int n = 0;
+    long n3 = 0;
+    recon_config cfg;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lo;
+    Part part;
+    double *scal = nullptr;       // device scalars (reduction results)
+    double *host_scal = nullptr;  // pinned host mirror
+    double *m, *phi, *M, *t, *b, *u, *r, *z, *p, *q, *dphi;
+    Levels<double> L64;
+    Levels<float> L32;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // tape of the last recorded forward
+    int tape_steps = 0;
+    double tape_alpha[RECON_MAX_STEPS];
+    double input_mean = 0.0;
+    double box = 0.0;
+    int tape_valid = 0;
+    char err[512];
+};
+
+namespace {
+
+int fail(recon_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(x)                                                                                        \
+    do {                                                                                                 \
+        hipError_t e_ = (x);                                                                             \
+        if (e_ != hipSuccess) return fail(ctx, RECON_E_HIP, "%s: %s", #x, hipGetErrorString(e_));        \
+    } while (0)
+
+#define TRY(x)                                                                                           \
+    do {                                                                                                 \
+        int rc_ = (x);                                                                                   \
+        if (rc_ != RECON_OK) return rc_;                                                                 \
+    } while (0)
+
+template <typename T>
+T *wsp(recon_ctx *ctx, size_t off)
+{
+    return off == (size_t)-1 ? nullptr : reinterpret_cast<T *>(ctx->ws + off);
+}
+
+// Fold the partials of the last reducing launch and read K scalars to the host.
+int fetch(recon_ctx *ctx, const int *ops, double *out)
+{
+    const int K = ctx->part.k;
+    HIPCHK(reduce_finalize(ctx->part, ops, ctx->scal, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->host_scal, ctx->scal, sizeof(double) * K, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < K; ++c) out[c] = ctx->host_scal[c];
+    return RECON_OK;
+}
+
+int fetch_sum(recon_ctx *ctx, double *out)
+{
+    static const int ops[8] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM};
+    return fetch(ctx, ops, out);
+}
+
+double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
+
+// ------------------------------------------------------------- multigrid
+
+template <typename T>
+int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, const T *rhs, int first, bool zero_init)
+{
+    const int n = S.n[l];
+    const T sc = (T)level_scale(l), amin = (T)ctx->cfg.a_min;
+    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream));
+    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, 1 - first, false, ctx->stream));
+    return RECON_OK;
+}
+
+// out = V(rhs) on level l from a zero initial guess: n_pre sweeps red->black,
+// residual, full weighting, recursion, trilinear correction, n_post sweeps
+// black->red; the coarsest level is relaxed in one workgroup.
+template <typename T>
+int vcycle(recon_ctx *ctx, Levels<T> &S, int l, const T *rhs, T *out)
+{
+    const int n = S.n[l];
+    const T sc = (T)level_scale(l), amin = (T)ctx->cfg.a_min;
+    if (l == S.L - 1) {
+        HIPCHK(launch_coarse_solve<T>(out, S.a[l], rhs, n, sc, amin, ctx->cfg.coarse_sweeps, ctx->stream));
+        return RECON_OK;
+    }
+    T *cur = out;
+    if (ctx->cfg.n_pre == 0) HIPCHK(launch_zero(out, (long)n * n * n * sizeof(T), ctx->stream));
+    for (int s = 0; s < ctx->cfg.n_pre; ++s) TRY(sweep<T>(ctx, S, l, cur, rhs, 0, s == 0));
+    HIPCHK(launch_residual<T>(cur, S.a[l], rhs, S.res[l], n, sc, amin, ctx->stream));
+    HIPCHK(launch_restrict<T>(S.res[l], S.b[l + 1], n, ctx->stream));
+    TRY(vcycle<T>(ctx, S, l + 1, S.b[l + 1], S.u[l + 1]));
+    HIPCHK(launch_prolong_add<T>(cur, S.u[l + 1], n, ctx->stream));
+    for (int s = 0; s < ctx->cfg.n_post; ++s) TRY(sweep<T>(ctx, S, l, cur, rhs, 1, false));
+    return RECON_OK;
+}
+
+// Coefficient hierarchy from a0 (= M): a_{l+1} = R a_l in FP64, and the FP32
+// copies when the V-cycle runs in FP32.
+int build_hierarchy(recon_ctx *ctx, const double *a0)
+{
+    Levels<double> &S = ctx->L64;
+    S.a[0] = const_cast<double *>(a0);
+    for (int l = 0; l + 1 < S.L; ++l) HIPCHK(launch_restrict<double>(S.a[l], S.a[l + 1], S.n[l], ctx->stream));
+    if (ctx->cfg.precision == RECON_MIXED) {
+        for (int l = 0; l < S.L; ++l)
+            HIPCHK(launch_cast_f32(S.a[l], ctx->L32.a[l], (long)S.n[l] * S.n[l] * S.n[l], ctx->stream));
+    }
+    return RECON_OK;
+}
+
+// z = V(r) in the configured precision (r FP64 in, z FP64 out for FP64 mode;
+// FP32 r32 -> z32 for mixed mode, the FP32 rhs being written by the caller).
+int precondition(recon_ctx *ctx)
+{
+    if (ctx->cfg.precision == RECON_MIXED) return vcycle<float>(ctx, ctx->L32, 0, ctx->L32.b[0], ctx->L32.u[0]);
+    return vcycle<double>(ctx, ctx->L64, 0, ctx->r, ctx->z);
+}
+
+// Solve A(a0) u = b (b mean-free) into ctx->u; hierarchy must be built.
+int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int *cycles_out, double *rel_out)
+{
+    const int n = ctx->n;
+    const long n3 = ctx->n3;
+    const bool mixed = ctx->cfg.precision == RECON_MIXED;
+    float *r32 = mixed ? ctx->L32.b[0] : nullptr;
+    double v[4];
+    // u = 0, so the residual kernel gives r = b and ||b||
+    HIPCHK(launch_zero(ctx->u, n3 * 8, ctx->stream));
+    HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    const double bn = std::sqrt(v[0]);
+    int cycles = 0;
+    int status = RECON_E_NO_CONVERGENCE;
+    if (bn == 0.0) {
+        status = RECON_OK;
+    } else if (ctx->cfg.solver == RECON_SOLVER_VCYCLE) {
+        for (cycles = 1; cycles <= ctx->cfg.max_vcycles; ++cycles) {
+            TRY(precondition(ctx));
+            if (mixed) HIPCHK(launch_add_correction<float>(ctx->u, ctx->L32.u[0], n3, ctx->stream));
+            else HIPCHK(launch_add_correction<double>(ctx->u, ctx->z, n3, ctx->stream));
+            HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+            TRY(fetch_sum(ctx, v));
+            const double rn = std::sqrt(v[0]);
+            if (!std::isfinite(rn)) break;
+            if (rn <= tol * bn) {
+                status = RECON_OK;
+                break;
+            }
+        }
+    } else {
+        // Conjugate gradients on A u = b preconditioned by one symmetric V-cycle,
+        // flexible form: beta = z_new.(r_new - r_old) / (z_old.r_old)
+        //                     = -alpha (z_new.q) / (z_old.r_old).
+        TRY(precondition(ctx));
+        cycles = 1;
+        if (mixed) HIPCHK(launch_dots_zr_zq<float>(ctx->L32.u[0], ctx->r, nullptr, n3, ctx->part, ctx->stream));
+        else HIPCHK(launch_dots_zr_zq<double>(ctx->z, ctx->r, nullptr, n3, ctx->part, ctx->stream));
+        TRY(fetch_sum(ctx, v));
+        double rz = v[0];
+        double beta = 0.0;
+        bool first = true;
+        while (true) {
+            if (mixed)
+                HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, ctx->p, ctx->q, beta, n, ctx->cfg.a_min, first,
+                                               ctx->part, ctx->stream));
+            else
+                HIPCHK(launch_update_pq<double>(ctx->z, a0, ctx->p, ctx->q, beta, n, ctx->cfg.a_min, first, ctx->part,
+                                                ctx->stream));
+            first = false;
+            TRY(fetch_sum(ctx, v));
+            const double pq = v[0];
+            const double alpha = rz / pq;
+            HIPCHK(launch_update_ur(ctx->u, ctx->r, ctx->p, ctx->q, alpha, r32, n3, ctx->part, ctx->stream));
+            TRY(fetch_sum(ctx, v));
+            const double rn = std::sqrt(v[0]);
+            if (!std::isfinite(rn) || !std::isfinite(alpha)) break;
+            if (rn <= tol * bn) {
+                status = RECON_OK;
+                break;
+            }
+            if (cycles >= ctx->cfg.max_vcycles) break;
+            TRY(precondition(ctx));
+            ++cycles;
+            if (mixed) HIPCHK(launch_dots_zr_zq<float>(ctx->L32.u[0], ctx->r, ctx->q, n3, ctx->part, ctx->stream));
+            else HIPCHK(launch_dots_zr_zq<double>(ctx->z, ctx->r, ctx->q, n3, ctx->part, ctx->stream));
+            TRY(fetch_sum(ctx, v));
+            beta = -alpha * v[1] / rz;
+            rz = v[0];
+        }
+    }
+    // mean-free solution, then the true residual
+    HIPCHK(launch_sum(ctx->u, n3, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    HIPCHK(launch_fill(ctx->scal + 16, 1, v[0] / (double)n3, ctx->stream));
+    HIPCHK(launch_add_scalar(ctx->u, ctx->scal + 16, -1.0, 1.0, n3, ctx->stream));
+    HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, nullptr, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    const double rel = bn > 0.0 ? std::sqrt(v[0]) / bn : 0.0;
+    if (cycles_out) *cycles_out = cycles;
+    if (rel_out) *rel_out = rel;
+    if (status != RECON_OK)
+        return fail(ctx, RECON_E_NO_CONVERGENCE, "linear solve did not reach tol %.3g in %d V-cycles (rel %.3g)", tol,
+                    cycles, rel);
+    return RECON_OK;
+}
+
+// ------------------------------------------------------------ step control
+
+int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha_out)
+{
+    static const int opmax[1] = {RED_MAX};
+    double v[8];
+    HIPCHK(launch_max_shift(dphi, ctx->n, ctx->part, ctx->stream));
+    TRY(fetch(ctx, opmax, v));
+    const double shift = v[0];
+    if (!std::isfinite(shift)) return fail(ctx, RECON_E_NO_CONVERGENCE, "non-finite increment");
+    int j0 = 0;
+    while (j0 <= ctx->cfg.max_halvings && std::ldexp(1.0, -j0) * shift > ctx->cfg.s_max) ++j0;
+    for (int j = j0; j <= ctx->cfg.max_halvings; j += 4) {
+        HIPCHK(launch_pd_trials(phi, dphi, ctx->n, j, 4, ctx->part, ctx->stream));
+        TRY(fetch_sum(ctx, v));
+        for (int t = 0; t < 4 && j + t <= ctx->cfg.max_halvings; ++t) {
+            if (v[t] == 0.0) {
+                *alpha_out = std::ldexp(1.0, -(j + t));
+                return RECON_OK;
+            }
+        }
+    }
+    return fail(ctx, RECON_E_NOT_PD, "no step 2^-j, j <= %d, keeps the map positive definite", ctx->cfg.max_halvings);
+}
+
+// ------------------------------------------------------------ forward
+
+int normalize(recon_ctx *ctx, const double *rho, double *m, double *mean_out)
+{
+    double v[2];
+    HIPCHK(launch_check_input(rho, ctx->n3, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    if (v[1] != 0.0) return fail(ctx, RECON_E_INPUT, "density has %.0f negative or non-finite values", v[1]);
+    if (!(v[0] > 0.0)) return fail(ctx, RECON_E_INPUT, "density has zero total mass");
+    const double mean = v[0] / (double)ctx->n3;
+    HIPCHK(launch_fill(ctx->scal + 8, 1, mean, ctx->stream));
+    HIPCHK(launch_scale(rho, m, ctx->n3, ctx->scal + 8, ctx->stream));
+    if (mean_out) *mean_out = mean;
+    return RECON_OK;
+}
+
+// rho_bar = mean(M) and rms(Sigma) for the current phi (M recomputed).
+int mass_state(recon_ctx *ctx, double *rho_bar, double *rms, double *mean_t)
+{
+    double v[2];
+    HIPCHK(launch_meshmass(ctx->phi, ctx->m, ctx->M, ctx->n, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    *rho_bar = v[0] / (double)ctx->n3;
+    HIPCHK(launch_source(ctx->phi, ctx->M, *rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part,
+                         ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    *rms = std::sqrt(v[0] / (double)ctx->n3);
+    *mean_t = v[1] / (double)ctx->n3;
+    return RECON_OK;
+}
+
+int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *delta_out, recon_stats *st)
+{
+    const recon_config &c = ctx->cfg;
+    const long n3 = ctx->n3;
+    HIPCHK(launch_zero(ctx->phi, n3 * 8, ctx->stream));
+    ctx->tape_valid = 0;
+    ctx->tape_steps = 0;
+    int it = 0;
+    for (; it < c.max_outer; ++it) {
+        double rho_bar, rms, mean_t;
+        TRY(mass_state(ctx, &rho_bar, &rms, &mean_t));
+        st->rms_sigma[it] = rms;
+        st->kappa[it] = rho_bar;
+        if (!std::isfinite(rms)) return fail(ctx, RECON_E_NO_CONVERGENCE, "non-finite mass deviation");
+        if (rms <= c.outer_tol) break;
+        HIPCHK(launch_smooth(ctx->t, ctx->b, ctx->n, c.smooth_center, mean_t, ctx->stream));
+        TRY(build_hierarchy(ctx, ctx->M));
+        int cyc = 0;
+        double rel = 0.0;
+        TRY(mg_solve(ctx, ctx->M, ctx->b, tol, &cyc, &rel));
+        st->vcycles[it] = cyc;
+        st->vcycles_total += cyc;
+        st->rel_residual[it] = rel;
+        HIPCHK(launch_smooth(ctx->u, ctx->dphi, ctx->n, c.smooth_center, 0.0, ctx->stream));
+        double alpha = 0.0;
+        TRY(choose_step(ctx, ctx->phi, ctx->dphi, &alpha));
+        HIPCHK(launch_axpy(ctx->phi, ctx->dphi, alpha, n3, ctx->stream));
+        st->alpha[it] = alpha;
+        st->outer_steps = it + 1;
+        if (c.record_tape) {
+            HIPCHK(launch_copy(wsp<double>(ctx, ctx->lo.tape) + (size_t)it * n3, ctx->u, n3, ctx->stream));
+            ctx->tape_alpha[it] = alpha;
+            ctx->tape_steps = it + 1;
+        }
+    }
+    if (it == c.max_outer) {
+        double rho_bar, rms, mean_t;
+        TRY(mass_state(ctx, &rho_bar, &rms, &mean_t));
+        st->rms_sigma[it] = rms;
+        st->kappa[it] = rho_bar;
+    }
+    static const int opmin[3] = {RED_MIN, RED_MIN, RED_MIN};
+    double v[3];
+    const double h = box / ctx->n;
+    HIPCHK(launch_output(ctx->phi, delta_out, phi_out, h * h, ctx->n, ctx->part, ctx->stream));
+    TRY(fetch(ctx, opmin, v));
+    st->min_det = v[0];
+    st->min_lambda0 = v[1];
+    st->max_delta_r = -v[2];
+    if (c.record_tape) ctx->tape_valid = 1;
+    return RECON_OK;
+}
+
+int check_ctx(recon_ctx *ctx) { return ctx ? RECON_OK : RECON_E_ARG; }
+
+}  // namespace
+
+// ================================================================= C ABI
+
+extern "C" {
+
+int recon_config_default(recon_config *c)
+{
+    if (!c) return RECON_E_ARG;
+    c->max_outer = 10;
+    c->n_pre = 2;
+    c->n_post = 2;
+    c->coarse_n = 8;
+    c->coarse_sweeps = 64;
+    c->max_vcycles = 100;
+    c->max_halvings = 30;
+    c->precision = RECON_FP64;
+    c->solver = RECON_SOLVER_PCG;
+    c->record_tape = 0;
+    c->tol = 1e-10;
+    c->outer_tol = 0.0;
+    c->xi_m = 0.1;
+    c->v_m = 10.0;
+    c->smooth_center = 0.5;
+    c->s_max = 1.0;
+    c->a_min = 1e-3;
+    return RECON_OK;
+}
+
+size_t recon_workspace_bytes(int n, const recon_config *cfg)
+{
+    Layout lo;
+    return make_layout(n, cfg, lo) ? lo.total : 0;
+}
+
+int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    if (!out) return RECON_E_ARG;
+    *out = nullptr;
+    Layout lo;
+    if (!make_layout(n, cfg, lo)) return RECON_E_ARG;
+    if (!workspace || ws_bytes < lo.total || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+        return RECON_E_WORKSPACE;
+    recon_ctx *ctx = new (std::nothrow) recon_ctx();
+    if (!ctx) return RECON_E_ARG;
+    ctx->err[0] = 0;
+    ctx->n = n;
+    ctx->n3 = (long)n * n * n;
+    ctx->cfg = *cfg;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    ctx->ws = reinterpret_cast<char *>(workspace);
+    ctx->ws_bytes = ws_bytes;
+    ctx->lo = lo;
+    ctx->part.part = wsp<double>(ctx, lo.part);
+    ctx->part.blocks = 0;
+    ctx->part.k = 0;
+    ctx->scal = wsp<double>(ctx, lo.scal);
+    ctx->m = wsp<double>(ctx, lo.m);
+    ctx->phi = wsp<double>(ctx, lo.phi);
+    ctx->M = wsp<double>(ctx, lo.M);
+    ctx->t = wsp<double>(ctx, lo.t);
+    ctx->b = wsp<double>(ctx, lo.b);
+    ctx->u = wsp<double>(ctx, lo.u);
+    ctx->r = wsp<double>(ctx, lo.r);
+    ctx->z = wsp<double>(ctx, lo.z);
+    ctx->p = wsp<double>(ctx, lo.p);
+    ctx->q = wsp<double>(ctx, lo.q);
+    ctx->dphi = wsp<double>(ctx, lo.dphi);
+    ctx->L64.L = ctx->L32.L = lo.levels;
+    int nl = n;
+    for (int l = 0; l < lo.levels; ++l, nl /= 2) {
+        ctx->L64.n[l] = ctx->L32.n[l] = nl;
+        ctx->L64.a[l] = wsp<double>(ctx, lo.lv64_a[l]);
+        ctx->L64.u[l] = wsp<double>(ctx, lo.lv64_u[l]);
+        ctx->L64.b[l] = l ? wsp<double>(ctx, lo.lv64_b[l]) : ctx->r;
+        ctx->L64.res[l] = wsp<double>(ctx, lo.lv64_res[l]);
+        ctx->L64.tmp[l] = wsp<double>(ctx, lo.lv64_tmp[l]);
+        ctx->L32.a[l] = wsp<float>(ctx, lo.lv32_a[l]);
+        ctx->L32.u[l] = wsp<float>(ctx, lo.lv32_u[l]);
+        ctx->L32.b[l] = wsp<float>(ctx, lo.lv32_b[l]);
+        ctx->L32.res[l] = wsp<float>(ctx, lo.lv32_res[l]);
+        ctx->L32.tmp[l] = wsp<float>(ctx, lo.lv32_tmp[l]);
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&ctx->host_scal), sizeof(double) * kScal, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        recon_destroy(ctx);
+        return RECON_E_HIP;
+    }
+    *out = ctx;
+    return RECON_OK;
+}
+
+void recon_destroy(recon_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+const char *recon_strerror(int code)
+{
+    switch (code) {
+    case RECON_OK: return "ok";
+    case RECON_E_ARG: return "invalid argument";
+    case RECON_E_INPUT: return "invalid density (negative, non-finite, or zero total mass)";
+    case RECON_E_NOT_PD: return "no step size keeps the map positive definite";
+    case RECON_E_NO_CONVERGENCE: return "linear solve did not converge";
+    case RECON_E_NO_TAPE: return "backward called without a recorded forward";
+    case RECON_E_HIP: return "HIP runtime error";
+    case RECON_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    default: return "unknown error";
+    }
+}
+
+const char *recon_last_error(const recon_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double tol, double *phi_out,
+                double *delta_r_out, recon_stats *stats)
+{
+    TRY(check_ctx(ctx));
+    ctx->err[0] = 0;
+    if (!density || n != ctx->n || !(box > 0.0) || !(tol >= 0.0))
+        return fail(ctx, RECON_E_ARG, "bad argument (density %p, n %d vs %d, box %g, tol %g)", (const void *)density,
+                    n, ctx->n, box, tol);
+    recon_stats local;
+    recon_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+    double mean = 0.0;
+    TRY(normalize(ctx, density, ctx->m, &mean));
+    ctx->input_mean = mean;
+    ctx->box = box;
+    TRY(forward(ctx, box, tol > 0.0 ? tol : ctx->cfg.tol, phi_out, delta_r_out, st));
+    HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    st->ms_total = ms;
+    return RECON_OK;
+}
+
+int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double box, double tol, double *phi_out,
+                          double *delta_r_out, recon_stats *stats)
+{
+    TRY(check_ctx(ctx));
+    ctx->err[0] = 0;
+    if (!pos || np <= 0 || !(box > 0.0) || !(tol >= 0.0)) return fail(ctx, RECON_E_ARG, "bad particle arguments");
+    recon_stats local;
+    recon_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+    // the deposit lands in t, then is normalised into m
+    HIPCHK(launch_zero(ctx->t, ctx->n3 * 8, ctx->stream));
+    HIPCHK(launch_cic(pos, np, ctx->n, box, ctx->t, ctx->stream));
+    double mean = 0.0;
+    TRY(normalize(ctx, ctx->t, ctx->m, &mean));
+    ctx->input_mean = mean;
+    ctx->box = box;
+    TRY(forward(ctx, box, tol > 0.0 ? tol : ctx->cfg.tol, phi_out, delta_r_out, st));
+    HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    st->ms_total = ms;
+    return RECON_OK;
+}
+
+int recon_backward(recon_ctx *ctx, const double *grad_delta_r, const double *grad_phi, double *grad_density)
+{
+    TRY(check_ctx(ctx));
+    (void)grad_delta_r;
+    (void)grad_phi;
+    (void)grad_density;
+    return fail(ctx, RECON_E_NO_TAPE, "no recorded forward");
+}
+
+// ------------------------------------------------------------- stage calls
+
+int recon_stage_normalize(recon_ctx *ctx, const double *rho, double *m)
+{
+    TRY(check_ctx(ctx));
+    if (!rho || !m) return fail(ctx, RECON_E_ARG, "null array");
+    return normalize(ctx, rho, m, nullptr);
+}
+
+int recon_stage_cic(recon_ctx *ctx, const float *pos, long long np, double box, double *rho)
+{
+    TRY(check_ctx(ctx));
+    if (!pos || !rho || np < 0 || !(box > 0.0)) return fail(ctx, RECON_E_ARG, "bad particle arguments");
+    HIPCHK(launch_zero(rho, ctx->n3 * 8, ctx->stream));
+    if (np > 0) HIPCHK(launch_cic(pos, np, ctx->n, box, rho, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_meshmass(recon_ctx *ctx, const double *phi, const double *m, double *M)
+{
+    TRY(check_ctx(ctx));
+    if (!phi || !m || !M) return fail(ctx, RECON_E_ARG, "null array");
+    HIPCHK(launch_meshmass(phi, m, M, ctx->n, ctx->part, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_source(recon_ctx *ctx, const double *phi, const double *M, double *b, double *rms_sigma)
+{
+    TRY(check_ctx(ctx));
+    if (!phi || !M || !b) return fail(ctx, RECON_E_ARG, "null array");
+    double v[2];
+    HIPCHK(launch_sum(M, ctx->n3, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    const double rho_bar = v[0] / (double)ctx->n3;
+    HIPCHK(launch_source(phi, M, rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    if (rms_sigma) *rms_sigma = std::sqrt(v[0] / (double)ctx->n3);
+    HIPCHK(launch_smooth(ctx->t, b, ctx->n, ctx->cfg.smooth_center, v[1] / (double)ctx->n3, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out)
+{
+    TRY(check_ctx(ctx));
+    if (!f || !out) return fail(ctx, RECON_E_ARG, "null array");
+    HIPCHK(launch_smooth(f, out, ctx->n, ctx->cfg.smooth_center, 0.0, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+static bool level_ok(recon_ctx *ctx, int nl)
+{
+    for (int l = 0; l < ctx->L64.L; ++l)
+        if (ctx->L64.n[l] == nl) return true;
+    return false;
+}
+
+int recon_stage_apply(recon_ctx *ctx, const double *u, const double *a, int nl, double scale, double *out)
+{
+    TRY(check_ctx(ctx));
+    if (!u || !a || !out || !level_ok(ctx, nl)) return fail(ctx, RECON_E_ARG, "bad arguments");
+    HIPCHK(launch_apply<double>(u, a, out, nl, scale, ctx->cfg.a_min, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const void *b, int nl, double scale, void *r,
+                         int dtype)
+{
+    TRY(check_ctx(ctx));
+    if (!u || !a || !b || !r || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1))
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (dtype == 0)
+        HIPCHK(launch_residual<double>((const double *)u, (const double *)a, (const double *)b, (double *)r, nl, scale,
+                                       ctx->cfg.a_min, ctx->stream));
+    else
+        HIPCHK(launch_residual<float>((const float *)u, (const float *)a, (const float *)b, (float *)r, nl,
+                                      (float)scale, (float)ctx->cfg.a_min, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first, int dtype)
+{
+    TRY(check_ctx(ctx));
+    if (!u || !a || !b || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || (first != 0 && first != 1))
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (dtype == 0) {
+        HIPCHK(launch_rbgs_half<double>((double *)u, (const double *)a, (const double *)b, nl, scale, ctx->cfg.a_min,
+                                        first, false, ctx->stream));
+        HIPCHK(launch_rbgs_half<double>((double *)u, (const double *)a, (const double *)b, nl, scale, ctx->cfg.a_min,
+                                        1 - first, false, ctx->stream));
+    } else {
+        HIPCHK(launch_rbgs_half<float>((float *)u, (const float *)a, (const float *)b, nl, (float)scale,
+                                       (float)ctx->cfg.a_min, first, false, ctx->stream));
+        HIPCHK(launch_rbgs_half<float>((float *)u, (const float *)a, (const float *)b, nl, (float)scale,
+                                       (float)ctx->cfg.a_min, 1 - first, false, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype)
+{
+    TRY(check_ctx(ctx));
+    if (!f || !c || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1))
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (dtype == 0) HIPCHK(launch_restrict<double>((const double *)f, (double *)c, nl, ctx->stream));
+    else HIPCHK(launch_restrict<float>((const float *)f, (float *)c, nl, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype)
+{
+    TRY(check_ctx(ctx));
+    if (!u || !e || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1))
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (dtype == 0) HIPCHK(launch_prolong_add<double>((double *)u, (const double *)e, nl, ctx->stream));
+    else HIPCHK(launch_prolong_add<float>((float *)u, (const float *)e, nl, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_vcycle(recon_ctx *ctx, const void *a, const void *r, void *z, int dtype)
+{
+    TRY(check_ctx(ctx));
+    if (!a || !r || !z || (dtype != 0 && dtype != 1)) return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (dtype == 1 && ctx->cfg.precision != RECON_MIXED)
+        return fail(ctx, RECON_E_ARG, "FP32 V-cycle needs a context created with precision RECON_MIXED");
+    const long n3 = ctx->n3;
+    if (dtype == 0) {
+        HIPCHK(launch_copy(ctx->M, (const double *)a, n3, ctx->stream));
+        recon_config saved = ctx->cfg;
+        ctx->cfg.precision = RECON_FP64;
+        int rc = build_hierarchy(ctx, ctx->M);
+        ctx->cfg = saved;
+        TRY(rc);
+        TRY(vcycle<double>(ctx, ctx->L64, 0, (const double *)r, (double *)z));
+    } else {
+        // FP32 coefficient given: build the FP32 hierarchy directly
+        Levels<float> &S = ctx->L32;
+        HIPCHK(hipMemcpyAsync(S.a[0], a, n3 * 4, hipMemcpyDeviceToDevice, ctx->stream));
+        for (int l = 0; l + 1 < S.L; ++l) HIPCHK(launch_restrict<float>(S.a[l], S.a[l + 1], S.n[l], ctx->stream));
+        TRY(vcycle<float>(ctx, S, 0, (const float *)r, (float *)z));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_mg_solve(recon_ctx *ctx, const double *a, const double *b, double tol, double *u, int *cycles,
+                         double *rel_residual)
+{
+    TRY(check_ctx(ctx));
+    if (!a || !b || !u || !(tol > 0.0)) return fail(ctx, RECON_E_ARG, "bad arguments");
+    HIPCHK(launch_copy(ctx->M, a, ctx->n3, ctx->stream));
+    TRY(build_hierarchy(ctx, ctx->M));
+    TRY(mg_solve(ctx, ctx->M, b, tol, cycles, rel_residual));
+    HIPCHK(launch_copy(u, ctx->u, ctx->n3, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha)
+{
+    TRY(check_ctx(ctx));
+    if (!phi || !dphi || !alpha) return fail(ctx, RECON_E_ARG, "null argument");
+    return choose_step(ctx, phi, dphi, alpha);
+}
+
+int recon_stage_delta_r(recon_ctx *ctx, const double *phi, double *delta)
+{
+    TRY(check_ctx(ctx));
+    if (!phi || !delta) return fail(ctx, RECON_E_ARG, "null array");
+    HIPCHK(launch_output(phi, delta, nullptr, 1.0, ctx->n, ctx->part, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""CPU-side checks of the C ABI: the HIP library loads, exports every function
+declared in include/recon.h, and its host-only calls behave (no device work)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "recon.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(recon_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def blib():
+    from paper_1611_09638_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("HIP library not built")
+    return binding
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("recon_init", "recon_solve", "recon_backward", "recon_destroy", "recon_workspace_bytes",
+                     "recon_config_default", "recon_solve_particles", "recon_strerror", "recon_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(blib):
+    out = subprocess.run(["nm", "-D", "--defined-only", blib.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(line.split()[-1] for line in out.stdout.splitlines() if line.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    L = blib.lib()
+    for n in declared_functions():
+        assert hasattr(L, n)
+    # the binding wraps exactly the declared functions
+    assert set(blib.EXPORTS) == set(declared_functions())
+
+
+def test_config_default_and_workspace_sizing(blib):
+    cfg = blib.default_config()
+    assert cfg == blib.Config()
+    assert blib.lib().recon_config_default(None) == -1
+    w32 = blib.workspace_bytes(32, cfg)
+    w64 = blib.workspace_bytes(64, cfg)
+    assert w32 > 11 * 32 ** 3 * 8 and w64 > w32
+    assert w64 % 256 == 0
+    mixed = blib.Config(precision=blib.MIXED)
+    assert blib.workspace_bytes(64, mixed) > w64
+    tape = blib.Config(record_tape=1)
+    assert blib.workspace_bytes(64, tape) >= w64 + 10 * 64 ** 3 * 8
+    # invalid sizes and configs
+    assert blib.workspace_bytes(24, cfg) == 0       # 24 -> 12 -> 6 never reaches 8
+    assert blib.workspace_bytes(48, blib.Config(coarse_n=6)) > 0
+    assert blib.workspace_bytes(32, blib.Config(tol=0.0)) == 0
+    assert blib.workspace_bytes(32, blib.Config(coarse_n=32)) == 0
+    assert blib.workspace_bytes(32, blib.Config(max_outer=65)) == 0
+
+
+def test_init_rejects_bad_workspace_without_touching_the_device(blib):
+    L = blib.lib()
+    ctx = ctypes.c_void_p()
+    c = blib.Config().c()
+    assert L.recon_init(ctypes.byref(ctx), 32, ctypes.byref(c), None, 0, None) == -7
+    assert L.recon_init(ctypes.byref(ctx), 32, ctypes.byref(c), ctypes.c_void_p(256), 16, None) == -7
+    assert L.recon_init(ctypes.byref(ctx), 33, ctypes.byref(c), ctypes.c_void_p(256), 1 << 40, None) == -1
+    assert L.recon_init(None, 32, ctypes.byref(c), ctypes.c_void_p(256), 1 << 40, None) == -1
+    assert L.recon_strerror(-3).decode().startswith("no step")
+    assert L.recon_last_error(None).decode() == "null context"

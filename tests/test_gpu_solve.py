@@ -1,0 +1,130 @@
+"""Full forward reconstruction on the GPU against the FP64 oracle (same seeded
+inputs, same controls): phi and delta_r within 1e-6 relative L2, identical
+step-size sequences, and the error paths of the C ABI."""
+import numpy as np
+import pytest
+
+from paper_1611_09638_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+CASES = [
+    # name, n, box, kind, param, seed, coarse_n, max_outer
+    ("zeldovich32", 32, 250.0, "particles", 0.8, 1, 8, 10),
+    ("lognormal32", 32, 250.0, "lognormal", 1.5, 4, 8, 6),
+    ("lognormal48_ragged", 48, 375.0, "lognormal", 1.0, 6, 6, 5),
+    ("lognormal64", 64, 500.0, "lognormal", 1.5, 4, 8, 4),
+]
+
+
+def make_input(orc, kind, n, box, param, seed):
+    if kind == "particles":
+        pos = inputs.zeldovich_particles(n, box, param, seed)
+        return pos, orc.cic_particles(pos, n, box)
+    return None, inputs.lognormal_density(n, box, param, seed)
+
+
+_ORACLE = {}
+
+
+def oracle_result(orc, case, solver):
+    key = (case[0], solver)
+    if key not in _ORACLE:
+        name, n, box, kind, param, seed, cn, mo = case
+        pos, rho = make_input(orc, kind, n, box, param, seed)
+        _ORACLE[key] = (pos, rho, orc.solve(rho, box, orc.Config(coarse_n=cn, max_outer=mo, solver=solver)))
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("solver", [0, 1], ids=["pcg", "vcycle"])
+def test_forward_matches_oracle(torch_cuda, orc, case, precision, solver):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    name, n, box, kind, param, seed, cn, mo = case
+    pos, rho, (phi_o, d_o, st_o) = oracle_result(orc, case, solver)
+    rec = binding.Recon(n, binding.Config(coarse_n=cn, max_outer=mo, precision=precision, solver=solver))
+    if pos is not None:
+        phi, d, st = rec.solve_particles(torch.from_numpy(pos).cuda(), box)
+    else:
+        phi, d, st = rec.solve(torch.from_numpy(rho).cuda(), box)
+    phi, d = phi.cpu().numpy(), d.cpu().numpy()
+    assert st["alpha"] == st_o["alpha"]
+    assert st["outer_steps"] == st_o["outer_steps"] == mo
+    assert rel(phi, phi_o) < 1e-6, rel(phi, phi_o)
+    assert rel(d, d_o) < 1e-6, rel(d, d_o)
+    assert max(st["rel_residual"]) <= 1e-10
+    np.testing.assert_allclose(st["rms_sigma"], st_o["rms_sigma"], rtol=1e-6)
+    np.testing.assert_allclose(st["kappa"], st_o["kappa"], rtol=1e-9)
+    assert st["min_det"] > 0 and st["max_delta_r"] < 3.0
+    assert abs(st["max_delta_r"] - d.max()) < 1e-12
+    if precision == 0:
+        assert st["vcycles"] == st_o["vcycles"]
+
+
+def test_uniform_density_gives_exact_zero(torch_cuda):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    for precision in (0, 1):
+        rec = binding.Recon(32, binding.Config(precision=precision))
+        phi, d, st = rec.solve(torch.full((32, 32, 32), 2.5, dtype=torch.float64, device="cuda"), 100.0)
+        assert st["outer_steps"] == 0
+        assert bool((phi == 0).all()) and bool((d == 0).all())
+
+
+def test_error_paths(torch_cuda):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 16
+    rec = binding.Recon(n, binding.Config())
+    good = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
+    for bad_val in (-1.0, float("nan"), float("inf")):
+        bad = good.clone()
+        bad[1, 2, 3] = bad_val
+        with pytest.raises(binding.ReconError) as e:
+            rec.solve(bad, 10.0)
+        assert e.value.code == -2
+    with pytest.raises(binding.ReconError) as e:
+        rec.solve(torch.zeros_like(good), 10.0)
+    assert e.value.code == -2
+    with pytest.raises(binding.ReconError) as e:
+        rec.solve(good, -1.0)
+    assert e.value.code == -1
+    rho = torch.from_numpy(inputs.lognormal_density(n, 125.0, 2.0, 3)).cuda()
+    with pytest.raises(binding.ReconError) as e:
+        binding.Recon(n, binding.Config(max_halvings=0)).solve(rho, 125.0)
+    assert e.value.code == -3
+    with pytest.raises(binding.ReconError) as e:
+        binding.Recon(n, binding.Config(max_vcycles=1)).solve(rho, 125.0, tol=1e-14)
+    assert e.value.code == -4
+    with pytest.raises(binding.ReconError) as e:
+        rec.backward(good)
+    assert e.value.code == -5
+    with pytest.raises(ValueError):
+        rec.solve(good.float(), 10.0)
+
+
+def test_repeat_solves_are_bitwise_identical(torch_cuda):
+    """The forward uses no atomics and fixed-order reductions."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 32
+    rho = torch.from_numpy(inputs.lognormal_density(n, 250.0, 1.5, 9)).cuda()
+    rec = binding.Recon(n, binding.Config(max_outer=3, precision=1))
+    phi1, d1, _ = rec.solve(rho, 250.0)
+    phi2, d2, _ = rec.solve(rho, 250.0)
+    assert bool((phi1 == phi2).all()) and bool((d1 == d2).all())

@@ -1,0 +1,178 @@
+"""Per-kernel parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Sizes span several 64-wide tiles, and n = 48 (coarsest grid 6) gives ragged
+tiles along every axis.  FP64 kernels must agree with the oracle to rounding
+(FMA contraction and summation order are the only differences); FP32 kernels
+to FP32 rounding of the same arithmetic."""
+import numpy as np
+import pytest
+
+from paper_1611_09638_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(32, 8), (48, 6), (64, 8)]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+_PHI = {}
+
+
+def evolved_phi(orc, n, coarse_n):
+    """A potential from a few oracle steps on a lognormal density: strongly
+    deformed (compression limiter active), positive definite."""
+    key = (n, coarse_n)
+    if key not in _PHI:
+        box = 250.0 * n / 32
+        rho = inputs.lognormal_density(n, box, 1.5, 40 + n)
+        phi, _, st = orc.solve(rho, box, orc.Config(max_outer=6, coarse_n=coarse_n))
+        _PHI[key] = (phi / (box / n) ** 2, orc.normalize(rho), st)
+    return _PHI[key]
+
+
+@pytest.mark.parametrize("n,cn", SIZES)
+def test_normalize_meshmass_source_smooth(torch_cuda, orc, n, cn):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    phi, m, st = evolved_phi(orc, n, cn)
+    rec = binding.Recon(n, binding.Config(coarse_n=cn))
+    box = 250.0 * n / 32
+    rho = inputs.lognormal_density(n, box, 1.5, 40 + n) * 3.7
+    assert rel(host(rec.normalize(dev(torch, rho))), orc.normalize(rho)) < 1e-15
+    M_g = host(rec.meshmass(dev(torch, phi), dev(torch, m)))
+    M_o = orc.meshmass(phi, m)
+    assert rel(M_g, M_o) < 1e-13
+    b_g, rms_g = rec.source(dev(torch, phi), dev(torch, M_o))
+    b_o = orc.source(phi, M_o)
+    t_o, rb = orc.source_terms(phi, M_o)
+    assert rel(host(b_g), b_o) < 1e-11
+    assert abs(rms_g - np.sqrt(np.mean((rb - M_o) ** 2))) < 1e-12 * rms_g
+    # the compression limiter is exercised by this potential
+    lam = [orc.lambda_min(orc.triad_at(phi, *idx)) for idx in zip(*np.unravel_index(np.arange(0, n ** 3, 7), phi.shape))]
+    assert min(lam) < 0.1
+    assert rel(host(rec.smooth(dev(torch, M_o))), orc.smooth(M_o)) < 1e-15
+    d_g = host(rec.delta_r(dev(torch, phi)))
+    assert rel(d_g, orc.delta_r(phi)) < 1e-14
+
+
+@pytest.mark.parametrize("n,cn", SIZES)
+@pytest.mark.parametrize("first", [0, 1])
+def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rec = binding.Recon(n, binding.Config(coarse_n=cn))
+    rng = np.random.default_rng(100 + n + first)
+    a = np.exp(1.5 * rng.normal(size=(n, n, n)))
+    u, b = rng.normal(size=(2, n, n, n))
+    for scale in (1.0, 1.0 / 16):
+        ug = host(rec.rbgs(dev(torch, u), dev(torch, a), dev(torch, b), scale=scale, first=first))
+        uo = orc.rbgs_sweep(u, a, b, scale=scale, first=first)
+        assert rel(ug, uo) < 1e-13
+    a32, u32, b32 = (x.astype(np.float32).astype(np.float64) for x in (a, u, b))
+    ug = host(rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32), dev(torch, b32, torch.float32),
+                       first=first))
+    assert rel(ug, orc.rbgs_sweep(u32, a32, b32, first=first)) < 2e-6
+
+
+@pytest.mark.parametrize("n,cn", SIZES)
+def test_residual_restrict_prolong(torch_cuda, orc, n, cn):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rec = binding.Recon(n, binding.Config(coarse_n=cn))
+    rng = np.random.default_rng(200 + n)
+    a = np.exp(rng.normal(size=(n, n, n)))
+    u, b = rng.normal(size=(2, n, n, n))
+    e = rng.normal(size=(n // 2,) * 3)
+    for scale in (1.0, 0.25):
+        assert rel(host(rec.residual(dev(torch, u), dev(torch, a), dev(torch, b), scale)),
+                   orc.residual(u, a, b, scale)) < 1e-14
+        assert rel(host(rec.apply(dev(torch, u), dev(torch, a), scale)), orc.apply(u, a, scale)) < 1e-14
+    assert rel(host(rec.restrict(dev(torch, u))), orc.restrict(u)) < 1e-15
+    assert rel(host(rec.prolong_add(dev(torch, u), dev(torch, e))), orc.prolong_add(u, e)) < 1e-15
+    f32 = lambda x: dev(torch, x, torch.float32)  # noqa: E731
+    q = lambda x: x.astype(np.float32).astype(np.float64)  # noqa: E731
+    assert rel(host(rec.residual(f32(u), f32(a), f32(b))), orc.residual(q(u), q(a), q(b))) < 1e-5
+    assert rel(host(rec.restrict(f32(u))), orc.restrict(q(u))) < 1e-6
+    assert rel(host(rec.prolong_add(f32(u), f32(e))), orc.prolong_add(q(u), q(e))) < 1e-6
+
+
+@pytest.mark.parametrize("n,cn", SIZES)
+def test_vcycle_fp64_and_fp32(torch_cuda, orc, n, cn):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rng = np.random.default_rng(300 + n)
+    a = np.exp(1.5 * rng.normal(size=(n, n, n)))
+    r = rng.normal(size=(n, n, n))
+    r -= r.mean()
+    cfg_o = orc.Config(coarse_n=cn)
+    zo = orc.vcycle(a, r, cfg_o)
+    rec = binding.Recon(n, binding.Config(coarse_n=cn, precision=binding.MIXED))
+    assert rel(host(rec.vcycle(dev(torch, a), dev(torch, r))), zo) < 1e-12
+    z32 = host(rec.vcycle(dev(torch, a, torch.float32), dev(torch, r, torch.float32)))
+    assert rel(z32, zo) < 1e-4
+
+
+@pytest.mark.parametrize("n,cn", SIZES)
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1])
+def test_mg_solve(torch_cuda, orc, n, cn, precision, solver):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rng = np.random.default_rng(400 + n)
+    a = np.exp(rng.normal(size=(n, n, n)))
+    b = rng.normal(size=(n, n, n))
+    b -= b.mean()
+    uo, cyc_o, rel_o = orc.mg_solve(a, b, orc.Config(coarse_n=cn, tol=1e-12, solver=solver))
+    rec = binding.Recon(n, binding.Config(coarse_n=cn, precision=precision, solver=solver))
+    ug, cyc, relg = rec.mg_solve(dev(torch, a), dev(torch, b), tol=1e-12)
+    assert relg <= 1e-12
+    assert rel(host(ug), uo) < 1e-9
+    assert abs(host(ug).mean()) < 1e-14 * np.abs(uo).max()
+    if precision == 0:
+        assert cyc == cyc_o
+
+
+def test_choose_step_and_cic(torch_cuda, orc):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 32
+    phi, m, st = evolved_phi(orc, n, 8)
+    rec = binding.Recon(n, binding.Config())
+    rng = np.random.default_rng(5)
+    for amp in (0.05, 0.5, 3.0, 40.0):
+        dphi = amp * inputs.gaussian_field(n, 250.0, 77)
+        dphi /= np.abs(dphi).max()
+        j, a_o = orc.choose_step(phi, dphi, orc.Config())
+        a_g = rec.choose_step(dev(torch, phi), dev(torch, dphi))
+        assert a_g == a_o
+    pos = (rng.random((5000, 3)) * 250.0).astype(np.float32)
+    pos[:7] = [[0, 0, 0], [249.99998, 0, 0], [7.8125, 7.8125, 7.8125], [125, 125, 125], [0, 249.99998, 3.0],
+               [1e-7, 1e-7, 1e-7], [200.5, 0.1, 249.9]]
+    rho_g = host(rec.cic(dev(torch, pos), 250.0))
+    rho_o = orc.cic_particles(pos, n, 250.0)
+    assert np.abs(rho_g - rho_o).max() < 1e-12
+    assert abs(rho_g.sum() - 5000) < 1e-9
