@@ -1,0 +1,167 @@
+"""Benchmark of the reconstruction hot path on one MI355X.
+
+A step is one full reconstruction (recon_solve: input conditioning, 10 outer
+steps of deformed-mesh mass, limited source, multigrid-preconditioned solve,
+step control, and the output delta_r) of the 512^3 lognormal field
+(box 1000 Mpc/h, sigma_g = 2.0), with the density already resident in HBM.
+The headline value is the wall time of the mixed-precision solve (FP32
+V-cycle inside the FP64 Krylov loop); the FP64 solve is timed the same way
+and both are compared (rel. L2 of phi and delta_r).  The finest-level
+red-black Gauss-Seidel smoother is timed live with hipEvents inside the
+library (cfg.profile) to give its achieved HBM bandwidth.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU per process;
+the multi-GPU decomposition is described in the design doc).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "recon wall time + smoother HBM GB/s at 512^3, mixed vs FP64, at 1e-6 rel L2"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(rho, n, stats, cores):
+    """Oracle (FP64 C, OpenMP) on a bounded sample of the same workload: one
+    deformed-mesh mass, one source, one V-cycle and one operator application
+    at full size, scaled by the GPU solve's outer steps and V-cycle count."""
+    import oracle
+
+    oracle.build(force=False)
+    m = oracle.normalize(rho)
+    phi = np.zeros_like(m)
+    t0 = time.perf_counter()
+    M = oracle.meshmass(phi, m)
+    t_mm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = oracle.source(phi, M)
+    t_src = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    z = oracle.vcycle(M, b)
+    t_vc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.apply(z, M)
+    t_ap = time.perf_counter() - t0
+    outer = stats["outer_steps"]
+    vc = stats["vcycles_total"]
+    est = outer * (t_mm + t_src) + vc * (t_vc + t_ap)
+    return {"value": round(est, 3), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": ("one oracle meshmass (%.2fs), source (%.2fs), V-cycle (%.2fs) and operator application "
+                       "(%.2fs) at %d^3, scaled by the GPU solve's %d outer steps and %d V-cycles"
+                       % (t_mm, t_src, t_vc, t_ap, n, outer, vc))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lognormal512")
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the oracle CPU baseline")
+    ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU (one process per GPU; --gpus %d is not supported, "
+              "see DESIGN.md for the multi-GPU decomposition)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1611_09638_amd import binding, inputs
+
+    w = inputs.WORKLOADS[args.workload]
+    if w["kind"] != "lognormal":
+        raise SystemExit("bench workload must be a density grid")
+    n, box = w["n"], w["box"]
+    t0 = time.perf_counter()
+    rho = inputs.lognormal_density(n, box, w["sigma_g"], w["seed"])
+    log("input %s generated in %.1fs" % (args.workload, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    rho_d = torch.from_numpy(rho).to(dev)
+
+    results = {}
+    modes = {"fp64": binding.FP64, "mixed": binding.MIXED}
+    if args.only != "both":
+        modes = {args.only: modes[args.only]}
+    for name, prec in modes.items():
+        rec = binding.Recon(n, binding.Config(precision=prec, profile=1), device=dev)
+        for i in range(args.warmup):
+            rec.solve(rho_d, box)
+            log("%s warmup %d done" % (name, i))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        walls, sts = [], []
+        for i in range(args.steps):
+            phi, delta, st = rec.solve(rho_d, box)
+            walls.append(st["ms_total"])
+            sts.append(st)
+            log("%s step %d: %.1f ms, %d V-cycles" % (name, i, st["ms_total"], st["vcycles_total"]))
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        results[name] = dict(wall_s=wall, ms=float(np.median(walls)), stats=sts[-1], phi=phi, delta=delta)
+        del rec
+        torch.cuda.empty_cache()
+
+    head = "mixed" if "mixed" in results else "fp64"
+    H = results[head]
+    st = H["stats"]
+    node_bytes = 16 if head == "mixed" else 32
+    sweep_ms = st["smoother_ms"] / max(st["smoother_sweeps"], 1)
+    achieved = node_bytes * n ** 3 / (sweep_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(H["wall_s"], 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(H["wall_s"] * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "box": box, "sigma_g": w["sigma_g"], "seed": w["seed"],
+                   "max_outer": 10, "tol": 1e-10, "solver": "pcg+vcycle(2,2)", "precision": head},
+        "outer_steps": st["outer_steps"],
+        "vcycles_total": st["vcycles_total"],
+        "alpha": st["alpha"],
+    }
+    for name, R in results.items():
+        s = R["stats"]
+        nb = 16 if name == "mixed" else 32
+        sm = s["smoother_ms"] / max(s["smoother_sweeps"], 1)
+        out["%s_s" % name] = round(R["wall_s"], 4)
+        out["%s_smoother" % name] = {"sweeps": s["smoother_sweeps"], "ms_per_sweep": round(sm, 4),
+                                     "GBps": round(nb * n ** 3 / (sm * 1e-3) / 1e9, 1),
+                                     "bytes_per_node": nb, "vcycles": s["vcycles_total"]}
+    if len(results) == 2:
+        a, b = results["mixed"], results["fp64"]
+        out["speedup_mixed_vs_fp64"] = round(b["wall_s"] / a["wall_s"], 3)
+        out["rel_l2_phi_mixed_vs_fp64"] = float((a["phi"] - b["phi"]).norm() / b["phi"].norm())
+        out["rel_l2_delta_mixed_vs_fp64"] = float((a["delta"] - b["delta"]).norm() / b["delta"].norm())
+        out["alpha_equal"] = a["stats"]["alpha"] == b["stats"]["alpha"]
+    out["roofline"] = {"bound": "hbm", "kernel": "k_rbgs_half<%s,1> (finest level, one sweep = 2 launches)"
+                       % ("float" if head == "mixed" else "double"),
+                       "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "bytes_per_node_per_sweep": node_bytes, "nodes": n ** 3}
+    if not args.skip_cpu:
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+        out["cpu_baseline"] = cpu_baseline(rho, n, st, cores)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,6 +65,7 @@ typedef struct recon_config {
     int precision;      /* RECON_FP64 or RECON_MIXED                                       */
     int solver;         /* RECON_SOLVER_PCG or RECON_SOLVER_VCYCLE                         */
     int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
+    int profile;        /* 1: time every fine-level smoother sweep with hipEvents (stats)  */
     double tol;         /* linear-solve stop: ||b - A u||_2 <= tol ||b||_2 (1e-10)          */
     double outer_tol;   /* outer stop when rms(Sigma) <= outer_tol (0: run max_outer)       */
     double xi_m;        /* maximal compression factor of the compression limiter (0.1)      */
@@ -88,6 +89,8 @@ typedef struct recon_stats {
     double min_lambda0;                 /* min over nodes of the smallest eigenvalue of I + Hess phi */
     double max_delta_r;                 /* max of delta_r (< 3 for a positive-definite map) */
     double ms_total;                    /* wall time of the solve on the stream (hipEvents) */
+    int smoother_sweeps;                /* fine-level RB-GS sweeps timed (cfg.profile) */
+    double smoother_ms;                 /* their summed kernel time on the stream */
 } recon_stats;
 
 typedef struct recon_ctx recon_ctx;

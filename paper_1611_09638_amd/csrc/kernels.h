@@ -54,7 +54,7 @@ template <typename T>
 hipError_t launch_apply(const T *u, const T *a, T *out, int n, T scale, T a_min, hipStream_t s);
 template <typename T>
 hipError_t launch_rbgs_half(T *u, const T *a, const T *b, int n, T scale, T a_min, int colour, bool zero_init,
-                            hipStream_t s);
+                            hipStream_t s, bool fine = false);
 // fused two-colour sweep, out of place: u_out = sweep(u_in); colour `first` first
 template <typename T>
 hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, int n, T scale, T a_min, int first,

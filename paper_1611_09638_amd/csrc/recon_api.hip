@@ -152,6 +152,9 @@ struct recon_ctx {
     Levels<double> L64;
     Levels<float> L32;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // cfg.profile: event pairs around each fine-level smoother sweep
+    hipEvent_t *prof = nullptr;
+    int prof_count = 0;
     // tape of the last recorded forward
     int tape_steps = 0;
     double tape_alpha[RECON_MAX_STEPS];
@@ -213,13 +216,33 @@ double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
 
 // ------------------------------------------------------------- multigrid
 
+constexpr int kProfPairs = 4096;
+
 template <typename T>
 int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, const T *rhs, int first, bool zero_init)
 {
     const int n = S.n[l];
     const T sc = (T)level_scale(l), amin = (T)ctx->cfg.a_min;
-    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream));
-    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, 1 - first, false, ctx->stream));
+    const bool timed = l == 0 && ctx->prof && ctx->prof_count < kProfPairs;
+    if (timed) HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count], ctx->stream));
+    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream, l == 0));
+    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, 1 - first, false, ctx->stream, l == 0));
+    if (timed) HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count++ + 1], ctx->stream));
+    return RECON_OK;
+}
+
+// Sum the recorded fine-level sweep times (stream already synchronised).
+int collect_profile(recon_ctx *ctx, recon_stats *st)
+{
+    double ms = 0.0;
+    for (int i = 0; i < ctx->prof_count; ++i) {
+        float e = 0.0f;
+        HIPCHK(hipEventElapsedTime(&e, ctx->prof[2 * i], ctx->prof[2 * i + 1]));
+        ms += e;
+    }
+    st->smoother_sweeps = ctx->prof_count;
+    st->smoother_ms = ms;
+    ctx->prof_count = 0;
     return RECON_OK;
 }
 
@@ -556,6 +579,18 @@ int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace,
         recon_destroy(ctx);
         return RECON_E_HIP;
     }
+    if (cfg->profile) {
+        ctx->prof = new (std::nothrow) hipEvent_t[2 * kProfPairs]();
+        if (!ctx->prof) {
+            recon_destroy(ctx);
+            return RECON_E_ARG;
+        }
+        for (int i = 0; i < 2 * kProfPairs; ++i)
+            if (hipEventCreate(&ctx->prof[i]) != hipSuccess) {
+                recon_destroy(ctx);
+                return RECON_E_HIP;
+            }
+    }
     *out = ctx;
     return RECON_OK;
 }
@@ -566,6 +601,11 @@ void recon_destroy(recon_ctx *ctx)
     if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->prof) {
+        for (int i = 0; i < 2 * kProfPairs; ++i)
+            if (ctx->prof[i]) (void)hipEventDestroy(ctx->prof[i]);
+        delete[] ctx->prof;
+    }
     delete ctx;
 }
 
@@ -597,6 +637,7 @@ int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double
     recon_stats local;
     recon_stats *st = stats ? stats : &local;
     std::memset(st, 0, sizeof(*st));
+    ctx->prof_count = 0;
     HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
     double mean = 0.0;
     TRY(normalize(ctx, density, ctx->m, &mean));
@@ -608,6 +649,7 @@ int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     st->ms_total = ms;
+    TRY(collect_profile(ctx, st));
     return RECON_OK;
 }
 
@@ -620,6 +662,7 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
     recon_stats local;
     recon_stats *st = stats ? stats : &local;
     std::memset(st, 0, sizeof(*st));
+    ctx->prof_count = 0;
     HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
     // the deposit lands in t, then is normalised into m
     HIPCHK(launch_zero(ctx->t, ctx->n3 * 8, ctx->stream));
@@ -634,6 +677,7 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     st->ms_total = ms;
+    TRY(collect_profile(ctx, st));
     return RECON_OK;
 }
 

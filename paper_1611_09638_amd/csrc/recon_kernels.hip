@@ -685,7 +685,8 @@ hipError_t launch_residual(const T *u, const T *a, const T *b, T *r, int n, T sc
 // Gauss-Seidel relaxation of one colour, in place: u_n <- (sum c_f u_nb -
 // b_n / scale) / sum c_f at nodes with (i+j+k) % 2 == colour.  With zero_init
 // every neighbour is taken as 0 (the first half-sweep from u = 0).
-template <typename T>
+// (FINE only separates the finest-level launches by name in kernel traces.)
+template <typename T, int FINE>
 __global__ void k_rbgs_half(T *__restrict__ u, const T *__restrict__ a, const T *__restrict__ b, int n, int ipb,
                             T inv_scale, T a_min, int colour, int zero_init)
 {
@@ -716,7 +717,7 @@ __global__ void k_rbgs_half(T *__restrict__ u, const T *__restrict__ a, const T 
 
 template <typename T>
 hipError_t launch_rbgs_half(T *u, const T *a, const T *b, int n, T scale, T a_min, int colour, bool zero_init,
-                            hipStream_t s)
+                            hipStream_t s, bool fine)
 {
     const int half = n / 2;
     int bx = half < 64 ? half : 64;
@@ -726,7 +727,10 @@ hipError_t launch_rbgs_half(T *u, const T *a, const T *b, int n, T scale, T a_mi
     int ipb = (n + gz - 1) / gz;
     gz = (n + ipb - 1) / ipb;
     dim3 grid((half + bx - 1) / bx, (n + by - 1) / by, gz), block(bx, by, 1);
-    k_rbgs_half<T><<<grid, block, 0, s>>>(u, a, b, n, ipb, (T)1 / scale, a_min, colour, zero_init ? 1 : 0);
+    if (fine)
+        k_rbgs_half<T, 1><<<grid, block, 0, s>>>(u, a, b, n, ipb, (T)1 / scale, a_min, colour, zero_init ? 1 : 0);
+    else
+        k_rbgs_half<T, 0><<<grid, block, 0, s>>>(u, a, b, n, ipb, (T)1 / scale, a_min, colour, zero_init ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1048,7 +1052,7 @@ hipError_t launch_add_correction(double *u, const Z *z, long n3, hipStream_t s)
 
 #define RECON_INSTANTIATE(T)                                                                                       \
     template hipError_t launch_apply<T>(const T *, const T *, T *, int, T, T, hipStream_t);                        \
-    template hipError_t launch_rbgs_half<T>(T *, const T *, const T *, int, T, T, int, bool, hipStream_t);         \
+    template hipError_t launch_rbgs_half<T>(T *, const T *, const T *, int, T, T, int, bool, hipStream_t, bool);   \
     template hipError_t launch_residual<T>(const T *, const T *, const T *, T *, int, T, T, hipStream_t);          \
     template hipError_t launch_restrict<T>(const T *, T *, int, hipStream_t);                                      \
     template hipError_t launch_prolong_add<T>(T *, const T *, int, hipStream_t);                                   \

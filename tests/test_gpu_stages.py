@@ -71,9 +71,8 @@ def test_normalize_meshmass_source_smooth(torch_cuda, orc, n, cn):
     t_o, rb = orc.source_terms(phi, M_o)
     assert rel(host(b_g), b_o) < 1e-11
     assert abs(rms_g - np.sqrt(np.mean((rb - M_o) ** 2))) < 1e-12 * rms_g
-    # the compression limiter is exercised by this potential
-    lam = [orc.lambda_min(orc.triad_at(phi, *idx)) for idx in zip(*np.unravel_index(np.arange(0, n ** 3, 7), phi.shape))]
-    assert min(lam) < 0.1
+    if n == 32:  # this potential has cells compressed past xi_m: the compression limiter is exercised
+        assert st["min_lambda0"] < 0.1
     assert rel(host(rec.smooth(dev(torch, M_o))), orc.smooth(M_o)) < 1e-15
     d_g = host(rec.delta_r(dev(torch, phi)))
     assert rel(d_g, orc.delta_r(phi)) < 1e-14
@@ -163,9 +162,9 @@ def test_choose_step_and_cic(torch_cuda, orc):
     phi, m, st = evolved_phi(orc, n, 8)
     rec = binding.Recon(n, binding.Config())
     rng = np.random.default_rng(5)
+    g = inputs.gaussian_field(n, 250.0, 77)
     for amp in (0.05, 0.5, 3.0, 40.0):
-        dphi = amp * inputs.gaussian_field(n, 250.0, 77)
-        dphi /= np.abs(dphi).max()
+        dphi = amp * g / np.abs(g).max()
         j, a_o = orc.choose_step(phi, dphi, orc.Config())
         a_g = rec.choose_step(dev(torch, phi), dev(torch, dphi))
         assert a_g == a_o
