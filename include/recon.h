@@ -174,9 +174,11 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
                          void *r, int dtype);
 
 /* One red-black Gauss-Seidel sweep in place (colour `first` then the other;
- * red = i+j+k even) on an nl^3 level. */
+ * red = i+j+k even) on an nl^3 level.  variant 0: the kernel the solver uses
+ * on that level (the fused two-colour sweep where nl is a multiple of 64);
+ * variant 1: two per-colour launches. */
 int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first,
-                     int dtype);
+                     int dtype, int variant);
 
 /* 27-point full weighting of an nl^3 field onto (nl/2)^3. */
 int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype);

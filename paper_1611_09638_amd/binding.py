@@ -122,7 +122,7 @@ def lib():
         "recon_stage_smooth": (i, [vp, vp, vp]),
         "recon_stage_apply": (i, [vp, vp, vp, i, d, vp]),
         "recon_stage_residual": (i, [vp, vp, vp, vp, i, d, vp, i]),
-        "recon_stage_rbgs": (i, [vp, vp, vp, vp, i, d, i, i]),
+        "recon_stage_rbgs": (i, [vp, vp, vp, vp, i, d, i, i, i]),
         "recon_stage_restrict": (i, [vp, vp, i, vp, i]),
         "recon_stage_prolong_add": (i, [vp, vp, vp, i, i]),
         "recon_stage_vcycle": (i, [vp, vp, vp, vp, i]),
@@ -275,10 +275,10 @@ class Recon:
                                                u.shape[0], float(scale), _ptr(r), self._dt(u)))
         return r
 
-    def rbgs(self, u, a, b, scale=1.0, first=0):
+    def rbgs(self, u, a, b, scale=1.0, first=0, variant=0):
         u = u.clone()
         self._check(lib().recon_stage_rbgs(self._ctx, _ptr(u, u.dtype), _ptr(a, u.dtype), _ptr(b, u.dtype),
-                                           u.shape[0], float(scale), first, self._dt(u)))
+                                           u.shape[0], float(scale), first, self._dt(u), variant))
         return u
 
     def restrict(self, f):

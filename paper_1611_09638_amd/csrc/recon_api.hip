@@ -218,15 +218,23 @@ double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
 
 constexpr int kProfPairs = 4096;
 
+// One red-black sweep on level l.  Levels the fused kernel supports are swept
+// out of place between `cur` and `alt` (the pointers are swapped); smaller
+// levels are swept in place by two per-colour launches.
 template <typename T>
-int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, const T *rhs, int first, bool zero_init)
+int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, int first, bool zero_init)
 {
     const int n = S.n[l];
     const T sc = (T)level_scale(l), amin = (T)ctx->cfg.a_min;
     const bool timed = l == 0 && ctx->prof && ctx->prof_count < kProfPairs;
     if (timed) HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count], ctx->stream));
-    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream, l == 0));
-    HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, 1 - first, false, ctx->stream, l == 0));
+    if (rbgs_fused_supported<T>(n)) {
+        HIPCHK(launch_rbgs_fused<T>(cur, alt, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream));
+        std::swap(cur, alt);
+    } else {
+        HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream, l == 0));
+        HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, 1 - first, false, ctx->stream, l == 0));
+    }
     if (timed) HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count++ + 1], ctx->stream));
     return RECON_OK;
 }
@@ -258,14 +266,16 @@ int vcycle(recon_ctx *ctx, Levels<T> &S, int l, const T *rhs, T *out)
         HIPCHK(launch_coarse_solve<T>(out, S.a[l], rhs, n, sc, amin, ctx->cfg.coarse_sweeps, ctx->stream));
         return RECON_OK;
     }
-    T *cur = out;
-    if (ctx->cfg.n_pre == 0) HIPCHK(launch_zero(out, (long)n * n * n * sizeof(T), ctx->stream));
-    for (int s = 0; s < ctx->cfg.n_pre; ++s) TRY(sweep<T>(ctx, S, l, cur, rhs, 0, s == 0));
+    T *cur = out, *alt = S.tmp[l];
+    const long n3 = (long)n * n * n;
+    if (ctx->cfg.n_pre == 0) HIPCHK(launch_zero(out, n3 * sizeof(T), ctx->stream));
+    for (int s = 0; s < ctx->cfg.n_pre; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 0, s == 0));
     HIPCHK(launch_residual<T>(cur, S.a[l], rhs, S.res[l], n, sc, amin, ctx->stream));
     HIPCHK(launch_restrict<T>(S.res[l], S.b[l + 1], n, ctx->stream));
     TRY(vcycle<T>(ctx, S, l + 1, S.b[l + 1], S.u[l + 1]));
     HIPCHK(launch_prolong_add<T>(cur, S.u[l + 1], n, ctx->stream));
-    for (int s = 0; s < ctx->cfg.n_post; ++s) TRY(sweep<T>(ctx, S, l, cur, rhs, 1, false));
+    for (int s = 0; s < ctx->cfg.n_post; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 1, false));
+    if (cur != out) HIPCHK(hipMemcpyAsync(out, cur, n3 * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     return RECON_OK;
 }
 
@@ -775,12 +785,29 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
     return RECON_OK;
 }
 
-int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first, int dtype)
+extern "C++" {
+template <typename T>
+static int stage_rbgs_fused(recon_ctx *ctx, T *u, const T *a, const T *b, int nl, double scale, int first)
+{
+    T *scratch = reinterpret_cast<T *>(ctx->t);  // n^3 doubles >= nl^3 values of T
+    HIPCHK(launch_rbgs_fused<T>(u, scratch, a, b, nl, (T)scale, (T)ctx->cfg.a_min, first, false, ctx->stream));
+    HIPCHK(hipMemcpyAsync(u, scratch, (size_t)nl * nl * nl * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    return RECON_OK;
+}
+}
+
+int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first, int dtype,
+                     int variant)
 {
     TRY(check_ctx(ctx));
-    if (!u || !a || !b || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || (first != 0 && first != 1))
+    if (!u || !a || !b || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || (first != 0 && first != 1) ||
+        (variant != 0 && variant != 1))
         return fail(ctx, RECON_E_ARG, "bad arguments");
-    if (dtype == 0) {
+    const bool fused = variant == 0 && (dtype == 0 ? rbgs_fused_supported<double>(nl) : rbgs_fused_supported<float>(nl));
+    if (fused) {
+        if (dtype == 0) TRY(stage_rbgs_fused<double>(ctx, (double *)u, (const double *)a, (const double *)b, nl, scale, first));
+        else TRY(stage_rbgs_fused<float>(ctx, (float *)u, (const float *)a, (const float *)b, nl, scale, first));
+    } else if (dtype == 0) {
         HIPCHK(launch_rbgs_half<double>((double *)u, (const double *)a, (const double *)b, nl, scale, ctx->cfg.a_min,
                                         first, false, ctx->stream));
         HIPCHK(launch_rbgs_half<double>((double *)u, (const double *)a, (const double *)b, nl, scale, ctx->cfg.a_min,

@@ -734,6 +734,237 @@ hipError_t launch_rbgs_half(T *u, const T *a, const T *b, int n, T scale, T a_mi
     return hipGetLastError();
 }
 
+// ---------------------------------------------- fused two-colour RB-GS sweep
+//
+// u_out = one full red-black sweep of u_in (colour `first` relaxed first),
+// streaming every field through HBM once.  A workgroup owns a TJ x 64 tile of
+// (j, k) and a chunk of CI consecutive i-planes.  Planes of u_in and a enter
+// LDS ring buffers with a 2-cell halo in j and k, b with a 1-cell halo, two
+// planes ahead of use (register-staged prefetch).  Iteration s relaxes the
+// first colour on plane s+1 over the tile plus a 1-cell ring (the ring values
+// are recomputed here rather than exchanged with neighbouring tiles), then
+// the second colour on plane s over the tile, and writes plane s.  The old
+// first-colour values are never read (Gauss-Seidel overwrites them), so the
+// new ones are stored in place in the u ring.  Out of place because the
+// neighbouring tiles read this tile's halo from u_in.
+template <typename T, int TJ>
+struct Fused {
+    static constexpr int TK = 64, NT = 256;
+    static constexpr int H = TJ + 4, W = TK + 4, PLANE = H * W;     // u, a: halo 2
+    static constexpr int HB = TJ + 2, WB = TK + 2, PLANEB = HB * WB;  // b: halo 1
+    static constexpr int LU = (PLANE + NT - 1) / NT;
+    static constexpr int LB = (PLANEB + NT - 1) / NT;
+    static constexpr int N1 = (TJ + 2) * (TK / 2 + 1);  // first-colour nodes on tile + ring
+    static constexpr int N2 = TJ * (TK / 2);            // second-colour nodes on the tile
+    static constexpr int R1 = (N1 + NT - 1) / NT, R2 = (N2 + NT - 1) / NT;
+    static constexpr int RS = TJ * TK / NT;             // stores per thread
+    static constexpr int US = 5, BS = 3;                // ring depths
+};
+
+// Face order in both relaxations: +i, -i, +j, -j, +k, -k (as in k_rbgs_half),
+// so the fused and per-colour sweeps round identically.
+template <typename T, int TJ>
+__global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
+                                                    const T *__restrict__ ag, const T *__restrict__ bg, int n,
+                                                    int ci, T inv_scale, T a_min, int first, int zero_init)
+{
+    using F = Fused<T, TJ>;
+    constexpr int W = F::W, PLANE = F::PLANE, WB = F::WB, PLANEB = F::PLANEB, NT = F::NT;
+    __shared__ T sU[F::US][PLANE];
+    __shared__ T sA[F::US][PLANE];
+    __shared__ T sB[F::BS][PLANEB];
+
+    const int tid = threadIdx.x;
+    const int tiles_k = n / F::TK, tiles_j = n / TJ, chunks = n / ci;
+    const int nblk = tiles_k * tiles_j * chunks;
+    int t = blockIdx.x;
+    if ((nblk & 7) == 0) t = (t & 7) * (nblk >> 3) + (t >> 3);  // one contiguous tile range per XCD
+    const int tk = t % tiles_k, tj = (t / tiles_k) % tiles_j, ch = t / (tiles_k * tiles_j);
+    const int j0 = tj * TJ, k0 = tk * F::TK, i0 = ch * ci;
+    const size_t n2 = (size_t)n * n;
+
+    // in-plane global offsets of this thread's halo-2 and halo-1 load slots
+    int offU[F::LU], offB[F::LB];
+#pragma unroll
+    for (int r = 0; r < F::LU; ++r) {
+        const int q = tid + r * NT;
+        const int row = q / W, col = q % W;
+        const int gj = wrapc(j0 - 2 + row, n), gk = wrapc(k0 - 2 + col, n);
+        offU[r] = q < PLANE ? gj * n + gk : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < F::LB; ++r) {
+        const int q = tid + r * NT;
+        const int row = q / WB, col = q % WB;
+        const int gj = wrapc(j0 - 1 + row, n), gk = wrapc(k0 - 1 + col, n);
+        offB[r] = q < PLANEB ? gj * n + gk : -1;
+    }
+
+    T ru[2][F::LU], ra[2][F::LU], rb[2][F::LB];
+    auto fetch = [&](int set, int pu, int pb) {
+        const size_t bu = (size_t)wrapc(pu, n) * n2, bb = (size_t)wrapc(pb, n) * n2;
+#pragma unroll
+        for (int r = 0; r < F::LU; ++r) {
+            if (offU[r] >= 0) {
+                ru[set][r] = zero_init ? (T)0 : uin[bu + offU[r]];
+                ra[set][r] = ag[bu + offU[r]];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < F::LB; ++r)
+            if (offB[r] >= 0) rb[set][r] = bg[bb + offB[r]];
+    };
+    auto deposit = [&](int set, int pu, int pb) {
+        const int su = (pu - i0 + 10) % F::US, sb = (pb - i0 + 9) % F::BS;
+#pragma unroll
+        for (int r = 0; r < F::LU; ++r) {
+            const int q = tid + r * NT;
+            if (q < PLANE) {
+                sU[su][q] = ru[set][r];
+                sA[su][q] = ra[set][r];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < F::LB; ++r) {
+            const int q = tid + r * NT;
+            if (q < PLANEB) sB[sb][q] = rb[set][r];
+        }
+    };
+    auto slotU = [&](int p) { return (p - i0 + 10) % F::US; };
+    auto slotB = [&](int p) { return (p - i0 + 9) % F::BS; };
+
+    const int c1 = first, c2 = 1 - first;
+    // relax colour c1 on plane p over the tile plus a 1-cell ring
+    auto relax_first = [&](int p) {
+        const int gi = wrapc(p, n);
+        const T *Uc = sU[slotU(p)], *Ac = sA[slotU(p)];
+        const T *Uu = sU[slotU(p + 1)], *Au = sA[slotU(p + 1)];
+        const T *Ud = sU[slotU(p - 1)], *Ad = sA[slotU(p - 1)];
+        const T *Bc = sB[slotB(p)];
+        T *Uw = sU[slotU(p)];
+#pragma unroll
+        for (int r = 0; r < F::R1; ++r) {
+            const int q = tid + r * NT;
+            if (q < F::N1) {
+                const int row = q / (F::TK / 2 + 1), pr = q % (F::TK / 2 + 1);
+                const int jj = row - 1;
+                const int e = (c1 + gi + jj + 1) & 1;  // (gi + jj + kk) % 2 == c1 with kk = 2 pr - 1 + e
+                const int kk = 2 * pr - 1 + e;
+                const int c = (jj + 2) * W + (kk + 2);
+                const T Aa[7] = {Ac[c], Au[c], Ad[c], Ac[c + W], Ac[c - W], Ac[c + 1], Ac[c - 1]};
+                const T an = Aa[0];
+                T num = 0, den = 0, cf;
+                cf = facec(an, Aa[1], a_min); num += cf * Uu[c]; den += cf;
+                cf = facec(an, Aa[2], a_min); num += cf * Ud[c]; den += cf;
+                cf = facec(an, Aa[3], a_min); num += cf * Uc[c + W]; den += cf;
+                cf = facec(an, Aa[4], a_min); num += cf * Uc[c - W]; den += cf;
+                cf = facec(an, Aa[5], a_min); num += cf * Uc[c + 1]; den += cf;
+                cf = facec(an, Aa[6], a_min); num += cf * Uc[c - 1]; den += cf;
+                Uw[c] = (num - Bc[(jj + 1) * WB + (kk + 1)] * inv_scale) / den;
+            }
+        }
+    };
+    // relax colour c2 on plane p over the tile (reads the new c1 values)
+    auto relax_second = [&](int p) {
+        const int gi = wrapc(p, n);
+        const T *Uc = sU[slotU(p)], *Ac = sA[slotU(p)];
+        const T *Uu = sU[slotU(p + 1)], *Au = sA[slotU(p + 1)];
+        const T *Ud = sU[slotU(p - 1)], *Ad = sA[slotU(p - 1)];
+        const T *Bc = sB[slotB(p)];
+        T vals[F::R2];
+        int cs[F::R2];
+#pragma unroll
+        for (int r = 0; r < F::R2; ++r) {
+            const int q = tid + r * NT;
+            cs[r] = -1;
+            if (q < F::N2) {
+                const int jj = q / (F::TK / 2), pr = q % (F::TK / 2);
+                const int kk = 2 * pr + ((c2 + gi + jj) & 1);
+                const int c = (jj + 2) * W + (kk + 2);
+                const T an = Ac[c];
+                T num = 0, den = 0, cf;
+                cf = facec(an, Au[c], a_min); num += cf * Uu[c]; den += cf;
+                cf = facec(an, Ad[c], a_min); num += cf * Ud[c]; den += cf;
+                cf = facec(an, Ac[c + W], a_min); num += cf * Uc[c + W]; den += cf;
+                cf = facec(an, Ac[c - W], a_min); num += cf * Uc[c - W]; den += cf;
+                cf = facec(an, Ac[c + 1], a_min); num += cf * Uc[c + 1]; den += cf;
+                cf = facec(an, Ac[c - 1], a_min); num += cf * Uc[c - 1]; den += cf;
+                vals[r] = (num - Bc[(jj + 1) * WB + (kk + 1)] * inv_scale) / den;
+                cs[r] = c;
+            }
+        }
+        // all reads of plane p's first-colour values are done by this thread;
+        // the second-colour slots written here are read by no other thread
+        T *Uw = sU[slotU(p)];
+#pragma unroll
+        for (int r = 0; r < F::R2; ++r)
+            if (cs[r] >= 0) Uw[cs[r]] = vals[r];
+    };
+    auto store_plane = [&](int p) {
+        const size_t base = (size_t)wrapc(p, n) * n2;
+        const T *Uc = sU[slotU(p)];
+#pragma unroll
+        for (int r = 0; r < F::RS; ++r) {
+            const int q = tid + r * NT;
+            const int row = q / F::TK, col = q % F::TK;
+            uout[base + (size_t)(j0 + row) * n + (k0 + col)] = Uc[(row + 2) * W + (col + 2)];
+        }
+    };
+
+    // prologue: u, a planes i0-2 .. i0 and b plane i0-1 resident; planes
+    // i0+1 (u, a) / i0 (b) and i0+2 / i0+1 staged in registers
+    fetch(0, i0 - 2, i0 - 1);
+    deposit(0, i0 - 2, i0 - 1);
+    fetch(0, i0 - 1, i0 - 1);
+    deposit(0, i0 - 1, i0 - 1);
+    fetch(0, i0, i0 - 1);
+    deposit(0, i0, i0 - 1);
+    fetch(0, i0 + 1, i0);
+    fetch(1, i0 + 2, i0 + 1);
+    __syncthreads();
+
+    const int s_end = i0 + ci - 1;
+    for (int s = i0 - 2; s <= s_end; s += 2) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ss = s + h;
+            if (ss <= s_end) {
+                relax_first(ss + 1);
+                __syncthreads();
+                if (ss >= i0) relax_second(ss);
+                if (ss + 3 <= i0 + ci + 1) deposit(h, ss + 3, ss + 2);
+                __syncthreads();
+                if (ss >= i0) store_plane(ss);
+                if (ss + 5 <= i0 + ci + 1) fetch(h, ss + 5, ss + 4);
+            }
+        }
+    }
+}
+
+template <typename T>
+static constexpr int fused_tj()
+{
+    return sizeof(T) == 4 ? 16 : 8;
+}
+
+template <typename T>
+bool rbgs_fused_supported(int n)
+{
+    return n >= 64 && n % 64 == 0 && n % fused_tj<T>() == 0;
+}
+
+template <typename T>
+hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, int n, T scale, T a_min, int first,
+                             bool zero_init, hipStream_t s)
+{
+    if (!rbgs_fused_supported<T>(n)) return hipErrorInvalidValue;
+    constexpr int TJ = fused_tj<T>();
+    const int ci = n >= 256 ? n / 4 : n;
+    const int nblk = (n / 64) * (n / TJ) * (n / ci);
+    k_rbgs_fused<T, TJ><<<nblk, 256, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first, zero_init ? 1 : 0);
+    return hipGetLastError();
+}
+
 // 27-point full weighting: coarse node I <- sum_d w(d) f(2I + d), w = prod
 // over axes of 1/2 (d = 0) or 1/4 (d = +-1).
 template <typename T>
@@ -1060,7 +1291,10 @@ hipError_t launch_add_correction(double *u, const Z *z, long n3, hipStream_t s)
     template hipError_t launch_dots_zr_zq<T>(const T *, const double *, const double *, long, Part &, hipStream_t); \
     template hipError_t launch_update_pq<T>(const T *, const double *, double *, double *, double, int, double,     \
                                             bool, Part &, hipStream_t);                                           \
-    template hipError_t launch_add_correction<T>(double *, const T *, long, hipStream_t);
+    template hipError_t launch_add_correction<T>(double *, const T *, long, hipStream_t);                        \
+    template hipError_t launch_rbgs_fused<T>(const T *, T *, const T *, const T *, int, T, T, int, bool,           \
+                                             hipStream_t);                                                       \
+    template bool rbgs_fused_supported<T>(int);
 
 RECON_INSTANTIATE(double)
 RECON_INSTANTIATE(float)

@@ -78,9 +78,11 @@ def test_normalize_meshmass_source_smooth(torch_cuda, orc, n, cn):
     assert rel(d_g, orc.delta_r(phi)) < 1e-14
 
 
-@pytest.mark.parametrize("n,cn", SIZES)
+@pytest.mark.parametrize("n,cn", SIZES + [(128, 8)])
 @pytest.mark.parametrize("first", [0, 1])
 def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
+    """Both sweep kernels (fused two-colour where n is a multiple of 64, and
+    per-colour) against the oracle; the two kernels round identically."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
     rec = binding.Recon(n, binding.Config(coarse_n=cn))
@@ -88,13 +90,17 @@ def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
     a = np.exp(1.5 * rng.normal(size=(n, n, n)))
     u, b = rng.normal(size=(2, n, n, n))
     for scale in (1.0, 1.0 / 16):
-        ug = host(rec.rbgs(dev(torch, u), dev(torch, a), dev(torch, b), scale=scale, first=first))
         uo = orc.rbgs_sweep(u, a, b, scale=scale, first=first)
-        assert rel(ug, uo) < 1e-13
+        ug = [host(rec.rbgs(dev(torch, u), dev(torch, a), dev(torch, b), scale=scale, first=first, variant=v))
+              for v in (0, 1)]
+        assert rel(ug[0], uo) < 1e-13 and rel(ug[1], uo) < 1e-13
+        assert np.array_equal(ug[0], ug[1])
     a32, u32, b32 = (x.astype(np.float32).astype(np.float64) for x in (a, u, b))
-    ug = host(rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32), dev(torch, b32, torch.float32),
-                       first=first))
-    assert rel(ug, orc.rbgs_sweep(u32, a32, b32, first=first)) < 2e-6
+    uo = orc.rbgs_sweep(u32, a32, b32, first=first)
+    ug = [host(rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32),
+                        dev(torch, b32, torch.float32), first=first, variant=v)) for v in (0, 1)]
+    assert rel(ug[0], uo) < 2e-6 and rel(ug[1], uo) < 2e-6
+    assert np.array_equal(ug[0], ug[1])
 
 
 @pytest.mark.parametrize("n,cn", SIZES)
