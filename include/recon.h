@@ -175,8 +175,8 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
 
 /* One red-black Gauss-Seidel sweep in place (colour `first` then the other;
  * red = i+j+k even) on an nl^3 level.  variant 0: the kernel the solver uses
- * on that level (the fused two-colour sweep where nl is a multiple of 64);
- * variant 1: two per-colour launches. */
+ * on that level; 1: two per-colour launches; 2: the fused two-colour kernel
+ * (nl a multiple of 64, else RECON_E_ARG). */
 int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first,
                      int dtype, int variant);
 

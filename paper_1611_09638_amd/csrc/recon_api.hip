@@ -218,9 +218,17 @@ double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
 
 constexpr int kProfPairs = 4096;
 
-// One red-black sweep on level l.  Levels the fused kernel supports are swept
-// out of place between `cur` and `alt` (the pointers are swapped); smaller
-// levels are swept in place by two per-colour launches.
+// Levels of at least 256^3 whose edge is a multiple of 64 are swept by the
+// fused two-colour kernel; smaller levels (resident in L2/MALL) by two
+// per-colour launches, which keep more workgroups busy there.
+template <typename T>
+bool use_fused(int n)
+{
+    return n >= 256 && rbgs_fused_supported<T>(n);
+}
+
+// One red-black sweep on level l: fused levels out of place between `cur` and
+// `alt` (the pointers are swapped), the others in place.
 template <typename T>
 int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, int first, bool zero_init)
 {
@@ -228,7 +236,7 @@ int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, i
     const T sc = (T)level_scale(l), amin = (T)ctx->cfg.a_min;
     const bool timed = l == 0 && ctx->prof && ctx->prof_count < kProfPairs;
     if (timed) HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count], ctx->stream));
-    if (rbgs_fused_supported<T>(n)) {
+    if (use_fused<T>(n)) {
         HIPCHK(launch_rbgs_fused<T>(cur, alt, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream));
         std::swap(cur, alt);
     } else {
@@ -801,9 +809,11 @@ int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int 
 {
     TRY(check_ctx(ctx));
     if (!u || !a || !b || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || (first != 0 && first != 1) ||
-        (variant != 0 && variant != 1))
+        variant < 0 || variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
-    const bool fused = variant == 0 && (dtype == 0 ? rbgs_fused_supported<double>(nl) : rbgs_fused_supported<float>(nl));
+    const bool can_fuse = dtype == 0 ? rbgs_fused_supported<double>(nl) : rbgs_fused_supported<float>(nl);
+    if (variant == 2 && !can_fuse) return fail(ctx, RECON_E_ARG, "fused sweep needs an edge that is a multiple of 64");
+    const bool fused = variant == 2 || (variant == 0 && (dtype == 0 ? use_fused<double>(nl) : use_fused<float>(nl)));
     if (fused) {
         if (dtype == 0) TRY(stage_rbgs_fused<double>(ctx, (double *)u, (const double *)a, (const double *)b, nl, scale, first));
         else TRY(stage_rbgs_fused<float>(ctx, (float *)u, (const float *)a, (const float *)b, nl, scale, first));

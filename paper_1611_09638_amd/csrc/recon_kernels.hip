@@ -761,6 +761,16 @@ struct Fused {
     static constexpr int US = 5, BS = 3;                // ring depths
 };
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for every
+// outstanding global load, which would drain the register prefetch at each
+// barrier; here the loads stay in flight until their registers are used.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Face order in both relaxations: +i, -i, +j, -j, +k, -k (as in k_rbgs_half),
 // so the fused and per-colour sweeps round identically.
 template <typename T, int TJ>
@@ -921,7 +931,7 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
     deposit(0, i0, i0 - 1);
     fetch(0, i0 + 1, i0);
     fetch(1, i0 + 2, i0 + 1);
-    __syncthreads();
+    lds_barrier();
 
     const int s_end = i0 + ci - 1;
     for (int s = i0 - 2; s <= s_end; s += 2) {
@@ -930,10 +940,10 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
             const int ss = s + h;
             if (ss <= s_end) {
                 relax_first(ss + 1);
-                __syncthreads();
+                lds_barrier();
                 if (ss >= i0) relax_second(ss);
                 if (ss + 3 <= i0 + ci + 1) deposit(h, ss + 3, ss + 2);
-                __syncthreads();
+                lds_barrier();
                 if (ss >= i0) store_plane(ss);
                 if (ss + 5 <= i0 + ci + 1) fetch(h, ss + 5, ss + 4);
             }
@@ -959,7 +969,10 @@ hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, in
 {
     if (!rbgs_fused_supported<T>(n)) return hipErrorInvalidValue;
     constexpr int TJ = fused_tj<T>();
-    const int ci = n >= 256 ? n / 4 : n;
+    // i-chunk: as long as possible while the launch still has >= 1024
+    // workgroups (each chunk re-reads 4 planes of u and a)
+    int ci = n;
+    while (ci > 16 && (n / 64) * (n / TJ) * (n / ci) < 1024) ci /= 2;
     const int nblk = (n / 64) * (n / TJ) * (n / ci);
     k_rbgs_fused<T, TJ><<<nblk, 256, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first, zero_init ? 1 : 0);
     return hipGetLastError();

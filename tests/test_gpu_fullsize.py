@@ -1,0 +1,90 @@
+"""Parity at the benchmark's size (512^3 lognormal, sigma_g = 2) in the launch
+configuration the benchmark uses: the fused smoother against the oracle's
+sweep over the whole grid, a V-cycle at 256^3 against the oracle's, and the
+full mixed-precision solve against the FP64 solve with the invariants that
+hold at any size (positive-definite map, delta_r < 3, every linear solve at
+tolerance, identical step sizes)."""
+import numpy as np
+import pytest
+
+from paper_1611_09638_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def field512():
+    w = inputs.WORKLOADS["lognormal512"]
+    return inputs.lognormal_density(w["n"], w["box"], w["sigma_g"], w["seed"])
+
+
+def test_fused_sweep_512(torch_cuda, orc, field512):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 512
+    a = field512 / field512.mean()
+    rng = np.random.default_rng(512)
+    u = rng.standard_normal((n, n, n))
+    b = rng.standard_normal((n, n, n))
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
+    uo = orc.rbgs_sweep(u, a, b, first=1)
+    ug = rec.rbgs(torch.from_numpy(u).cuda(), torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), first=1,
+                  variant=0).cpu().numpy()
+    assert rel(ug, uo) < 1e-13
+    del ug
+    q = lambda x: torch.from_numpy(x.astype(np.float32)).cuda()  # noqa: E731
+    ug = rec.rbgs(q(u), q(a), q(b), first=0, variant=0).cpu().numpy()
+    uo = orc.rbgs_sweep(u.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64),
+                        b.astype(np.float32).astype(np.float64), first=0)
+    assert rel(ug, uo) < 2e-6
+
+
+def test_vcycle_256(torch_cuda, orc):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 256
+    rho = inputs.lognormal_density(n, 500.0, 2.0, 33)
+    a = rho / rho.mean()
+    r = np.random.default_rng(256).standard_normal((n, n, n))
+    r -= r.mean()
+    zo = orc.vcycle(a, r)
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
+    z = rec.vcycle(torch.from_numpy(a).cuda(), torch.from_numpy(r).cuda()).cpu().numpy()
+    assert rel(z, zo) < 1e-12
+    z32 = rec.vcycle(torch.from_numpy(a).float().cuda(), torch.from_numpy(r).float().cuda()).cpu().numpy()
+    assert rel(z32, zo) < 1e-4
+
+
+def test_mixed_matches_fp64_at_512(torch_cuda, field512):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 512, 1000.0
+    rho = torch.from_numpy(field512).cuda()
+    out = {}
+    for prec in (binding.FP64, binding.MIXED):
+        rec = binding.Recon(n, binding.Config(precision=prec, max_outer=3))
+        phi, d, st = rec.solve(rho, box)
+        out[prec] = (phi.cpu().numpy(), d.cpu().numpy(), st)
+        del rec
+    (p64, d64, s64), (p32, d32, s32) = out[binding.FP64], out[binding.MIXED]
+    assert s64["alpha"] == s32["alpha"]
+    assert rel(p32, p64) < 1e-6 and rel(d32, d64) < 1e-6
+    for st, d in ((s64, d64), (s32, d32)):
+        assert st["outer_steps"] == 3
+        assert max(st["rel_residual"]) <= 1e-10
+        assert st["min_det"] > 0 and st["min_lambda0"] > 0
+        assert d.max() < 3.0
+        assert np.isfinite(d).all()
+        assert abs(st["kappa"][0] - 1.0) < 1e-12  # mass on the undeformed mesh is the input mass

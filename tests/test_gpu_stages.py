@@ -89,18 +89,21 @@ def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
     rng = np.random.default_rng(100 + n + first)
     a = np.exp(1.5 * rng.normal(size=(n, n, n)))
     u, b = rng.normal(size=(2, n, n, n))
+    variants = (1, 2) if n % 64 == 0 else (1,)
     for scale in (1.0, 1.0 / 16):
         uo = orc.rbgs_sweep(u, a, b, scale=scale, first=first)
         ug = [host(rec.rbgs(dev(torch, u), dev(torch, a), dev(torch, b), scale=scale, first=first, variant=v))
-              for v in (0, 1)]
-        assert rel(ug[0], uo) < 1e-13 and rel(ug[1], uo) < 1e-13
-        assert np.array_equal(ug[0], ug[1])
+              for v in variants]
+        for x in ug:
+            assert rel(x, uo) < 1e-13
+            assert np.array_equal(x, ug[0])
     a32, u32, b32 = (x.astype(np.float32).astype(np.float64) for x in (a, u, b))
     uo = orc.rbgs_sweep(u32, a32, b32, first=first)
     ug = [host(rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32),
-                        dev(torch, b32, torch.float32), first=first, variant=v)) for v in (0, 1)]
-    assert rel(ug[0], uo) < 2e-6 and rel(ug[1], uo) < 2e-6
-    assert np.array_equal(ug[0], ug[1])
+                        dev(torch, b32, torch.float32), first=first, variant=v)) for v in variants]
+    for x in ug:
+        assert rel(x, uo) < 2e-6
+        assert np.array_equal(x, ug[0])
 
 
 @pytest.mark.parametrize("n,cn", SIZES)
