@@ -152,8 +152,8 @@ def main():
         out["rel_l2_phi_mixed_vs_fp64"] = float((a["phi"] - b["phi"]).norm() / b["phi"].norm())
         out["rel_l2_delta_mixed_vs_fp64"] = float((a["delta"] - b["delta"]).norm() / b["delta"].norm())
         out["alpha_equal"] = a["stats"]["alpha"] == b["stats"]["alpha"]
-    out["roofline"] = {"bound": "hbm", "kernel": "k_rbgs_half<%s,1> (finest level, one sweep = 2 launches)"
-                       % ("float" if head == "mixed" else "double"),
+    out["roofline"] = {"bound": "hbm", "kernel": "k_rbgs_fused<%s> (finest level, one launch per sweep)"
+                       % ("float,16" if head == "mixed" else "double,4"),
                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                        "bytes_per_node_per_sweep": node_bytes, "nodes": n ** 3}

@@ -643,6 +643,27 @@ __device__ __forceinline__ T facec(T an, T anb, T a_min)
     return c > a_min ? c : a_min;
 }
 
+// Quotient x / d for d > 0 (a sum of floored face coefficients) without the
+// IEEE division sequence: hardware reciprocal, Newton refinement of the
+// reciprocal (FP64), then one residual correction of the quotient
+// (Markstein's method); within an ulp of the rounded quotient.  Every
+// Gauss-Seidel kernel of the smoother uses it, so they round identically.
+__device__ __forceinline__ float qdiv(float x, float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float q = x * r;
+    return fmaf(fmaf(-d, q, x), r, q);
+}
+
+__device__ __forceinline__ double qdiv(double x, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    const double q = x * r;
+    return fma(fma(-d, q, x), r, q);
+}
+
 template <typename T>
 __global__ void k_apply(const T *__restrict__ u, const T *__restrict__ a, T *__restrict__ out, int n, int ipb, T scale,
                         T a_min, const T *__restrict__ b)
@@ -711,7 +732,7 @@ __global__ void k_rbgs_half(T *__restrict__ u, const T *__restrict__ a, const T 
             if (!zero_init) num += c * u[q[f]];
             den += c;
         }
-        u[p] = (num - b[p] * inv_scale) / den;
+        u[p] = qdiv(num - b[p] * inv_scale, den);
     }
 }
 
@@ -754,6 +775,10 @@ struct Fused {
     static constexpr int HB = TJ + 2, WB = TK + 2, PLANEB = HB * WB;  // b: halo 1
     static constexpr int LU = (PLANE + NT - 1) / NT;
     static constexpr int LB = (PLANEB + NT - 1) / NT;
+    // LDS planes padded to whole rounds of NT loads: every thread loads and
+    // deposits unconditionally (lanes past the plane load a valid address and
+    // write into the padding), which keeps the load queue countable.
+    static constexpr int PU = LU * NT, PB = LB * NT;
     static constexpr int N1 = (TJ + 2) * (TK / 2 + 1);  // first-colour nodes on tile + ring
     static constexpr int N2 = TJ * (TK / 2);            // second-colour nodes on the tile
     static constexpr int R1 = (N1 + NT - 1) / NT, R2 = (N2 + NT - 1) / NT;
@@ -773,16 +798,17 @@ __device__ __forceinline__ void lds_barrier()
 
 // Face order in both relaxations: +i, -i, +j, -j, +k, -k (as in k_rbgs_half),
 // so the fused and per-colour sweeps round identically.
-template <typename T, int TJ>
+// ZERO: u_in is taken as 0 and not read (the first sweep from a zero guess).
+template <typename T, int TJ, int ZERO>
 __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
                                                     const T *__restrict__ ag, const T *__restrict__ bg, int n,
-                                                    int ci, T inv_scale, T a_min, int first, int zero_init)
+                                                    int ci, T inv_scale, T a_min, int first)
 {
     using F = Fused<T, TJ>;
     constexpr int W = F::W, PLANE = F::PLANE, WB = F::WB, PLANEB = F::PLANEB, NT = F::NT;
-    __shared__ T sU[F::US][PLANE];
-    __shared__ T sA[F::US][PLANE];
-    __shared__ T sB[F::BS][PLANEB];
+    __shared__ T sU[F::US][F::PU];
+    __shared__ T sA[F::US][F::PU];
+    __shared__ T sB[F::BS][F::PB];
 
     const int tid = threadIdx.x;
     const int tiles_k = n / F::TK, tiles_j = n / TJ, chunks = n / ci;
@@ -800,14 +826,14 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
         const int q = tid + r * NT;
         const int row = q / W, col = q % W;
         const int gj = wrapc(j0 - 2 + row, n), gk = wrapc(k0 - 2 + col, n);
-        offU[r] = q < PLANE ? gj * n + gk : -1;
+        offU[r] = q < PLANE ? gj * n + gk : 0;
     }
 #pragma unroll
     for (int r = 0; r < F::LB; ++r) {
         const int q = tid + r * NT;
         const int row = q / WB, col = q % WB;
         const int gj = wrapc(j0 - 1 + row, n), gk = wrapc(k0 - 1 + col, n);
-        offB[r] = q < PLANEB ? gj * n + gk : -1;
+        offB[r] = q < PLANEB ? gj * n + gk : 0;
     }
 
     T ru[2][F::LU], ra[2][F::LU], rb[2][F::LB];
@@ -815,38 +841,71 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
         const size_t bu = (size_t)wrapc(pu, n) * n2, bb = (size_t)wrapc(pb, n) * n2;
 #pragma unroll
         for (int r = 0; r < F::LU; ++r) {
-            if (offU[r] >= 0) {
-                ru[set][r] = zero_init ? (T)0 : uin[bu + offU[r]];
-                ra[set][r] = ag[bu + offU[r]];
-            }
+            ru[set][r] = ZERO ? (T)0 : uin[bu + offU[r]];
+            ra[set][r] = ag[bu + offU[r]];
         }
 #pragma unroll
-        for (int r = 0; r < F::LB; ++r)
-            if (offB[r] >= 0) rb[set][r] = bg[bb + offB[r]];
+        for (int r = 0; r < F::LB; ++r) rb[set][r] = bg[bb + offB[r]];
     };
     auto deposit = [&](int set, int pu, int pb) {
         const int su = (pu - i0 + 10) % F::US, sb = (pb - i0 + 9) % F::BS;
 #pragma unroll
         for (int r = 0; r < F::LU; ++r) {
-            const int q = tid + r * NT;
-            if (q < PLANE) {
-                sU[su][q] = ru[set][r];
-                sA[su][q] = ra[set][r];
-            }
+            sU[su][tid + r * NT] = ru[set][r];
+            sA[su][tid + r * NT] = (T)0.5 * ra[set][r];
         }
 #pragma unroll
-        for (int r = 0; r < F::LB; ++r) {
-            const int q = tid + r * NT;
-            if (q < PLANEB) sB[sb][q] = rb[set][r];
-        }
+        for (int r = 0; r < F::LB; ++r) sB[sb][tid + r * NT] = rb[set][r];
     };
     auto slotU = [&](int p) { return (p - i0 + 10) % F::US; };
     auto slotB = [&](int p) { return (p - i0 + 9) % F::BS; };
 
     const int c1 = first, c2 = 1 - first;
-    // relax colour c1 on plane p over the tile plus a 1-cell ring
+    // LDS offsets (u/a plane, b plane) of this thread's relaxation nodes, for
+    // both plane parities.  First colour: tile + 1-cell ring, node q at row
+    // jj = q / 33 - 1 and column kk = 2 (q % 33) - 1 + e; second colour: tile,
+    // jj = q / 32, kk = 2 (q % 32) + e; e makes (i + j + k) % 2 the colour.
+    int o1[F::R1][2], b1[F::R1][2], o2[F::R2][2], b2[F::R2][2];
+#pragma unroll
+    for (int r = 0; r < F::R1; ++r) {
+        const int q = tid + r * NT;
+        const int jj = q / (F::TK / 2 + 1) - 1, pr = q % (F::TK / 2 + 1);
+#pragma unroll
+        for (int P = 0; P < 2; ++P) {
+            const int kk = 2 * pr - 1 + ((P + jj + 1) & 1);
+            o1[r][P] = q < F::N1 ? (jj + 2) * W + (kk + 2) : 2 * W + 2;
+            b1[r][P] = q < F::N1 ? (jj + 1) * WB + (kk + 1) : 0;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < F::R2; ++r) {
+        const int q = tid + r * NT;
+        const int jj = q / (F::TK / 2), pr = q % (F::TK / 2);
+#pragma unroll
+        for (int P = 0; P < 2; ++P) {
+            const int kk = 2 * pr + ((P + jj) & 1);
+            o2[r][P] = q < F::N2 ? (jj + 2) * W + (kk + 2) : 2 * W + 2;
+            b2[r][P] = q < F::N2 ? (jj + 1) * WB + (kk + 1) : 0;
+        }
+    }
+    // one Gauss-Seidel relaxation from the LDS planes (a is stored halved:
+    // the face coefficient max(a_min, (a_n + a_nb) / 2) is max(a_min, h_n + h_nb))
+    auto relax = [&](const T *Uc, const T *Uu, const T *Ud, const T *Ac, const T *Au, const T *Ad, int c,
+                     T bval) {
+        const T hn = Ac[c];
+        T num = 0, den = 0, cf;
+        cf = fmax(hn + Au[c], a_min); num += cf * Uu[c]; den += cf;
+        cf = fmax(hn + Ad[c], a_min); num += cf * Ud[c]; den += cf;
+        cf = fmax(hn + Ac[c + W], a_min); num += cf * Uc[c + W]; den += cf;
+        cf = fmax(hn + Ac[c - W], a_min); num += cf * Uc[c - W]; den += cf;
+        cf = fmax(hn + Ac[c + 1], a_min); num += cf * Uc[c + 1]; den += cf;
+        cf = fmax(hn + Ac[c - 1], a_min); num += cf * Uc[c - 1]; den += cf;
+        return qdiv(num - bval * inv_scale, den);
+    };
+    // relax colour c1 on plane p over the tile plus a 1-cell ring (reads only
+    // second-colour values, writes first-colour slots)
     auto relax_first = [&](int p) {
-        const int gi = wrapc(p, n);
+        const int P = (c1 + wrapc(p, n)) & 1;
         const T *Uc = sU[slotU(p)], *Ac = sA[slotU(p)];
         const T *Uu = sU[slotU(p + 1)], *Au = sA[slotU(p + 1)];
         const T *Ud = sU[slotU(p - 1)], *Ad = sA[slotU(p - 1)];
@@ -854,61 +913,28 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
         T *Uw = sU[slotU(p)];
 #pragma unroll
         for (int r = 0; r < F::R1; ++r) {
-            const int q = tid + r * NT;
-            if (q < F::N1) {
-                const int row = q / (F::TK / 2 + 1), pr = q % (F::TK / 2 + 1);
-                const int jj = row - 1;
-                const int e = (c1 + gi + jj + 1) & 1;  // (gi + jj + kk) % 2 == c1 with kk = 2 pr - 1 + e
-                const int kk = 2 * pr - 1 + e;
-                const int c = (jj + 2) * W + (kk + 2);
-                const T Aa[7] = {Ac[c], Au[c], Ad[c], Ac[c + W], Ac[c - W], Ac[c + 1], Ac[c - 1]};
-                const T an = Aa[0];
-                T num = 0, den = 0, cf;
-                cf = facec(an, Aa[1], a_min); num += cf * Uu[c]; den += cf;
-                cf = facec(an, Aa[2], a_min); num += cf * Ud[c]; den += cf;
-                cf = facec(an, Aa[3], a_min); num += cf * Uc[c + W]; den += cf;
-                cf = facec(an, Aa[4], a_min); num += cf * Uc[c - W]; den += cf;
-                cf = facec(an, Aa[5], a_min); num += cf * Uc[c + 1]; den += cf;
-                cf = facec(an, Aa[6], a_min); num += cf * Uc[c - 1]; den += cf;
-                Uw[c] = (num - Bc[(jj + 1) * WB + (kk + 1)] * inv_scale) / den;
+            if (tid + r * NT < F::N1) {
+                const int c = o1[r][P];
+                Uw[c] = relax(Uc, Uu, Ud, Ac, Au, Ad, c, Bc[b1[r][P]]);
             }
         }
     };
-    // relax colour c2 on plane p over the tile (reads the new c1 values)
+    // relax colour c2 on plane p over the tile (reads only the new first-colour
+    // values, writes second-colour slots that no other thread reads here)
     auto relax_second = [&](int p) {
-        const int gi = wrapc(p, n);
+        const int P = (c2 + wrapc(p, n)) & 1;
         const T *Uc = sU[slotU(p)], *Ac = sA[slotU(p)];
         const T *Uu = sU[slotU(p + 1)], *Au = sA[slotU(p + 1)];
         const T *Ud = sU[slotU(p - 1)], *Ad = sA[slotU(p - 1)];
         const T *Bc = sB[slotB(p)];
-        T vals[F::R2];
-        int cs[F::R2];
-#pragma unroll
-        for (int r = 0; r < F::R2; ++r) {
-            const int q = tid + r * NT;
-            cs[r] = -1;
-            if (q < F::N2) {
-                const int jj = q / (F::TK / 2), pr = q % (F::TK / 2);
-                const int kk = 2 * pr + ((c2 + gi + jj) & 1);
-                const int c = (jj + 2) * W + (kk + 2);
-                const T an = Ac[c];
-                T num = 0, den = 0, cf;
-                cf = facec(an, Au[c], a_min); num += cf * Uu[c]; den += cf;
-                cf = facec(an, Ad[c], a_min); num += cf * Ud[c]; den += cf;
-                cf = facec(an, Ac[c + W], a_min); num += cf * Uc[c + W]; den += cf;
-                cf = facec(an, Ac[c - W], a_min); num += cf * Uc[c - W]; den += cf;
-                cf = facec(an, Ac[c + 1], a_min); num += cf * Uc[c + 1]; den += cf;
-                cf = facec(an, Ac[c - 1], a_min); num += cf * Uc[c - 1]; den += cf;
-                vals[r] = (num - Bc[(jj + 1) * WB + (kk + 1)] * inv_scale) / den;
-                cs[r] = c;
-            }
-        }
-        // all reads of plane p's first-colour values are done by this thread;
-        // the second-colour slots written here are read by no other thread
         T *Uw = sU[slotU(p)];
 #pragma unroll
-        for (int r = 0; r < F::R2; ++r)
-            if (cs[r] >= 0) Uw[cs[r]] = vals[r];
+        for (int r = 0; r < F::R2; ++r) {
+            if (tid + r * NT < F::N2) {
+                const int c = o2[r][P];
+                Uw[c] = relax(Uc, Uu, Ud, Ac, Au, Ad, c, Bc[b2[r][P]]);
+            }
+        }
     };
     auto store_plane = [&](int p) {
         const size_t base = (size_t)wrapc(p, n) * n2;
@@ -933,20 +959,31 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
     fetch(1, i0 + 2, i0 + 1);
     lds_barrier();
 
-    const int s_end = i0 + ci - 1;
-    for (int s = i0 - 2; s <= s_end; s += 2) {
+    // warm-up: first colour on planes i0-1 and i0 only
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int ss = i0 - 2 + h;
+        relax_first(ss + 1);
+        lds_barrier();
+        deposit(h, ss + 3, ss + 2);
+        lds_barrier();
+        fetch(h, ss + 5, ss + 4);
+    }
+    // Steady state, branch-free so that the compiler can count the loads in
+    // flight and wait only for the register set being deposited (ci is even).
+    // The last two iterations fetch and deposit planes past the chunk: they
+    // wrap to valid addresses and land in ring slots that are no longer read.
+    for (int s = i0; s < i0 + ci; s += 2) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int ss = s + h;
-            if (ss <= s_end) {
-                relax_first(ss + 1);
-                lds_barrier();
-                if (ss >= i0) relax_second(ss);
-                if (ss + 3 <= i0 + ci + 1) deposit(h, ss + 3, ss + 2);
-                lds_barrier();
-                if (ss >= i0) store_plane(ss);
-                if (ss + 5 <= i0 + ci + 1) fetch(h, ss + 5, ss + 4);
-            }
+            relax_first(ss + 1);
+            lds_barrier();
+            relax_second(ss);
+            deposit(h, ss + 3, ss + 2);
+            lds_barrier();
+            store_plane(ss);
+            fetch(h, ss + 5, ss + 4);
         }
     }
 }
@@ -954,7 +991,7 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
 template <typename T>
 static constexpr int fused_tj()
 {
-    return sizeof(T) == 4 ? 16 : 8;
+    return sizeof(T) == 4 ? 16 : 4;
 }
 
 template <typename T>
@@ -973,8 +1010,12 @@ hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, in
     // workgroups (each chunk re-reads 4 planes of u and a)
     int ci = n;
     while (ci > 16 && (n / 64) * (n / TJ) * (n / ci) < 1024) ci /= 2;
+    if (ci & 1) return hipErrorInvalidValue;  // the kernel's steady-state loop takes planes in pairs
     const int nblk = (n / 64) * (n / TJ) * (n / ci);
-    k_rbgs_fused<T, TJ><<<nblk, 256, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first, zero_init ? 1 : 0);
+    if (zero_init)
+        k_rbgs_fused<T, TJ, 1><<<nblk, 256, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first);
+    else
+        k_rbgs_fused<T, TJ, 0><<<nblk, 256, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first);
     return hipGetLastError();
 }
 
