@@ -138,6 +138,8 @@ def lib():
             "orc_det3": (dbl, [d]),
             "orc_triad_at": (None, [d, i, i, i, i, d]),
             "orc_tape_steps": (i, []),
+            "orc_backward": (i, [d, d, dbl, ctypes.POINTER(OrcConfig), d]),
+            "orc_eig_min_vec": (None, [d, d, d]),
             "orc_tape_clear": (None, []),
         }
         for name, (res, args) in sig.items():
@@ -314,6 +316,27 @@ def det3(e) -> float:
 
 def num_levels(n: int, coarse_n: int = 8) -> int:
     return lib().orc_num_levels(n, coarse_n)
+
+
+def eig_min_vec(e):
+    e = np.ascontiguousarray(e, dtype=np.float64).reshape(9)
+    lam = ctypes.c_double()
+    v = np.empty(3)
+    lib().orc_eig_min_vec(_p(e), ctypes.byref(lam), _p(v))
+    return lam.value, v
+
+
+def backward(grad_delta, grad_phi, box: float, cfg: Config | None = None) -> np.ndarray:
+    """dL/d(density) for the last solve run with record_tape=1."""
+    cfg = cfg or Config()
+    gd = _f64(grad_delta)
+    gp = None if grad_phi is None else _f64(grad_phi)
+    out = np.empty_like(gd)
+    c = cfg.c()
+    rc = lib().orc_backward(_p(gd), None if gp is None else _p(gp), box, ctypes.byref(c), _p(out))
+    if rc:
+        raise OracleError(rc)
+    return out
 
 
 def solve(rho, box: float, cfg: Config | None = None, raise_on_error: bool = True):

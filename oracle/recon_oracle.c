@@ -900,3 +900,274 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
 }
 
 int orc_tape_steps(void) { return g_tape.steps; }
+
+/* ======================================================================
+ * Reverse mode (adjoint) of orc_solve for a recorded tape.
+ *
+ * The forward step i maps phi_i to phi_{i+1} through
+ *   M = det(e) * CIC(m)(xi + D_c phi),  e = I + Hess(phi)
+ *   Sigma = mean(M) - M;  t = Sigma + C(lambda_0(e)) - 2 [det e > v_m] |Sigma|
+ *   b = S t - mean(S t);  u = A(M)^+ b;  phi_{i+1} = phi_i + alpha_i S u
+ * with alpha_i and the limiter masks held fixed (piecewise constant), and
+ * the linear solve differentiated as exact: for u = A^+ b with A symmetric,
+ * lambda = A^+ ubar gives bbar = lambda and, per face f of coefficient
+ * c_f = max(a_min, (M_n + M_nb)/2), cbar_f = (lambda_nb - lambda_n)(u_nb - u_n).
+ * ====================================================================== */
+
+/* Smallest eigenvalue and its unit eigenvector, cyclic Jacobi with the
+ * rotations accumulated. */
+static double eig_min_vec(const double e_in[3][3], double v[3])
+{
+    double a[3][3], V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    memcpy(a, e_in, sizeof(a));
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        double diag = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off <= 1e-34 * diag || off == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int r = 0; r < 3; ++r) {
+                    double arp = a[r][p], arq = a[r][q];
+                    a[r][p] = c * arp - s * arq;
+                    a[r][q] = s * arp + c * arq;
+                }
+                for (int r = 0; r < 3; ++r) {
+                    double apr = a[p][r], aqr = a[q][r];
+                    a[p][r] = c * apr - s * aqr;
+                    a[q][r] = s * apr + c * aqr;
+                }
+                for (int r = 0; r < 3; ++r) {
+                    double vrp = V[r][p], vrq = V[r][q];
+                    V[r][p] = c * vrp - s * vrq;
+                    V[r][q] = s * vrp + c * vrq;
+                }
+            }
+    }
+    int k = 0;
+    if (a[1][1] < a[k][k]) k = 1;
+    if (a[2][2] < a[k][k]) k = 2;
+    for (int r = 0; r < 3; ++r) v[r] = V[r][k];
+    return a[k][k];
+}
+
+void orc_eig_min_vec(const double *e9, double *lam, double *v)
+{
+    *lam = eig_min_vec((const double(*)[3])e9, v);
+}
+
+/* cofactor matrix: d det(e) / d e_ab */
+static void cofactor(const double e[3][3], double c[3][3])
+{
+    c[0][0] = e[1][1] * e[2][2] - e[1][2] * e[2][1];
+    c[0][1] = -(e[1][0] * e[2][2] - e[1][2] * e[2][0]);
+    c[0][2] = e[1][0] * e[2][1] - e[1][1] * e[2][0];
+    c[1][0] = -(e[0][1] * e[2][2] - e[0][2] * e[2][1]);
+    c[1][1] = e[0][0] * e[2][2] - e[0][2] * e[2][0];
+    c[1][2] = -(e[0][0] * e[2][1] - e[0][1] * e[2][0]);
+    c[2][0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];
+    c[2][1] = -(e[0][0] * e[1][2] - e[0][2] * e[1][0]);
+    c[2][2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+}
+
+/* phibar += Hess^T applied to the per-node partials hb[n][a][b] with respect
+ * to the entries of e (a symmetric matrix whose off-diagonal pair is the
+ * single quantity H_ab, hence the factor hb_ab + hb_ba). */
+static void hess_transpose_add(const double *hb, int n, double *phibar)
+{
+    int d[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                const double *h = hb + at(n, i, j, k) * 9;
+                for (int a = 0; a < 3; ++a) {
+                    /* H_aa = phi(+a) - 2 phi + phi(-a) */
+                    phibar[at(n, i + d[a][0], j + d[a][1], k + d[a][2])] += h[a * 3 + a];
+                    phibar[at(n, i, j, k)] -= 2.0 * h[a * 3 + a];
+                    phibar[at(n, i - d[a][0], j - d[a][1], k - d[a][2])] += h[a * 3 + a];
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = a + 1; b < 3; ++b) {
+                        double w = 0.25 * (h[a * 3 + b] + h[b * 3 + a]);
+                        int pi = d[a][0] + d[b][0], pj = d[a][1] + d[b][1], pk = d[a][2] + d[b][2];
+                        int qi = d[a][0] - d[b][0], qj = d[a][1] - d[b][1], qk = d[a][2] - d[b][2];
+                        phibar[at(n, i + pi, j + pj, k + pk)] += w;
+                        phibar[at(n, i + qi, j + qj, k + qk)] -= w;
+                        phibar[at(n, i - qi, j - qj, k - qk)] -= w;
+                        phibar[at(n, i - pi, j - pj, k - pk)] += w;
+                    }
+            }
+}
+
+/* Gradient of the loss L(delta_r, phi_out) with respect to the input density
+ * of the last recorded orc_solve.  grad_delta = dL/d delta_r, grad_phi =
+ * dL/d phi_out (may be NULL).  box as in the forward. */
+int orc_backward(const double *grad_delta, const double *grad_phi, double box, const orc_config *cfg,
+                 double *grad_rho)
+{
+    if (!g_tape.m || g_tape.steps < 0 || !grad_delta || !grad_rho) return ORC_E_NO_TAPE;
+    const int n = g_tape.n, K = g_tape.steps;
+    const long N3 = cube(n);
+    const double h = box / n;
+    double *phis = (double *)malloc(sizeof(double) * N3 * (K + 1));
+    double *tmp = (double *)malloc(sizeof(double) * N3);
+    double *phibar = (double *)malloc(sizeof(double) * N3);
+    double *mbar = (double *)calloc(N3, sizeof(double));
+    double *M = (double *)malloc(sizeof(double) * N3);
+    double *ubar = (double *)malloc(sizeof(double) * N3);
+    double *lam = (double *)malloc(sizeof(double) * N3);
+    double *Mbar = (double *)malloc(sizeof(double) * N3);
+    double *tbar = (double *)malloc(sizeof(double) * N3);
+    double *hb = (double *)malloc(sizeof(double) * N3 * 9);
+    double *xb = (double *)malloc(sizeof(double) * N3 * 3);
+    int status = ORC_OK;
+
+    /* replay the potentials phi_0 .. phi_K exactly as the forward formed them */
+    memset(phis, 0, sizeof(double) * N3);
+    for (int s = 0; s < K; ++s) {
+        orc_smooth(g_tape.u[s], n, cfg->smooth_center, tmp);
+        for (long p = 0; p < N3; ++p) phis[(s + 1) * N3 + p] = phis[s * N3 + p] + g_tape.alpha[s] * tmp[p];
+    }
+    /* output: delta_r = -L7 phi_K (L7 symmetric), phi_out = h^2 phi_K */
+    orc_delta_r(grad_delta, n, phibar);
+    if (grad_phi)
+        for (long p = 0; p < N3; ++p) phibar[p] += h * h * grad_phi[p];
+
+    for (int s = K - 1; s >= 0 && status == ORC_OK; --s) {
+        const double *phi = phis + s * N3;
+        const double *u = g_tape.u[s];
+        orc_meshmass(phi, g_tape.m, n, M);
+        double rho_bar = field_mean(M, n);
+        /* phi_{s+1} = phi_s + alpha S u  ->  ubar = alpha S phibar */
+        orc_smooth(phibar, n, cfg->smooth_center, ubar);
+        for (long p = 0; p < N3; ++p) ubar[p] *= g_tape.alpha[s];
+        /* u = A^+ b (mean-free)  ->  lambda = A^+ (ubar - mean ubar), bbar = lambda */
+        double mu = field_mean(ubar, n);
+        for (long p = 0; p < N3; ++p) ubar[p] -= mu;
+        double rel = 0.0;
+        int cyc = orc_mg_solve(M, ubar, n, cfg, lam, &rel);
+        if (cyc < 0) {
+            status = cyc;
+            break;
+        }
+        /* coefficient gradient, fine level: Mbar_n = 1/2 sum over the unfloored
+         * faces of n of (lambda_nb - lambda_n)(u_nb - u_n) */
+        int off[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) {
+                    long c = at(n, i, j, k);
+                    double acc = 0.0;
+                    for (int f = 0; f < 6; ++f) {
+                        long q = at(n, i + off[f][0], j + off[f][1], k + off[f][2]);
+                        if (0.5 * (M[c] + M[q]) > cfg->a_min) acc += (lam[q] - lam[c]) * (u[q] - u[c]);
+                    }
+                    Mbar[c] = 0.5 * acc;
+                }
+        /* b = S t - mean(S t)  ->  tbar = S (lambda - mean lambda) */
+        double ml = field_mean(lam, n);
+        for (long p = 0; p < N3; ++p) lam[p] -= ml;
+        orc_smooth(lam, n, cfg->smooth_center, tbar);
+        /* source: Sigma = rho_bar - M, E = -2 [g > v_m] |Sigma|, C(lambda_0) */
+        double sum_sigbar = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) {
+                    long c = at(n, i, j, k);
+                    double e[3][3], v[3];
+                    triad(phi, n, i, j, k, e);
+                    double g = det3(e);
+                    double l0 = eig_min_vec(e, v);
+                    double sigma = rho_bar - M[c];
+                    double sgn = sigma > 0 ? 1.0 : (sigma < 0 ? -1.0 : 0.0);
+                    double sigbar = tbar[c] * (1.0 - (g > cfg->v_m ? 2.0 * sgn : 0.0));
+                    /* Sigma = rho_bar - M: Mbar -= sigbar, and every M_k gets mean(sigbar) */
+                    Mbar[c] -= sigbar;
+                    sum_sigbar += sigbar;
+                    double r = cfg->xi_m / l0 - 1.0;
+                    double lbar = r > 0.0 ? tbar[c] * 8.0 * r * (-cfg->xi_m / (l0 * l0)) : 0.0;
+                    double *hh = hb + c * 9;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) hh[a * 3 + b] = lbar * v[a] * v[b];
+                }
+        double msb = sum_sigbar / (double)N3;
+        for (long p = 0; p < N3; ++p) Mbar[p] += msb;
+        /* M = det(e) * rho~(x):  gbar = Mbar rho~,  xbar = Mbar det(e) grad rho~,
+         * mbar += Mbar det(e) W(x - j)  (the transposed CIC deposit) */
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) {
+                    long c = at(n, i, j, k);
+                    double e[3][3], cof[3][3], s3[3], x[3];
+                    triad(phi, n, i, j, k, e);
+                    double g = det3(e);
+                    cofactor(e, cof);
+                    displacement(phi, n, i, j, k, s3);
+                    x[0] = i + s3[0];
+                    x[1] = j + s3[1];
+                    x[2] = k + s3[2];
+                    int f[3];
+                    double w1[3];
+                    for (int a = 0; a < 3; ++a) {
+                        double fl = floor(x[a]);
+                        f[a] = (int)fl;
+                        w1[a] = x[a] - fl;
+                    }
+                    double rho_t = 0.0, grad[3] = {0, 0, 0};
+                    for (int cc = 0; cc < 8; ++cc) {
+                        int o[3] = {(cc >> 2) & 1, (cc >> 1) & 1, cc & 1};
+                        double w[3], dw[3];
+                        for (int a = 0; a < 3; ++a) {
+                            w[a] = o[a] ? w1[a] : 1.0 - w1[a];
+                            dw[a] = o[a] ? 1.0 : -1.0;
+                        }
+                        long q = at(n, f[0] + o[0], f[1] + o[1], f[2] + o[2]);
+                        double mv = g_tape.m[q];
+                        rho_t += w[0] * w[1] * w[2] * mv;
+                        grad[0] += dw[0] * w[1] * w[2] * mv;
+                        grad[1] += w[0] * dw[1] * w[2] * mv;
+                        grad[2] += w[0] * w[1] * dw[2] * mv;
+                        mbar[q] += Mbar[c] * g * w[0] * w[1] * w[2];
+                    }
+                    double gbar = Mbar[c] * rho_t;
+                    double *hh = hb + c * 9;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) hh[a * 3 + b] += gbar * cof[a][b];
+                    for (int a = 0; a < 3; ++a) xb[c * 3 + a] = Mbar[c] * g * grad[a];
+                }
+        /* phi enters through e (Hessian) and x (central differences) */
+        hess_transpose_add(hb, n, phibar);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) {
+                    long c = at(n, i, j, k);
+                    /* x_a(n) = n_a + (phi(n+a) - phi(n-a)) / 2 */
+                    phibar[at(n, i + 1, j, k)] += 0.5 * xb[c * 3 + 0];
+                    phibar[at(n, i - 1, j, k)] -= 0.5 * xb[c * 3 + 0];
+                    phibar[at(n, i, j + 1, k)] += 0.5 * xb[c * 3 + 1];
+                    phibar[at(n, i, j - 1, k)] -= 0.5 * xb[c * 3 + 1];
+                    phibar[at(n, i, j, k + 1)] += 0.5 * xb[c * 3 + 2];
+                    phibar[at(n, i, j, k - 1)] -= 0.5 * xb[c * 3 + 2];
+                }
+    }
+    if (status == ORC_OK) {
+        /* m = rho / mean(rho):  rhobar = (mbar - mean(mbar m)) / mean(rho) */
+        double mm = field_dot(mbar, g_tape.m, n) / (double)N3;
+        for (long p = 0; p < N3; ++p) grad_rho[p] = (mbar[p] - mm) / g_tape.mean;
+    }
+    free(phis);
+    free(tmp);
+    free(phibar);
+    free(mbar);
+    free(M);
+    free(ubar);
+    free(lam);
+    free(Mbar);
+    free(tbar);
+    free(hb);
+    free(xb);
+    return status;
+}
