@@ -1,0 +1,227 @@
+// Device helpers shared by the kernel files (internal, not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace recon {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ size_t lin(int i, int j, int k, int n)
+{
+    return ((size_t)i * n + j) * (size_t)n + k;
+}
+
+template <int OP>
+__device__ __forceinline__ double red_op(double a, double b)
+{
+    if (OP == RED_SUM) return a + b;
+    if (OP == RED_MAX) return a > b ? a : b;
+    return a < b ? a : b;
+}
+
+template <int OP>
+__device__ __forceinline__ double red_identity()
+{
+    if (OP == RED_SUM) return 0.0;
+    if (OP == RED_MAX) return -INFINITY;
+    return INFINITY;
+}
+
+// Block reduction of K values per thread into one row of partials.  Fixed
+// order: wavefront butterfly (64 lanes), then waves in index order.
+// Blocks must have at most 256 threads; blocks that are not a whole number of
+// 64-lane waves (grids below 8^3) take an LDS tree instead of the shuffles.
+template <int K, int OP>
+__device__ void block_reduce_store(double (&v)[K], double *part, int row)
+{
+    __shared__ double sm[16][K];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+    if (nthreads & 63) {
+        __shared__ double lds[256][K];
+        for (int s = tid; s < 256; s += nthreads)
+#pragma unroll
+            for (int c = 0; c < K; ++c) lds[s][c] = s == tid ? v[c] : red_identity<OP>();
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            for (int s = tid; s < w; s += nthreads)
+#pragma unroll
+                for (int c = 0; c < K; ++c) lds[s][c] = red_op<OP>(lds[s][c], lds[s + w][c]);
+            __syncthreads();
+        }
+        if (tid == 0)
+#pragma unroll
+            for (int c = 0; c < K; ++c) part[(size_t)row * K + c] = lds[0][c];
+        return;
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        double x = v[c];
+        for (int off = 32; off > 0; off >>= 1) x = red_op<OP>(x, __shfl_down(x, off, 64));
+        v[c] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) sm[wave][c] = v[c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int nw = (nthreads + 63) >> 6;
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            double x = sm[0][c];
+            for (int w = 1; w < nw; ++w) x = red_op<OP>(x, sm[w][c]);
+            part[(size_t)row * K + c] = x;
+        }
+    }
+}
+
+__device__ __forceinline__ int block_row()
+{
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+
+// Launch shape for n^3 stencil kernels: blocks of (bx, by) threads over
+// (k, j), each thread walking `ipb` consecutive i-planes.
+struct Shape3 {
+    dim3 grid, block;
+    int ipb;
+};
+
+static inline Shape3 shape3(int n)
+{
+    Shape3 sh;
+    // power-of-two block edges: whole 64-lane waves for every n >= 8
+    int bx = 1;
+    while (bx < n && bx < 64) bx <<= 1;
+    int by = 1;
+    while (by < n && by < 256 / bx) by <<= 1;
+    int gz = n < 64 ? n : 64;
+    int ipb = (n + gz - 1) / gz;
+    gz = (n + ipb - 1) / ipb;
+    sh.block = dim3(bx, by, 1);
+    sh.grid = dim3((n + bx - 1) / bx, (n + by - 1) / by, gz);
+    sh.ipb = ipb;
+    return sh;
+}
+
+static inline int rows_of(const Shape3 &sh) { return sh.grid.x * sh.grid.y * sh.grid.z; }
+
+// Launch shape for flat streams over n3 elements (grid-stride, fixed grid).
+static inline int flat_blocks(long n3)
+{
+    long b = (n3 + 255) / 256;
+    return (int)(b < 8192 ? b : 8192);
+}
+
+// ------------------------------------------------------------ symmetric 3x3
+
+struct Sym3 {
+    double xx, yy, zz, xy, xz, yz;
+};
+
+__device__ __forceinline__ double det_sym(const Sym3 &e)
+{
+    return e.xx * (e.yy * e.zz - e.yz * e.yz) - e.xy * (e.xy * e.zz - e.yz * e.xz) + e.xz * (e.xy * e.yz - e.yy * e.xz);
+}
+
+// Smallest eigenvalue of a symmetric 3x3 matrix, trigonometric closed form of
+// the characteristic cubic (O. K. Smith, CACM 4 (1961) 168).
+__device__ double lambda_min_sym(const Sym3 &e)
+{
+    const double p1 = e.xy * e.xy + e.xz * e.xz + e.yz * e.yz;
+    const double q = (e.xx + e.yy + e.zz) * (1.0 / 3.0);
+    const double dx = e.xx - q, dy = e.yy - q, dz = e.zz - q;
+    const double p2 = dx * dx + dy * dy + dz * dz + 2.0 * p1;
+    if (p2 <= 0.0) return q;
+    const double p = sqrt(p2 * (1.0 / 6.0));
+    const double ip = 1.0 / p;
+    Sym3 b{dx * ip, dy * ip, dz * ip, e.xy * ip, e.xz * ip, e.yz * ip};
+    double r = 0.5 * det_sym(b);
+    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+    const double ang = acos(r) * (1.0 / 3.0);
+    return q + 2.0 * p * cos(ang + 2.0943951023931954923);  // + 2 pi / 3
+}
+
+// 19-point neighbourhood of a node (centre, 6 faces, 12 edges), periodic.
+struct Stencil19 {
+    double c, xp, xm, yp, ym, zp, zm;
+    double xpyp, xpym, xmyp, xmym, xpzp, xpzm, xmzp, xmzm, ypzp, ypzm, ymzp, ymzm;
+};
+
+__device__ __forceinline__ void load19(const double *__restrict__ f, int i, int j, int k, int n, Stencil19 &s)
+{
+    const int ip = wrapc(i + 1, n), im = wrapc(i - 1, n);
+    const int jp = wrapc(j + 1, n), jm = wrapc(j - 1, n);
+    const int kp = wrapc(k + 1, n), km = wrapc(k - 1, n);
+    s.c = f[lin(i, j, k, n)];
+    s.xp = f[lin(ip, j, k, n)];
+    s.xm = f[lin(im, j, k, n)];
+    s.yp = f[lin(i, jp, k, n)];
+    s.ym = f[lin(i, jm, k, n)];
+    s.zp = f[lin(i, j, kp, n)];
+    s.zm = f[lin(i, j, km, n)];
+    s.xpyp = f[lin(ip, jp, k, n)];
+    s.xpym = f[lin(ip, jm, k, n)];
+    s.xmyp = f[lin(im, jp, k, n)];
+    s.xmym = f[lin(im, jm, k, n)];
+    s.xpzp = f[lin(ip, j, kp, n)];
+    s.xpzm = f[lin(ip, j, km, n)];
+    s.xmzp = f[lin(im, j, kp, n)];
+    s.xmzm = f[lin(im, j, km, n)];
+    s.ypzp = f[lin(i, jp, kp, n)];
+    s.ypzm = f[lin(i, jp, km, n)];
+    s.ymzp = f[lin(i, jm, kp, n)];
+    s.ymzm = f[lin(i, jm, km, n)];
+}
+
+// e = I + compact Hessian of the 19-point neighbourhood.
+__device__ __forceinline__ Sym3 triad19(const Stencil19 &s)
+{
+    Sym3 e;
+    e.xx = 1.0 + (s.xp - 2.0 * s.c + s.xm);
+    e.yy = 1.0 + (s.yp - 2.0 * s.c + s.ym);
+    e.zz = 1.0 + (s.zp - 2.0 * s.c + s.zm);
+    e.xy = 0.25 * (s.xpyp - s.xpym - s.xmyp + s.xmym);
+    e.xz = 0.25 * (s.xpzp - s.xpzm - s.xmzp + s.xmzm);
+    e.yz = 0.25 * (s.ypzp - s.ypzm - s.ymzp + s.ymzm);
+    return e;
+}
+
+template <typename T>
+__device__ __forceinline__ T facec(T an, T anb, T a_min)
+{
+    const T c = (T)0.5 * (an + anb);
+    return c > a_min ? c : a_min;
+}
+
+// Quotient x / d for d > 0 (a sum of floored face coefficients) without the
+// IEEE division sequence: hardware reciprocal, Newton refinement of the
+// reciprocal (FP64), then one residual correction of the quotient
+// (Markstein's method); within an ulp of the rounded quotient.  Every
+// Gauss-Seidel kernel of the smoother uses it, so they round identically.
+__device__ __forceinline__ float qdiv(float x, float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float q = x * r;
+    return fmaf(fmaf(-d, q, x), r, q);
+}
+
+__device__ __forceinline__ double qdiv(double x, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    const double q = x * r;
+    return fma(fma(-d, q, x), r, q);
+}
+
+
+}  // namespace recon

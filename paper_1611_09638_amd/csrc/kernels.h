@@ -89,4 +89,19 @@ hipError_t launch_update_ur(double *u, double *r, const double *pv, const double
 template <typename Z>
 hipError_t launch_add_correction(double *u, const Z *z, long n3, hipStream_t s);
 
+// ------------------------------------------------------------ adjoint (FP64)
+hipError_t launch_out_adj(const double *gd, const double *gp, double h2, double *phibar, int n, hipStream_t s);
+hipError_t launch_smooth_scaled(const double *f, double *out, int n, double c0, double scale, hipStream_t s);
+hipError_t launch_coefgrad(const double *lam, const double *u, const double *M, double a_min, double *Mbar, int n,
+                           hipStream_t s);
+// hb: 6 fields (xx, yy, zz, xy, xz, yz); partial K=1: sum of Sigmabar
+hipError_t launch_source_adj(const double *phi, const double *M, double rho_bar, const double *tbar, double xi_m,
+                             double v_m, double *Mbar, double *hb, int n, Part &p, hipStream_t s);
+// xb: 3 fields; mbar accumulated with atomics
+hipError_t launch_meshmass_adj(const double *phi, const double *m, const double *Mbar, double *hb, double *xb,
+                               double *mbar, int n, hipStream_t s);
+hipError_t launch_phibar_update(const double *hb, const double *xb, double *phibar, int n, hipStream_t s);
+hipError_t launch_dot(const double *a, const double *b, long n3, Part &p, hipStream_t s);  // K=1
+hipError_t launch_rho_grad(const double *mbar, double mm, double mu, double *g, long n3, hipStream_t s);
+
 }  // namespace recon

@@ -130,7 +130,11 @@ bool make_layout(int n, const recon_config *cfg, Layout &Lo)
         }
     }
     Lo.tape = cfg->record_tape ? take(f64 * (size_t)std::max(cfg->max_outer, 1)) : (size_t)-1;
+    // adjoint: phibar, Mbar, mbar, replayed phi, ebar (6 fields), xbar (3 fields)
+    const size_t adj_fields[6] = {1, 1, 1, 1, 6, 3};
     for (int i = 0; i < 8; ++i) Lo.adj[i] = (size_t)-1;
+    if (cfg->record_tape)
+        for (int i = 0; i < 6; ++i) Lo.adj[i] = take(f64 * adj_fields[i]);
     Lo.total = off;
     return true;
 }
@@ -160,6 +164,7 @@ struct recon_ctx {
     double tape_alpha[RECON_MAX_STEPS];
     double input_mean = 0.0;
     double box = 0.0;
+    double last_tol = 0.0;
     int tape_valid = 0;
     char err[512];
 };
@@ -506,6 +511,72 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
     return RECON_OK;
 }
 
+// Reverse sweep over the tape (transposes of the forward maps, in reverse
+// order); the discrete decisions of the forward are held fixed and each
+// linear solve is differentiated as exact.
+int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad)
+{
+    const recon_config &c = ctx->cfg;
+    const int n = ctx->n;
+    const long n3 = ctx->n3;
+    const double h = ctx->box / n;
+    double *phibar = wsp<double>(ctx, ctx->lo.adj[0]);
+    double *Mbar = wsp<double>(ctx, ctx->lo.adj[1]);
+    double *mbar = wsp<double>(ctx, ctx->lo.adj[2]);
+    double *phi = wsp<double>(ctx, ctx->lo.adj[3]);
+    double *hb = wsp<double>(ctx, ctx->lo.adj[4]);
+    double *xb = wsp<double>(ctx, ctx->lo.adj[5]);
+    const double *tape = wsp<double>(ctx, ctx->lo.tape);
+    double *ubar = ctx->b, *tbar = ctx->t;
+    double v[2];
+
+    HIPCHK(launch_out_adj(gd, gp, h * h, phibar, n, ctx->stream));
+    HIPCHK(launch_zero(mbar, n3 * 8, ctx->stream));
+    for (int s = ctx->tape_steps - 1; s >= 0; --s) {
+        const double *u_s = tape + (size_t)s * n3;
+        // phi_s, rebuilt from the increments exactly as the forward built it
+        HIPCHK(launch_zero(phi, n3 * 8, ctx->stream));
+        for (int q = 0; q < s; ++q) {
+            HIPCHK(launch_smooth(tape + (size_t)q * n3, ctx->dphi, n, c.smooth_center, 0.0, ctx->stream));
+            HIPCHK(launch_axpy(phi, ctx->dphi, ctx->tape_alpha[q], n3, ctx->stream));
+        }
+        HIPCHK(launch_meshmass(phi, ctx->m, ctx->M, n, ctx->part, ctx->stream));
+        TRY(fetch_sum(ctx, v));
+        const double rho_bar = v[0] / (double)n3;
+        // phi_{s+1} = phi_s + alpha S u:  ubar = alpha S phibar, made mean-free
+        HIPCHK(launch_smooth_scaled(phibar, ubar, n, c.smooth_center, ctx->tape_alpha[s], ctx->stream));
+        HIPCHK(launch_sum(ubar, n3, ctx->part, ctx->stream));
+        TRY(fetch_sum(ctx, v));
+        HIPCHK(launch_fill(ctx->scal + 16, 1, v[0] / (double)n3, ctx->stream));
+        HIPCHK(launch_add_scalar(ubar, ctx->scal + 16, -1.0, 1.0, n3, ctx->stream));
+        // u = A(M)^+ b:  lambda = A^+ ubar (same symmetric operator and solver)
+        TRY(build_hierarchy(ctx, ctx->M));
+        int cyc = 0;
+        double rel = 0.0;
+        TRY(mg_solve(ctx, ctx->M, ubar, ctx->last_tol, &cyc, &rel));
+        const double *lam = ctx->u;
+        HIPCHK(launch_coefgrad(lam, u_s, ctx->M, c.a_min, Mbar, n, ctx->stream));
+        // b = S t - mean:  tbar = S (lambda - mean lambda)
+        HIPCHK(launch_sum(lam, n3, ctx->part, ctx->stream));
+        TRY(fetch_sum(ctx, v));
+        HIPCHK(launch_smooth(lam, tbar, n, c.smooth_center, v[0] / (double)n3, ctx->stream));
+        // source, then Sigma = mean(M) - M
+        HIPCHK(launch_source_adj(phi, ctx->M, rho_bar, tbar, c.xi_m, c.v_m, Mbar, hb, n, ctx->part, ctx->stream));
+        TRY(fetch_sum(ctx, v));
+        HIPCHK(launch_fill(ctx->scal + 16, 1, v[0] / (double)n3, ctx->stream));
+        HIPCHK(launch_add_scalar(Mbar, ctx->scal + 16, 1.0, 1.0, n3, ctx->stream));
+        // M = det(e) rho~(x), then phibar through e and x
+        HIPCHK(launch_meshmass_adj(phi, ctx->m, Mbar, hb, xb, mbar, n, ctx->stream));
+        HIPCHK(launch_phibar_update(hb, xb, phibar, n, ctx->stream));
+    }
+    // m = rho / mean(rho)
+    HIPCHK(launch_dot(mbar, ctx->m, n3, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    HIPCHK(launch_rho_grad(mbar, v[0] / (double)n3, ctx->input_mean, grad, n3, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
 int check_ctx(recon_ctx *ctx) { return ctx ? RECON_OK : RECON_E_ARG; }
 
 }  // namespace
@@ -661,7 +732,8 @@ int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double
     TRY(normalize(ctx, density, ctx->m, &mean));
     ctx->input_mean = mean;
     ctx->box = box;
-    TRY(forward(ctx, box, tol > 0.0 ? tol : ctx->cfg.tol, phi_out, delta_r_out, st));
+    ctx->last_tol = tol > 0.0 ? tol : ctx->cfg.tol;
+    TRY(forward(ctx, box, ctx->last_tol, phi_out, delta_r_out, st));
     HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev1));
     float ms = 0.0f;
@@ -689,7 +761,8 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
     TRY(normalize(ctx, ctx->t, ctx->m, &mean));
     ctx->input_mean = mean;
     ctx->box = box;
-    TRY(forward(ctx, box, tol > 0.0 ? tol : ctx->cfg.tol, phi_out, delta_r_out, st));
+    ctx->last_tol = tol > 0.0 ? tol : ctx->cfg.tol;
+    TRY(forward(ctx, box, ctx->last_tol, phi_out, delta_r_out, st));
     HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev1));
     float ms = 0.0f;
@@ -702,10 +775,11 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
 int recon_backward(recon_ctx *ctx, const double *grad_delta_r, const double *grad_phi, double *grad_density)
 {
     TRY(check_ctx(ctx));
-    (void)grad_delta_r;
-    (void)grad_phi;
-    (void)grad_density;
-    return fail(ctx, RECON_E_NO_TAPE, "no recorded forward");
+    ctx->err[0] = 0;
+    if (!ctx->cfg.record_tape || !ctx->tape_valid)
+        return fail(ctx, RECON_E_NO_TAPE, "no forward with record_tape has completed on this context");
+    if (!grad_delta_r || !grad_density) return fail(ctx, RECON_E_ARG, "null gradient array");
+    return backward(ctx, grad_delta_r, grad_phi, grad_density);
 }
 
 // ------------------------------------------------------------- stage calls

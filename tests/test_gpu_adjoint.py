@@ -1,0 +1,111 @@
+"""The hand-written adjoint on the GPU (recon_backward through the C ABI)
+against the oracle's reverse mode and against central finite differences of
+the GPU forward, plus the torch.autograd.Function wrapper."""
+import numpy as np
+import pytest
+
+from paper_1611_09638_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+CASES = [
+    # n, box, sigma_g, seed, extra config, precision
+    (16, 125.0, 1.0, 7, {}, 0),
+    (32, 250.0, 1.5, 8, {}, 0),
+    (32, 250.0, 1.5, 8, {}, 1),
+    (16, 125.0, 2.0, 9, {"v_m": 1.05}, 0),
+    (48, 375.0, 1.0, 10, {"coarse_n": 6}, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=["16", "32", "32-mixed", "16-expansion", "48-ragged-mixed"])
+def test_gradient_matches_oracle(torch_cuda, orc, case):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box, sig, seed, extra, prec = case
+    rho = inputs.lognormal_density(n, box, sig, seed)
+    base = dict(max_outer=3, tol=1e-13, max_vcycles=300, **extra)
+    rng = np.random.default_rng(seed)
+    gd = rng.normal(size=rho.shape)
+    gp = rng.normal(size=rho.shape) * 1e-3
+    phi_o, d_o, st_o = orc.solve(rho, box, orc.Config(record_tape=1, **base))
+    g_o = orc.backward(gd, gp, box, orc.Config(**base))
+    rec = binding.Recon(n, binding.Config(record_tape=1, precision=prec, **base))
+    phi, d, st = rec.solve(torch.from_numpy(rho).cuda(), box)
+    assert st["alpha"] == st_o["alpha"]
+    g = rec.backward(torch.from_numpy(gd).cuda(), torch.from_numpy(gp).cuda()).cpu().numpy()
+    assert rel(g, g_o) < 1e-8, rel(g, g_o)
+
+
+def test_gradient_matches_finite_differences_on_gpu(torch_cuda):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 32, 250.0
+    rho = inputs.lognormal_density(n, box, 1.5, 21)
+    base = dict(max_outer=4, tol=1e-13, max_vcycles=300)
+    rec = binding.Recon(n, binding.Config(record_tape=1, **base))
+    fwd = binding.Recon(n, binding.Config(**base))
+    rho_d = torch.from_numpy(rho).cuda()
+    gd = torch.from_numpy(np.random.default_rng(2).normal(size=rho.shape)).cuda()
+    _, d0, st = rec.solve(rho_d, box)
+    g = rec.backward(gd).cpu().numpy()
+    vox = np.random.default_rng(44).choice(n ** 3, 16, replace=False)
+    errs = []
+    for flat in vox:
+        idx = np.unravel_index(flat, rho.shape)
+        eps = 1e-6 * rho[idx]
+        rp, rm = rho_d.clone(), rho_d.clone()
+        rp[idx] += eps
+        rm[idx] -= eps
+        _, dp, sp = fwd.solve(rp, box)
+        _, dm, sm = fwd.solve(rm, box)
+        assert sp["alpha"] == st["alpha"] == sm["alpha"]
+        fd = float((gd * (dp - dm)).sum()) / (2 * eps)
+        errs.append(abs(fd - g[idx]) / abs(fd))
+    assert max(errs) < 1e-4, errs
+
+
+def test_autograd_function(torch_cuda):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 16, 125.0
+    rho = torch.from_numpy(inputs.lognormal_density(n, box, 1.0, 3)).cuda().requires_grad_(True)
+    rec = binding.Recon(n, binding.Config(record_tape=1, max_outer=3, tol=1e-12))
+    w = torch.from_numpy(np.random.default_rng(1).normal(size=(n, n, n))).cuda()
+    delta, phi = binding.Reconstruct.apply(rho, rec, box)
+    loss = (w * delta).sum() + 1e-3 * (w * phi).sum()
+    loss.backward()
+    g_ref = rec.backward(w, 1e-3 * w)
+    assert torch.allclose(rho.grad, g_ref, rtol=1e-12, atol=1e-15)
+
+
+def test_backward_requires_a_recorded_forward(torch_cuda):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 16
+    g = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(binding.ReconError) as e:
+        binding.Recon(n, binding.Config()).backward(g)
+    assert e.value.code == -5
+    rec = binding.Recon(n, binding.Config(record_tape=1))
+    with pytest.raises(binding.ReconError) as e:
+        rec.backward(g)  # tape not recorded yet
+    assert e.value.code == -5
+    with pytest.raises(binding.ReconError):
+        rec.solve(-torch.ones_like(g), 10.0)  # a failed forward leaves no tape
+    with pytest.raises(binding.ReconError) as e:
+        rec.backward(g)
+    assert e.value.code == -5
