@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--workload", default="lognormal512")
     ap.add_argument("--skip-cpu", action="store_true", help="omit the oracle CPU baseline")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter run: one plain 1 GiB copy (calibration) and one fused sweep per precision at 512^3")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (one process per GPU; --gpus %d is not supported, "
@@ -79,6 +81,25 @@ def main():
     import torch
 
     from paper_1611_09638_amd import binding, inputs
+
+    if args.probe:
+        n = 512
+        dev = torch.device("cuda:0")
+        g = torch.Generator(device=dev).manual_seed(0)
+        a = torch.rand((n, n, n), dtype=torch.float64, device=dev, generator=g) + 0.01
+        u = torch.rand((n, n, n), dtype=torch.float64, device=dev, generator=g)
+        b = torch.rand((n, n, n), dtype=torch.float64, device=dev, generator=g)
+        y = torch.empty_like(a)
+        y.copy_(a)  # calibration: 1 GiB read + 1 GiB written
+        torch.cuda.synchronize()
+        rec = binding.Recon(n, binding.Config(precision=binding.MIXED), device=dev)
+        rec.rbgs(u.float(), a.float(), b.float(), first=1, variant=2)
+        rec.rbgs(u, a, b, first=1, variant=2)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy 1 GiB + fused sweep f32 + fused sweep f64", "n": n,
+                          "copy_bytes_read": n ** 3 * 8, "copy_bytes_written": n ** 3 * 8,
+                          "sweep_alg_bytes_f32": 16 * n ** 3, "sweep_alg_bytes_f64": 32 * n ** 3}), flush=True)
+        return
 
     w = inputs.WORKLOADS[args.workload]
     if w["kind"] != "lognormal":

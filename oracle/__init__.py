@@ -45,7 +45,7 @@ class OrcConfig(ctypes.Structure):
     _fields_ = [
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
-        ("max_halvings", ctypes.c_int), ("record_tape", ctypes.c_int), ("solver", ctypes.c_int),
+        ("max_halvings", ctypes.c_int), ("record_tape", ctypes.c_int), ("solver", ctypes.c_int), ("warm_start", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
         ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
         ("a_min", ctypes.c_double),
@@ -83,6 +83,7 @@ class Config:
     max_halvings: int = 30
     record_tape: int = 0
     solver: int = 0  # 0: V-cycle-preconditioned CG, 1: plain V-cycle iteration
+    warm_start: int = 1  # start each linear solve from the previous outer step's solution
     tol: float = 1e-10
     outer_tol: float = 0.0
     xi_m: float = 0.1

@@ -65,6 +65,7 @@ typedef struct {
     int max_halvings;
     int record_tape;
     int solver;
+    int warm_start;
     double tol;
     double outer_tol;
     double xi_m, v_m;
@@ -589,13 +590,15 @@ int orc_vcycle(const double *a0, const double *r, int n, const orc_config *cfg, 
     return ORC_OK;
 }
 
-/* Solve A(a) u = b on mean-free fields from u = 0, to ||b - A u|| <= tol ||b||.
+/* Solve A(a) u = b on mean-free fields to ||b - A u|| <= tol ||b||, starting
+ * from u0 when one is given and ||b - A u0|| < ||b||, else from u = 0.
  * solver 0: conjugate gradients preconditioned by one V-cycle per iteration
  *           (flexible form: beta = z_new.(r_new - r_old) / z_old.r_old);
  * solver 1: plain V-cycle iteration u += V(b - A u).
  * Returns the number of V-cycles (>= 0) or a negative error; *rel receives
  * the final true relative residual. */
-int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cfg, double *u_out, double *rel)
+int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_config *cfg, const double *u0,
+                      double *u_out, double *rel)
 {
     mg_t mg;
     int rc = mg_alloc(&mg, a0, n, cfg);
@@ -611,6 +614,14 @@ int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cf
     int status = ORC_E_NO_CONVERGENCE;
     double bn = norm2(b0, n);
     int cycles = 0;
+    memcpy(r, b0, sizeof(double) * N3);
+    if (u0 && bn > 0.0) {
+        orc_residual(u0, a0, b0, n, 1.0, cfg->a_min, z);
+        if (norm2(z, n) < bn) {
+            memcpy(u, u0, sizeof(double) * N3);
+            memcpy(r, z, sizeof(double) * N3);
+        }
+    }
     if (bn == 0.0) {
         status = 0;
     } else if (cfg->solver == 1) {
@@ -627,7 +638,6 @@ int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cf
             }
         }
     } else {
-        memcpy(r, b0, sizeof(double) * N3);
         precondition(&mg, r, z);
         cycles = 1;
         memcpy(p, z, sizeof(double) * N3);
@@ -668,6 +678,11 @@ int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cf
     free(r_old);
     mg_free(&mg);
     return status;
+}
+
+int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cfg, double *u_out, double *rel)
+{
+    return orc_mg_solve_from(a0, b0, n, cfg, NULL, u_out, rel);
 }
 
 /* ------------------------------------------------ positive-definite step control */
@@ -742,6 +757,7 @@ void orc_config_default(orc_config *c)
     c->max_halvings = 30;
     c->record_tape = 0;
     c->solver = 0;
+    c->warm_start = 1;
     c->tol = 1e-10;
     c->outer_tol = 0.0;
     c->xi_m = 0.1;
@@ -842,7 +858,8 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
             if (rms <= cfg->outer_tol) break;
             orc_source(phi, M, n, cfg->xi_m, cfg->v_m, cfg->smooth_center, b);
             double rel = 0.0;
-            int cyc = orc_mg_solve(M, b, n, cfg, u, &rel);
+            /* warm start: the previous step's solution (the steps are small) */
+            int cyc = orc_mg_solve_from(M, b, n, cfg, (cfg->warm_start && it > 0) ? u : NULL, u, &rel);
             st->rel_residual[it] = rel;
             if (cyc < 0) {
                 status = cyc;

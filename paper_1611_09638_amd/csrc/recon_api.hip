@@ -314,19 +314,31 @@ int precondition(recon_ctx *ctx)
     return vcycle<double>(ctx, ctx->L64, 0, ctx->r, ctx->z);
 }
 
-// Solve A(a0) u = b (b mean-free) into ctx->u; hierarchy must be built.
-int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int *cycles_out, double *rel_out)
+// Solve A(a0) u = b (b mean-free) into ctx->u; hierarchy must be built.  With
+// warm set, ctx->u holds the previous solution and is kept as the starting
+// guess when ||b - A u|| < ||b||; otherwise the solve starts from u = 0.
+int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int *cycles_out, double *rel_out,
+             bool warm = false)
 {
     const int n = ctx->n;
     const long n3 = ctx->n3;
     const bool mixed = ctx->cfg.precision == RECON_MIXED;
     float *r32 = mixed ? ctx->L32.b[0] : nullptr;
     double v[4];
-    // u = 0, so the residual kernel gives r = b and ||b||
-    HIPCHK(launch_zero(ctx->u, n3 * 8, ctx->stream));
-    HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+    HIPCHK(launch_dot(b, b, n3, ctx->part, ctx->stream));
     TRY(fetch_sum(ctx, v));
     const double bn = std::sqrt(v[0]);
+    bool started = false;
+    if (warm && bn > 0.0) {
+        HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+        TRY(fetch_sum(ctx, v));
+        started = std::sqrt(v[0]) < bn;
+    }
+    if (!started) {
+        // u = 0, so the residual kernel gives r = b
+        HIPCHK(launch_zero(ctx->u, n3 * 8, ctx->stream));
+        HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+    }
     int cycles = 0;
     int status = RECON_E_NO_CONVERGENCE;
     if (bn == 0.0) {
@@ -477,7 +489,7 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         TRY(build_hierarchy(ctx, ctx->M));
         int cyc = 0;
         double rel = 0.0;
-        TRY(mg_solve(ctx, ctx->M, ctx->b, tol, &cyc, &rel));
+        TRY(mg_solve(ctx, ctx->M, ctx->b, tol, &cyc, &rel, c.warm_start && it > 0));
         st->vcycles[it] = cyc;
         st->vcycles_total += cyc;
         st->rel_residual[it] = rel;
@@ -597,7 +609,9 @@ int recon_config_default(recon_config *c)
     c->max_halvings = 30;
     c->precision = RECON_FP64;
     c->solver = RECON_SOLVER_PCG;
+    c->warm_start = 1;
     c->record_tape = 0;
+    c->profile = 0;
     c->tol = 1e-10;
     c->outer_tol = 0.0;
     c->xi_m = 0.1;

@@ -554,9 +554,9 @@ hipError_t launch_rbgs_half(T *u, const T *a, const T *b, int n, T scale, T a_mi
 // first-colour values are never read (Gauss-Seidel overwrites them), so the
 // new ones are stored in place in the u ring.  Out of place because the
 // neighbouring tiles read this tile's halo from u_in.
-template <typename T, int TJ>
+template <typename T, int TJ, int TK_ = 64, int NT_ = 256>
 struct Fused {
-    static constexpr int TK = 64, NT = 256;
+    static constexpr int TK = TK_, NT = NT_;
     static constexpr int H = TJ + 4, W = TK + 4, PLANE = H * W;     // u, a: halo 2
     static constexpr int HB = TJ + 2, WB = TK + 2, PLANEB = HB * WB;  // b: halo 1
     static constexpr int LU = (PLANE + NT - 1) / NT;
@@ -585,12 +585,13 @@ __device__ __forceinline__ void lds_barrier()
 // Face order in both relaxations: +i, -i, +j, -j, +k, -k (as in k_rbgs_half),
 // so the fused and per-colour sweeps round identically.
 // ZERO: u_in is taken as 0 and not read (the first sweep from a zero guess).
-template <typename T, int TJ, int ZERO>
-__global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
+template <typename T, int TJ, int ZERO, int TK_ = 64, int NT_ = 256>
+__global__ void __launch_bounds__(NT_) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
                                                     const T *__restrict__ ag, const T *__restrict__ bg, int n,
                                                     int ci, T inv_scale, T a_min, int first)
 {
-    using F = Fused<T, TJ>;
+    using F = Fused<T, TJ, TK_, NT_>;
+    static_assert(TJ * TK_ % NT_ == 0, "every thread stores whole rounds of the tile");
     constexpr int W = F::W, PLANE = F::PLANE, WB = F::WB, PLANEB = F::PLANEB, NT = F::NT;
     __shared__ T sU[F::US][F::PU];
     __shared__ T sA[F::US][F::PU];
@@ -777,7 +778,7 @@ __global__ void __launch_bounds__(256) k_rbgs_fused(const T *__restrict__ uin, T
 template <typename T>
 static constexpr int fused_tj()
 {
-    return sizeof(T) == 4 ? 16 : 4;
+    return sizeof(T) == 4 ? 16 : 8;
 }
 
 template <typename T>
@@ -799,9 +800,9 @@ hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, in
     if (ci & 1) return hipErrorInvalidValue;  // the kernel's steady-state loop takes planes in pairs
     const int nblk = (n / 64) * (n / TJ) * (n / ci);
     if (zero_init)
-        k_rbgs_fused<T, TJ, 1><<<nblk, 256, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first);
+        k_rbgs_fused<T, TJ, 1, 64, 512><<<nblk, 512, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first);
     else
-        k_rbgs_fused<T, TJ, 0><<<nblk, 256, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first);
+        k_rbgs_fused<T, TJ, 0, 64, 512><<<nblk, 512, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min, first);
     return hipGetLastError();
 }
 
