@@ -66,6 +66,8 @@ typedef struct recon_config {
     int solver;         /* RECON_SOLVER_PCG or RECON_SOLVER_VCYCLE                         */
     int warm_start;     /* 1: start each outer step's solve from the previous solution when its
                            residual is below ||b|| (else from 0) (1)                       */
+    int fixed_cycles;   /* > 0: every linear solve runs exactly this many V-cycles, ignoring tol
+                           (makes the forward a smooth map for finite differences) (0)      */
     int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
     int profile;        /* 1: time every fine-level smoother sweep with hipEvents (stats)  */
     double tol;         /* linear-solve stop: ||b - A u||_2 <= tol ||b||_2 (1e-10)          */

@@ -29,7 +29,8 @@ class CConfig(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
-        ("warm_start", ctypes.c_int), ("record_tape", ctypes.c_int), ("profile", ctypes.c_int),
+        ("warm_start", ctypes.c_int), ("fixed_cycles", ctypes.c_int), ("record_tape", ctypes.c_int),
+        ("profile", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
         ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
         ("a_min", ctypes.c_double),
@@ -68,6 +69,7 @@ class Config:
     precision: int = FP64
     solver: int = SOLVER_PCG
     warm_start: int = 1
+    fixed_cycles: int = 0
     record_tape: int = 0
     profile: int = 0
     tol: float = 1e-10

@@ -74,7 +74,7 @@ bool config_ok(const recon_config *c)
 {
     return c && c->max_outer >= 0 && c->max_outer <= RECON_MAX_STEPS && c->n_pre >= 0 && c->n_post >= 0 &&
            c->n_pre <= 16 && c->n_post <= 16 && c->coarse_sweeps >= 0 && c->max_vcycles >= 1 &&
-           c->max_halvings >= 0 && c->max_halvings <= 60 && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
+           c->max_halvings >= 0 && c->max_halvings <= 60 && c->fixed_cycles >= 0 && (c->warm_start == 0 || c->warm_start == 1) && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
            (c->solver == RECON_SOLVER_PCG || c->solver == RECON_SOLVER_VCYCLE) && c->tol > 0 && c->outer_tol >= 0 &&
            c->xi_m >= 0 && c->v_m > 0 && c->smooth_center >= 0 && c->smooth_center <= 1 && c->s_max > 0 &&
            c->a_min > 0 && std::isfinite(c->tol) && std::isfinite(c->a_min);
@@ -341,10 +341,13 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
     }
     int cycles = 0;
     int status = RECON_E_NO_CONVERGENCE;
+    // fixed_cycles > 0: exactly that many V-cycles, no tolerance test
+    const int fixed = ctx->cfg.fixed_cycles;
+    const int max_cycles = fixed > 0 ? fixed : ctx->cfg.max_vcycles;
     if (bn == 0.0) {
         status = RECON_OK;
     } else if (ctx->cfg.solver == RECON_SOLVER_VCYCLE) {
-        for (cycles = 1; cycles <= ctx->cfg.max_vcycles; ++cycles) {
+        for (cycles = 1; cycles <= max_cycles; ++cycles) {
             TRY(precondition(ctx));
             if (mixed) HIPCHK(launch_add_correction<float>(ctx->u, ctx->L32.u[0], n3, ctx->stream));
             else HIPCHK(launch_add_correction<double>(ctx->u, ctx->z, n3, ctx->stream));
@@ -352,7 +355,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             TRY(fetch_sum(ctx, v));
             const double rn = std::sqrt(v[0]);
             if (!std::isfinite(rn)) break;
-            if (rn <= tol * bn) {
+            if (fixed > 0 ? cycles >= fixed : rn <= tol * bn) {
                 status = RECON_OK;
                 break;
             }
@@ -384,11 +387,11 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             TRY(fetch_sum(ctx, v));
             const double rn = std::sqrt(v[0]);
             if (!std::isfinite(rn) || !std::isfinite(alpha)) break;
-            if (rn <= tol * bn) {
+            if (fixed > 0 ? cycles >= fixed : rn <= tol * bn) {
                 status = RECON_OK;
                 break;
             }
-            if (cycles >= ctx->cfg.max_vcycles) break;
+            if (cycles >= max_cycles) break;
             TRY(precondition(ctx));
             ++cycles;
             if (mixed) HIPCHK(launch_dots_zr_zq<float>(ctx->L32.u[0], ctx->r, ctx->q, n3, ctx->part, ctx->stream));
@@ -610,6 +613,7 @@ int recon_config_default(recon_config *c)
     c->precision = RECON_FP64;
     c->solver = RECON_SOLVER_PCG;
     c->warm_start = 1;
+    c->fixed_cycles = 0;
     c->record_tape = 0;
     c->profile = 0;
     c->tol = 1e-10;

@@ -115,8 +115,12 @@ def test_lognormal128_filtered_power_loss(torch_cuda):
     """128^3 lognormal (box 500, sigma_g 1.5), 10 outer steps, loss
     L = sum_k exp(-k^2 R^2) |delta_r(k)|^2 with R = 10 Mpc/h: the GPU gradient
     at 64 seeded voxels against the FP64 oracle's (stored by
-    tests/golden/make_lognormal128_grad.py) and against central finite
-    differences of the GPU forward (eps = 1e-6 rho), both within 1e-4."""
+    tests/golden/make_lognormal128_grad.py), within 1e-4, and against central
+    finite differences of the GPU forward.  At this conditioning (coefficient
+    contrast ~1e5, ten nonlinear steps) the forward carries ~1e-10 relative
+    rounding noise, so differences with eps = 1e-6 rho scatter by up to a few
+    percent while eps = 1e-4 rho (truncation O(eps^2)) agrees to 1e-4; the
+    eps = 1e-6 check is made at 32^3 above."""
     import json
     import os
     torch = torch_cuda
@@ -144,7 +148,7 @@ def test_lognormal128_filtered_power_loss(torch_cuda):
     fd = []
     for flat in vox:
         idx = np.unravel_index(flat, (n, n, n))
-        eps = 1e-6 * float(rho[idx])
+        eps = 1e-4 * float(rho[idx])
         rp, rm = rho.clone(), rho.clone()
         rp[idx] += eps
         rm[idx] -= eps
@@ -156,3 +160,15 @@ def test_lognormal128_filtered_power_loss(torch_cuda):
     fd = np.array(fd)
     assert np.linalg.norm(g[vox] - fd) <= 1e-4 * np.linalg.norm(fd)
     assert np.abs(g[vox] - fd).max() <= 1e-4 * np.abs(fd).max()
+
+
+def test_fixed_cycles_option(torch_cuda):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 32
+    rho = torch.from_numpy(inputs.lognormal_density(n, 250.0, 1.0, 5)).cuda()
+    _, d1, st = binding.Recon(n, binding.Config(max_outer=3, fixed_cycles=7)).solve(rho, 250.0)
+    assert st["vcycles"] == [7, 7, 7]
+    _, d2, st2 = binding.Recon(n, binding.Config(max_outer=3, tol=1e-12)).solve(rho, 250.0)
+    if max(st2["vcycles"]) <= 7:
+        assert float((d1 - d2).norm() / d2.norm()) < 1e-8
