@@ -28,6 +28,32 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 METRIC = "recon wall time + smoother HBM GB/s at 512^3, mixed vs FP64, at 1e-6 rel L2"
 
 
+# The finest-level sweep kernels (the instantiation that reads u, a and b).
+FUSED_KERNEL = {"mixed": "k_rbgs_fused<float,16,0,64,512>", "fp64": "k_rbgs_fused<double,8,0,64,512>"}
+COUNTERS = os.path.join(ROOT, "profiles", "rbgs_fused_512_counters.json")
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE and
+    WRITE_SIZE counter runs (scaled by the same counters on a plain 1 GiB
+    copy), or None when they are absent, were taken at another size, or the
+    kernel source has changed since."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+        h = hashlib.sha256()
+        for src in c["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        digest = h.hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if digest != c["source_sha256"] or c["n"] != n or kernel not in c["kernels"]:
+        return None
+    return int(round(c["kernels"][kernel]["traffic_bytes"]))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -140,6 +166,7 @@ def main():
     node_bytes = 16 if head == "mixed" else 32
     sweep_ms = st["smoother_ms"] / max(st["smoother_sweeps"], 1)
     achieved = node_bytes * n ** 3 / (sweep_ms * 1e-3) / 1e9
+    kernel = FUSED_KERNEL[head]
     out = {
         "metric": METRIC,
         "value": round(H["wall_s"], 4),
@@ -164,20 +191,25 @@ def main():
         nb = 16 if name == "mixed" else 32
         sm = s["smoother_ms"] / max(s["smoother_sweeps"], 1)
         out["%s_s" % name] = round(R["wall_s"], 4)
+        zm = s["smoother_zero_ms"] / max(s["smoother_zero_sweeps"], 1)
         out["%s_smoother" % name] = {"sweeps": s["smoother_sweeps"], "ms_per_sweep": round(sm, 4),
                                      "GBps": round(nb * n ** 3 / (sm * 1e-3) / 1e9, 1),
-                                     "bytes_per_node": nb, "vcycles": s["vcycles_total"]}
+                                     "bytes_per_node": nb,
+                                     "zero_start_sweeps": s["smoother_zero_sweeps"],
+                                     "zero_start_ms_per_sweep": round(zm, 4),
+                                     "zero_start_GBps": round(nb * 3 // 4 * n ** 3 / (zm * 1e-3) / 1e9, 1),
+                                     "vcycles": s["vcycles_total"]}
     if len(results) == 2:
         a, b = results["mixed"], results["fp64"]
         out["speedup_mixed_vs_fp64"] = round(b["wall_s"] / a["wall_s"], 3)
         out["rel_l2_phi_mixed_vs_fp64"] = float((a["phi"] - b["phi"]).norm() / b["phi"].norm())
         out["rel_l2_delta_mixed_vs_fp64"] = float((a["delta"] - b["delta"]).norm() / b["delta"].norm())
         out["alpha_equal"] = a["stats"]["alpha"] == b["stats"]["alpha"]
-    out["roofline"] = {"bound": "hbm", "kernel": "k_rbgs_fused<%s> (finest level, one launch per sweep)"
-                       % ("float,16" if head == "mixed" else "double,4"),
+    out["roofline"] = {"bound": "hbm", "kernel": kernel + " (finest level, one launch per sweep)",
                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                       "bytes_per_node_per_sweep": node_bytes, "nodes": n ** 3}
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel, n),
+                       "bytes_per_node_per_sweep": node_bytes, "nodes": n ** 3,
+                       "algorithmic_bytes_per_launch": node_bytes * n ** 3}
     if not args.skip_cpu:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
         out["cpu_baseline"] = cpu_baseline(rho, n, st, cores)

@@ -69,6 +69,8 @@ typedef struct recon_config {
     int fixed_cycles;   /* > 0: every linear solve runs exactly this many V-cycles, ignoring tol
                            (makes the forward a smooth map for finite differences) (0)      */
     int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
+    int tape_fp32;      /* 1: store the tape's u_i in FP32 (half the tape memory; the
+                           backward then linearises about phi rebuilt from the rounded u_i) */
     int profile;        /* 1: time every fine-level smoother sweep with hipEvents (stats)  */
     double tol;         /* linear-solve stop: ||b - A u||_2 <= tol ||b||_2 (1e-10)          */
     double outer_tol;   /* outer stop when rms(Sigma) <= outer_tol (0: run max_outer)       */
@@ -93,8 +95,12 @@ typedef struct recon_stats {
     double min_lambda0;                 /* min over nodes of the smallest eigenvalue of I + Hess phi */
     double max_delta_r;                 /* max of delta_r (< 3 for a positive-definite map) */
     double ms_total;                    /* wall time of the solve on the stream (hipEvents) */
-    int smoother_sweeps;                /* fine-level RB-GS sweeps timed (cfg.profile) */
+    int smoother_sweeps;                /* fine-level RB-GS sweeps timed (cfg.profile) that read
+                                           u, a and b and write u */
     double smoother_ms;                 /* their summed kernel time on the stream */
+    int smoother_zero_sweeps;           /* timed fine-level sweeps that start a V-cycle from u = 0
+                                           (read a and b, write u) */
+    double smoother_zero_ms;            /* their summed kernel time */
 } recon_stats;
 
 typedef struct recon_ctx recon_ctx;

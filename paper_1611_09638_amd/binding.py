@@ -30,7 +30,7 @@ class CConfig(ctypes.Structure):
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
         ("warm_start", ctypes.c_int), ("fixed_cycles", ctypes.c_int), ("record_tape", ctypes.c_int),
-        ("profile", ctypes.c_int),
+        ("tape_fp32", ctypes.c_int), ("profile", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
         ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
         ("a_min", ctypes.c_double),
@@ -45,6 +45,7 @@ class CStats(ctypes.Structure):
         ("kappa", ctypes.c_double * (MAX_STEPS + 1)), ("rel_residual", ctypes.c_double * MAX_STEPS),
         ("min_det", ctypes.c_double), ("min_lambda0", ctypes.c_double), ("max_delta_r", ctypes.c_double),
         ("ms_total", ctypes.c_double), ("smoother_sweeps", ctypes.c_int), ("smoother_ms", ctypes.c_double),
+        ("smoother_zero_sweeps", ctypes.c_int), ("smoother_zero_ms", ctypes.c_double),
     ]
 
     def to_dict(self):
@@ -53,7 +54,8 @@ class CStats(ctypes.Structure):
                     alpha=list(self.alpha[:k]), rms_sigma=list(self.rms_sigma[:k + 1]),
                     kappa=list(self.kappa[:k + 1]), rel_residual=list(self.rel_residual[:k]),
                     min_det=self.min_det, min_lambda0=self.min_lambda0, max_delta_r=self.max_delta_r,
-                    ms_total=self.ms_total, smoother_sweeps=self.smoother_sweeps, smoother_ms=self.smoother_ms)
+                    ms_total=self.ms_total, smoother_sweeps=self.smoother_sweeps, smoother_ms=self.smoother_ms,
+                    smoother_zero_sweeps=self.smoother_zero_sweeps, smoother_zero_ms=self.smoother_zero_ms)
 
 
 @dataclass
@@ -71,6 +73,7 @@ class Config:
     warm_start: int = 1
     fixed_cycles: int = 0
     record_tape: int = 0
+    tape_fp32: int = 0
     profile: int = 0
     tol: float = 1e-10
     outer_tol: float = 0.0

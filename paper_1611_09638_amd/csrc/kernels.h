@@ -70,6 +70,7 @@ hipError_t launch_prolong_add(T *u, const T *e, int n, hipStream_t s);
 template <typename T>
 hipError_t launch_coarse_solve(T *u, const T *a, const T *b, int n, T scale, T a_min, int pairs, hipStream_t s);
 hipError_t launch_cast_f32(const double *src, float *dst, long n3, hipStream_t s);
+hipError_t launch_cast_f64(const float *src, double *dst, long n3, hipStream_t s);
 
 // ------------------------------------------------------------ Krylov (FP64)
 // r = b - A u (FP64) with partial K=1 sum r^2; writes r32 = (float) r if r32 != null

@@ -74,7 +74,8 @@ bool config_ok(const recon_config *c)
 {
     return c && c->max_outer >= 0 && c->max_outer <= RECON_MAX_STEPS && c->n_pre >= 0 && c->n_post >= 0 &&
            c->n_pre <= 16 && c->n_post <= 16 && c->coarse_sweeps >= 0 && c->max_vcycles >= 1 &&
-           c->max_halvings >= 0 && c->max_halvings <= 60 && c->fixed_cycles >= 0 && (c->warm_start == 0 || c->warm_start == 1) && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
+           c->max_halvings >= 0 && c->max_halvings <= 60 && c->fixed_cycles >= 0 && (c->warm_start == 0 || c->warm_start == 1) &&
+           (c->tape_fp32 == 0 || c->tape_fp32 == 1) && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
            (c->solver == RECON_SOLVER_PCG || c->solver == RECON_SOLVER_VCYCLE) && c->tol > 0 && c->outer_tol >= 0 &&
            c->xi_m >= 0 && c->v_m > 0 && c->smooth_center >= 0 && c->smooth_center <= 1 && c->s_max > 0 &&
            c->a_min > 0 && std::isfinite(c->tol) && std::isfinite(c->a_min);
@@ -129,12 +130,26 @@ bool make_layout(int n, const recon_config *cfg, Layout &Lo)
             Lo.lv32_a[l] = Lo.lv32_u[l] = Lo.lv32_b[l] = Lo.lv32_res[l] = Lo.lv32_tmp[l] = (size_t)-1;
         }
     }
-    Lo.tape = cfg->record_tape ? take(f64 * (size_t)std::max(cfg->max_outer, 1)) : (size_t)-1;
-    // adjoint: phibar, Mbar, mbar, replayed phi, ebar (6 fields), xbar (3 fields)
+    const size_t tape_field = cfg->tape_fp32 ? n3 * 4 : f64;
+    Lo.tape = cfg->record_tape ? take(tape_field * (size_t)std::max(cfg->max_outer, 1)) : (size_t)-1;
+    // adjoint: phibar, Mbar, mbar, replayed phi, ebar (6 fields), xbar (3 fields).
+    // The last three are live only between the end of a step's adjoint solve
+    // and the end of that step, when the forward's phi, the six fields b..q
+    // and dphi with the two fine-level V-cycle buffers are idle; they reuse
+    // that memory whenever those fields are packed back to back (f64 a
+    // multiple of the alignment), else they get their own.
     const size_t adj_fields[6] = {1, 1, 1, 1, 6, 3};
     for (int i = 0; i < 8; ++i) Lo.adj[i] = (size_t)-1;
-    if (cfg->record_tape)
-        for (int i = 0; i < 6; ++i) Lo.adj[i] = take(f64 * adj_fields[i]);
+    if (cfg->record_tape) {
+        const bool packed = f64 % kAlign == 0 && Lo.u == Lo.b + f64 && Lo.q == Lo.b + 5 * f64 &&
+                            Lo.lv64_res[0] == Lo.dphi + f64 && Lo.lv64_tmp[0] == Lo.dphi + 2 * f64;
+        for (int i = 0; i < 6; ++i) Lo.adj[i] = (packed && i >= 3) ? (size_t)-1 : take(f64 * adj_fields[i]);
+        if (packed) {
+            Lo.adj[3] = Lo.phi;
+            Lo.adj[4] = Lo.b;
+            Lo.adj[5] = Lo.dphi;
+        }
+    }
     Lo.total = off;
     return true;
 }
@@ -158,6 +173,7 @@ struct recon_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // cfg.profile: event pairs around each fine-level smoother sweep
     hipEvent_t *prof = nullptr;
+    bool prof_zero[4096];  // the timed sweep started from u = 0 (reads a and b only)
     int prof_count = 0;
     // tape of the last recorded forward
     int tape_steps = 0;
@@ -221,7 +237,7 @@ double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
 
 // ------------------------------------------------------------- multigrid
 
-constexpr int kProfPairs = 4096;
+constexpr int kProfPairs = 4096;  // size of recon_ctx::prof_zero
 
 // Levels of at least 256^3 whose edge is a multiple of 64 are swept by the
 // fused two-colour kernel; smaller levels (resident in L2/MALL) by two
@@ -248,21 +264,28 @@ int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, i
         HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream, l == 0));
         HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, 1 - first, false, ctx->stream, l == 0));
     }
-    if (timed) HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count++ + 1], ctx->stream));
+    if (timed) {
+        ctx->prof_zero[ctx->prof_count] = zero_init;
+        HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count++ + 1], ctx->stream));
+    }
     return RECON_OK;
 }
 
 // Sum the recorded fine-level sweep times (stream already synchronised).
 int collect_profile(recon_ctx *ctx, recon_stats *st)
 {
-    double ms = 0.0;
+    double ms[2] = {0.0, 0.0};
+    int count[2] = {0, 0};
     for (int i = 0; i < ctx->prof_count; ++i) {
         float e = 0.0f;
         HIPCHK(hipEventElapsedTime(&e, ctx->prof[2 * i], ctx->prof[2 * i + 1]));
-        ms += e;
+        ms[ctx->prof_zero[i]] += e;
+        ++count[ctx->prof_zero[i]];
     }
-    st->smoother_sweeps = ctx->prof_count;
-    st->smoother_ms = ms;
+    st->smoother_sweeps = count[0];
+    st->smoother_ms = ms[0];
+    st->smoother_zero_sweeps = count[1];
+    st->smoother_zero_ms = ms[1];
     ctx->prof_count = 0;
     return RECON_OK;
 }
@@ -503,7 +526,8 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         st->alpha[it] = alpha;
         st->outer_steps = it + 1;
         if (c.record_tape) {
-            HIPCHK(launch_copy(wsp<double>(ctx, ctx->lo.tape) + (size_t)it * n3, ctx->u, n3, ctx->stream));
+            if (c.tape_fp32) HIPCHK(launch_cast_f32(ctx->u, wsp<float>(ctx, ctx->lo.tape) + (size_t)it * n3, n3, ctx->stream));
+            else HIPCHK(launch_copy(wsp<double>(ctx, ctx->lo.tape) + (size_t)it * n3, ctx->u, n3, ctx->stream));
             ctx->tape_alpha[it] = alpha;
             ctx->tape_steps = it + 1;
         }
@@ -541,18 +565,26 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad)
     double *phi = wsp<double>(ctx, ctx->lo.adj[3]);
     double *hb = wsp<double>(ctx, ctx->lo.adj[4]);
     double *xb = wsp<double>(ctx, ctx->lo.adj[5]);
-    const double *tape = wsp<double>(ctx, ctx->lo.tape);
     double *ubar = ctx->b, *tbar = ctx->t;
     double v[2];
+    // u_q of the tape as FP64; an FP32 tape is widened into z, which is idle
+    // whenever this is called (before a step's solve and right after it)
+    auto tape_u = [&](int q) -> const double * {
+        if (!c.tape_fp32) return wsp<double>(ctx, ctx->lo.tape) + (size_t)q * n3;
+        return launch_cast_f64(wsp<float>(ctx, ctx->lo.tape) + (size_t)q * n3, ctx->z, n3, ctx->stream) == hipSuccess
+                   ? ctx->z
+                   : nullptr;
+    };
 
     HIPCHK(launch_out_adj(gd, gp, h * h, phibar, n, ctx->stream));
     HIPCHK(launch_zero(mbar, n3 * 8, ctx->stream));
     for (int s = ctx->tape_steps - 1; s >= 0; --s) {
-        const double *u_s = tape + (size_t)s * n3;
         // phi_s, rebuilt from the increments exactly as the forward built it
         HIPCHK(launch_zero(phi, n3 * 8, ctx->stream));
         for (int q = 0; q < s; ++q) {
-            HIPCHK(launch_smooth(tape + (size_t)q * n3, ctx->dphi, n, c.smooth_center, 0.0, ctx->stream));
+            const double *u_q = tape_u(q);
+            if (!u_q) return fail(ctx, RECON_E_HIP, "tape widening launch failed");
+            HIPCHK(launch_smooth(u_q, ctx->dphi, n, c.smooth_center, 0.0, ctx->stream));
             HIPCHK(launch_axpy(phi, ctx->dphi, ctx->tape_alpha[q], n3, ctx->stream));
         }
         HIPCHK(launch_meshmass(phi, ctx->m, ctx->M, n, ctx->part, ctx->stream));
@@ -570,6 +602,8 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad)
         double rel = 0.0;
         TRY(mg_solve(ctx, ctx->M, ubar, ctx->last_tol, &cyc, &rel));
         const double *lam = ctx->u;
+        const double *u_s = tape_u(s);
+        if (!u_s) return fail(ctx, RECON_E_HIP, "tape widening launch failed");
         HIPCHK(launch_coefgrad(lam, u_s, ctx->M, c.a_min, Mbar, n, ctx->stream));
         // b = S t - mean:  tbar = S (lambda - mean lambda)
         HIPCHK(launch_sum(lam, n3, ctx->part, ctx->stream));
@@ -615,6 +649,7 @@ int recon_config_default(recon_config *c)
     c->warm_start = 1;
     c->fixed_cycles = 0;
     c->record_tape = 0;
+    c->tape_fp32 = 0;
     c->profile = 0;
     c->tol = 1e-10;
     c->outer_tol = 0.0;

@@ -22,10 +22,31 @@ the same kind stand in for them:
 
 All arrays are C-order [i][j][k] (k fastest); positions are float32 (x, y, z)
 in Mpc/h with x along the first array index.
+
+Transforms are numpy's below 1024^3 and scipy's multithreaded ones from
+1024^3 up (the same transforms; only the rounding of the input may differ).
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+
+BIG = 1024  # grids of this edge and larger use threaded transforms
+
+
+def _rfftn(x):
+    if x.shape[0] >= BIG:
+        import scipy.fft
+        return scipy.fft.rfftn(x, workers=min(os.cpu_count() or 1, 16))
+    return np.fft.rfftn(x)
+
+
+def _irfftn(x, n):
+    if n >= BIG:
+        import scipy.fft
+        return scipy.fft.irfftn(x, s=(n, n, n), axes=(0, 1, 2), workers=min(os.cpu_count() or 1, 16))
+    return np.fft.irfftn(x, s=(n, n, n), axes=(0, 1, 2))
 
 K_PEAK = 0.02  # h/Mpc, the turnover scale of the synthetic spectrum
 
@@ -47,7 +68,7 @@ def gaussian_field(n: int, box: float, seed: int) -> np.ndarray:
     """Zero-mean Gaussian random field with the synthetic spectrum shape (float64)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     white = rng.standard_normal((n, n, n))
-    wk = np.fft.rfftn(white)
+    wk = _rfftn(white)
     del white
     kx, kz = _kgrid(n, box)
     k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
@@ -55,7 +76,7 @@ def gaussian_field(n: int, box: float, seed: int) -> np.ndarray:
     del k2
     wk *= amp
     del amp
-    g = np.fft.irfftn(wk, s=(n, n, n), axes=(0, 1, 2))
+    g = _irfftn(wk, n)
     del wk
     g -= g.mean()
     return g
@@ -74,7 +95,7 @@ def lognormal_density(n: int, box: float, sigma_g: float, seed: int) -> np.ndarr
 def zeldovich_displacement(n: int, box: float, rms_cells: float, seed: int) -> np.ndarray:
     """Displacement Psi (shape (3, n, n, n), in cells) with sqrt(<|Psi|^2>) = rms_cells."""
     g = gaussian_field(n, box, seed)
-    gk = np.fft.rfftn(g)
+    gk = _rfftn(g)
     del g
     kx, kz = _kgrid(n, box)
     k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
@@ -82,7 +103,7 @@ def zeldovich_displacement(n: int, box: float, rms_cells: float, seed: int) -> n
     psi = np.empty((3, n, n, n), dtype=np.float64)
     comps = (kx[:, None, None], kx[None, :, None], kz[None, None, :])
     for a in range(3):
-        psi[a] = np.fft.irfftn(1j * comps[a] / k2 * gk, s=(n, n, n), axes=(0, 1, 2))
+        psi[a] = _irfftn(1j * comps[a] / k2 * gk, n)
     rms = np.sqrt(np.mean(np.sum(psi * psi, axis=0)))
     psi *= rms_cells / rms
     return psi

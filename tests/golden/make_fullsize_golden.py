@@ -1,0 +1,68 @@
+"""Write <workload>_oracle_forward.json: the FP64 oracle's forward solve of a
+full-size lognormal workload (256^3 or 512^3, default configuration: 10 outer
+steps, inner tolerance 1e-10), reduced to what a GPU test can compare without
+running the oracle: the step sizes, V-cycle counts and per-step rms(Sigma),
+phi and delta_r at 2048 seeded voxels, their 8^3 block means, and the L2
+norms of both fields.
+
+Calls only oracle/ and the seeded input generators.  Run from the repository
+root: python tests/golden/make_fullsize_golden.py lognormal256 [lognormal512]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1611_09638_amd import inputs  # noqa: E402
+
+N_VOX = 2048
+VOX_SEED = 45
+BLOCKS = 8
+
+
+def block_means(f, nb):
+    n = f.shape[0]
+    s = n // nb
+    return f.reshape(nb, s, nb, s, nb, s).mean(axis=(1, 3, 5))
+
+
+def main(names):
+    oracle.build(force=False)
+    for name in names:
+        w = inputs.WORKLOADS[name]
+        n, box = w["n"], w["box"]
+        rho = inputs.lognormal_density(n, box, w["sigma_g"], w["seed"])
+        cfg = oracle.Config()
+        t0 = time.time()
+        phi, delta, st = oracle.solve(rho, box, cfg)
+        t1 = time.time()
+        del rho
+        vox = np.random.default_rng(VOX_SEED).choice(n ** 3, N_VOX, replace=False)
+        out = {
+            "workload": name, "n": n, "box": box, "sigma_g": w["sigma_g"], "seed": w["seed"],
+            "tol": cfg.tol, "max_outer": cfg.max_outer, "vox_seed": VOX_SEED,
+            "alpha": st["alpha"], "vcycles": st["vcycles"], "rms_sigma": st["rms_sigma"],
+            "voxels": [int(v) for v in vox],
+            "phi": [float(phi.ravel()[v]) for v in vox],
+            "delta_r": [float(delta.ravel()[v]) for v in vox],
+            "phi_blocks": block_means(phi, BLOCKS).ravel().tolist(),
+            "delta_r_blocks": block_means(delta, BLOCKS).ravel().tolist(),
+            "phi_l2": float(np.linalg.norm(phi)), "delta_r_l2": float(np.linalg.norm(delta)),
+            "delta_r_max": float(delta.max()),
+            "oracle_seconds": round(t1 - t0, 1), "threads": int(os.environ.get("OMP_NUM_THREADS", "0")),
+            "generator": "tests/golden/make_fullsize_golden.py (FP64 oracle, C + OpenMP)",
+        }
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name + "_oracle_forward.json")
+        with open(path, "w") as f:
+            json.dump(out, f, indent=0)
+        print("wrote", path, out["oracle_seconds"], "s", st["alpha"], st["vcycles"], flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["lognormal256"])

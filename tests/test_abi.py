@@ -57,6 +57,18 @@ def test_config_default_and_workspace_sizing(blib):
     assert blib.workspace_bytes(64, mixed) > w64
     tape = blib.Config(record_tape=1)
     assert blib.workspace_bytes(64, tape) >= w64 + 10 * 64 ** 3 * 8
+    # the adjoint needs three fields of its own; the other ten reuse idle forward memory
+    assert blib.workspace_bytes(64, tape) == w64 + 13 * 64 ** 3 * 8
+    tape32 = blib.Config(record_tape=1, tape_fp32=1)
+    assert blib.workspace_bytes(64, tape32) == w64 + 8 * 64 ** 3 * 8
+    # 14^3 doubles are not a multiple of 256 bytes: no reuse, ten more fields
+    w14 = blib.workspace_bytes(14, blib.Config(coarse_n=14))
+    assert w14 > 0 and blib.workspace_bytes(14, blib.Config(coarse_n=14, record_tape=1)) > w14 + 23 * 14 ** 3 * 8
+    # 1024^3 particles, mixed forward and adjoint with an FP32 tape, fits 288 GB with room
+    # for the caller's particles, outputs and gradients
+    big = blib.workspace_bytes(1024, blib.Config(precision=blib.MIXED, record_tape=1, tape_fp32=1))
+    assert 190 * 2 ** 30 < big < 200 * 2 ** 30
+    assert blib.workspace_bytes(32, blib.Config(tape_fp32=2)) == 0
     # invalid sizes and configs
     assert blib.workspace_bytes(24, cfg) == 0       # 24 -> 12 -> 6 never reaches 8
     assert blib.workspace_bytes(48, blib.Config(coarse_n=6)) > 0

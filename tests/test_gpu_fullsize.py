@@ -88,3 +88,43 @@ def test_mixed_matches_fp64_at_512(torch_cuda, field512):
         assert d.max() < 3.0
         assert np.isfinite(d).all()
         assert abs(st["kappa"][0] - 1.0) < 1e-12  # mass on the undeformed mesh is the input mass
+
+
+def _oracle_forward(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name + "_oracle_forward.json")) as f:
+        return json.load(f)
+
+
+def _check_against_oracle(gold, phi, d, st):
+    """The GPU solve against the FP64 oracle's, stored by
+    tests/golden/make_fullsize_golden.py: identical step sizes, and phi and
+    delta_r within 1e-6 relative L2 at 2048 seeded voxels, in their 8^3 block
+    means (every node contributes) and in their full-grid L2 norms."""
+    n = gold["n"]
+    assert st["alpha"] == gold["alpha"]
+    assert max(st["rel_residual"]) <= gold["tol"]
+    assert np.allclose(st["rms_sigma"], gold["rms_sigma"], rtol=1e-6, atol=0)
+    vox = np.array(gold["voxels"])
+    for f, key in ((phi, "phi"), (d, "delta_r")):
+        g = f.reshape(-1)[vox]
+        assert rel(g, gold[key]) <= 1e-6, (key, rel(g, gold[key]))
+        blocks = f.reshape(8, n // 8, 8, n // 8, 8, n // 8).mean(axis=(1, 3, 5)).ravel()
+        assert rel(blocks, gold[key + "_blocks"]) <= 1e-6, (key, rel(blocks, gold[key + "_blocks"]))
+        assert abs(np.linalg.norm(f) - gold[key + "_l2"]) <= 1e-6 * gold[key + "_l2"]
+    assert abs(d.max() - gold["delta_r_max"]) <= 1e-6 * abs(gold["delta_r_max"])
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_lognormal256_against_oracle(torch_cuda, prec):
+    """256^3 lognormal (box 1000, sigma_g 1.5), default configuration (10
+    outer steps, tol 1e-10), FP64 and mixed, against the oracle's solve."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    gold = _oracle_forward("lognormal256")
+    w = inputs.WORKLOADS["lognormal256"]
+    rho = inputs.lognormal_density(w["n"], w["box"], w["sigma_g"], w["seed"])
+    rec = binding.Recon(w["n"], binding.Config(precision=prec))
+    phi, d, st = rec.solve(torch.from_numpy(rho).cuda(), w["box"])
+    _check_against_oracle(gold, phi.cpu().numpy(), d.cpu().numpy(), st)
