@@ -94,7 +94,12 @@ def lognormal_density(n: int, box: float, sigma_g: float, seed: int) -> np.ndarr
 
 def zeldovich_displacement(n: int, box: float, rms_cells: float, seed: int) -> np.ndarray:
     """Displacement Psi (shape (3, n, n, n), in cells) with sqrt(<|Psi|^2>) = rms_cells."""
-    g = gaussian_field(n, box, seed)
+    return displacement_from_field(gaussian_field(n, box, seed), box, rms_cells)
+
+
+def displacement_from_field(g: np.ndarray, box: float, rms_cells: float) -> np.ndarray:
+    """Psi = IFFT(i k / k^2 FFT(g)) rescaled to sqrt(<|Psi|^2>) = rms_cells (consumes g)."""
+    n = g.shape[0]
     gk = _rfftn(g)
     del g
     kx, kz = _kgrid(n, box)
@@ -109,21 +114,25 @@ def zeldovich_displacement(n: int, box: float, rms_cells: float, seed: int) -> n
     return psi
 
 
-def zeldovich_particles(n: int, box: float, rms_cells: float, seed: int) -> np.ndarray:
-    """n^3 lattice particles displaced by a Zel'dovich field; float32 [n^3, 3] in Mpc/h."""
-    psi = zeldovich_displacement(n, box, rms_cells, seed)
+def particles_from_displacement(psi: np.ndarray, box: float) -> np.ndarray:
+    """Lattice sites q displaced by psi (cells), wrapped into [0, box); float32 [n^3, 3] in Mpc/h."""
+    n = psi.shape[1]
     q = np.arange(n, dtype=np.float64)
     pos = np.empty((n, n, n, 3), dtype=np.float64)
     pos[..., 0] = q[:, None, None] + psi[0]
     pos[..., 1] = q[None, :, None] + psi[1]
     pos[..., 2] = q[None, None, :] + psi[2]
-    del psi
     pos *= box / n
     np.mod(pos, box, out=pos)
     out = pos.reshape(-1, 3).astype(np.float32)
     # float32 rounding can turn a value just below box into exactly box
     out[out >= np.float32(box)] = 0.0
     return out
+
+
+def zeldovich_particles(n: int, box: float, rms_cells: float, seed: int) -> np.ndarray:
+    """n^3 lattice particles displaced by a Zel'dovich field; float32 [n^3, 3] in Mpc/h."""
+    return particles_from_displacement(zeldovich_displacement(n, box, rms_cells, seed), box)
 
 
 # Workloads used by the tests and the benchmark: (n, box, kind, parameter, seed).

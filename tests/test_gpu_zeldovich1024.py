@@ -49,7 +49,13 @@ def test_zeldovich1024_mixed_forward_and_adjoint():
     w = inputs.WORKLOADS["zeldovich1024"]
     n, box = w["n"], w["box"]
     t0 = time.perf_counter()
-    pos_h = inputs.zeldovich_particles(n, box, w["rms_cells"], w["seed"])
+    g = inputs.gaussian_field(n, box, w["seed"])
+    say("zeldovich1024: Gaussian field %.1fs" % (time.perf_counter() - t0))
+    psi = inputs.displacement_from_field(g, box, w["rms_cells"])
+    del g
+    say("zeldovich1024: displacement %.1fs" % (time.perf_counter() - t0))
+    pos_h = inputs.particles_from_displacement(psi, box)
+    del psi
     say("zeldovich1024: %d particles generated in %.1fs" % (pos_h.shape[0], time.perf_counter() - t0))
     pos = torch.from_numpy(pos_h).cuda()
     del pos_h
