@@ -13,7 +13,27 @@ any size (the oracle parity of every piece is tested at smaller sizes and at
 * the gradient is blind to a rescaling of the density (the input is
   normalised by its mean);
 * the gradient's directional derivative along a smooth relative modulation
-  of the density matches central differences of two more forward solves.
+  of the density matches central differences of two more forward solves;
+* the mixed-precision solve matches the FP64 solve to 1e-6 relative L2.
+
+The directional check is bounded by the forward map, not by the adjoint.
+The deformed-mesh mass interpolates the density trilinearly, so its
+derivative jumps wherever a node crosses a cell face. A global perturbation
+of size eps moves O(eps n^3) nodes across faces, which gives the central
+difference an O(eps) bias. Below eps ~ 1e-6 the rounding of the forward
+(relative ~1e-13 per solve) divided by eps takes over. Measured on these
+inputs at 1.95 Mpc/h cells, as the relative difference of adjoint and
+central difference:
+
+    eps        64^3      128^3     256^3
+    1e-4     2.7e-3   -2.1e-3    2.1e-3
+    1e-5     5.2e-4   -2.1e-5    2.7e-3
+    1e-6     3.7e-5   -3.7e-4    7.4e-5
+    1e-7     2.1e-5    1.5e-4   -9.9e-5
+
+The 64^3 column is also the oracle's.  The check uses eps = 1e-6 and allows
+2e-3.  The adjoint itself is pinned against the oracle's to 1e-8 and against
+per-voxel differences to 1e-4 at the smaller sizes.
 """
 import math
 import sys
@@ -59,8 +79,10 @@ def test_zeldovich1024_mixed_forward_and_adjoint():
     say("zeldovich1024: %d particles generated in %.1fs" % (pos_h.shape[0], time.perf_counter() - t0))
     pos = torch.from_numpy(pos_h).cuda()
     del pos_h
-    cfg = binding.Config(precision=binding.MIXED, record_tape=1, tape_fp32=1)
-    rec = binding.Recon(n, cfg)
+    # tol 1e-12 so that the central differences below resolve eps = 1e-6 (the
+    # recomputed true residual has an FP64 rounding floor near 5e-13 here)
+    base = dict(tol=1e-12, max_vcycles=200)
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED, record_tape=1, tape_fp32=1, **base))
     say("workspace %.1f GiB" % (rec.workspace.numel() / 2 ** 30))
 
     rho = rec.cic(pos, box)
@@ -73,16 +95,16 @@ def test_zeldovich1024_mixed_forward_and_adjoint():
     say("forward %.1fs, V-cycles %s, alpha %s" % (time.perf_counter() - t0, st["vcycles"], st["alpha"]))
     del pos
     assert st["outer_steps"] == 10
-    assert max(st["rel_residual"]) <= 1e-10
+    assert max(st["rel_residual"]) <= 2e-12
     assert st["min_det"] > 0 and st["min_lambda0"] > 0
     assert st["max_delta_r"] < 3.0 and float(d.max()) < 3.0
     assert bool(torch.isfinite(d).all())
     assert abs(st["kappa"][0] - 1.0) < 1e-12
+    d_mixed = d.cpu()
+    del d
 
     # L = sum_n W_n delta_r,n with a smooth weight
     W = wave(torch, n, (3, 1, 2), torch.cos)
-    L0 = float(torch.dot(W.view(-1), d.view(-1)))
-    del d
     t0 = time.perf_counter()
     g = rec.backward(W)
     torch.cuda.synchronize()
@@ -97,8 +119,8 @@ def test_zeldovich1024_mixed_forward_and_adjoint():
     v.mul_(rho)
     dir_adj = float(torch.dot(g.view(-1), v.view(-1)))
     del g
-    eps = 1e-4
-    Ls = []
+    eps = 1e-6
+    fields = []
     for sgn in (1.0, -1.0):
         r = torch.add(rho, v, alpha=sgn * eps)
         t0 = time.perf_counter()
@@ -106,10 +128,27 @@ def test_zeldovich1024_mixed_forward_and_adjoint():
         torch.cuda.synchronize()
         say("forward at %+g: %.1fs" % (sgn * eps, time.perf_counter() - t0))
         assert ss["alpha"] == st["alpha"]
-        Ls.append(float(torch.dot(W.view(-1), ds.view(-1))))
-        del r, ds
-    dir_fd = (Ls[0] - Ls[1]) / (2 * eps)
-    say("L %.6e, directional derivative adjoint %.9e, central difference %.9e, rel %.2e"
-        % (L0, dir_adj, dir_fd, abs(dir_adj - dir_fd) / abs(dir_fd)))
-    assert abs(dir_adj - dir_fd) <= 1e-4 * abs(dir_fd)
-    assert np.isfinite(L0)
+        fields.append(ds)
+        del r
+    # difference the fields before the loss: no cancellation in L itself
+    fields[0].sub_(fields[1])
+    dir_fd = float(torch.dot(W.view(-1), fields[0].view(-1))) / (2 * eps)
+    del fields, v, W
+    rel_dir = abs(dir_adj - dir_fd) / abs(dir_fd)
+    say("directional derivative: adjoint %.9e, central difference %.9e, rel %.2e" % (dir_adj, dir_fd, rel_dir))
+    assert rel_dir <= 2e-3
+
+    # the same grid through the FP64 solve
+    del rec
+    torch.cuda.empty_cache()
+    rec = binding.Recon(n, binding.Config(precision=binding.FP64, **base))
+    t0 = time.perf_counter()
+    _, d64, s64 = rec.solve(rho, box, want_phi=False)
+    torch.cuda.synchronize()
+    say("FP64 forward %.1fs, V-cycles %s" % (time.perf_counter() - t0, s64["vcycles"]))
+    assert s64["alpha"] == st["alpha"]
+    d64 = d64.cpu()
+    rel_mixed = float((d_mixed - d64).norm() / d64.norm())
+    say("delta_r mixed vs FP64: rel L2 %.2e" % rel_mixed)
+    assert rel_mixed <= 1e-6
+    assert np.isfinite(rel_mixed)
