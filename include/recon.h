@@ -179,9 +179,21 @@ int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out);
 /* out = A u with A = div(a grad .) in flux form on an nl^3 level (scale 4^-l). */
 int recon_stage_apply(recon_ctx *ctx, const double *u, const double *a, int nl, double scale, double *out);
 
-/* r = b - A u on an nl^3 level. */
+/* r = b - A u on an nl^3 level.  variant 0: the kernel the solver uses on
+ * that level; 1: per-node gathers; 2: the LDS-streaming kernel (nl a
+ * multiple of 64, else RECON_E_ARG). */
 int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const void *b, int nl, double scale,
-                         void *r, int dtype);
+                         void *r, int dtype, int variant);
+
+/* One conjugate-gradient direction on the fine level (the Krylov loop around
+ * the V-cycle preconditioner): p_new = z (first != 0) or z + beta p_old,
+ * q = A p_new, and *pq (host) <- p_new . q.  z is FP64 (z_dtype 0) or FP32
+ * (z_dtype 1); p_old, p_new, a, q are FP64 and p_new must differ from p_old
+ * (p_old is not read, and may be NULL, when first != 0).  variant as for
+ * recon_stage_residual (1: in-place update then gathers; 2: one fused
+ * streaming pass). */
+int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const double *p_old, const double *a,
+                          double beta, int first, double *p_new, double *q, double *pq, int variant);
 
 /* One red-black Gauss-Seidel sweep in place (colour `first` then the other;
  * red = i+j+k even) on an nl^3 level.  variant 0: the kernel the solver uses

@@ -127,7 +127,8 @@ def lib():
         "recon_stage_source": (i, [vp, vp, vp, vp, pd]),
         "recon_stage_smooth": (i, [vp, vp, vp]),
         "recon_stage_apply": (i, [vp, vp, vp, i, d, vp]),
-        "recon_stage_residual": (i, [vp, vp, vp, vp, i, d, vp, i]),
+        "recon_stage_residual": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
+        "recon_stage_direction": (i, [vp, vp, i, vp, vp, d, i, vp, vp, pd, i]),
         "recon_stage_rbgs": (i, [vp, vp, vp, vp, i, d, i, i, i]),
         "recon_stage_restrict": (i, [vp, vp, i, vp, i]),
         "recon_stage_prolong_add": (i, [vp, vp, vp, i, i]),
@@ -275,11 +276,22 @@ class Recon:
     def _dt(t):
         return 0 if t.dtype == torch.float64 else 1
 
-    def residual(self, u, a, b, scale=1.0):
+    def residual(self, u, a, b, scale=1.0, variant=0):
         r = torch.empty_like(u)
         self._check(lib().recon_stage_residual(self._ctx, _ptr(u, u.dtype), _ptr(a, u.dtype), _ptr(b, u.dtype),
-                                               u.shape[0], float(scale), _ptr(r), self._dt(u)))
+                                               u.shape[0], float(scale), _ptr(r), self._dt(u), variant))
         return r
+
+    def direction(self, z, p_old, a, beta, first=False, variant=0):
+        """(p_new, q, p_new.q): one conjugate-gradient direction and its operator product."""
+        p_new = self._field()
+        q = self._field()
+        pq = ctypes.c_double()
+        self._check(lib().recon_stage_direction(self._ctx, _ptr(z, z.dtype), self._dt(z),
+                                                None if p_old is None else _ptr(p_old, torch.float64),
+                                                _ptr(a, torch.float64), float(beta), 1 if first else 0, _ptr(p_new),
+                                                _ptr(q), ctypes.byref(pq), variant))
+        return p_new, q, pq.value
 
     def rbgs(self, u, a, b, scale=1.0, first=0, variant=0):
         u = u.clone()

@@ -74,6 +74,19 @@ hipError_t launch_cast_f64(const float *src, double *dst, long n3, hipStream_t s
 
 // ------------------------------------------------------------ Krylov (FP64)
 // r = b - A u (FP64) with partial K=1 sum r^2; writes r32 = (float) r if r32 != null
+// LDS-streaming variants (stencil25.hip): edge a multiple of 64 (FP32 and
+// FP64) and of the j-tile.  launch_direction25 writes p_new = first ? z :
+// z + beta p_old (p_new != p_old), q = A p_new and the partial sums of p_new.q.
+template <typename T>
+bool stencil25_supported(int n);
+template <typename T>
+hipError_t launch_residual25(const T *u, const T *a, const T *b, T *r, int n, T scale, T a_min, hipStream_t s);
+hipError_t launch_residual_norm25(const double *u, const double *a, const double *b, double *r, float *r32, int n,
+                                  double a_min, Part &p, hipStream_t s);
+template <typename Z>
+hipError_t launch_direction25(const Z *z, const double *p_old, double *p_new, const double *a, double *q,
+                              double beta, int n, double a_min, bool first, Part &p, hipStream_t s);
+
 hipError_t launch_residual_norm(const double *u, const double *a, const double *b, double *r, float *r32, int n,
                                 double a_min, Part &p, hipStream_t s);
 // partials K=2: sum z*r, sum z*q (q may be null -> 0).  Z = double or float

@@ -271,6 +271,32 @@ int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, i
     return RECON_OK;
 }
 
+// Levels of at least 256^3 whose edge is a multiple of 64 apply the operator
+// with the LDS-streaming kernels; smaller levels (resident in L2/MALL) with
+// per-node gathers.  variant: 0 = that choice, 1 = gather, 2 = streaming.
+template <typename T>
+bool use_stream(int n)
+{
+    return n >= 256 && stencil25_supported<T>(n);
+}
+
+template <typename T>
+hipError_t residual_level(const T *u, const T *a, const T *b, T *r, int n, T scale, T a_min, hipStream_t s,
+                          int variant = 0)
+{
+    if (variant == 2 || (variant == 0 && use_stream<T>(n))) return launch_residual25<T>(u, a, b, r, n, scale, a_min, s);
+    return launch_residual<T>(u, a, b, r, n, scale, a_min, s);
+}
+
+// r = b - A u on the fine level in FP64, its squared norm, and optionally r
+// in FP32 (the mixed preconditioner's input).
+hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const double *b, double *r, float *r32)
+{
+    if (use_stream<double>(ctx->n))
+        return launch_residual_norm25(u, a, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
+    return launch_residual_norm(u, a, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
+}
+
 // Sum the recorded fine-level sweep times (stream already synchronised).
 int collect_profile(recon_ctx *ctx, recon_stats *st)
 {
@@ -306,7 +332,7 @@ int vcycle(recon_ctx *ctx, Levels<T> &S, int l, const T *rhs, T *out)
     const long n3 = (long)n * n * n;
     if (ctx->cfg.n_pre == 0) HIPCHK(launch_zero(out, n3 * sizeof(T), ctx->stream));
     for (int s = 0; s < ctx->cfg.n_pre; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 0, s == 0));
-    HIPCHK(launch_residual<T>(cur, S.a[l], rhs, S.res[l], n, sc, amin, ctx->stream));
+    HIPCHK(residual_level<T>(cur, S.a[l], rhs, S.res[l], n, sc, amin, ctx->stream));
     HIPCHK(launch_restrict<T>(S.res[l], S.b[l + 1], n, ctx->stream));
     TRY(vcycle<T>(ctx, S, l + 1, S.b[l + 1], S.u[l + 1]));
     HIPCHK(launch_prolong_add<T>(cur, S.u[l + 1], n, ctx->stream));
@@ -353,14 +379,14 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
     const double bn = std::sqrt(v[0]);
     bool started = false;
     if (warm && bn > 0.0) {
-        HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+        HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32));
         TRY(fetch_sum(ctx, v));
         started = std::sqrt(v[0]) < bn;
     }
     if (!started) {
         // u = 0, so the residual kernel gives r = b
         HIPCHK(launch_zero(ctx->u, n3 * 8, ctx->stream));
-        HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+        HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32));
     }
     int cycles = 0;
     int status = RECON_E_NO_CONVERGENCE;
@@ -374,7 +400,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             TRY(precondition(ctx));
             if (mixed) HIPCHK(launch_add_correction<float>(ctx->u, ctx->L32.u[0], n3, ctx->stream));
             else HIPCHK(launch_add_correction<double>(ctx->u, ctx->z, n3, ctx->stream));
-            HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+            HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32));
             TRY(fetch_sum(ctx, v));
             const double rn = std::sqrt(v[0]);
             if (!std::isfinite(rn)) break;
@@ -395,18 +421,31 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         double rz = v[0];
         double beta = 0.0;
         bool first = true;
+        // Streaming levels form the new direction out of place, fused with its
+        // operator product; it alternates between p and t (idle during a solve).
+        const bool stream = use_stream<double>(n);
+        double *pc = ctx->p, *pn = ctx->t;
         while (true) {
-            if (mixed)
-                HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, ctx->p, ctx->q, beta, n, ctx->cfg.a_min, first,
+            if (stream) {
+                if (mixed)
+                    HIPCHK(launch_direction25<float>(ctx->L32.u[0], pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min, first,
+                                                     ctx->part, ctx->stream));
+                else
+                    HIPCHK(launch_direction25<double>(ctx->z, pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min, first,
+                                                      ctx->part, ctx->stream));
+                std::swap(pc, pn);
+            } else if (mixed) {
+                HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, pc, ctx->q, beta, n, ctx->cfg.a_min, first,
                                                ctx->part, ctx->stream));
-            else
-                HIPCHK(launch_update_pq<double>(ctx->z, a0, ctx->p, ctx->q, beta, n, ctx->cfg.a_min, first, ctx->part,
+            } else {
+                HIPCHK(launch_update_pq<double>(ctx->z, a0, pc, ctx->q, beta, n, ctx->cfg.a_min, first, ctx->part,
                                                 ctx->stream));
+            }
             first = false;
             TRY(fetch_sum(ctx, v));
             const double pq = v[0];
             const double alpha = rz / pq;
-            HIPCHK(launch_update_ur(ctx->u, ctx->r, ctx->p, ctx->q, alpha, r32, n3, ctx->part, ctx->stream));
+            HIPCHK(launch_update_ur(ctx->u, ctx->r, pc, ctx->q, alpha, r32, n3, ctx->part, ctx->stream));
             TRY(fetch_sum(ctx, v));
             const double rn = std::sqrt(v[0]);
             if (!std::isfinite(rn) || !std::isfinite(alpha)) break;
@@ -429,7 +468,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
     TRY(fetch_sum(ctx, v));
     HIPCHK(launch_fill(ctx->scal + 16, 1, v[0] / (double)n3, ctx->stream));
     HIPCHK(launch_add_scalar(ctx->u, ctx->scal + 16, -1.0, 1.0, n3, ctx->stream));
-    HIPCHK(launch_residual_norm(ctx->u, a0, b, ctx->r, nullptr, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+    HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, nullptr));
     TRY(fetch_sum(ctx, v));
     const double rel = bn > 0.0 ? std::sqrt(v[0]) / bn : 0.0;
     if (cycles_out) *cycles_out = cycles;
@@ -905,19 +944,53 @@ int recon_stage_apply(recon_ctx *ctx, const double *u, const double *a, int nl, 
 }
 
 int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const void *b, int nl, double scale, void *r,
-                         int dtype)
+                         int dtype, int variant)
 {
     TRY(check_ctx(ctx));
-    if (!u || !a || !b || !r || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1))
+    if (!u || !a || !b || !r || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || variant < 0 || variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (variant == 2 && !(dtype == 0 ? stencil25_supported<double>(nl) : stencil25_supported<float>(nl)))
+        return fail(ctx, RECON_E_ARG, "the streaming residual needs an edge that is a multiple of 64");
     if (dtype == 0)
-        HIPCHK(launch_residual<double>((const double *)u, (const double *)a, (const double *)b, (double *)r, nl, scale,
-                                       ctx->cfg.a_min, ctx->stream));
+        HIPCHK(residual_level<double>((const double *)u, (const double *)a, (const double *)b, (double *)r, nl, scale,
+                                      ctx->cfg.a_min, ctx->stream, variant));
     else
-        HIPCHK(launch_residual<float>((const float *)u, (const float *)a, (const float *)b, (float *)r, nl,
-                                      (float)scale, (float)ctx->cfg.a_min, ctx->stream));
+        HIPCHK(residual_level<float>((const float *)u, (const float *)a, (const float *)b, (float *)r, nl,
+                                     (float)scale, (float)ctx->cfg.a_min, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
+}
+
+int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const double *p_old, const double *a,
+                          double beta, int first, double *p_new, double *q, double *pq, int variant)
+{
+    TRY(check_ctx(ctx));
+    const int n = ctx->n;
+    const long n3 = ctx->n3;
+    if (!z || !a || !p_new || !q || !pq || (!first && !p_old) || (z_dtype != 0 && z_dtype != 1) || variant < 0 ||
+        variant > 2 || (p_old && p_old == p_new) || q == p_new)
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
+    if (stream && !stencil25_supported<double>(n))
+        return fail(ctx, RECON_E_ARG, "the streaming direction update needs an edge that is a multiple of 64");
+    if (stream) {
+        const double *po = first ? q : p_old;  // not read when first; any array other than p_new
+        if (z_dtype == 0)
+            HIPCHK(launch_direction25<double>((const double *)z, po, p_new, a, q, beta, n, ctx->cfg.a_min, first != 0,
+                                              ctx->part, ctx->stream));
+        else
+            HIPCHK(launch_direction25<float>((const float *)z, po, p_new, a, q, beta, n, ctx->cfg.a_min, first != 0,
+                                             ctx->part, ctx->stream));
+    } else {
+        if (!first) HIPCHK(launch_copy(p_new, p_old, n3, ctx->stream));
+        if (z_dtype == 0)
+            HIPCHK(launch_update_pq<double>((const double *)z, a, p_new, q, beta, n, ctx->cfg.a_min, first != 0,
+                                            ctx->part, ctx->stream));
+        else
+            HIPCHK(launch_update_pq<float>((const float *)z, a, p_new, q, beta, n, ctx->cfg.a_min, first != 0,
+                                           ctx->part, ctx->stream));
+    }
+    return fetch_sum(ctx, pq);
 }
 
 extern "C++" {

@@ -42,6 +42,14 @@ def host(t):
 _PHI = {}
 
 
+class _no_error:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
 def evolved_phi(orc, n, coarse_n):
     """A potential from a few oracle steps on a lognormal density: strongly
     deformed (compression limiter active), positive definite."""
@@ -126,6 +134,50 @@ def test_residual_restrict_prolong(torch_cuda, orc, n, cn):
     assert rel(host(rec.residual(f32(u), f32(a), f32(b))), orc.residual(q(u), q(a), q(b))) < 1e-5
     assert rel(host(rec.restrict(f32(u))), orc.restrict(q(u))) < 1e-6
     assert rel(host(rec.prolong_add(f32(u), f32(e))), orc.prolong_add(q(u), q(e))) < 1e-6
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_streaming_operator_kernels(torch_cuda, orc, n):
+    """The LDS-streaming residual and Krylov direction kernels against the
+    per-node gather kernels (same arithmetic, same face order) and the oracle,
+    with coefficients that hit the a_min floor."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rec = binding.Recon(n, binding.Config())
+    rng = np.random.default_rng(300 + n)
+    a = np.exp(2.0 * rng.normal(size=(n, n, n)))
+    a[rng.random((n, n, n)) < 0.05] = 0.0  # empty cells: floored faces
+    u, b, z, p_old = rng.normal(size=(4, n, n, n))
+    for scale in (1.0, 0.25):
+        r1 = host(rec.residual(dev(torch, u), dev(torch, a), dev(torch, b), scale, variant=1))
+        r2 = host(rec.residual(dev(torch, u), dev(torch, a), dev(torch, b), scale, variant=2))
+        assert np.abs(r2 - r1).max() <= 1e-15 * np.abs(r1).max()
+        assert rel(r2, orc.residual(u, a, b, scale)) < 1e-14
+    f32 = lambda x: dev(torch, x, torch.float32)  # noqa: E731
+    q32 = lambda x: x.astype(np.float32).astype(np.float64)  # noqa: E731
+    r1 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=1))
+    r2 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=2))
+    assert np.abs(r2 - r1).max() <= 1e-6 * np.abs(r1).max()
+    assert rel(r2, orc.residual(q32(u), q32(a), q32(b), 0.25)) < 1e-5
+    beta = -0.37
+    for zt, zq in ((torch.float64, lambda x: x), (torch.float32, q32)):
+        for first in (True, False):
+            out = [rec.direction(dev(torch, z, zt), dev(torch, p_old), dev(torch, a), beta, first, variant=v)
+                   for v in (1, 2)]
+            (p1, qv1, pq1), (p2, qv2, pq2) = [(host(pn), host(qv), pq) for pn, qv, pq in out]
+            p_ref = zq(z) if first else zq(z) + beta * p_old
+            assert np.array_equal(p1, p2)
+            # z + beta p is contracted to one fused multiply-add on the GPU
+            assert np.abs(p2 - p_ref).max() <= 2.3e-16 * np.abs(p_ref).max()
+            assert np.abs(qv2 - qv1).max() <= 1e-15 * np.abs(qv1).max()
+            q_ref = orc.apply(p_ref, a)
+            assert rel(qv2, q_ref) < 1e-14
+            assert abs(pq2 - pq1) <= 1e-13 * abs(pq1)
+            assert abs(pq2 - float(np.dot(p_ref.ravel(), q_ref.ravel()))) <= 1e-12 * abs(pq1)
+    h = n // 2  # a coarser level of this context whose edge is not a multiple of 64 for n = 64
+    with pytest.raises(binding.ReconError) if h % 64 else _no_error():
+        rec.residual(dev(torch, u[:h, :h, :h].copy()), dev(torch, a[:h, :h, :h].copy()),
+                     dev(torch, b[:h, :h, :h].copy()), 1.0, variant=2)
 
 
 @pytest.mark.parametrize("n,cn", SIZES)
