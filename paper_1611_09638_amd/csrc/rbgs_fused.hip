@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -53,14 +55,23 @@ struct Ring4 {
     static constexpr int RS = TJ * TK / NT;
 };
 
-template <typename T, int TJ, int ZERO, int TK_ = 64, int NT_ = 512>
-__global__ void __launch_bounds__(NT_) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
+template <int X>
+using IC = std::integral_constant<int, X>;
+
+// FIRST: the colour relaxed first (a template parameter: chunks start on
+// planes that are multiples of 4, so with the steady loop unrolled by the
+// ring depth every ring slot and every plane parity is a compile-time
+// constant, and each LDS access is one per-thread offset plus an immediate).
+template <typename T, int TJ, int ZERO, int FIRST, int TK_ = 64, int NT_ = 512, int MINW = 1>
+__global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
                                                     const T *__restrict__ ag, const T *__restrict__ bg, int n,
-                                                    int ci, T inv_scale, T a_min, int first)
+                                                    int ci, T inv_scale, T a_min)
 {
     using F = Ring4<T, TJ, TK_, NT_>;
     static_assert(TJ * TK_ % NT_ == 0, "every thread stores whole rounds of the tile");
-    constexpr int W = F::W, PLANE = F::PLANE, NT = F::NT, LU = F::LU, R1 = F::R1, R2 = F::R2;
+    constexpr int W = F::W, HW = W / 2, PLANE = F::PLANE, NT = F::NT, LU = F::LU, R1 = F::R1, R2 = F::R2;
+    constexpr int RS = F::RS, C1 = FIRST, C2 = 1 - FIRST;
+    static_assert(W % 2 == 0, "rows split into equal even and odd halves");
     __shared__ T sU[4][F::PU];
     __shared__ T sA[4][F::PU];
 
@@ -71,200 +82,215 @@ __global__ void __launch_bounds__(NT_) k_rbgs_fused(const T *__restrict__ uin, T
     if ((nblk & 7) == 0) t = (t & 7) * (nblk >> 3) + (t >> 3);  // one contiguous tile range per XCD
     const int tk = t % tiles_k, tj = (t / tiles_k) % tiles_j, ch = t / (tiles_k * tiles_j);
     const int j0 = tj * TJ, k0 = tk * F::TK, i0 = ch * ci;
-    const size_t n2 = (size_t)n * n;
+    const size_t plane_bytes = (size_t)n * n * sizeof(T);
+    // LDS position of halo-plane row `row`, column `col`: the even and odd
+    // columns of each row sit in separate halves, so that the nodes of one
+    // colour and each of their neighbours are contiguous across a wavefront
+    auto lidx = [](int row, int col) { return row * W + (col & 1) * HW + (col >> 1); };
 
-    // halo load slots: global in-plane offset and LDS destination
-    int offU[LU], dstU[LU];
+    // halo load slots: in-plane byte offset and LDS destination
+    unsigned offU[LU];
+    int dstU[LU];
 #pragma unroll
     for (int r = 0; r < LU; ++r) {
         const int q = tid + r * NT;
         const int row = q / W, col = q % W;
         const int gj = wrapc(j0 - 2 + row, n), gk = wrapc(k0 - 2 + col, n);
-        offU[r] = q < PLANE ? gj * n + gk : 0;
-        dstU[r] = q < PLANE ? q : PLANE;
+        offU[r] = q < PLANE ? (unsigned)(gj * n + gk) * (unsigned)sizeof(T) : 0u;
+        dstU[r] = q < PLANE ? lidx(row, col) : PLANE;
     }
-
-    const int c1 = first, c2 = 1 - first;
-    // relaxation nodes for both plane parities: LDS offset and global in-plane
-    // offset (for b).  First colour: tile + 1-cell ring, node q at row
-    // jj = q / (TK/2 + 1) - 1, column kk = 2 (q % (TK/2 + 1)) - 1 + e; second
-    // colour: tile, jj = q / (TK/2), kk = 2 (q % (TK/2)) + e; e makes
-    // (i + j + k) % 2 the colour.  Lanes past the node count use slot 0 and skip.
-    int o1[R1][2], g1[R1][2], o2[R2][2], g2[R2][2];
+    // relaxation nodes for both plane parities P: LDS offsets of the node and
+    // of its +k neighbour (the -k neighbour is the next word down in the other
+    // half), and the in-plane byte offset of b.  First colour: tile + 1-cell
+    // ring, node q at row jj = q / (TK/2 + 1) - 1, column kk = 2 (q % (TK/2 + 1))
+    // - 1 + e; second colour: tile, jj = q / (TK/2), kk = 2 (q % (TK/2)) + e; e
+    // makes (i + j + k) % 2 the colour.  Lanes past the node count use a valid
+    // node and skip the relaxation.
+    int c1[R1][2], p1[R1][2], c2[R2][2], p2[R2][2];
+    unsigned g1[R1][2], g2[R2][2];
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
         const int q = tid + r * NT;
-        const int jj = q / (F::TK / 2 + 1) - 1, pr = q % (F::TK / 2 + 1);
+        const bool on = q < F::N1;
+        const int jj = on ? q / (F::TK / 2 + 1) - 1 : 0, pr = on ? q % (F::TK / 2 + 1) : 1;
 #pragma unroll
         for (int P = 0; P < 2; ++P) {
             const int kk = 2 * pr - 1 + ((P + jj + 1) & 1);
-            const bool on = q < F::N1;
-            o1[r][P] = on ? (jj + 2) * W + (kk + 2) : 2 * W + 2;
-            g1[r][P] = on ? wrapc(j0 + jj, n) * n + wrapc(k0 + kk, n) : 0;
+            c1[r][P] = lidx(jj + 2, kk + 2);
+            p1[r][P] = lidx(jj + 2, kk + 3);
+            g1[r][P] = (unsigned)(wrapc(j0 + jj, n) * n + wrapc(k0 + kk, n)) * (unsigned)sizeof(T);
         }
     }
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
         const int q = tid + r * NT;
-        const int jj = q / (F::TK / 2), pr = q % (F::TK / 2);
+        const bool on = q < F::N2;
+        const int jj = on ? q / (F::TK / 2) : 0, pr = on ? q % (F::TK / 2) : 0;
 #pragma unroll
         for (int P = 0; P < 2; ++P) {
             const int kk = 2 * pr + ((P + jj) & 1);
-            const bool on = q < F::N2;
-            o2[r][P] = on ? (jj + 2) * W + (kk + 2) : 2 * W + 2;
-            g2[r][P] = on ? (j0 + jj) * n + (k0 + kk) : 0;
+            c2[r][P] = lidx(jj + 2, kk + 2);
+            p2[r][P] = lidx(jj + 2, kk + 3);
+            g2[r][P] = (unsigned)((j0 + jj) * n + (k0 + kk)) * (unsigned)sizeof(T);
         }
     }
-    auto slot = [&](int p) { return (p - i0 + 8) & 3; };
-    auto par1 = [&](int p) { return (c1 + wrapc(p, n)) & 1; };
-    auto par2 = [&](int p) { return (c2 + wrapc(p, n)) & 1; };
+    // this thread's nodes of the tile for the plane store
+    int sN[RS];
+    unsigned gS[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+        const int q = tid + r * NT;
+        const int row = q / F::TK, col = q % F::TK;
+        sN[r] = lidx(row + 2, col + 2);
+        gS[r] = (unsigned)((j0 + row) * n + (k0 + col)) * (unsigned)sizeof(T);
+    }
+
+    auto plane = [&](const T *f, int p) {
+        return reinterpret_cast<const char *>(f) + (size_t)wrapc(p, n) * plane_bytes;
+    };
+    auto at = [](const char *base, unsigned off) { return *reinterpret_cast<const T *>(base + off); };
 
     T ru[2][LU], ra[2][LU];
-    auto fetch = [&](int set, int p) {
-        const size_t bu = (size_t)wrapc(p, n) * n2;
+    auto fetch = [&](auto SETc, int p) {
+        constexpr int SET = decltype(SETc)::value;
+        const char *ub = plane(uin, p), *ab = plane(ag, p);
 #pragma unroll
         for (int r = 0; r < LU; ++r) {
-            ru[set][r] = ZERO ? (T)0 : uin[bu + offU[r]];
-            ra[set][r] = ag[bu + offU[r]];
+            ru[SET][r] = ZERO ? (T)0 : at(ub, offU[r]);
+            ra[SET][r] = at(ab, offU[r]);
         }
     };
-    auto deposit = [&](int set, int p) {
-        T *U = sU[slot(p)], *A = sA[slot(p)];
+    auto deposit = [&](auto SETc, auto SLOTc) {
+        constexpr int SET = decltype(SETc)::value, SLOT = decltype(SLOTc)::value;
 #pragma unroll
         for (int r = 0; r < LU; ++r) {
-            U[dstU[r]] = ru[set][r];
-            A[dstU[r]] = (T)0.5 * ra[set][r];
+            sU[SLOT][dstU[r]] = ru[SET][r];
+            sA[SLOT][dstU[r]] = (T)0.5 * ra[SET][r];
         }
     };
-    // b at the first-colour nodes of plane p1 and the second-colour nodes of plane p2
+    // b at the first-colour nodes of plane q1 (parity P1) and at the
+    // second-colour nodes of plane q2 (parity P2)
     T rb1[2][R1], rb2[2][R2];
-    auto fetch_b = [&](int set, int p1, int p2) {
-        const size_t b1 = (size_t)wrapc(p1, n) * n2, b2 = (size_t)wrapc(p2, n) * n2;
-        const int P1 = par1(p1), P2 = par2(p2);
+    auto fetch_b = [&](auto SETc, int q1, auto P1c, int q2, auto P2c) {
+        constexpr int SET = decltype(SETc)::value, P1 = decltype(P1c)::value, P2 = decltype(P2c)::value;
+        const char *b1 = plane(bg, q1), *b2 = plane(bg, q2);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) rb1[set][r] = bg[b1 + g1[r][P1]];
+        for (int r = 0; r < R1; ++r) rb1[SET][r] = at(b1, g1[r][P1]);
 #pragma unroll
-        for (int r = 0; r < R2; ++r) rb2[set][r] = bg[b2 + g2[r][P2]];
+        for (int r = 0; r < R2; ++r) rb2[SET][r] = at(b2, g2[r][P2]);
     };
 
-    // one Gauss-Seidel relaxation from the LDS planes (a stored halved)
-    auto relax = [&](const T *Uc, const T *Uu, const T *Ud, const T *Ac, const T *Au, const T *Ad, int c,
-                     T bval) {
-        const T hn = Ac[c];
+    // one Gauss-Seidel relaxation from ring slots SC (the node's plane), SU
+    // (+i) and SD (-i); c: node, pk: its +k neighbour, pk - 1: its -k neighbour
+    auto relax = [&](auto SCc, auto SUc, auto SDc, int c, int pk, T bval) {
+        constexpr int SC = decltype(SCc)::value, SU = decltype(SUc)::value, SD = decltype(SDc)::value;
+        const T hn = sA[SC][c];
         T num = 0, den = 0, cf;
-        cf = fmax(hn + Au[c], a_min); num += cf * Uu[c]; den += cf;
-        cf = fmax(hn + Ad[c], a_min); num += cf * Ud[c]; den += cf;
-        cf = fmax(hn + Ac[c + W], a_min); num += cf * Uc[c + W]; den += cf;
-        cf = fmax(hn + Ac[c - W], a_min); num += cf * Uc[c - W]; den += cf;
-        cf = fmax(hn + Ac[c + 1], a_min); num += cf * Uc[c + 1]; den += cf;
-        cf = fmax(hn + Ac[c - 1], a_min); num += cf * Uc[c - 1]; den += cf;
+        cf = fmax(hn + sA[SU][c], a_min); num += cf * sU[SU][c]; den += cf;
+        cf = fmax(hn + sA[SD][c], a_min); num += cf * sU[SD][c]; den += cf;
+        cf = fmax(hn + sA[SC][c + W], a_min); num += cf * sU[SC][c + W]; den += cf;
+        cf = fmax(hn + sA[SC][c - W], a_min); num += cf * sU[SC][c - W]; den += cf;
+        cf = fmax(hn + sA[SC][pk], a_min); num += cf * sU[SC][pk]; den += cf;
+        cf = fmax(hn + sA[SC][pk - 1], a_min); num += cf * sU[SC][pk - 1]; den += cf;
         return qdiv(num - bval * inv_scale, den);
     };
-    auto relax_first = [&](int p, const T (&bv)[R1]) {
-        const int P = par1(p);
-        const T *Uc = sU[slot(p)], *Ac = sA[slot(p)];
-        const T *Uu = sU[slot(p + 1)], *Au = sA[slot(p + 1)];
-        const T *Ud = sU[slot(p - 1)], *Ad = sA[slot(p - 1)];
-        T *Uw = sU[slot(p)];
+    // first colour over the tile and its ring (reads only second-colour values)
+    auto relax_first = [&](auto SCc, auto SUc, auto SDc, auto Pc, const T (&bv)[R1]) {
+        constexpr int SC = decltype(SCc)::value, P = decltype(Pc)::value;
 #pragma unroll
-        for (int r = 0; r < R1; ++r) {
-            if (tid + r * NT < F::N1) {
-                const int c = o1[r][P];
-                Uw[c] = relax(Uc, Uu, Ud, Ac, Au, Ad, c, bv[r]);
-            }
-        }
+        for (int r = 0; r < R1; ++r)
+            if (tid + r * NT < F::N1) sU[SC][c1[r][P]] = relax(SCc, SUc, SDc, c1[r][P], p1[r][P], bv[r]);
     };
-    auto relax_second = [&](int p, const T (&bv)[R2]) {
-        const int P = par2(p);
-        const T *Uc = sU[slot(p)], *Ac = sA[slot(p)];
-        const T *Uu = sU[slot(p + 1)], *Au = sA[slot(p + 1)];
-        const T *Ud = sU[slot(p - 1)], *Ad = sA[slot(p - 1)];
-        T *Uw = sU[slot(p)];
+    // second colour over the tile (reads only new first-colour values)
+    auto relax_second = [&](auto SCc, auto SUc, auto SDc, auto Pc, const T (&bv)[R2]) {
+        constexpr int SC = decltype(SCc)::value, P = decltype(Pc)::value;
 #pragma unroll
-        for (int r = 0; r < R2; ++r) {
-            if (tid + r * NT < F::N2) {
-                const int c = o2[r][P];
-                Uw[c] = relax(Uc, Uu, Ud, Ac, Au, Ad, c, bv[r]);
-            }
-        }
+        for (int r = 0; r < R2; ++r)
+            if (tid + r * NT < F::N2) sU[SC][c2[r][P]] = relax(SCc, SUc, SDc, c2[r][P], p2[r][P], bv[r]);
     };
-    auto store_plane = [&](int p) {
-        const size_t base = (size_t)wrapc(p, n) * n2;
-        const T *Uc = sU[slot(p)];
+    auto store_plane = [&](auto SLOTc, int p) {
+        constexpr int SLOT = decltype(SLOTc)::value;
+        char *ob = reinterpret_cast<char *>(uout) + (size_t)wrapc(p, n) * plane_bytes;
 #pragma unroll
-        for (int r = 0; r < F::RS; ++r) {
-            const int q = tid + r * NT;
-            const int row = q / F::TK, col = q % F::TK;
-            uout[base + (size_t)(j0 + row) * n + (k0 + col)] = Uc[(row + 2) * W + (col + 2)];
-        }
+        for (int r = 0; r < RS; ++r) *reinterpret_cast<T *>(ob + gS[r]) = sU[SLOT][sN[r]];
     };
 
-    // prologue: u, a planes i0-2 .. i0+1 resident; i0+2 (set 1) and i0+3 (set 0)
-    // staged; b for the first two steady iterations staged
-    fetch(0, i0 - 2);
-    deposit(0, i0 - 2);
-    fetch(0, i0 - 1);
-    deposit(0, i0 - 1);
-    fetch(0, i0);
-    deposit(0, i0);
-    fetch(0, i0 + 1);
-    deposit(0, i0 + 1);
-    fetch(1, i0 + 2);
-    fetch(0, i0 + 3);
-    fetch_b(0, i0 + 1, i0);
-    fetch_b(1, i0 + 2, i0 + 1);
+    // Ring slot of plane i0 + d is d & 3 (d >= -2: slot (d + 4) & 3); the
+    // first colour's parity on plane i0 + d is (C1 + d) & 1, the second's
+    // (C2 + d) & 1 (i0 is even).
+    // prologue: planes i0-2 .. i0+1 resident, i0+2 (set 1) and i0+3 (set 0)
+    // staged, b for the first two steady steps staged
+    fetch(IC<0>{}, i0 - 2);
+    deposit(IC<0>{}, IC<2>{});
+    fetch(IC<0>{}, i0 - 1);
+    deposit(IC<0>{}, IC<3>{});
+    fetch(IC<0>{}, i0);
+    deposit(IC<0>{}, IC<0>{});
+    fetch(IC<0>{}, i0 + 1);
+    deposit(IC<0>{}, IC<1>{});
+    fetch(IC<1>{}, i0 + 2);
+    fetch(IC<0>{}, i0 + 3);
+    fetch_b(IC<0>{}, i0 + 1, IC<(C1 + 1) & 1>{}, i0, IC<C2 & 1>{});
+    fetch_b(IC<1>{}, i0 + 2, IC<C1 & 1>{}, i0 + 1, IC<(C2 + 1) & 1>{});
     lds_barrier();
     // warm-up: first colour on planes i0-1 and i0
     {
         T bw[R1];
-        const size_t bb = (size_t)wrapc(i0 - 1, n) * n2;
+        const char *bb = plane(bg, i0 - 1);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) bw[r] = bg[bb + g1[r][par1(i0 - 1)]];
-        relax_first(i0 - 1, bw);
+        for (int r = 0; r < R1; ++r) bw[r] = at(bb, g1[r][(C1 + 1) & 1]);
+        relax_first(IC<3>{}, IC<0>{}, IC<2>{}, IC<(C1 + 1) & 1>{}, bw);
     }
     lds_barrier();
-    deposit(1, i0 + 2);  // into the slot of plane i0-2, read last just above
-    fetch(1, i0 + 4);
+    deposit(IC<1>{}, IC<2>{});  // plane i0+2 into the slot of plane i0-2, read last just above
+    fetch(IC<1>{}, i0 + 4);
     lds_barrier();
     {
         T bw[R1];
-        const size_t bb = (size_t)wrapc(i0, n) * n2;
+        const char *bb = plane(bg, i0);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) bw[r] = bg[bb + g1[r][par1(i0)]];
-        relax_first(i0, bw);
+        for (int r = 0; r < R1; ++r) bw[r] = at(bb, g1[r][C1 & 1]);
+        relax_first(IC<0>{}, IC<1>{}, IC<3>{}, IC<C1 & 1>{}, bw);
     }
-    // Steady state, branch-free (ci is even).  The last two iterations fetch and
-    // deposit planes past the chunk: they wrap to valid addresses and land in
-    // ring slots that are no longer read.
-    for (int s = i0; s < i0 + ci; s += 2) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int ss = s + h;
-            relax_first(ss + 1, rb1[h]);
-            lds_barrier();
-            relax_second(ss, rb2[h]);
-            lds_barrier();
-            deposit(h, ss + 3);  // into the slot of plane ss-1
-            store_plane(ss);
-            fetch(h, ss + 5);
-            fetch_b(h, ss + 3, ss + 2);
-            lds_barrier();
-        }
+    // Steady state, branch-free, four planes per trip (ci is a multiple of 4).
+    // Step H (plane ss = i0 + 4m + H): first colour on ss+1, second colour on
+    // ss, store ss, deposit ss+3 into the slot of ss-1, stage ss+5 and the b
+    // values of the step after next.  The last steps fetch and deposit planes
+    // past the chunk: they wrap to valid addresses and land in ring slots that
+    // are no longer read.
+    auto step = [&](auto Hc, int ss) {
+        constexpr int H = decltype(Hc)::value, h = H & 1;
+        relax_first(IC<(H + 1) & 3>{}, IC<(H + 2) & 3>{}, IC<H & 3>{}, IC<(C1 + H + 1) & 1>{}, rb1[h]);
+        lds_barrier();
+        relax_second(IC<H & 3>{}, IC<(H + 1) & 3>{}, IC<(H + 3) & 3>{}, IC<(C2 + H) & 1>{}, rb2[h]);
+        lds_barrier();
+        deposit(IC<h>{}, IC<(H + 3) & 3>{});
+        store_plane(IC<H & 3>{}, ss);
+        fetch(IC<h>{}, ss + 5);
+        fetch_b(IC<h>{}, ss + 3, IC<(C1 + H + 3) & 1>{}, ss + 2, IC<(C2 + H + 2) & 1>{});
+        lds_barrier();
+    };
+    for (int s = i0; s < i0 + ci; s += 4) {
+        step(IC<0>{}, s);
+        step(IC<1>{}, s + 1);
+        step(IC<2>{}, s + 2);
+        step(IC<3>{}, s + 3);
     }
 }
 
-// Tile rows, workgroup size and the smallest launch, per precision: FP32 takes
-// 32 x 64 tiles (78 KB of LDS, two workgroups per CU), FP64 8 x 64 tiles with
-// 256 threads (52 KB, three per CU), sizes measured best at 512^3.
+// Tile rows, workgroup size, smallest launch and waves per SIMD (register
+// budget), per precision, as measured best at 512^3: FP32 16 x 64 tiles with
+// 256 threads (44 KB of LDS, up to three workgroups per CU), FP64 16 x 64
+// tiles with 512 threads (87 KB, one per CU; its halo re-reads are the lowest).
 template <typename T>
 struct FusedLaunch;
 template <>
 struct FusedLaunch<float> {
-    static constexpr int TJ = 32, NT = 512, MIN_BLOCKS = 512;
+    static constexpr int TJ = 16, NT = 256, MIN_BLOCKS = 1024, MINW = 4;
 };
 template <>
 struct FusedLaunch<double> {
-    static constexpr int TJ = 8, NT = 256, MIN_BLOCKS = 2048;
+    static constexpr int TJ = 16, NT = 512, MIN_BLOCKS = 1024, MINW = 2;
 };
 
 template <typename T>
@@ -283,14 +309,20 @@ hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, in
     // workgroups (each chunk re-reads 4 planes of u and a)
     int ci = n;
     while (ci > 16 && (n / 64) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
-    if (ci & 1) return hipErrorInvalidValue;  // the kernel's steady-state loop takes planes in pairs
+    if (ci % 4) return hipErrorInvalidValue;  // the steady-state loop takes planes in fours
     const int nblk = (n / 64) * (n / C::TJ) * (n / ci);
-    if (zero_init)
-        k_rbgs_fused<T, C::TJ, 1, 64, C::NT><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min,
-                                                                    first);
-    else
-        k_rbgs_fused<T, C::TJ, 0, 64, C::NT><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, (T)1 / scale, a_min,
-                                                                    first);
+    const T inv = (T)1 / scale;
+    if (zero_init) {
+        if (first)
+            k_rbgs_fused<T, C::TJ, 1, 1, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+        else
+            k_rbgs_fused<T, C::TJ, 1, 0, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+    } else {
+        if (first)
+            k_rbgs_fused<T, C::TJ, 0, 1, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+        else
+            k_rbgs_fused<T, C::TJ, 0, 0, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+    }
     return hipGetLastError();
 }
 
