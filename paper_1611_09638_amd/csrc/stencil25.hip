@@ -3,7 +3,7 @@
 // FP64 residual of the Krylov loop, and the Krylov direction update fused
 // with its operator product.
 //
-// A workgroup owns a TJ x 64 tile of (j, k) and a chunk of consecutive
+// A workgroup owns a TJ x TK tile of (j, k) and a chunk of consecutive
 // i-planes.  Each plane of the operand and of the coefficient enters an LDS
 // slot with a 1-cell halo in j and k (two slots: the plane being computed
 // and the next one), staged two planes ahead in registers; the value one
@@ -26,9 +26,9 @@ namespace {
 
 enum { S25_RESID = 0, S25_RESNORM = 1, S25_DIRECTION = 2 };
 
-template <int TJ, int NT>
+template <int TJ, int NT, int TK_ = 64>
 struct S25 {
-    static constexpr int TK = 64, H = TJ + 2, W = TK + 2, PLANE = H * W;
+    static constexpr int TK = TK_, H = TJ + 2, W = TK + 2, PLANE = H * W;
     static constexpr int LU = (PLANE + NT - 1) / NT;
     // slots padded to whole rounds of NT loads: every thread loads and
     // deposits unconditionally (spare lanes load a valid address and write
@@ -48,13 +48,14 @@ __device__ __forceinline__ void lds_fence_barrier()
 // MODE S25_RESNORM:   out = b - A x, out32 = (float) out, sum out^2   (T = double)
 // MODE S25_DIRECTION: x = first ? z : z + beta xin (written to pout),
 //                     out = A x, sum x out                   (T = double, z of type Z)
-template <typename T, typename Z, int MODE, int TJ, int NT>
+// FIRST (direction only): the first Krylov step, p = z, p_old not read.
+template <typename T, typename Z, int MODE, int TJ, int NT, int TK = 64, int FIRST = 0>
 __global__ void __launch_bounds__(NT)
     k_flux25(const T *__restrict__ xin, const Z *__restrict__ zg, const T *__restrict__ ag,
              const T *__restrict__ bg, T *__restrict__ out, float *__restrict__ out32, T *__restrict__ pout, int n,
-             int ci, T scale, T a_min, T beta, int first, double *part)
+             int ci, T scale, T a_min, T beta, double *part)
 {
-    using F = S25<TJ, NT>;
+    using F = S25<TJ, NT, TK>;
     static_assert(TJ * F::TK % NT == 0, "every thread owns whole rounds of the tile");
     constexpr int W = F::W, PLANE = F::PLANE, LU = F::LU, RS = F::RS;
     constexpr bool HAS_B = MODE != S25_DIRECTION;
@@ -93,7 +94,10 @@ __global__ void __launch_bounds__(NT)
     auto operand = [&](size_t g) -> T {
         if constexpr (MODE == S25_DIRECTION) {
             const T zv = (T)zg[g];
-            return first ? zv : zv + beta * xin[g];
+            if constexpr (FIRST)
+                return zv;
+            else
+                return zv + beta * xin[g];
         } else {
             return xin[g];
         }
@@ -195,28 +199,47 @@ __global__ void __launch_bounds__(NT)
     }
 }
 
-template <typename T>
-constexpr int s25_tj()
+// Launch shape per operation: tile rows TJ, tile width TK (a multiple of 64),
+// threads, and the smallest launch (the i-chunk is halved from n until the
+// launch has that many workgroups; each chunk reads one extra plane of every
+// field).  Wide tiles keep the halo lines of the narrow FP32 rows down.
+template <typename T, int MODE>
+struct S25Launch;
+template <>
+struct S25Launch<float, S25_RESID> {
+    static constexpr int TJ = 4, TK = 256, NT = 256, MIN_BLOCKS = 2048;
+};
+template <>
+struct S25Launch<double, S25_RESID> {
+    static constexpr int TJ = 8, TK = 64, NT = 256, MIN_BLOCKS = 2048;
+};
+template <>
+struct S25Launch<double, S25_RESNORM> {
+    static constexpr int TJ = 8, TK = 64, NT = 256, MIN_BLOCKS = 2048;
+};
+template <>
+struct S25Launch<double, S25_DIRECTION> {
+    static constexpr int TJ = 8, TK = 64, NT = 256, MIN_BLOCKS = 2048;
+};
+
+template <typename C>
+bool s25_fits(int n)
 {
-    return sizeof(T) == 4 ? 16 : 8;
+    return n >= C::TK && n % C::TK == 0 && n % C::TJ == 0;
 }
 
-constexpr int kS25Threads = 256;
-
-// i-chunk: halved from n while the launch has fewer than 2048 workgroups
-// (each chunk reads one extra plane of every field)
-template <typename T>
+template <typename C>
 int s25_chunk(int n)
 {
     int ci = n;
-    while (ci > 4 && (n / 64) * (n / s25_tj<T>()) * (n / ci) < 2048) ci /= 2;
+    while (ci > 4 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
     return ci;
 }
 
-template <typename T>
+template <typename C>
 int s25_blocks(int n, int ci)
 {
-    return (n / 64) * (n / s25_tj<T>()) * (n / ci);
+    return (n / C::TK) * (n / C::TJ) * (n / ci);
 }
 
 }  // namespace
@@ -224,27 +247,33 @@ int s25_blocks(int n, int ci)
 template <typename T>
 bool stencil25_supported(int n)
 {
-    return n >= 64 && n % 64 == 0 && n % s25_tj<T>() == 0;
+    if constexpr (sizeof(T) == 4)
+        return s25_fits<S25Launch<float, S25_RESID>>(n);
+    else
+        return s25_fits<S25Launch<double, S25_RESID>>(n) && s25_fits<S25Launch<double, S25_RESNORM>>(n) &&
+               s25_fits<S25Launch<double, S25_DIRECTION>>(n);
 }
 
 template <typename T>
 hipError_t launch_residual25(const T *u, const T *a, const T *b, T *r, int n, T scale, T a_min, hipStream_t s)
 {
-    if (!stencil25_supported<T>(n)) return hipErrorInvalidValue;
-    const int ci = s25_chunk<T>(n), nb = s25_blocks<T>(n, ci);
-    k_flux25<T, T, S25_RESID, s25_tj<T>(), kS25Threads><<<nb, kS25Threads, 0, s>>>(
-        u, nullptr, a, b, r, nullptr, nullptr, n, ci, scale, a_min, (T)0, 0, nullptr);
+    using C = S25Launch<T, S25_RESID>;
+    if (!s25_fits<C>(n)) return hipErrorInvalidValue;
+    const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
+    k_flux25<T, T, S25_RESID, C::TJ, C::NT, C::TK><<<nb, C::NT, 0, s>>>(u, nullptr, a, b, r, nullptr, nullptr, n, ci,
+                                                                       scale, a_min, (T)0, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_residual_norm25(const double *u, const double *a, const double *b, double *r, float *r32, int n,
                                   double a_min, Part &p, hipStream_t s)
 {
-    if (!stencil25_supported<double>(n)) return hipErrorInvalidValue;
-    const int ci = s25_chunk<double>(n), nb = s25_blocks<double>(n, ci);
+    using C = S25Launch<double, S25_RESNORM>;
+    if (!s25_fits<C>(n)) return hipErrorInvalidValue;
+    const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
-    k_flux25<double, double, S25_RESNORM, s25_tj<double>(), kS25Threads><<<nb, kS25Threads, 0, s>>>(
-        u, nullptr, a, b, r, r32, nullptr, n, ci, 1.0, a_min, 0.0, 0, p.part);
+    k_flux25<double, double, S25_RESNORM, C::TJ, C::NT, C::TK><<<nb, C::NT, 0, s>>>(
+        u, nullptr, a, b, r, r32, nullptr, n, ci, 1.0, a_min, 0.0, p.part);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -254,11 +283,16 @@ template <typename Z>
 hipError_t launch_direction25(const Z *z, const double *p_old, double *p_new, const double *a, double *q,
                               double beta, int n, double a_min, bool first, Part &p, hipStream_t s)
 {
-    if (!stencil25_supported<double>(n) || p_old == p_new) return hipErrorInvalidValue;
-    const int ci = s25_chunk<double>(n), nb = s25_blocks<double>(n, ci);
+    using C = S25Launch<double, S25_DIRECTION>;
+    if (!s25_fits<C>(n) || p_old == p_new) return hipErrorInvalidValue;
+    const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
-    k_flux25<double, Z, S25_DIRECTION, s25_tj<double>(), kS25Threads><<<nb, kS25Threads, 0, s>>>(
-        p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, first ? 1 : 0, p.part);
+    if (first)
+        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 1><<<nb, C::NT, 0, s>>>(
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part);
+    else
+        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0><<<nb, C::NT, 0, s>>>(
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();

@@ -42,14 +42,6 @@ def host(t):
 _PHI = {}
 
 
-class _no_error:
-    def __enter__(self):
-        return self
-
-    def __exit__(self, *exc):
-        return False
-
-
 def evolved_phi(orc, n, coarse_n):
     """A potential from a few oracle steps on a lognormal density: strongly
     deformed (compression limiter active), positive definite."""
@@ -136,11 +128,12 @@ def test_residual_restrict_prolong(torch_cuda, orc, n, cn):
     assert rel(host(rec.prolong_add(f32(u), f32(e))), orc.prolong_add(q(u), q(e))) < 1e-6
 
 
-@pytest.mark.parametrize("n", [64, 128])
+@pytest.mark.parametrize("n", [64, 128, 256])
 def test_streaming_operator_kernels(torch_cuda, orc, n):
     """The LDS-streaming residual and Krylov direction kernels against the
     per-node gather kernels (same arithmetic, same face order) and the oracle,
-    with coefficients that hit the a_min floor."""
+    with coefficients that hit the a_min floor.  The FP32 residual streams
+    256-wide tiles, so it needs an edge that is a multiple of 256."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
     rec = binding.Recon(n, binding.Config())
@@ -156,9 +149,13 @@ def test_streaming_operator_kernels(torch_cuda, orc, n):
     f32 = lambda x: dev(torch, x, torch.float32)  # noqa: E731
     q32 = lambda x: x.astype(np.float32).astype(np.float64)  # noqa: E731
     r1 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=1))
-    r2 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=2))
-    assert np.abs(r2 - r1).max() <= 1e-6 * np.abs(r1).max()
-    assert rel(r2, orc.residual(q32(u), q32(a), q32(b), 0.25)) < 1e-5
+    assert rel(r1, orc.residual(q32(u), q32(a), q32(b), 0.25)) < 1e-5
+    if n % 256 == 0:
+        r2 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=2))
+        assert np.abs(r2 - r1).max() <= 1e-6 * np.abs(r1).max()
+    else:
+        with pytest.raises(binding.ReconError):
+            rec.residual(f32(u), f32(a), f32(b), 0.25, variant=2)
     beta = -0.37
     for zt, zq in ((torch.float64, lambda x: x), (torch.float32, q32)):
         for first in (True, False):
@@ -174,10 +171,6 @@ def test_streaming_operator_kernels(torch_cuda, orc, n):
             assert rel(qv2, q_ref) < 1e-14
             assert abs(pq2 - pq1) <= 1e-13 * abs(pq1)
             assert abs(pq2 - float(np.dot(p_ref.ravel(), q_ref.ravel()))) <= 1e-12 * abs(pq1)
-    h = n // 2  # a coarser level of this context whose edge is not a multiple of 64 for n = 64
-    with pytest.raises(binding.ReconError) if h % 64 else _no_error():
-        rec.residual(dev(torch, u[:h, :h, :h].copy()), dev(torch, a[:h, :h, :h].copy()),
-                     dev(torch, b[:h, :h, :h].copy()), 1.0, variant=2)
 
 
 @pytest.mark.parametrize("n,cn", SIZES)
