@@ -202,11 +202,14 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const doub
 int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first,
                      int dtype, int variant);
 
-/* 27-point full weighting of an nl^3 field onto (nl/2)^3. */
-int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype);
+/* 27-point full weighting of an nl^3 field onto (nl/2)^3.  variant 0: the
+ * kernel the solver uses on that level; 1: per-node gathers; 2: the
+ * LDS-streaming kernel (nl a multiple of 256, else RECON_E_ARG). */
+int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype, int variant);
 
-/* u += trilinear prolongation of the (nl/2)^3 field e onto the nl^3 field u. */
-int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype);
+/* u += trilinear prolongation of the (nl/2)^3 field e onto the nl^3 field u
+ * (P = 8 R^T).  variant as for recon_stage_restrict. */
+int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype, int variant);
 
 /* z = one symmetric V-cycle applied to r for coefficient a (fine level n). */
 int recon_stage_vcycle(recon_ctx *ctx, const void *a, const void *r, void *z, int dtype);

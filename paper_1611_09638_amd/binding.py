@@ -130,8 +130,8 @@ def lib():
         "recon_stage_residual": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
         "recon_stage_direction": (i, [vp, vp, i, vp, vp, d, i, vp, vp, pd, i]),
         "recon_stage_rbgs": (i, [vp, vp, vp, vp, i, d, i, i, i]),
-        "recon_stage_restrict": (i, [vp, vp, i, vp, i]),
-        "recon_stage_prolong_add": (i, [vp, vp, vp, i, i]),
+        "recon_stage_restrict": (i, [vp, vp, i, vp, i, i]),
+        "recon_stage_prolong_add": (i, [vp, vp, vp, i, i, i]),
         "recon_stage_vcycle": (i, [vp, vp, vp, vp, i]),
         "recon_stage_mg_solve": (i, [vp, vp, vp, d, vp, pi, pd]),
         "recon_stage_choose_step": (i, [vp, vp, vp, pd]),
@@ -299,16 +299,17 @@ class Recon:
                                            u.shape[0], float(scale), first, self._dt(u), variant))
         return u
 
-    def restrict(self, f):
+    def restrict(self, f, variant=0):
         nc = f.shape[0] // 2
         c = torch.empty((nc,) * 3, dtype=f.dtype, device=f.device)
-        self._check(lib().recon_stage_restrict(self._ctx, _ptr(f, f.dtype), f.shape[0], _ptr(c), self._dt(f)))
+        self._check(lib().recon_stage_restrict(self._ctx, _ptr(f, f.dtype), f.shape[0], _ptr(c), self._dt(f),
+                                               variant))
         return c
 
-    def prolong_add(self, u, e):
+    def prolong_add(self, u, e, variant=0):
         u = u.clone()
         self._check(lib().recon_stage_prolong_add(self._ctx, _ptr(u, u.dtype), _ptr(e, u.dtype), u.shape[0],
-                                                  self._dt(u)))
+                                                  self._dt(u), variant))
         return u
 
     def vcycle(self, a, r):

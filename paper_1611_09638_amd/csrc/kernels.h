@@ -83,6 +83,14 @@ template <typename T>
 hipError_t launch_residual25(const T *u, const T *a, const T *b, T *r, int n, T scale, T a_min, hipStream_t s);
 hipError_t launch_residual_norm25(const double *u, const double *a, const double *b, double *r, float *r32, int n,
                                   double a_min, Part &p, hipStream_t s);
+// Streaming grid transfers (transfer25.hip): fine edge a multiple of 256.
+template <typename T>
+bool transfer25_supported(int n);
+template <typename T>
+hipError_t launch_restrict25(const T *f, T *c, int n, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong25(T *u, const T *e, int n, hipStream_t s);
+
 template <typename Z>
 hipError_t launch_direction25(const Z *z, const double *p_old, double *p_new, const double *a, double *q,
                               double beta, int n, double a_min, bool first, Part &p, hipStream_t s);

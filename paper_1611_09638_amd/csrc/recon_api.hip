@@ -288,6 +288,28 @@ hipError_t residual_level(const T *u, const T *a, const T *b, T *r, int n, T sca
     return launch_residual<T>(u, a, b, r, n, scale, a_min, s);
 }
 
+// Grid transfers from fine levels of at least 256^3: streaming kernels;
+// otherwise per-node gathers.  variant as for residual_level.
+template <typename T>
+bool use_transfer_stream(int n)
+{
+    return n >= 256 && transfer25_supported<T>(n);
+}
+
+template <typename T>
+hipError_t restrict_level(const T *f, T *c, int n, hipStream_t s, int variant = 0)
+{
+    if (variant == 2 || (variant == 0 && use_transfer_stream<T>(n))) return launch_restrict25<T>(f, c, n, s);
+    return launch_restrict<T>(f, c, n, s);
+}
+
+template <typename T>
+hipError_t prolong_level(T *u, const T *e, int n, hipStream_t s, int variant = 0)
+{
+    if (variant == 2 || (variant == 0 && use_transfer_stream<T>(n))) return launch_prolong25<T>(u, e, n, s);
+    return launch_prolong_add<T>(u, e, n, s);
+}
+
 // r = b - A u on the fine level in FP64, its squared norm, and optionally r
 // in FP32 (the mixed preconditioner's input).
 hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const double *b, double *r, float *r32)
@@ -333,9 +355,9 @@ int vcycle(recon_ctx *ctx, Levels<T> &S, int l, const T *rhs, T *out)
     if (ctx->cfg.n_pre == 0) HIPCHK(launch_zero(out, n3 * sizeof(T), ctx->stream));
     for (int s = 0; s < ctx->cfg.n_pre; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 0, s == 0));
     HIPCHK(residual_level<T>(cur, S.a[l], rhs, S.res[l], n, sc, amin, ctx->stream));
-    HIPCHK(launch_restrict<T>(S.res[l], S.b[l + 1], n, ctx->stream));
+    HIPCHK(restrict_level<T>(S.res[l], S.b[l + 1], n, ctx->stream));
     TRY(vcycle<T>(ctx, S, l + 1, S.b[l + 1], S.u[l + 1]));
-    HIPCHK(launch_prolong_add<T>(cur, S.u[l + 1], n, ctx->stream));
+    HIPCHK(prolong_level<T>(cur, S.u[l + 1], n, ctx->stream));
     for (int s = 0; s < ctx->cfg.n_post; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 1, false));
     if (cur != out) HIPCHK(hipMemcpyAsync(out, cur, n3 * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     return RECON_OK;
@@ -347,7 +369,7 @@ int build_hierarchy(recon_ctx *ctx, const double *a0)
 {
     Levels<double> &S = ctx->L64;
     S.a[0] = const_cast<double *>(a0);
-    for (int l = 0; l + 1 < S.L; ++l) HIPCHK(launch_restrict<double>(S.a[l], S.a[l + 1], S.n[l], ctx->stream));
+    for (int l = 0; l + 1 < S.L; ++l) HIPCHK(restrict_level<double>(S.a[l], S.a[l + 1], S.n[l], ctx->stream));
     if (ctx->cfg.precision == RECON_MIXED) {
         for (int l = 0; l < S.L; ++l)
             HIPCHK(launch_cast_f32(S.a[l], ctx->L32.a[l], (long)S.n[l] * S.n[l] * S.n[l], ctx->stream));
@@ -1032,24 +1054,30 @@ int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int 
     return RECON_OK;
 }
 
-int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype)
+int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype, int variant)
 {
     TRY(check_ctx(ctx));
-    if (!f || !c || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1))
+    if (!f || !c || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1) || variant < 0 ||
+        variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
-    if (dtype == 0) HIPCHK(launch_restrict<double>((const double *)f, (double *)c, nl, ctx->stream));
-    else HIPCHK(launch_restrict<float>((const float *)f, (float *)c, nl, ctx->stream));
+    if (variant == 2 && !(dtype == 0 ? transfer25_supported<double>(nl) : transfer25_supported<float>(nl)))
+        return fail(ctx, RECON_E_ARG, "the streaming transfers need a fine edge that is a multiple of 256");
+    if (dtype == 0) HIPCHK(restrict_level<double>((const double *)f, (double *)c, nl, ctx->stream, variant));
+    else HIPCHK(restrict_level<float>((const float *)f, (float *)c, nl, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }
 
-int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype)
+int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype, int variant)
 {
     TRY(check_ctx(ctx));
-    if (!u || !e || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1))
+    if (!u || !e || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1) || variant < 0 ||
+        variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
-    if (dtype == 0) HIPCHK(launch_prolong_add<double>((double *)u, (const double *)e, nl, ctx->stream));
-    else HIPCHK(launch_prolong_add<float>((float *)u, (const float *)e, nl, ctx->stream));
+    if (variant == 2 && !(dtype == 0 ? transfer25_supported<double>(nl) : transfer25_supported<float>(nl)))
+        return fail(ctx, RECON_E_ARG, "the streaming transfers need a fine edge that is a multiple of 256");
+    if (dtype == 0) HIPCHK(prolong_level<double>((double *)u, (const double *)e, nl, ctx->stream, variant));
+    else HIPCHK(prolong_level<float>((float *)u, (const float *)e, nl, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }

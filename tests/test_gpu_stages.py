@@ -173,6 +173,36 @@ def test_streaming_operator_kernels(torch_cuda, orc, n):
             assert abs(pq2 - float(np.dot(p_ref.ravel(), q_ref.ravel()))) <= 1e-12 * abs(pq1)
 
 
+def test_streaming_transfers(torch_cuda, orc):
+    """The LDS-streaming restriction and prolongation at 256^3 against the
+    per-node gather kernels (bitwise, same arithmetic and order) and against
+    the oracle; smaller edges are rejected."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 256
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
+    rng = np.random.default_rng(401)
+    f = rng.normal(size=(n, n, n))
+    e = rng.normal(size=(n // 2,) * 3)
+    c1 = host(rec.restrict(dev(torch, f), variant=1))
+    c2 = host(rec.restrict(dev(torch, f), variant=2))
+    assert np.array_equal(c1, c2)
+    assert rel(c2, orc.restrict(f)) < 1e-15
+    u1 = host(rec.prolong_add(dev(torch, f), dev(torch, e), variant=1))
+    u2 = host(rec.prolong_add(dev(torch, f), dev(torch, e), variant=2))
+    assert np.array_equal(u1, u2)
+    assert rel(u2, orc.prolong_add(f, e)) < 1e-15
+    f32 = lambda x: dev(torch, x, torch.float32)  # noqa: E731
+    assert np.array_equal(host(rec.restrict(f32(f), variant=1)), host(rec.restrict(f32(f), variant=2)))
+    assert np.array_equal(host(rec.prolong_add(f32(f), f32(e), variant=1)),
+                          host(rec.prolong_add(f32(f), f32(e), variant=2)))
+    h = n // 2  # a level whose edge is not a multiple of 256
+    with pytest.raises(binding.ReconError):
+        rec.restrict(dev(torch, f[:h, :h, :h].copy()), variant=2)
+    with pytest.raises(binding.ReconError):
+        rec.prolong_add(dev(torch, f[:h, :h, :h].copy()), dev(torch, e[:h // 2, :h // 2, :h // 2].copy()), variant=2)
+
+
 @pytest.mark.parametrize("n,cn", SIZES)
 def test_vcycle_fp64_and_fp32(torch_cuda, orc, n, cn):
     torch = torch_cuda
