@@ -41,6 +41,19 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_sanitized(path: str) -> str:
+    """Compile a copy of the oracle with AddressSanitizer and UBSan (any error
+    aborts) into ``path``.  Loaded instead of the normal build when the
+    environment variable RECON_ORACLE_LIB names it; the process must preload
+    the ASan runtime."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-o", path] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    return path
+
+
 class OrcConfig(ctypes.Structure):
     _fields_ = [
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
@@ -109,9 +122,10 @@ _dp = ctypes.POINTER(ctypes.c_double)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        path = os.environ.get("RECON_ORACLE_LIB", _LIB_PATH)
+        if not os.path.exists(path):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
+        L = ctypes.CDLL(path)
         d, i, dbl, ll = _dp, ctypes.c_int, ctypes.c_double, ctypes.c_longlong
         fp = ctypes.POINTER(ctypes.c_float)
         sig = {

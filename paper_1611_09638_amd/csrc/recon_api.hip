@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -513,10 +514,12 @@ int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *a
     if (!std::isfinite(shift)) return fail(ctx, RECON_E_NO_CONVERGENCE, "non-finite increment");
     int j0 = 0;
     while (j0 <= ctx->cfg.max_halvings && std::ldexp(1.0, -j0) * shift > ctx->cfg.s_max) ++j0;
-    for (int j = j0; j <= ctx->cfg.max_halvings; j += 4) {
-        HIPCHK(launch_pd_trials(phi, dphi, ctx->n, j, 4, ctx->part, ctx->stream));
+    // The largest step the shift bound allows usually passes: try it alone,
+    // then four halvings per launch.
+    for (int j = j0, batch = 1; j <= ctx->cfg.max_halvings; j += batch, batch = 4) {
+        HIPCHK(launch_pd_trials(phi, dphi, ctx->n, j, batch, ctx->part, ctx->stream));
         TRY(fetch_sum(ctx, v));
-        for (int t = 0; t < 4 && j + t <= ctx->cfg.max_halvings; ++t) {
+        for (int t = 0; t < batch && j + t <= ctx->cfg.max_halvings; ++t) {
             if (v[t] == 0.0) {
                 *alpha_out = std::ldexp(1.0, -(j + t));
                 return RECON_OK;
@@ -557,6 +560,13 @@ int mass_state(recon_ctx *ctx, double *rho_bar, double *rms, double *mean_t)
     return RECON_OK;
 }
 
+// RECON_LOG set to anything but "0": one line per outer step on stderr.
+bool log_steps()
+{
+    const char *e = std::getenv("RECON_LOG");
+    return e && *e && !(e[0] == '0' && e[1] == 0);
+}
+
 int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *delta_out, recon_stats *st)
 {
     const recon_config &c = ctx->cfg;
@@ -586,6 +596,9 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         HIPCHK(launch_axpy(ctx->phi, ctx->dphi, alpha, n3, ctx->stream));
         st->alpha[it] = alpha;
         st->outer_steps = it + 1;
+        if (log_steps())
+            std::fprintf(stderr, "recon step %d: rms(Sigma) %.6e, mean M %.12f, V-cycles %d, residual %.3e, alpha %.6e\n",
+                         it, rms, rho_bar, cyc, rel, alpha);
         if (c.record_tape) {
             if (c.tape_fp32) HIPCHK(launch_cast_f32(ctx->u, wsp<float>(ctx, ctx->lo.tape) + (size_t)it * n3, n3, ctx->stream));
             else HIPCHK(launch_copy(wsp<double>(ctx, ctx->lo.tape) + (size_t)it * n3, ctx->u, n3, ctx->stream));

@@ -128,3 +128,19 @@ def test_repeat_solves_are_bitwise_identical(torch_cuda):
     phi1, d1, _ = rec.solve(rho, 250.0)
     phi2, d2, _ = rec.solve(rho, 250.0)
     assert bool((phi1 == phi2).all()) and bool((d1 == d2).all())
+
+
+def test_step_log(torch_cuda, capfd, monkeypatch):
+    """RECON_LOG=1 prints one line per outer step on stderr; unset, nothing."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rho = torch.from_numpy(inputs.lognormal_density(16, 125.0, 1.0, 3)).cuda()
+    rec = binding.Recon(16, binding.Config(max_outer=3))
+    monkeypatch.setenv("RECON_LOG", "1")
+    rec.solve(rho, 125.0)
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("recon step")]
+    assert len(lines) == 3 and "alpha" in lines[0], err
+    monkeypatch.setenv("RECON_LOG", "0")
+    rec.solve(rho, 125.0)
+    assert "recon step" not in capfd.readouterr().err
