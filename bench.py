@@ -88,6 +88,46 @@ def cpu_baseline(rho, n, stats, cores):
                        % (t_mm, t_src, t_vc, t_ap, n, outer, vc))}
 
 
+def oracle_samples(workload):
+    """The FP64 oracle's solve of this workload at 2048 seeded voxels, stored
+    by the tests' golden-value script (None if not stored)."""
+    path = os.path.join(ROOT, "tests", "golden", workload + "_oracle_forward.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def stream_ceilings(torch, dev, reps=10):
+    """Achievable HBM bandwidth on this GPU for the access patterns of the
+    path, from torch's own streaming kernels over 1 GiB arrays (FP32): read
+    only (sum), copy (1 read, 1 write) and 3 reads + 1 write (addcmul, the
+    smoother's mix).  GB/s counted as bytes moved / kernel time."""
+    nel = (1 << 30) // 4
+    x = torch.rand(nel, device=dev)
+    y = torch.rand(nel, device=dev)
+    z = torch.rand(nel, device=dev)
+    o = torch.empty(nel, device=dev)
+    s = torch.empty((), device=dev)
+    cases = {"read": (lambda: torch.sum(x, out=s), 1), "copy": (lambda: o.copy_(x), 2),
+             "three_reads_one_write": (lambda: torch.addcmul(x, y, z, out=o), 4)}
+    out = {}
+    for name, (fn, arrays) in cases.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_GBps"] = round(arrays * (1 << 30) / (ms * 1e-3) / 1e9, 1)
+    del x, y, z, o
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +138,7 @@ def main():
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--probe", action="store_true",
                     help="counter run: one plain 1 GiB copy (calibration) and one fused sweep per precision at 512^3")
+    ap.add_argument("--stream", action="store_true", help="only the streaming-bandwidth ceilings of this GPU")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (one process per GPU; --gpus %d is not supported, "
@@ -107,6 +148,10 @@ def main():
     import torch
 
     from paper_1611_09638_amd import binding, inputs
+
+    if args.stream:
+        print(json.dumps({"stream": stream_ceilings(torch, torch.device("cuda:0"), reps=20)}), flush=True)
+        return
 
     if args.probe:
         n = 512
@@ -135,6 +180,8 @@ def main():
     rho = inputs.lognormal_density(n, box, w["sigma_g"], w["seed"])
     log("input %s generated in %.1fs" % (args.workload, time.perf_counter() - t0))
     dev = torch.device("cuda:0")
+    stream = stream_ceilings(torch, dev)
+    log("stream ceilings %s" % stream)
     rho_d = torch.from_numpy(rho).to(dev)
 
     results = {}
@@ -184,6 +231,7 @@ def main():
                    "max_outer": 10, "tol": 1e-10, "solver": "pcg+vcycle(2,2)", "precision": head},
         "outer_steps": st["outer_steps"],
         "vcycles_total": st["vcycles_total"],
+        "vcycles": st["vcycles"],
         "alpha": st["alpha"],
     }
     for name, R in results.items():
@@ -199,6 +247,15 @@ def main():
                                      "zero_start_ms_per_sweep": round(zm, 4),
                                      "zero_start_GBps": round(nb * 3 // 4 * n ** 3 / (zm * 1e-3) / 1e9, 1),
                                      "vcycles": s["vcycles_total"]}
+    gold = oracle_samples(args.workload)
+    if gold is not None:
+        vox = torch.tensor(gold["voxels"], device=dev)
+        for name, R in results.items():
+            cmp = {"alpha_equal": R["stats"]["alpha"] == gold["alpha"]}
+            for key, f in (("phi", R["phi"]), ("delta_r", R["delta"])):
+                g = torch.tensor(gold[key], dtype=torch.float64, device=dev)
+                cmp["rel_l2_" + key] = float((f.reshape(-1)[vox] - g).norm() / g.norm())
+            out["%s_vs_oracle" % name] = cmp
     if len(results) == 2:
         a, b = results["mixed"], results["fp64"]
         out["speedup_mixed_vs_fp64"] = round(b["wall_s"] / a["wall_s"], 3)
@@ -209,7 +266,10 @@ def main():
                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel, n),
                        "bytes_per_node_per_sweep": node_bytes, "nodes": n ** 3,
-                       "algorithmic_bytes_per_launch": node_bytes * n ** 3}
+                       "algorithmic_bytes_per_launch": node_bytes * n ** 3,
+                       "stream_ceiling_GBps": stream["three_reads_one_write_GBps"],
+                       "frac_of_stream_ceiling": round(achieved / stream["three_reads_one_write_GBps"], 4)}
+    out["stream"] = stream
     if not args.skip_cpu:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
         out["cpu_baseline"] = cpu_baseline(rho, n, st, cores)

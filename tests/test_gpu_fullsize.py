@@ -128,3 +128,18 @@ def test_lognormal256_against_oracle(torch_cuda, prec):
     rec = binding.Recon(w["n"], binding.Config(precision=prec))
     phi, d, st = rec.solve(torch.from_numpy(rho).cuda(), w["box"])
     _check_against_oracle(gold, phi.cpu().numpy(), d.cpu().numpy(), st)
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["mixed", "fp64"])
+def test_lognormal512_against_oracle(torch_cuda, field512, prec):
+    """The benchmark's workload (512^3 lognormal, box 1000, sigma_g 2) in the
+    benchmark's configuration and launch: the full 10-step solve, mixed and
+    FP64, against the FP64 oracle's solve of the same input (stored samples,
+    block means and norms), within 1e-6 relative L2."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    gold = _oracle_forward("lognormal512")
+    w = inputs.WORKLOADS["lognormal512"]
+    rec = binding.Recon(w["n"], binding.Config(precision=prec))
+    phi, d, st = rec.solve(torch.from_numpy(field512).cuda(), w["box"])
+    _check_against_oracle(gold, phi.cpu().numpy(), d.cpu().numpy(), st)
