@@ -109,7 +109,7 @@ def stream_ceilings(torch, dev, reps=10):
     z = torch.rand(nel, device=dev)
     o = torch.empty(nel, device=dev)
     s = torch.empty((), device=dev)
-    cases = {"read": (lambda: torch.sum(x, out=s), 1), "copy": (lambda: o.copy_(x), 2),
+    cases = {"read": (lambda: torch.sum(x, dim=0, out=s), 1), "copy": (lambda: o.copy_(x), 2),
              "three_reads_one_write": (lambda: torch.addcmul(x, y, z, out=o), 4)}
     out = {}
     for name, (fn, arrays) in cases.items():

@@ -224,6 +224,16 @@ int recon_stage_mg_solve(recon_ctx *ctx, const double *a, const double *b, doubl
  * RECON_E_NOT_PD if none of j = 0..max_halvings does. */
 int recon_stage_choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha);
 
+/* Step trials of the map's positivity (Sec. II, App. A): counts[t] = number
+ * of nodes where I + Hess(phi + 2^-(j0+t) dphi) fails Sylvester's criterion,
+ * t = 0..ntrial-1, ntrial 1 or 4, 0 <= j0 <= 1000.  phi, dphi: device n^3
+ * FP64; counts: host, ntrial doubles.  variant 1 gathers the 19-point
+ * neighbourhood per node, 2 streams planes through LDS (n a multiple of 64,
+ * else RECON_E_ARG), 0 picks what recon_stage_choose_step uses; all variants
+ * give the same counts. */
+int recon_stage_pd_count(recon_ctx *ctx, const double *phi, const double *dphi, int j0, int ntrial, int variant,
+                         double *counts);
+
 /* delta = -laplacian phi (7-point, Eq. rec). */
 int recon_stage_delta_r(recon_ctx *ctx, const double *phi, double *delta);
 

@@ -145,6 +145,7 @@ def lib():
             "orc_num_levels": (i, [i, i]),
             "orc_mg_solve": (i, [d, d, i, ctypes.POINTER(OrcConfig), d, d]),
             "orc_is_pd": (i, [d, i]),
+            "orc_count_not_pd": (ctypes.c_long, [d, i]),
             "orc_max_shift": (dbl, [d, i]),
             "orc_choose_step": (i, [d, d, i, ctypes.POINTER(OrcConfig), d]),
             "orc_delta_r": (None, [d, i, d]),
@@ -289,6 +290,12 @@ def mg_solve(a, b, cfg: Config | None = None):
 def is_pd(phi) -> bool:
     phi = _f64(phi)
     return bool(lib().orc_is_pd(_p(phi), phi.shape[0]))
+
+
+def count_not_pd(phi) -> int:
+    """Nodes where I + Hess(phi) fails Sylvester's criterion."""
+    phi = _f64(phi)
+    return int(lib().orc_count_not_pd(_p(phi), phi.shape[0]))
 
 
 def max_shift(f) -> float:

@@ -687,12 +687,13 @@ int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cf
 
 /* ------------------------------------------------ positive-definite step control */
 
-/* 1 if I + Hess(phi) is positive definite at every node (leading principal
- * minors e11, e11 e22 - e12^2 and det all positive). */
-int orc_is_pd(const double *phi, int n)
+/* Number of nodes where I + Hess(phi) is not positive definite: some leading
+ * principal minor (e11, e11 e22 - e12^2, det) is not positive (Sec. II: the
+ * map x = xi + grad phi must stay positive definite). */
+long orc_count_not_pd(const double *phi, int n)
 {
-    int ok = 1;
-    #pragma omp parallel for reduction(&& : ok)
+    long bad = 0;
+    #pragma omp parallel for reduction(+ : bad)
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
             for (int k = 0; k < n; ++k) {
@@ -701,9 +702,15 @@ int orc_is_pd(const double *phi, int n)
                 double m1 = e[0][0];
                 double m2 = e[0][0] * e[1][1] - e[0][1] * e[1][0];
                 double m3 = det3(e);
-                if (!(m1 > 0.0 && m2 > 0.0 && m3 > 0.0)) ok = 0;
+                if (!(m1 > 0.0 && m2 > 0.0 && m3 > 0.0)) ++bad;
             }
-    return ok;
+    return bad;
+}
+
+/* 1 if I + Hess(phi) is positive definite at every node. */
+int orc_is_pd(const double *phi, int n)
+{
+    return orc_count_not_pd(phi, n) == 0;
 }
 
 double orc_max_shift(const double *f, int n)

@@ -135,6 +135,7 @@ def lib():
         "recon_stage_vcycle": (i, [vp, vp, vp, vp, i]),
         "recon_stage_mg_solve": (i, [vp, vp, vp, d, vp, pi, pd]),
         "recon_stage_choose_step": (i, [vp, vp, vp, pd]),
+        "recon_stage_pd_count": (i, [vp, vp, vp, i, i, i, pd]),
         "recon_stage_delta_r": (i, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -330,6 +331,12 @@ class Recon:
         self._check(lib().recon_stage_choose_step(self._ctx, _ptr(phi, torch.float64), _ptr(dphi, torch.float64),
                                                   ctypes.byref(alpha)))
         return alpha.value
+
+    def pd_count(self, phi, dphi, j0, ntrial=4, variant=0):
+        counts = (ctypes.c_double * ntrial)()
+        self._check(lib().recon_stage_pd_count(self._ctx, _ptr(phi, torch.float64), _ptr(dphi, torch.float64),
+                                               int(j0), int(ntrial), int(variant), counts))
+        return [int(c) for c in counts]
 
     def delta_r(self, phi):
         d = self._field()

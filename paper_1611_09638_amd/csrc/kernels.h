@@ -41,6 +41,9 @@ hipError_t launch_max_shift(const double *f, int n, Part &p, hipStream_t s);
 // partial K=ntrial (sum): nodes where I + Hess(phi + 2^-j dphi) is not PD, j = j0..j0+ntrial-1
 hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p,
                             hipStream_t s);
+// same counts from planes streamed through LDS; n a multiple of 64
+bool pd25_supported(int n);
+hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s);
 hipError_t launch_axpy(double *y, const double *x, double alpha, long n3, hipStream_t s);
 hipError_t launch_add_scalar(double *y, const double *c_dev, double sign, double scale, long n3, hipStream_t s);
 // delta = -L7 phi; phi_out = phi * h2 (if non-null); partials K=3: min det, min lambda0, max delta

@@ -504,6 +504,15 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
 
 // ------------------------------------------------------------ step control
 
+// Failing-node counts of `ntrial` step trials from 2^-j0; variant 1 gathers
+// per node, 2 streams planes through LDS, 0 takes 2 where it applies.
+hipError_t pd_trials(recon_ctx *ctx, const double *phi, const double *dphi, int j0, int ntrial, int variant)
+{
+    if (variant == 0) variant = pd25_supported(ctx->n) ? 2 : 1;
+    if (variant == 2) return launch_pd25(phi, dphi, ctx->n, j0, ntrial, ctx->part, ctx->stream);
+    return launch_pd_trials(phi, dphi, ctx->n, j0, ntrial, ctx->part, ctx->stream);
+}
+
 int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha_out)
 {
     static const int opmax[1] = {RED_MAX};
@@ -514,10 +523,9 @@ int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *a
     if (!std::isfinite(shift)) return fail(ctx, RECON_E_NO_CONVERGENCE, "non-finite increment");
     int j0 = 0;
     while (j0 <= ctx->cfg.max_halvings && std::ldexp(1.0, -j0) * shift > ctx->cfg.s_max) ++j0;
-    // The largest step the shift bound allows usually passes: try it alone,
-    // then four halvings per launch.
-    for (int j = j0, batch = 1; j <= ctx->cfg.max_halvings; j += batch, batch = 4) {
-        HIPCHK(launch_pd_trials(phi, dphi, ctx->n, j, batch, ctx->part, ctx->stream));
+    // four halvings per launch, from the largest step the shift bound allows
+    for (int j = j0, batch = 4; j <= ctx->cfg.max_halvings; j += batch) {
+        HIPCHK(pd_trials(ctx, phi, dphi, j, batch, 0));
         TRY(fetch_sum(ctx, v));
         for (int t = 0; t < batch && j + t <= ctx->cfg.max_halvings; ++t) {
             if (v[t] == 0.0) {
@@ -1139,6 +1147,22 @@ int recon_stage_choose_step(recon_ctx *ctx, const double *phi, const double *dph
     TRY(check_ctx(ctx));
     if (!phi || !dphi || !alpha) return fail(ctx, RECON_E_ARG, "null argument");
     return choose_step(ctx, phi, dphi, alpha);
+}
+
+int recon_stage_pd_count(recon_ctx *ctx, const double *phi, const double *dphi, int j0, int ntrial, int variant,
+                         double *counts)
+{
+    TRY(check_ctx(ctx));
+    if (!phi || !dphi || !counts || j0 < 0 || j0 > 1000 || (ntrial != 1 && ntrial != 4) || variant < 0 ||
+        variant > 2)
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (variant == 2 && !pd25_supported(ctx->n))
+        return fail(ctx, RECON_E_ARG, "the streaming step trials need an edge that is a multiple of 64");
+    double v[8];
+    HIPCHK(pd_trials(ctx, phi, dphi, j0, ntrial, variant));
+    TRY(fetch_sum(ctx, v));
+    for (int t = 0; t < ntrial; ++t) counts[t] = v[t];
+    return RECON_OK;
 }
 
 int recon_stage_delta_r(recon_ctx *ctx, const double *phi, double *delta)

@@ -239,6 +239,36 @@ def test_mg_solve(torch_cuda, orc, n, cn, precision, solver):
         assert cyc == cyc_o
 
 
+@pytest.mark.parametrize("n", [64, 128, 192])
+def test_pd_trial_counts(torch_cuda, orc, n):
+    """Failing-node counts of the step trials: the per-node gather kernel and
+    the LDS-streaming kernel agree exactly (same arithmetic per node), and
+    both match the oracle's count on phi + 2^-j dphi (its Hessian sums in
+    another order, so a node on the boundary may differ: at most 1e-5 of n^3).
+    n = 192 has 3 tiles along k; the chunking takes every plane once."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rec = binding.Recon(n, binding.Config(coarse_n=6 if n == 192 else 8))
+    box = 250.0 * n / 32
+    g = inputs.gaussian_field(n, box, 300 + n)
+    phi = 0.35 * g / np.abs(g).max()
+    dphi = inputs.gaussian_field(n, box, 400 + n)
+    dphi *= 6.0 / np.abs(dphi).max()
+    seen = set()
+    for j0 in (0, 4):
+        for nt in (1, 4):
+            c1 = rec.pd_count(dev(torch, phi), dev(torch, dphi), j0, nt, variant=1)
+            c2 = rec.pd_count(dev(torch, phi), dev(torch, dphi), j0, nt, variant=2)
+            assert c1 == c2
+            for t in range(nt):
+                co = orc.count_not_pd(phi + np.ldexp(1.0, -(j0 + t)) * dphi)
+                assert abs(c2[t] - co) <= 1e-5 * n ** 3
+                seen.add(co > 0)
+    assert seen == {True, False}  # both failing and passing trials were exercised
+    a_o = orc.choose_step(phi, dphi, orc.Config())[1]
+    assert rec.choose_step(dev(torch, phi), dev(torch, dphi)) == a_o
+
+
 def test_choose_step_and_cic(torch_cuda, orc):
     torch = torch_cuda
     from paper_1611_09638_amd import binding

@@ -55,6 +55,29 @@ def test_compact_hessian_symbol(orc):
         np.testing.assert_allclose(e, np.eye(3) + H, atol=1e-13)
 
 
+def test_count_not_pd_closed_form_and_eigenvalues(orc):
+    """Non-PD node count (Sec. II).  For phi = amp cos(2 pi i / n) the triad is
+    diag(1 - 4 sin^2(pi/n) amp cos(2 pi i/n), 1, 1), so whole i-planes fail;
+    on a random field it equals the count of nodes whose smallest eigenvalue
+    (LAPACK) is not positive."""
+    n = 16
+    i = np.arange(n)
+    for amp in (3.0, 10.0, -25.0, 40.0):
+        g = 1.0 - 4 * np.sin(np.pi / n) ** 2 * amp * np.cos(2 * np.pi * i / n)
+        assert np.abs(g).min() > 1e-3  # no node on the boundary
+        phi = np.broadcast_to((amp * np.cos(2 * np.pi * i / n))[:, None, None], (n, n, n)).copy()
+        assert orc.count_not_pd(phi) == n * n * int((g <= 0).sum())
+        assert orc.is_pd(phi) == (g > 0).all()
+    n = 6
+    rng = np.random.default_rng(17)
+    for amp in (0.05, 0.2, 0.6):
+        phi = amp * rng.normal(size=(n, n, n))
+        bad = sum(np.linalg.eigvalsh(orc.triad_at(phi, a, b, c)).min() <= 0
+                  for a in range(n) for b in range(n) for c in range(n))
+        assert orc.count_not_pd(phi) == bad
+    assert orc.count_not_pd(np.zeros((n, n, n))) == 0
+
+
 # ------------------------------------------------------------- operators
 
 def test_smoothing_operator_symbol_and_symmetry(orc):
