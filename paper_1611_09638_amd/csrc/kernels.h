@@ -79,7 +79,8 @@ hipError_t launch_cast_f64(const float *src, double *dst, long n3, hipStream_t s
 // r = b - A u (FP64) with partial K=1 sum r^2; writes r32 = (float) r if r32 != null
 // LDS-streaming variants (stencil25.hip): edge a multiple of 64 (FP32 and
 // FP64) and of the j-tile.  launch_direction25 writes p_new = first ? z :
-// z + beta p_old (p_new != p_old), q = A p_new and the partial sums of p_new.q.
+// z + beta p_old (p_new != p_old), q = A p_new and the partial sums of p_new.q;
+// with u != null (not first) it also applies u += alpha_u p_old.
 template <typename T>
 bool stencil25_supported(int n);
 template <typename T>
@@ -96,7 +97,8 @@ hipError_t launch_prolong25(T *u, const T *e, int n, hipStream_t s);
 
 template <typename Z>
 hipError_t launch_direction25(const Z *z, const double *p_old, double *p_new, const double *a, double *q,
-                              double beta, int n, double a_min, bool first, Part &p, hipStream_t s);
+                              double beta, int n, double a_min, bool first, double *u, double alpha_u, Part &p,
+                              hipStream_t s);
 
 hipError_t launch_residual_norm(const double *u, const double *a, const double *b, double *r, float *r32, int n,
                                 double a_min, Part &p, hipStream_t s);
@@ -107,7 +109,7 @@ hipError_t launch_dots_zr_zq(const Z *z, const double *r, const double *q, long 
 template <typename Z>
 hipError_t launch_update_pq(const Z *z, const double *a, double *pv, double *q, double beta, int n,
                             double a_min, bool first, Part &p, hipStream_t s);
-// u += alpha p; r -= alpha q; partial K=1: sum r^2; r32 = (float) r if r32 != null
+// u += alpha p (if u != null); r -= alpha q; partial K=1: sum r^2; r32 = (float) r if r32 != null
 hipError_t launch_update_ur(double *u, double *r, const double *pv, const double *q, double alpha,
                             float *r32, long n3, Part &p, hipStream_t s);
 // u += z (Z = double or float)

@@ -446,16 +446,23 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         bool first = true;
         // Streaming levels form the new direction out of place, fused with its
         // operator product; it alternates between p and t (idle during a solve).
+        // The solution update u += alpha p of one step is deferred into the next
+        // direction pass there (it reads p anyway), and applied after the loop
+        // for the last step.
         const bool stream = use_stream<double>(n);
         double *pc = ctx->p, *pn = ctx->t;
+        double alpha_due = 0.0;
+        bool due = false;
         while (true) {
             if (stream) {
+                double *ud = due ? ctx->u : nullptr;
                 if (mixed)
                     HIPCHK(launch_direction25<float>(ctx->L32.u[0], pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min, first,
-                                                     ctx->part, ctx->stream));
+                                                     ud, alpha_due, ctx->part, ctx->stream));
                 else
-                    HIPCHK(launch_direction25<double>(ctx->z, pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min, first,
-                                                      ctx->part, ctx->stream));
+                    HIPCHK(launch_direction25<double>(ctx->z, pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min, first, ud,
+                                                      alpha_due, ctx->part, ctx->stream));
+                due = false;
                 std::swap(pc, pn);
             } else if (mixed) {
                 HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, pc, ctx->q, beta, n, ctx->cfg.a_min, first,
@@ -468,7 +475,10 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             TRY(fetch_sum(ctx, v));
             const double pq = v[0];
             const double alpha = rz / pq;
-            HIPCHK(launch_update_ur(ctx->u, ctx->r, pc, ctx->q, alpha, r32, n3, ctx->part, ctx->stream));
+            HIPCHK(launch_update_ur(stream ? nullptr : ctx->u, ctx->r, pc, ctx->q, alpha, r32, n3, ctx->part,
+                                    ctx->stream));
+            due = stream;
+            alpha_due = alpha;
             TRY(fetch_sum(ctx, v));
             const double rn = std::sqrt(v[0]);
             if (!std::isfinite(rn) || !std::isfinite(alpha)) break;
@@ -485,6 +495,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             beta = -alpha * v[1] / rz;
             rz = v[0];
         }
+        if (due) HIPCHK(launch_axpy(ctx->u, pc, alpha_due, n3, ctx->stream));
     }
     // mean-free solution, then the true residual
     HIPCHK(launch_sum(ctx->u, n3, ctx->part, ctx->stream));
@@ -1005,13 +1016,15 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
 }
 
 int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const double *p_old, const double *a,
-                          double beta, int first, double *p_new, double *q, double *pq, int variant)
+                          double beta, int first, double *p_new, double *q, double *pq, int variant, double *u,
+                          double alpha_u)
 {
     TRY(check_ctx(ctx));
     const int n = ctx->n;
     const long n3 = ctx->n3;
     if (!z || !a || !p_new || !q || !pq || (!first && !p_old) || (z_dtype != 0 && z_dtype != 1) || variant < 0 ||
-        variant > 2 || (p_old && p_old == p_new) || q == p_new)
+        variant > 2 || (p_old && p_old == p_new) || q == p_new ||
+        (u && (first || u == p_old || u == p_new || u == q || u == a || u == z)))
         return fail(ctx, RECON_E_ARG, "bad arguments");
     const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
     if (stream && !stencil25_supported<double>(n))
@@ -1020,11 +1033,12 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const doub
         const double *po = first ? q : p_old;  // not read when first; any array other than p_new
         if (z_dtype == 0)
             HIPCHK(launch_direction25<double>((const double *)z, po, p_new, a, q, beta, n, ctx->cfg.a_min, first != 0,
-                                              ctx->part, ctx->stream));
+                                              u, alpha_u, ctx->part, ctx->stream));
         else
             HIPCHK(launch_direction25<float>((const float *)z, po, p_new, a, q, beta, n, ctx->cfg.a_min, first != 0,
-                                             ctx->part, ctx->stream));
+                                             u, alpha_u, ctx->part, ctx->stream));
     } else {
+        if (u) HIPCHK(launch_axpy(u, p_old, alpha_u, n3, ctx->stream));
         if (!first) HIPCHK(launch_copy(p_new, p_old, n3, ctx->stream));
         if (z_dtype == 0)
             HIPCHK(launch_update_pq<double>((const double *)z, a, p_new, q, beta, n, ctx->cfg.a_min, first != 0,

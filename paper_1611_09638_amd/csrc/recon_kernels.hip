@@ -829,12 +829,13 @@ hipError_t launch_update_pq(const Z *z, const double *a, double *pv, double *q, 
     return hipGetLastError();
 }
 
+template <bool U>
 __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, const double *__restrict__ pv,
                             const double *__restrict__ q, double alpha, float *__restrict__ r32, long n3, double *part)
 {
     double v[1] = {0.0};
     for (long p = blockIdx.x * 256L + threadIdx.x; p < n3; p += 256L * gridDim.x) {
-        u[p] += alpha * pv[p];
+        if (U) u[p] += alpha * pv[p];
         const double rv = r[p] - alpha * q[p];
         r[p] = rv;
         if (r32) r32[p] = (float)rv;
@@ -847,7 +848,8 @@ hipError_t launch_update_ur(double *u, double *r, const double *pv, const double
                             Part &p, hipStream_t s)
 {
     int nb = flat_blocks(n3);
-    k_update_ur<<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part);
+    if (u) k_update_ur<true><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part);
+    else k_update_ur<false><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();

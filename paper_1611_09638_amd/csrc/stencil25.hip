@@ -49,12 +49,15 @@ __device__ __forceinline__ void lds_fence_barrier()
 // MODE S25_DIRECTION: x = first ? z : z + beta xin (written to pout),
 //                     out = A x, sum x out                   (T = double, z of type Z)
 // FIRST (direction only): the first Krylov step, p = z, p_old not read.
-template <typename T, typename Z, int MODE, int TJ, int NT, int TK = 64, int FIRST = 0>
+// UPD (direction only, not FIRST): also ug += alpha_u xin, the solution update
+// of the previous Krylov step, deferred to this pass, which reads p_old anyway.
+template <typename T, typename Z, int MODE, int TJ, int NT, int TK = 64, int FIRST = 0, int UPD = 0>
 __global__ void __launch_bounds__(NT)
     k_flux25(const T *__restrict__ xin, const Z *__restrict__ zg, const T *__restrict__ ag,
              const T *__restrict__ bg, T *__restrict__ out, float *__restrict__ out32, T *__restrict__ pout, int n,
-             int ci, T scale, T a_min, T beta, double *part)
+             int ci, T scale, T a_min, T beta, double *part, double *__restrict__ ug, double alpha_u)
 {
+    static_assert(!UPD || (MODE == S25_DIRECTION && !FIRST), "the deferred update needs p_old");
     using F = S25<TJ, NT, TK>;
     static_assert(TJ * F::TK % NT == 0, "every thread owns whole rounds of the tile");
     constexpr int W = F::W, PLANE = F::PLANE, LU = F::LU, RS = F::RS;
@@ -103,8 +106,10 @@ __global__ void __launch_bounds__(NT)
         }
     };
 
-    // register stage: halo plane p of x and a, and b at this thread's nodes of plane p - 2
+    // register stage: halo plane p of x and a, and b (or u and p_old) at this
+    // thread's nodes of plane p - 2
     T rx[2][LU], ra[2][LU], rb[2][HAS_B ? RS : 1];
+    double ru[2][UPD ? RS : 1], rq[2][UPD ? RS : 1];
     auto fetch = [&](int set, int p) {
         const size_t base = (size_t)wrapc(p, n) * n2;
 #pragma unroll
@@ -116,6 +121,14 @@ __global__ void __launch_bounds__(NT)
             const size_t bb = (size_t)wrapc(p - 2, n) * n2;
 #pragma unroll
             for (int r = 0; r < RS; ++r) rb[set][r] = bg[bb + gN[r]];
+        }
+        if constexpr (UPD) {
+            const size_t bb = (size_t)wrapc(p - 2, n) * n2;
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                ru[set][r] = ug[bb + gN[r]];
+                rq[set][r] = xin[bb + gN[r]];
+            }
         }
     };
     auto deposit = [&](int set, int slot) {
@@ -165,6 +178,7 @@ __global__ void __launch_bounds__(NT)
                 pout[g] = xc;
                 out[g] = acc;
                 v += xc * acc;
+                if constexpr (UPD) ug[g] = ru[set][r] + alpha_u * rq[set][r];
             }
             xd[r] = xc;
             hd[r] = hc;
@@ -261,7 +275,7 @@ hipError_t launch_residual25(const T *u, const T *a, const T *b, T *r, int n, T 
     if (!s25_fits<C>(n)) return hipErrorInvalidValue;
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     k_flux25<T, T, S25_RESID, C::TJ, C::NT, C::TK><<<nb, C::NT, 0, s>>>(u, nullptr, a, b, r, nullptr, nullptr, n, ci,
-                                                                       scale, a_min, (T)0, nullptr);
+                                                                       scale, a_min, (T)0, nullptr, nullptr, 0.0);
     return hipGetLastError();
 }
 
@@ -273,7 +287,7 @@ hipError_t launch_residual_norm25(const double *u, const double *a, const double
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
     k_flux25<double, double, S25_RESNORM, C::TJ, C::NT, C::TK><<<nb, C::NT, 0, s>>>(
-        u, nullptr, a, b, r, r32, nullptr, n, ci, 1.0, a_min, 0.0, p.part);
+        u, nullptr, a, b, r, r32, nullptr, n, ci, 1.0, a_min, 0.0, p.part, nullptr, 0.0);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -281,18 +295,23 @@ hipError_t launch_residual_norm25(const double *u, const double *a, const double
 
 template <typename Z>
 hipError_t launch_direction25(const Z *z, const double *p_old, double *p_new, const double *a, double *q,
-                              double beta, int n, double a_min, bool first, Part &p, hipStream_t s)
+                              double beta, int n, double a_min, bool first, double *u, double alpha_u, Part &p,
+                              hipStream_t s)
 {
     using C = S25Launch<double, S25_DIRECTION>;
-    if (!s25_fits<C>(n) || p_old == p_new) return hipErrorInvalidValue;
+    if (!s25_fits<C>(n) || p_old == p_new || (u && (first || u == p_old || u == p_new || u == q)))
+        return hipErrorInvalidValue;
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
     if (first)
         k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 1><<<nb, C::NT, 0, s>>>(
-            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part);
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0);
+    else if (u)
+        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0, 1><<<nb, C::NT, 0, s>>>(
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, u, alpha_u);
     else
         k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0><<<nb, C::NT, 0, s>>>(
-            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part);
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -305,8 +324,8 @@ template hipError_t launch_residual25<float>(const float *, const float *, const
 template hipError_t launch_residual25<double>(const double *, const double *, const double *, double *, int, double,
                                               double, hipStream_t);
 template hipError_t launch_direction25<float>(const float *, const double *, double *, const double *, double *,
-                                              double, int, double, bool, Part &, hipStream_t);
+                                              double, int, double, bool, double *, double, Part &, hipStream_t);
 template hipError_t launch_direction25<double>(const double *, const double *, double *, const double *, double *,
-                                               double, int, double, bool, Part &, hipStream_t);
+                                               double, int, double, bool, double *, double, Part &, hipStream_t);
 
 }  // namespace recon

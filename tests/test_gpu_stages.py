@@ -171,6 +171,24 @@ def test_streaming_operator_kernels(torch_cuda, orc, n):
             assert rel(qv2, q_ref) < 1e-14
             assert abs(pq2 - pq1) <= 1e-13 * abs(pq1)
             assert abs(pq2 - float(np.dot(p_ref.ravel(), q_ref.ravel()))) <= 1e-12 * abs(pq1)
+    # the previous step's solution update, deferred into the direction pass:
+    # same direction and product, and u + alpha p_old (one FMA) in both variants
+    alpha_u = 0.8125
+    u_ref = u + alpha_u * p_old
+    for v in (1, 2):
+        ug = dev(torch, u)
+        pn, qv, pq = rec.direction(dev(torch, z), dev(torch, p_old), dev(torch, a), beta, False, variant=v, u=ug,
+                                   alpha_u=alpha_u)
+        p0, q0, pq0 = rec.direction(dev(torch, z), dev(torch, p_old), dev(torch, a), beta, False, variant=v)
+        assert torch.equal(pn, p0) and torch.equal(qv, q0) and pq == pq0
+        assert np.abs(host(ug) - u_ref).max() <= 2.3e-16 * np.abs(u_ref).max()
+        if v == 1:
+            u1 = host(ug)
+        else:
+            assert np.array_equal(host(ug), u1)
+    with pytest.raises(binding.ReconError):
+        ug = dev(torch, u)
+        rec.direction(dev(torch, z), dev(torch, p_old), dev(torch, a), beta, True, variant=2, u=ug, alpha_u=1.0)
 
 
 def test_streaming_transfers(torch_cuda, orc):
