@@ -188,15 +188,17 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
 /* One conjugate-gradient direction on the fine level (the Krylov loop around
  * the V-cycle preconditioner): p_new = z (first != 0) or z + beta p_old,
  * q = A p_new, and *pq (host) <- p_new . q.  z is FP64 (z_dtype 0) or FP32
- * (z_dtype 1); p_old, p_new, a, q are FP64 and p_new must differ from p_old
- * (p_old is not read, and may be NULL, when first != 0).  If u (FP64, device)
- * is not NULL, the previous step's solution update u += alpha_u p_old is
- * applied in the same pass (first must be 0; u distinct from every other
- * array).  variant as for recon_stage_residual (1: in-place update then
- * gathers; 2: one fused streaming pass). */
-int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const double *p_old, const double *a,
-                          double beta, int first, double *p_new, double *q, double *pq, int variant, double *u,
-                          double alpha_u);
+ * (z_dtype 1); a and q are FP64; p_old and p_new are FP64 (p_dtype 0) or FP32
+ * (p_dtype 1: needs z_dtype 1 and the streaming kernel; p_new is rounded to
+ * FP32 as it is formed and q is the product of the rounded values).  p_new
+ * must differ from p_old (p_old is not read, and may be NULL, when
+ * first != 0).  If u (FP64, device) is not NULL, the previous step's solution
+ * update u += alpha_u p_old is applied in the same pass (first must be 0; u
+ * distinct from every other array).  variant as for recon_stage_residual
+ * (1: in-place update then gathers; 2: one fused streaming pass). */
+int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void *p_old, const double *a,
+                          double beta, int first, void *p_new, double *q, double *pq, int variant, double *u,
+                          double alpha_u, int p_dtype);
 
 /* One red-black Gauss-Seidel sweep in place (colour `first` then the other;
  * red = i+j+k even) on an nl^3 level.  variant 0: the kernel the solver uses

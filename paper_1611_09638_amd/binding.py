@@ -128,7 +128,7 @@ def lib():
         "recon_stage_smooth": (i, [vp, vp, vp]),
         "recon_stage_apply": (i, [vp, vp, vp, i, d, vp]),
         "recon_stage_residual": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
-        "recon_stage_direction": (i, [vp, vp, i, vp, vp, d, i, vp, vp, pd, i, vp, d]),
+        "recon_stage_direction": (i, [vp, vp, i, vp, vp, d, i, vp, vp, pd, i, vp, d, i]),
         "recon_stage_rbgs": (i, [vp, vp, vp, vp, i, d, i, i, i]),
         "recon_stage_restrict": (i, [vp, vp, i, vp, i, i]),
         "recon_stage_prolong_add": (i, [vp, vp, vp, i, i, i]),
@@ -283,17 +283,19 @@ class Recon:
                                                u.shape[0], float(scale), _ptr(r), self._dt(u), variant))
         return r
 
-    def direction(self, z, p_old, a, beta, first=False, variant=0, u=None, alpha_u=0.0):
+    def direction(self, z, p_old, a, beta, first=False, variant=0, u=None, alpha_u=0.0, p_dtype=torch.float64):
         """(p_new, q, p_new.q): one conjugate-gradient direction and its operator
-        product; with u given (FP64, updated in place) also u += alpha_u p_old."""
-        p_new = self._field()
+        product; with u given (FP64, updated in place) also u += alpha_u p_old.
+        p_dtype: storage of p_old and p_new (float32 needs an FP32 z)."""
+        p_new = self._field(p_dtype)
         q = self._field()
         pq = ctypes.c_double()
         self._check(lib().recon_stage_direction(self._ctx, _ptr(z, z.dtype), self._dt(z),
-                                                None if p_old is None else _ptr(p_old, torch.float64),
-                                                _ptr(a, torch.float64), float(beta), 1 if first else 0, _ptr(p_new),
-                                                _ptr(q), ctypes.byref(pq), variant,
-                                                None if u is None else _ptr(u, torch.float64), float(alpha_u)))
+                                                None if p_old is None else _ptr(p_old, p_dtype),
+                                                _ptr(a, torch.float64), float(beta), 1 if first else 0,
+                                                _ptr(p_new, p_dtype), _ptr(q), ctypes.byref(pq), variant,
+                                                None if u is None else _ptr(u, torch.float64), float(alpha_u),
+                                                1 if p_dtype == torch.float32 else 0))
         return p_new, q, pq.value
 
     def rbgs(self, u, a, b, scale=1.0, first=0, variant=0):

@@ -44,7 +44,8 @@ hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0
 // same counts from planes streamed through LDS; n a multiple of 64
 bool pd25_supported(int n);
 hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s);
-hipError_t launch_axpy(double *y, const double *x, double alpha, long n3, hipStream_t s);
+template <typename X>
+hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s);  // X = double or float
 hipError_t launch_add_scalar(double *y, const double *c_dev, double sign, double scale, long n3, hipStream_t s);
 // delta = -L7 phi; phi_out = phi * h2 (if non-null); partials K=3: min det, min lambda0, max delta
 hipError_t launch_output(const double *phi, double *delta, double *phi_out, double h2, int n, Part &p,
@@ -95,10 +96,11 @@ hipError_t launch_restrict25(const T *f, T *c, int n, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong25(T *u, const T *e, int n, hipStream_t s);
 
-template <typename Z>
-hipError_t launch_direction25(const Z *z, const double *p_old, double *p_new, const double *a, double *q,
-                              double beta, int n, double a_min, bool first, double *u, double alpha_u, Part &p,
-                              hipStream_t s);
+// P: storage of p_old and p_new (double, or float with an FP32 z: p_new is
+// rounded to FP32 as it is formed and q = A p_new uses the rounded value).
+template <typename Z, typename P>
+hipError_t launch_direction25(const Z *z, const P *p_old, P *p_new, const double *a, double *q, double beta, int n,
+                              double a_min, bool first, double *u, double alpha_u, Part &p, hipStream_t s);
 
 hipError_t launch_residual_norm(const double *u, const double *a, const double *b, double *r, float *r32, int n,
                                 double a_min, Part &p, hipStream_t s);

@@ -445,23 +445,25 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         double beta = 0.0;
         bool first = true;
         // Streaming levels form the new direction out of place, fused with its
-        // operator product; it alternates between p and t (idle during a solve).
-        // The solution update u += alpha p of one step is deferred into the next
-        // direction pass there (it reads p anyway), and applied after the loop
-        // for the last step.
+        // operator product; it alternates between p and t (idle during a solve),
+        // stored in FP32 when the preconditioner is FP32.  The solution update
+        // u += alpha p of one step is deferred into the next direction pass there
+        // (it reads p anyway), and applied after the loop for the last step.
         const bool stream = use_stream<double>(n);
         double *pc = ctx->p, *pn = ctx->t;
+        auto f32 = [](double *x) { return reinterpret_cast<float *>(x); };
         double alpha_due = 0.0;
         bool due = false;
         while (true) {
             if (stream) {
                 double *ud = due ? ctx->u : nullptr;
                 if (mixed)
-                    HIPCHK(launch_direction25<float>(ctx->L32.u[0], pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min, first,
-                                                     ud, alpha_due, ctx->part, ctx->stream));
+                    HIPCHK(launch_direction25(ctx->L32.u[0], f32(pc), f32(pn), a0, ctx->q, beta, n,
+                                                            ctx->cfg.a_min, first, ud, alpha_due, ctx->part,
+                                                            ctx->stream));
                 else
-                    HIPCHK(launch_direction25<double>(ctx->z, pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min, first, ud,
-                                                      alpha_due, ctx->part, ctx->stream));
+                    HIPCHK(launch_direction25(ctx->z, pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min,
+                                                              first, ud, alpha_due, ctx->part, ctx->stream));
                 due = false;
                 std::swap(pc, pn);
             } else if (mixed) {
@@ -495,7 +497,8 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             beta = -alpha * v[1] / rz;
             rz = v[0];
         }
-        if (due) HIPCHK(launch_axpy(ctx->u, pc, alpha_due, n3, ctx->stream));
+        if (due && mixed) HIPCHK(launch_axpy(ctx->u, f32(pc), alpha_due, n3, ctx->stream));
+        else if (due) HIPCHK(launch_axpy(ctx->u, pc, alpha_due, n3, ctx->stream));
     }
     // mean-free solution, then the true residual
     HIPCHK(launch_sum(ctx->u, n3, ctx->part, ctx->stream));
@@ -1015,36 +1018,44 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
     return RECON_OK;
 }
 
-int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const double *p_old, const double *a,
-                          double beta, int first, double *p_new, double *q, double *pq, int variant, double *u,
-                          double alpha_u)
+int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void *p_old, const double *a,
+                          double beta, int first, void *p_new, double *q, double *pq, int variant, double *u,
+                          double alpha_u, int p_dtype)
 {
     TRY(check_ctx(ctx));
     const int n = ctx->n;
     const long n3 = ctx->n3;
     if (!z || !a || !p_new || !q || !pq || (!first && !p_old) || (z_dtype != 0 && z_dtype != 1) || variant < 0 ||
-        variant > 2 || (p_old && p_old == p_new) || q == p_new ||
-        (u && (first || u == p_old || u == p_new || u == q || u == a || u == z)))
+        variant > 2 || (p_old && p_old == p_new) || (void *)q == p_new || (p_dtype != 0 && p_dtype != 1) ||
+        (u && (first || (const void *)u == p_old || (void *)u == p_new || u == q || u == a || (const void *)u == z)))
         return fail(ctx, RECON_E_ARG, "bad arguments");
     const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
     if (stream && !stencil25_supported<double>(n))
         return fail(ctx, RECON_E_ARG, "the streaming direction update needs an edge that is a multiple of 64");
+    if (p_dtype == 1 && (!stream || z_dtype != 1))
+        return fail(ctx, RECON_E_ARG, "FP32 directions need an FP32 z and the streaming kernel");
     if (stream) {
-        const double *po = first ? q : p_old;  // not read when first; any array other than p_new
-        if (z_dtype == 0)
-            HIPCHK(launch_direction25<double>((const double *)z, po, p_new, a, q, beta, n, ctx->cfg.a_min, first != 0,
-                                              u, alpha_u, ctx->part, ctx->stream));
+        const void *po = first ? (const void *)q : p_old;  // not read when first; any array other than p_new
+        if (p_dtype == 1)
+            HIPCHK(launch_direction25((const float *)z, (const float *)po, (float *)p_new, a, q, beta, n,
+                                                    ctx->cfg.a_min, first != 0, u, alpha_u, ctx->part, ctx->stream));
+        else if (z_dtype == 0)
+            HIPCHK(launch_direction25((const double *)z, (const double *)po, (double *)p_new, a, q,
+                                                      beta, n, ctx->cfg.a_min, first != 0, u, alpha_u, ctx->part,
+                                                      ctx->stream));
         else
-            HIPCHK(launch_direction25<float>((const float *)z, po, p_new, a, q, beta, n, ctx->cfg.a_min, first != 0,
-                                             u, alpha_u, ctx->part, ctx->stream));
+            HIPCHK(launch_direction25((const float *)z, (const double *)po, (double *)p_new, a, q,
+                                                     beta, n, ctx->cfg.a_min, first != 0, u, alpha_u, ctx->part,
+                                                     ctx->stream));
     } else {
-        if (u) HIPCHK(launch_axpy(u, p_old, alpha_u, n3, ctx->stream));
-        if (!first) HIPCHK(launch_copy(p_new, p_old, n3, ctx->stream));
+        double *pn = (double *)p_new;
+        if (u) HIPCHK(launch_axpy(u, (const double *)p_old, alpha_u, n3, ctx->stream));
+        if (!first) HIPCHK(launch_copy(pn, (const double *)p_old, n3, ctx->stream));
         if (z_dtype == 0)
-            HIPCHK(launch_update_pq<double>((const double *)z, a, p_new, q, beta, n, ctx->cfg.a_min, first != 0,
+            HIPCHK(launch_update_pq<double>((const double *)z, a, pn, q, beta, n, ctx->cfg.a_min, first != 0,
                                             ctx->part, ctx->stream));
         else
-            HIPCHK(launch_update_pq<float>((const float *)z, a, p_new, q, beta, n, ctx->cfg.a_min, first != 0,
+            HIPCHK(launch_update_pq<float>((const float *)z, a, pn, q, beta, n, ctx->cfg.a_min, first != 0,
                                            ctx->part, ctx->stream));
     }
     return fetch_sum(ctx, pq);

@@ -367,16 +367,20 @@ hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0
     return hipGetLastError();
 }
 
-__global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, double alpha, long n3)
+template <typename X>
+__global__ void k_axpy(double *__restrict__ y, const X *__restrict__ x, double alpha, long n3)
 {
-    for (long p = blockIdx.x * 256L + threadIdx.x; p < n3; p += 256L * gridDim.x) y[p] += alpha * x[p];
+    for (long p = blockIdx.x * 256L + threadIdx.x; p < n3; p += 256L * gridDim.x) y[p] += alpha * (double)x[p];
 }
 
-hipError_t launch_axpy(double *y, const double *x, double alpha, long n3, hipStream_t s)
+template <typename X>
+hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s)
 {
-    k_axpy<<<flat_blocks(n3), 256, 0, s>>>(y, x, alpha, n3);
+    k_axpy<X><<<flat_blocks(n3), 256, 0, s>>>(y, x, alpha, n3);
     return hipGetLastError();
 }
+template hipError_t launch_axpy<double>(double *, const double *, double, long, hipStream_t);
+template hipError_t launch_axpy<float>(double *, const float *, double, long, hipStream_t);
 
 // y += sign * (*c) * scale
 __global__ void k_add_scalar(double *__restrict__ y, const double *c, double sign, double scale, long n3)

@@ -51,13 +51,18 @@ __device__ __forceinline__ void lds_fence_barrier()
 // FIRST (direction only): the first Krylov step, p = z, p_old not read.
 // UPD (direction only, not FIRST): also ug += alpha_u xin, the solution update
 // of the previous Krylov step, deferred to this pass, which reads p_old anyway.
-template <typename T, typename Z, int MODE, int TJ, int NT, int TK = 64, int FIRST = 0, int UPD = 0>
+// P (direction only): storage type of p_old and p_new.  With P = float the new
+// direction is rounded to FP32 as it is formed, so the stored p_new is exactly
+// the operand of A and of the later solution update.
+template <typename T, typename Z, int MODE, int TJ, int NT, int TK = 64, int FIRST = 0, int UPD = 0,
+          typename P = T>
 __global__ void __launch_bounds__(NT)
-    k_flux25(const T *__restrict__ xin, const Z *__restrict__ zg, const T *__restrict__ ag,
-             const T *__restrict__ bg, T *__restrict__ out, float *__restrict__ out32, T *__restrict__ pout, int n,
+    k_flux25(const P *__restrict__ xin, const Z *__restrict__ zg, const T *__restrict__ ag,
+             const T *__restrict__ bg, T *__restrict__ out, float *__restrict__ out32, P *__restrict__ pout, int n,
              int ci, T scale, T a_min, T beta, double *part, double *__restrict__ ug, double alpha_u)
 {
     static_assert(!UPD || (MODE == S25_DIRECTION && !FIRST), "the deferred update needs p_old");
+    static_assert(MODE == S25_DIRECTION || sizeof(P) == sizeof(T), "P differs from T only for directions");
     using F = S25<TJ, NT, TK>;
     static_assert(TJ * F::TK % NT == 0, "every thread owns whole rounds of the tile");
     constexpr int W = F::W, PLANE = F::PLANE, LU = F::LU, RS = F::RS;
@@ -97,10 +102,13 @@ __global__ void __launch_bounds__(NT)
     auto operand = [&](size_t g) -> T {
         if constexpr (MODE == S25_DIRECTION) {
             const T zv = (T)zg[g];
+            T x;
             if constexpr (FIRST)
-                return zv;
+                x = zv;
             else
-                return zv + beta * xin[g];
+                x = zv + beta * (T)xin[g];
+            if constexpr (sizeof(P) < sizeof(T)) x = (T)(P)x;
+            return x;
         } else {
             return xin[g];
         }
@@ -127,7 +135,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
             for (int r = 0; r < RS; ++r) {
                 ru[set][r] = ug[bb + gN[r]];
-                rq[set][r] = xin[bb + gN[r]];
+                rq[set][r] = (double)xin[bb + gN[r]];
             }
         }
     };
@@ -175,7 +183,7 @@ __global__ void __launch_bounds__(NT)
                 if (out32) out32[g] = (float)rv;
                 v += rv * rv;
             } else {
-                pout[g] = xc;
+                pout[g] = (P)xc;
                 out[g] = acc;
                 v += xc * acc;
                 if constexpr (UPD) ug[g] = ru[set][r] + alpha_u * rq[set][r];
@@ -274,7 +282,7 @@ hipError_t launch_residual25(const T *u, const T *a, const T *b, T *r, int n, T 
     using C = S25Launch<T, S25_RESID>;
     if (!s25_fits<C>(n)) return hipErrorInvalidValue;
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
-    k_flux25<T, T, S25_RESID, C::TJ, C::NT, C::TK><<<nb, C::NT, 0, s>>>(u, nullptr, a, b, r, nullptr, nullptr, n, ci,
+    k_flux25<T, T, S25_RESID, C::TJ, C::NT, C::TK, 0, 0, T><<<nb, C::NT, 0, s>>>(u, nullptr, a, b, r, nullptr, nullptr, n, ci,
                                                                        scale, a_min, (T)0, nullptr, nullptr, 0.0);
     return hipGetLastError();
 }
@@ -286,31 +294,31 @@ hipError_t launch_residual_norm25(const double *u, const double *a, const double
     if (!s25_fits<C>(n)) return hipErrorInvalidValue;
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
-    k_flux25<double, double, S25_RESNORM, C::TJ, C::NT, C::TK><<<nb, C::NT, 0, s>>>(
+    k_flux25<double, double, S25_RESNORM, C::TJ, C::NT, C::TK, 0, 0, double><<<nb, C::NT, 0, s>>>(
         u, nullptr, a, b, r, r32, nullptr, n, ci, 1.0, a_min, 0.0, p.part, nullptr, 0.0);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
 }
 
-template <typename Z>
-hipError_t launch_direction25(const Z *z, const double *p_old, double *p_new, const double *a, double *q,
-                              double beta, int n, double a_min, bool first, double *u, double alpha_u, Part &p,
-                              hipStream_t s)
+template <typename Z, typename P>
+hipError_t launch_direction25(const Z *z, const P *p_old, P *p_new, const double *a, double *q, double beta, int n,
+                              double a_min, bool first, double *u, double alpha_u, Part &p, hipStream_t s)
 {
     using C = S25Launch<double, S25_DIRECTION>;
-    if (!s25_fits<C>(n) || p_old == p_new || (u && (first || u == p_old || u == p_new || u == q)))
+    const void *po = p_old;
+    if (!s25_fits<C>(n) || po == p_new || (u && (first || po == u || (void *)p_new == u || u == q)))
         return hipErrorInvalidValue;
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
     if (first)
-        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 1><<<nb, C::NT, 0, s>>>(
+        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 1, 0, P><<<nb, C::NT, 0, s>>>(
             p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0);
     else if (u)
-        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0, 1><<<nb, C::NT, 0, s>>>(
+        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0, 1, P><<<nb, C::NT, 0, s>>>(
             p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, u, alpha_u);
     else
-        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0><<<nb, C::NT, 0, s>>>(
+        k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0, 0, P><<<nb, C::NT, 0, s>>>(
             p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0);
     p.blocks = nb;
     p.k = 1;
@@ -323,9 +331,14 @@ template hipError_t launch_residual25<float>(const float *, const float *, const
                                              hipStream_t);
 template hipError_t launch_residual25<double>(const double *, const double *, const double *, double *, int, double,
                                               double, hipStream_t);
-template hipError_t launch_direction25<float>(const float *, const double *, double *, const double *, double *,
-                                              double, int, double, bool, double *, double, Part &, hipStream_t);
-template hipError_t launch_direction25<double>(const double *, const double *, double *, const double *, double *,
-                                               double, int, double, bool, double *, double, Part &, hipStream_t);
+template hipError_t launch_direction25<float, double>(const float *, const double *, double *, const double *,
+                                                      double *, double, int, double, bool, double *, double, Part &,
+                                                      hipStream_t);
+template hipError_t launch_direction25<float, float>(const float *, const float *, float *, const double *, double *,
+                                                     double, int, double, bool, double *, double, Part &,
+                                                     hipStream_t);
+template hipError_t launch_direction25<double, double>(const double *, const double *, double *, const double *,
+                                                       double *, double, int, double, bool, double *, double, Part &,
+                                                       hipStream_t);
 
 }  // namespace recon

@@ -189,6 +189,28 @@ def test_streaming_operator_kernels(torch_cuda, orc, n):
     with pytest.raises(binding.ReconError):
         ug = dev(torch, u)
         rec.direction(dev(torch, z), dev(torch, p_old), dev(torch, a), beta, True, variant=2, u=ug, alpha_u=1.0)
+    # FP32 directions (the mixed solver's): p_new is z + beta p_old rounded to
+    # FP32, q and p.q are the FP64 product of exactly the stored values, and the
+    # deferred update adds alpha times the stored p_old
+    z32, po32 = z.astype(np.float32), p_old.astype(np.float32)
+    for first in (True, False):
+        ug = dev(torch, u)
+        pn, qv, pq = rec.direction(dev(torch, z32), None if first else dev(torch, po32), dev(torch, a), beta, first,
+                                   variant=2, u=None if first else ug, alpha_u=alpha_u, p_dtype=torch.float32)
+        assert pn.dtype == torch.float32
+        p32 = host(pn).astype(np.float64)
+        p_ref = z32.astype(np.float64) + (0.0 if first else beta * po32.astype(np.float64))
+        if first:
+            assert np.array_equal(p32, p_ref)
+        else:  # one rounding to FP32 (the FP64 sum may be contracted to an FMA)
+            assert np.abs(p32 - p_ref).max() <= 2.0 ** -24 * (1 + 1e-12) * np.abs(p_ref).max()
+            u_ref = u + alpha_u * po32.astype(np.float64)
+            assert np.abs(host(ug) - u_ref).max() <= 2.3e-16 * np.abs(u_ref).max()
+        q_ref = orc.apply(p32, a)
+        assert rel(host(qv), q_ref) < 1e-14
+        assert abs(pq - float(np.dot(p32.ravel(), q_ref.ravel()))) <= 1e-12 * abs(pq)
+    with pytest.raises(binding.ReconError):  # FP32 directions need an FP32 z
+        rec.direction(dev(torch, z), None, dev(torch, a), beta, True, variant=2, p_dtype=torch.float32)
 
 
 def test_streaming_transfers(torch_cuda, orc):
