@@ -181,7 +181,7 @@ int recon_stage_apply(recon_ctx *ctx, const double *u, const double *a, int nl, 
 
 /* r = b - A u on an nl^3 level.  variant 0: the kernel the solver uses on
  * that level; 1: per-node gathers; 2: the LDS-streaming kernel (nl a
- * multiple of 64, else RECON_E_ARG). */
+ * multiple of 128, else RECON_E_ARG). */
 int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const void *b, int nl, double scale,
                          void *r, int dtype, int variant);
 
@@ -203,7 +203,7 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void
 /* One red-black Gauss-Seidel sweep in place (colour `first` then the other;
  * red = i+j+k even) on an nl^3 level.  variant 0: the kernel the solver uses
  * on that level; 1: two per-colour launches; 2: the fused two-colour kernel
- * (nl a multiple of 64, else RECON_E_ARG). */
+ * (nl a multiple of 128 in FP32 or of 64 in FP64, else RECON_E_ARG). */
 int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first,
                      int dtype, int variant);
 

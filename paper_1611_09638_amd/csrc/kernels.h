@@ -78,7 +78,7 @@ hipError_t launch_cast_f64(const float *src, double *dst, long n3, hipStream_t s
 
 // ------------------------------------------------------------ Krylov (FP64)
 // r = b - A u (FP64) with partial K=1 sum r^2; writes r32 = (float) r if r32 != null
-// LDS-streaming variants (stencil25.hip): edge a multiple of 64 (FP32 and
+// LDS-streaming variants (stencil25.hip): edge a multiple of 128 (FP32 and
 // FP64) and of the j-tile.  launch_direction25 writes p_new = first ? z :
 // z + beta p_old (p_new != p_old), q = A p_new and the partial sums of p_new.q;
 // with u != null (not first) it also applies u += alpha_u p_old.

@@ -278,25 +278,28 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
     }
 }
 
-// Tile rows, workgroup size, smallest launch and waves per SIMD (register
-// budget), per precision, as measured best at 512^3: FP32 16 x 64 tiles with
-// 256 threads (44 KB of LDS, up to three workgroups per CU), FP64 16 x 64
+// Tile rows x width, workgroup size, smallest launch and waves per SIMD
+// (register budget), per precision, as measured best at 512^3 and 256^3:
+// FP32 8 x 128 tiles with 256 threads (50 KB of LDS; rows of 512 B, so the
+// k-halo columns cost fewer partly used cache lines than with 64-wide rows)
+// and 512 workgroups, two per CU, each streaming long i-chunks; FP64 16 x 64
 // tiles with 512 threads (87 KB, one per CU; its halo re-reads are the lowest).
 template <typename T>
 struct FusedLaunch;
 template <>
 struct FusedLaunch<float> {
-    static constexpr int TJ = 16, NT = 256, MIN_BLOCKS = 1024, MINW = 4;
+    static constexpr int TJ = 8, TK = 128, NT = 256, MIN_BLOCKS = 512, MINW = 2;
 };
 template <>
 struct FusedLaunch<double> {
-    static constexpr int TJ = 16, NT = 512, MIN_BLOCKS = 1024, MINW = 2;
+    static constexpr int TJ = 16, TK = 64, NT = 512, MIN_BLOCKS = 1024, MINW = 2;
 };
 
 template <typename T>
 bool rbgs_fused_supported(int n)
 {
-    return n >= 64 && n % 64 == 0 && n % FusedLaunch<T>::TJ == 0;
+    using C = FusedLaunch<T>;
+    return n >= C::TK && n % C::TK == 0 && n % C::TJ == 0;
 }
 
 template <typename T>
@@ -308,20 +311,20 @@ hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, in
     // i-chunk: as long as possible while the launch still has MIN_BLOCKS
     // workgroups (each chunk re-reads 4 planes of u and a)
     int ci = n;
-    while (ci > 16 && (n / 64) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
+    while (ci > 16 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
     if (ci % 4) return hipErrorInvalidValue;  // the steady-state loop takes planes in fours
-    const int nblk = (n / 64) * (n / C::TJ) * (n / ci);
+    const int nblk = (n / C::TK) * (n / C::TJ) * (n / ci);
     const T inv = (T)1 / scale;
     if (zero_init) {
         if (first)
-            k_rbgs_fused<T, C::TJ, 1, 1, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+            k_rbgs_fused<T, C::TJ, 1, 1, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
         else
-            k_rbgs_fused<T, C::TJ, 1, 0, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+            k_rbgs_fused<T, C::TJ, 1, 0, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
     } else {
         if (first)
-            k_rbgs_fused<T, C::TJ, 0, 1, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+            k_rbgs_fused<T, C::TJ, 0, 1, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
         else
-            k_rbgs_fused<T, C::TJ, 0, 0, 64, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+            k_rbgs_fused<T, C::TJ, 0, 0, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
     }
     return hipGetLastError();
 }

@@ -240,8 +240,9 @@ double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
 
 constexpr int kProfPairs = 4096;  // size of recon_ctx::prof_zero
 
-// Levels of at least 256^3 whose edge is a multiple of 64 are swept by the
-// fused two-colour kernel; smaller levels (resident in L2/MALL) by two
+// Levels of at least 256^3 whose edge is a multiple of the fused kernel's tile
+// (128 in FP32, 64 in FP64) are swept by the fused two-colour kernel; smaller
+// levels (resident in L2/MALL) by two
 // per-colour launches, which keep more workgroups busy there.
 template <typename T>
 bool use_fused(int n)
@@ -272,7 +273,7 @@ int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, i
     return RECON_OK;
 }
 
-// Levels of at least 256^3 whose edge is a multiple of 64 apply the operator
+// Levels of at least 256^3 whose edge is a multiple of 128 apply the operator
 // with the LDS-streaming kernels; smaller levels (resident in L2/MALL) with
 // per-node gathers.  variant: 0 = that choice, 1 = gather, 2 = streaming.
 template <typename T>
@@ -1007,7 +1008,7 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
     if (!u || !a || !b || !r || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || variant < 0 || variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
     if (variant == 2 && !(dtype == 0 ? stencil25_supported<double>(nl) : stencil25_supported<float>(nl)))
-        return fail(ctx, RECON_E_ARG, "the streaming residual needs an edge that is a multiple of 64");
+        return fail(ctx, RECON_E_ARG, "the streaming residual needs an edge that is a multiple of 128");
     if (dtype == 0)
         HIPCHK(residual_level<double>((const double *)u, (const double *)a, (const double *)b, (double *)r, nl, scale,
                                       ctx->cfg.a_min, ctx->stream, variant));
@@ -1031,7 +1032,7 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void
         return fail(ctx, RECON_E_ARG, "bad arguments");
     const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
     if (stream && !stencil25_supported<double>(n))
-        return fail(ctx, RECON_E_ARG, "the streaming direction update needs an edge that is a multiple of 64");
+        return fail(ctx, RECON_E_ARG, "the streaming direction update needs an edge that is a multiple of 128");
     if (p_dtype == 1 && (!stream || z_dtype != 1))
         return fail(ctx, RECON_E_ARG, "FP32 directions need an FP32 z and the streaming kernel");
     if (stream) {
@@ -1080,7 +1081,8 @@ int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int 
         variant < 0 || variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
     const bool can_fuse = dtype == 0 ? rbgs_fused_supported<double>(nl) : rbgs_fused_supported<float>(nl);
-    if (variant == 2 && !can_fuse) return fail(ctx, RECON_E_ARG, "fused sweep needs an edge that is a multiple of 64");
+    if (variant == 2 && !can_fuse)
+        return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 128 (FP32) or 64 (FP64)");
     const bool fused = variant == 2 || (variant == 0 && (dtype == 0 ? use_fused<double>(nl) : use_fused<float>(nl)));
     if (fused) {
         if (dtype == 0) TRY(stage_rbgs_fused<double>(ctx, (double *)u, (const double *)a, (const double *)b, nl, scale, first));

@@ -224,24 +224,27 @@ __global__ void __launch_bounds__(NT)
 // Launch shape per operation: tile rows TJ, tile width TK (a multiple of 64),
 // threads, and the smallest launch (the i-chunk is halved from n until the
 // launch has that many workgroups; each chunk reads one extra plane of every
-// field).  Wide tiles keep the halo lines of the narrow FP32 rows down.
+// field).  As measured best at 512^3 (and 256^3 for the residual): 128-wide
+// tiles, whose rows span whole cache lines with few partly used halo lines,
+// 512 threads, and long i-chunks (two workgroups per CU for the residuals,
+// one for the direction pass, which streams more fields).
 template <typename T, int MODE>
 struct S25Launch;
 template <>
 struct S25Launch<float, S25_RESID> {
-    static constexpr int TJ = 4, TK = 256, NT = 256, MIN_BLOCKS = 2048;
+    static constexpr int TJ = 8, TK = 128, NT = 512, MIN_BLOCKS = 512;
 };
 template <>
 struct S25Launch<double, S25_RESID> {
-    static constexpr int TJ = 8, TK = 64, NT = 256, MIN_BLOCKS = 2048;
+    static constexpr int TJ = 8, TK = 128, NT = 512, MIN_BLOCKS = 512;
 };
 template <>
 struct S25Launch<double, S25_RESNORM> {
-    static constexpr int TJ = 8, TK = 64, NT = 256, MIN_BLOCKS = 2048;
+    static constexpr int TJ = 8, TK = 128, NT = 512, MIN_BLOCKS = 512;
 };
 template <>
 struct S25Launch<double, S25_DIRECTION> {
-    static constexpr int TJ = 8, TK = 64, NT = 256, MIN_BLOCKS = 2048;
+    static constexpr int TJ = 16, TK = 128, NT = 512, MIN_BLOCKS = 256;
 };
 
 template <typename C>
@@ -254,7 +257,7 @@ template <typename C>
 int s25_chunk(int n)
 {
     int ci = n;
-    while (ci > 4 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
+    while (ci % 4 == 0 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;  // ci stays even
     return ci;
 }
 

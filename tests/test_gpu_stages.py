@@ -78,18 +78,19 @@ def test_normalize_meshmass_source_smooth(torch_cuda, orc, n, cn):
     assert rel(d_g, orc.delta_r(phi)) < 1e-14
 
 
-@pytest.mark.parametrize("n,cn", SIZES + [(128, 8)])
+@pytest.mark.parametrize("n,cn", SIZES + [(128, 8), (256, 8)])
 @pytest.mark.parametrize("first", [0, 1])
 def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
-    """Both sweep kernels (fused two-colour where n is a multiple of 64, and
-    per-colour) against the oracle; the two kernels round identically."""
+    """Both sweep kernels (fused two-colour where n is a multiple of its tile
+    width, and per-colour) against the oracle; the two kernels round
+    identically.  At 256 the FP32 fused kernel has two tiles along k."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
     rec = binding.Recon(n, binding.Config(coarse_n=cn))
     rng = np.random.default_rng(100 + n + first)
     a = np.exp(1.5 * rng.normal(size=(n, n, n)))
     u, b = rng.normal(size=(2, n, n, n))
-    variants = (1, 2) if n % 64 == 0 else (1,)
+    variants = (1, 2) if n % 64 == 0 else (1,)  # fused FP64: 16 x 64 tiles
     for scale in (1.0, 1.0 / 16):
         uo = orc.rbgs_sweep(u, a, b, scale=scale, first=first)
         ug = [host(rec.rbgs(dev(torch, u), dev(torch, a), dev(torch, b), scale=scale, first=first, variant=v))
@@ -98,6 +99,11 @@ def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
             assert rel(x, uo) < 1e-13
             assert np.array_equal(x, ug[0])
     a32, u32, b32 = (x.astype(np.float32).astype(np.float64) for x in (a, u, b))
+    variants = (1, 2) if n % 128 == 0 else (1,)  # fused FP32: 8 x 128 tiles
+    if n == 64:
+        with pytest.raises(binding.ReconError):
+            rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32), dev(torch, b32, torch.float32),
+                     variant=2)
     uo = orc.rbgs_sweep(u32, a32, b32, first=first)
     ug = [host(rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32),
                         dev(torch, b32, torch.float32), first=first, variant=v)) for v in variants]
@@ -128,19 +134,26 @@ def test_residual_restrict_prolong(torch_cuda, orc, n, cn):
     assert rel(host(rec.prolong_add(f32(u), f32(e))), orc.prolong_add(q(u), q(e))) < 1e-6
 
 
-@pytest.mark.parametrize("n", [64, 128, 256])
+@pytest.mark.parametrize("n", [64, 128, 256, 384])
 def test_streaming_operator_kernels(torch_cuda, orc, n):
     """The LDS-streaming residual and Krylov direction kernels against the
     per-node gather kernels (same arithmetic, same face order) and the oracle,
-    with coefficients that hit the a_min floor.  The FP32 residual streams
-    256-wide tiles, so it needs an edge that is a multiple of 256."""
+    with coefficients that hit the a_min floor.  They stream 128-wide tiles,
+    so an edge of 64 is rejected; at 384 there are three tiles along k."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
-    rec = binding.Recon(n, binding.Config())
+    rec = binding.Recon(n, binding.Config(coarse_n=6 if n == 384 else 8))
     rng = np.random.default_rng(300 + n)
     a = np.exp(2.0 * rng.normal(size=(n, n, n)))
     a[rng.random((n, n, n)) < 0.05] = 0.0  # empty cells: floored faces
     u, b, z, p_old = rng.normal(size=(4, n, n, n))
+    if n % 128:
+        for dt in (torch.float64, torch.float32):
+            with pytest.raises(binding.ReconError):
+                rec.residual(dev(torch, u, dt), dev(torch, a, dt), dev(torch, b, dt), 1.0, variant=2)
+        with pytest.raises(binding.ReconError):
+            rec.direction(dev(torch, z), None, dev(torch, a), 0.5, True, variant=2)
+        return
     for scale in (1.0, 0.25):
         r1 = host(rec.residual(dev(torch, u), dev(torch, a), dev(torch, b), scale, variant=1))
         r2 = host(rec.residual(dev(torch, u), dev(torch, a), dev(torch, b), scale, variant=2))
@@ -150,12 +163,8 @@ def test_streaming_operator_kernels(torch_cuda, orc, n):
     q32 = lambda x: x.astype(np.float32).astype(np.float64)  # noqa: E731
     r1 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=1))
     assert rel(r1, orc.residual(q32(u), q32(a), q32(b), 0.25)) < 1e-5
-    if n % 256 == 0:
-        r2 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=2))
-        assert np.abs(r2 - r1).max() <= 1e-6 * np.abs(r1).max()
-    else:
-        with pytest.raises(binding.ReconError):
-            rec.residual(f32(u), f32(a), f32(b), 0.25, variant=2)
+    r2 = host(rec.residual(f32(u), f32(a), f32(b), 0.25, variant=2))
+    assert np.abs(r2 - r1).max() <= 1e-6 * np.abs(r1).max()
     beta = -0.37
     for zt, zq in ((torch.float64, lambda x: x), (torch.float32, q32)):
         for first in (True, False):
