@@ -212,6 +212,16 @@ int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int 
  * LDS-streaming kernel (nl a multiple of 256, else RECON_E_ARG). */
 int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype, int variant);
 
+/* The V-cycle's coarse right-hand side c = R (b - scale A u) on an nl^3 level
+ * (App. A: residual, then 27-point full weighting), c of size (nl/2)^3, all
+ * arrays FP64 (dtype 0) or FP32 (dtype 1) on the device.  variant 0: what the
+ * solver does on that level; 1: the residual kernel, then the restriction
+ * kernel (through a library-owned fine buffer); 2: one fused streaming pass
+ * (nl/2 a multiple of 32, else RECON_E_ARG).  All variants give the same
+ * values. */
+int recon_stage_residual_restrict(recon_ctx *ctx, const void *u, const void *a, const void *b, int nl, double scale,
+                                  void *c, int dtype, int variant);
+
 /* u += trilinear prolongation of the (nl/2)^3 field e onto the nl^3 field u
  * (P = 8 R^T).  variant as for recon_stage_restrict. */
 int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype, int variant);

@@ -131,6 +131,7 @@ def lib():
         "recon_stage_direction": (i, [vp, vp, i, vp, vp, d, i, vp, vp, pd, i, vp, d, i]),
         "recon_stage_rbgs": (i, [vp, vp, vp, vp, i, d, i, i, i]),
         "recon_stage_restrict": (i, [vp, vp, i, vp, i, i]),
+        "recon_stage_residual_restrict": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
         "recon_stage_prolong_add": (i, [vp, vp, vp, i, i, i]),
         "recon_stage_vcycle": (i, [vp, vp, vp, vp, i]),
         "recon_stage_mg_solve": (i, [vp, vp, vp, d, vp, pi, pd]),
@@ -309,6 +310,15 @@ class Recon:
         c = torch.empty((nc,) * 3, dtype=f.dtype, device=f.device)
         self._check(lib().recon_stage_restrict(self._ctx, _ptr(f, f.dtype), f.shape[0], _ptr(c), self._dt(f),
                                                variant))
+        return c
+
+    def residual_restrict(self, u, a, b, scale=1.0, variant=0):
+        """c = R (b - scale A u): the V-cycle's coarse right-hand side."""
+        nc = u.shape[0] // 2
+        c = torch.empty((nc,) * 3, dtype=u.dtype, device=u.device)
+        self._check(lib().recon_stage_residual_restrict(self._ctx, _ptr(u, u.dtype), _ptr(a, u.dtype),
+                                                        _ptr(b, u.dtype), u.shape[0], float(scale), _ptr(c),
+                                                        self._dt(u), variant))
         return c
 
     def prolong_add(self, u, e, variant=0):

@@ -95,6 +95,13 @@ template <typename T>
 hipError_t launch_restrict25(const T *f, T *c, int n, hipStream_t s);
 template <typename T>
 hipError_t launch_prolong25(T *u, const T *e, int n, hipStream_t s);
+// c = R (b - scale A u) in one streaming pass (resrestrict25.hip): coarse edge
+// n/2 a multiple of 32; the same values as the residual and restriction
+// kernels one after the other
+template <typename T>
+bool resrestrict25_supported(int n);
+template <typename T>
+hipError_t launch_resrestrict25(const T *u, const T *a, const T *b, T *c, int n, T scale, T a_min, hipStream_t s);
 
 // P: storage of p_old and p_new (double, or float with an FP32 z: p_new is
 // rounded to FP32 as it is formed and q = A p_new uses the rounded value).

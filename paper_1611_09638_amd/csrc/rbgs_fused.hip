@@ -281,9 +281,10 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
 // Tile rows x width, workgroup size, smallest launch and waves per SIMD
 // (register budget), per precision, as measured best at 512^3 and 256^3:
 // FP32 8 x 128 tiles with 256 threads (50 KB of LDS; rows of 512 B, so the
-// k-halo columns cost fewer partly used cache lines than with 64-wide rows)
-// and 512 workgroups, two per CU, each streaming long i-chunks; FP64 16 x 64
-// tiles with 512 threads (87 KB, one per CU; its halo re-reads are the lowest).
+// k-halo columns cost fewer partly used cache lines than with 64-wide rows),
+// two workgroups per CU; FP64 16 x 64 tiles with 512 threads (87 KB, one per
+// CU; its halo re-reads are the lowest).  Both launch 512 workgroups at 512^3,
+// each streaming a 256-plane chunk (every chunk re-reads four planes).
 template <typename T>
 struct FusedLaunch;
 template <>
@@ -292,7 +293,7 @@ struct FusedLaunch<float> {
 };
 template <>
 struct FusedLaunch<double> {
-    static constexpr int TJ = 16, TK = 64, NT = 512, MIN_BLOCKS = 1024, MINW = 2;
+    static constexpr int TJ = 16, TK = 64, NT = 512, MIN_BLOCKS = 512, MINW = 2;
 };
 
 template <typename T>

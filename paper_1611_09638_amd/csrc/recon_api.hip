@@ -305,6 +305,21 @@ hipError_t restrict_level(const T *f, T *c, int n, hipStream_t s, int variant = 
     return launch_restrict<T>(f, c, n, s);
 }
 
+// Coarse right-hand side c = R (b - scale A u): streaming levels whose coarse
+// edge is a multiple of 32 form it in one fused pass; otherwise the residual
+// goes through `res` (a fine-level buffer) and is then restricted.  variant:
+// 0 = that choice, 1 = the two passes, 2 = the fused pass.
+template <typename T>
+hipError_t coarse_rhs(const T *u, const T *a, const T *b, T *res, T *c, int n, T scale, T a_min, hipStream_t s,
+                      int variant = 0)
+{
+    if (variant == 2 || (variant == 0 && use_stream<T>(n) && resrestrict25_supported<T>(n)))
+        return launch_resrestrict25<T>(u, a, b, c, n, scale, a_min, s);
+    hipError_t e = residual_level<T>(u, a, b, res, n, scale, a_min, s);
+    if (e != hipSuccess) return e;
+    return restrict_level<T>(res, c, n, s);
+}
+
 template <typename T>
 hipError_t prolong_level(T *u, const T *e, int n, hipStream_t s, int variant = 0)
 {
@@ -356,8 +371,7 @@ int vcycle(recon_ctx *ctx, Levels<T> &S, int l, const T *rhs, T *out)
     const long n3 = (long)n * n * n;
     if (ctx->cfg.n_pre == 0) HIPCHK(launch_zero(out, n3 * sizeof(T), ctx->stream));
     for (int s = 0; s < ctx->cfg.n_pre; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 0, s == 0));
-    HIPCHK(residual_level<T>(cur, S.a[l], rhs, S.res[l], n, sc, amin, ctx->stream));
-    HIPCHK(restrict_level<T>(S.res[l], S.b[l + 1], n, ctx->stream));
+    HIPCHK(coarse_rhs<T>(cur, S.a[l], rhs, S.res[l], S.b[l + 1], n, sc, amin, ctx->stream));
     TRY(vcycle<T>(ctx, S, l + 1, S.b[l + 1], S.u[l + 1]));
     HIPCHK(prolong_level<T>(cur, S.u[l + 1], n, ctx->stream));
     for (int s = 0; s < ctx->cfg.n_post; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 1, false));
@@ -1112,6 +1126,25 @@ int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dty
         return fail(ctx, RECON_E_ARG, "the streaming transfers need a fine edge that is a multiple of 256");
     if (dtype == 0) HIPCHK(restrict_level<double>((const double *)f, (double *)c, nl, ctx->stream, variant));
     else HIPCHK(restrict_level<float>((const float *)f, (float *)c, nl, ctx->stream, variant));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_residual_restrict(recon_ctx *ctx, const void *u, const void *a, const void *b, int nl, double scale,
+                                  void *c, int dtype, int variant)
+{
+    TRY(check_ctx(ctx));
+    if (!u || !a || !b || !c || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1) ||
+        variant < 0 || variant > 2)
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (variant == 2 && !(dtype == 0 ? resrestrict25_supported<double>(nl) : resrestrict25_supported<float>(nl)))
+        return fail(ctx, RECON_E_ARG, "the fused residual-restriction needs a coarse edge that is a multiple of 32");
+    if (dtype == 0)
+        HIPCHK(coarse_rhs<double>((const double *)u, (const double *)a, (const double *)b, ctx->t, (double *)c, nl,
+                                  scale, ctx->cfg.a_min, ctx->stream, variant));
+    else
+        HIPCHK(coarse_rhs<float>((const float *)u, (const float *)a, (const float *)b, reinterpret_cast<float *>(ctx->t),
+                                 (float *)c, nl, (float)scale, (float)ctx->cfg.a_min, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }

@@ -222,6 +222,37 @@ def test_streaming_operator_kernels(torch_cuda, orc, n):
         rec.direction(dev(torch, z), None, dev(torch, a), beta, True, variant=2, p_dtype=torch.float32)
 
 
+@pytest.mark.parametrize("n", [48, 64, 128, 256])
+def test_fused_residual_restriction(torch_cuda, orc, n):
+    """The V-cycle's coarse right-hand side R (b - scale A u) in one fused
+    pass against the residual and restriction kernels one after the other
+    (bitwise: same arithmetic, same order) and against the oracle, in FP64
+    and FP32.  It needs a coarse edge that is a multiple of 32 (48 is
+    rejected); at 256 the coarse grid has four tiles along k."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rec = binding.Recon(n, binding.Config(coarse_n=6 if n == 48 else 8, precision=binding.MIXED))
+    rng = np.random.default_rng(500 + n)
+    a = np.exp(2.0 * rng.normal(size=(n, n, n)))
+    a[rng.random((n, n, n)) < 0.05] = 0.0  # empty cells: floored faces
+    u, b = rng.normal(size=(2, n, n, n))
+    if n % 64:
+        with pytest.raises(binding.ReconError):
+            rec.residual_restrict(dev(torch, u), dev(torch, a), dev(torch, b), 1.0, variant=2)
+        return
+    for scale in (1.0, 0.25):
+        c1 = host(rec.residual_restrict(dev(torch, u), dev(torch, a), dev(torch, b), scale, variant=1))
+        c2 = host(rec.residual_restrict(dev(torch, u), dev(torch, a), dev(torch, b), scale, variant=2))
+        assert np.array_equal(c1, c2)
+        assert rel(c2, orc.restrict(orc.residual(u, a, b, scale))) < 1e-14
+    f32 = lambda x: dev(torch, x, torch.float32)  # noqa: E731
+    q32 = lambda x: x.astype(np.float32).astype(np.float64)  # noqa: E731
+    c1 = host(rec.residual_restrict(f32(u), f32(a), f32(b), 0.25, variant=1))
+    c2 = host(rec.residual_restrict(f32(u), f32(a), f32(b), 0.25, variant=2))
+    assert np.array_equal(c1, c2)
+    assert rel(c2, orc.restrict(orc.residual(q32(u), q32(a), q32(b), 0.25))) < 1e-5
+
+
 def test_streaming_transfers(torch_cuda, orc):
     """The LDS-streaming restriction and prolongation at 256^3 against the
     per-node gather kernels (bitwise, same arithmetic and order) and against
