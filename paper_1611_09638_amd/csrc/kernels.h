@@ -10,6 +10,20 @@ namespace recon {
 // in a fixed order into out[0..K).  Results are bitwise reproducible for a
 // given launch shape.
 constexpr long kPartCap = 1L << 21;
+
+// Device-resident scalars of the conjugate-gradient loop (8 doubles): the dot
+// products land here from the reductions, and the kernels that need the step
+// sizes form them from these values themselves, so the host reads back only
+// what its stop test needs.
+enum KrylovScalar {
+    KS_RZ = 0,      // z . r of the current step (written by the reduction)
+    KS_ZQ = 1,      // z . q_old (written with KS_RZ)
+    KS_PQ = 2,      // p . q
+    KS_RR = 3,      // ||r||^2 after the update
+    KS_ALPHA = 4,   // alpha = rz / pq (written by the residual update)
+    KS_RZ_OLD = 5,  // rz of the previous step (written by the residual update)
+    KS_COUNT = 8
+};
 enum RedOp { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2 };
 
 struct Part {
@@ -44,8 +58,10 @@ hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0
 // same counts from planes streamed through LDS; n a multiple of 64
 bool pd25_supported(int n);
 hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s);
+// y += alpha x, X = double or float; with alpha_dev != null alpha is read there
 template <typename X>
-hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s);  // X = double or float
+hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s,
+                       const double *alpha_dev = nullptr);
 hipError_t launch_add_scalar(double *y, const double *c_dev, double sign, double scale, long n3, hipStream_t s);
 // delta = -L7 phi; phi_out = phi * h2 (if non-null); partials K=3: min det, min lambda0, max delta
 hipError_t launch_output(const double *phi, double *delta, double *phi_out, double h2, int n, Part &p,
@@ -105,9 +121,12 @@ hipError_t launch_resrestrict25(const T *u, const T *a, const T *b, T *c, int n,
 
 // P: storage of p_old and p_new (double, or float with an FP32 z: p_new is
 // rounded to FP32 as it is formed and q = A p_new uses the rounded value).
+// With ks != null, beta = -ks[KS_ALPHA] ks[KS_ZQ] / ks[KS_RZ_OLD] and alpha_u =
+// ks[KS_ALPHA] are read on the device instead of the host values.
 template <typename Z, typename P>
 hipError_t launch_direction25(const Z *z, const P *p_old, P *p_new, const double *a, double *q, double beta, int n,
-                              double a_min, bool first, double *u, double alpha_u, Part &p, hipStream_t s);
+                              double a_min, bool first, double *u, double alpha_u, const double *ks, Part &p,
+                              hipStream_t s);
 
 hipError_t launch_residual_norm(const double *u, const double *a, const double *b, double *r, float *r32, int n,
                                 double a_min, Part &p, hipStream_t s);
@@ -115,12 +134,15 @@ hipError_t launch_residual_norm(const double *u, const double *a, const double *
 template <typename Z>
 hipError_t launch_dots_zr_zq(const Z *z, const double *r, const double *q, long n3, Part &p, hipStream_t s);
 // p = z + beta p; q = A z + beta q (first: p = z, q = A z); partial K=1: sum p*q
+// beta from ks as for launch_direction25 when ks != null
 template <typename Z>
 hipError_t launch_update_pq(const Z *z, const double *a, double *pv, double *q, double beta, int n,
-                            double a_min, bool first, Part &p, hipStream_t s);
-// u += alpha p (if u != null); r -= alpha q; partial K=1: sum r^2; r32 = (float) r if r32 != null
+                            double a_min, bool first, const double *ks, Part &p, hipStream_t s);
+// u += alpha p (if u != null); r -= alpha q; partial K=1: sum r^2; r32 = (float) r if r32 != null.
+// With ks != null: alpha = ks[KS_RZ] / ks[KS_PQ], and the kernel stores it in
+// ks[KS_ALPHA] and ks[KS_RZ] in ks[KS_RZ_OLD].
 hipError_t launch_update_ur(double *u, double *r, const double *pv, const double *q, double alpha,
-                            float *r32, long n3, Part &p, hipStream_t s);
+                            float *r32, long n3, double *ks, Part &p, hipStream_t s);
 // u += z (Z = double or float)
 template <typename Z>
 hipError_t launch_add_correction(double *u, const Z *z, long n3, hipStream_t s);

@@ -228,6 +228,20 @@ int fetch(recon_ctx *ctx, const int *ops, double *out)
     return RECON_OK;
 }
 
+// The device scalars of the conjugate-gradient loop (KS_* in kernels.h) sit at
+// this offset of ctx->scal; fetch_krylov copies all of them to the host.
+constexpr int kKrylovScal = 32;
+static_assert(kKrylovScal + KS_COUNT <= kScal, "the scalar block fits");
+
+int fetch_krylov(recon_ctx *ctx, double *out)
+{
+    HIPCHK(hipMemcpyAsync(ctx->host_scal, ctx->scal + kKrylovScal, sizeof(double) * KS_COUNT,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int c = 0; c < KS_COUNT; ++c) out[c] = ctx->host_scal[c];
+    return RECON_OK;
+}
+
 int fetch_sum(recon_ctx *ctx, double *out)
 {
     static const int ops[8] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM};
@@ -411,7 +425,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
     const long n3 = ctx->n3;
     const bool mixed = ctx->cfg.precision == RECON_MIXED;
     float *r32 = mixed ? ctx->L32.b[0] : nullptr;
-    double v[4];
+    double v[KS_COUNT];
     HIPCHK(launch_dot(b, b, n3, ctx->part, ctx->stream));
     TRY(fetch_sum(ctx, v));
     const double bn = std::sqrt(v[0]);
@@ -451,13 +465,16 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         // Conjugate gradients on A u = b preconditioned by one symmetric V-cycle,
         // flexible form: beta = z_new.(r_new - r_old) / (z_old.r_old)
         //                     = -alpha (z_new.q) / (z_old.r_old).
+        // The dot products land in the device scalar block ks, and the kernels
+        // form alpha and beta from it themselves (same operations as on the
+        // host), so the host waits once per step, for its stop test.
+        double *ks = ctx->scal + kKrylovScal;
+        static const int sums[2] = {RED_SUM, RED_SUM};
         TRY(precondition(ctx));
         cycles = 1;
         if (mixed) HIPCHK(launch_dots_zr_zq<float>(ctx->L32.u[0], ctx->r, nullptr, n3, ctx->part, ctx->stream));
         else HIPCHK(launch_dots_zr_zq<double>(ctx->z, ctx->r, nullptr, n3, ctx->part, ctx->stream));
-        TRY(fetch_sum(ctx, v));
-        double rz = v[0];
-        double beta = 0.0;
+        HIPCHK(reduce_finalize(ctx->part, sums, ks + KS_RZ, ctx->stream));
         bool first = true;
         // Streaming levels form the new direction out of place, fused with its
         // operator product; it alternates between p and t (idle during a solve),
@@ -467,38 +484,34 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         const bool stream = use_stream<double>(n);
         double *pc = ctx->p, *pn = ctx->t;
         auto f32 = [](double *x) { return reinterpret_cast<float *>(x); };
-        double alpha_due = 0.0;
         bool due = false;
         while (true) {
             if (stream) {
                 double *ud = due ? ctx->u : nullptr;
                 if (mixed)
-                    HIPCHK(launch_direction25(ctx->L32.u[0], f32(pc), f32(pn), a0, ctx->q, beta, n,
-                                                            ctx->cfg.a_min, first, ud, alpha_due, ctx->part,
-                                                            ctx->stream));
+                    HIPCHK(launch_direction25(ctx->L32.u[0], f32(pc), f32(pn), a0, ctx->q, 0.0, n, ctx->cfg.a_min,
+                                              first, ud, 0.0, ks, ctx->part, ctx->stream));
                 else
-                    HIPCHK(launch_direction25(ctx->z, pc, pn, a0, ctx->q, beta, n, ctx->cfg.a_min,
-                                                              first, ud, alpha_due, ctx->part, ctx->stream));
+                    HIPCHK(launch_direction25(ctx->z, pc, pn, a0, ctx->q, 0.0, n, ctx->cfg.a_min, first, ud, 0.0, ks,
+                                              ctx->part, ctx->stream));
                 due = false;
                 std::swap(pc, pn);
             } else if (mixed) {
-                HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, pc, ctx->q, beta, n, ctx->cfg.a_min, first,
+                HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, pc, ctx->q, 0.0, n, ctx->cfg.a_min, first, ks,
                                                ctx->part, ctx->stream));
             } else {
-                HIPCHK(launch_update_pq<double>(ctx->z, a0, pc, ctx->q, beta, n, ctx->cfg.a_min, first, ctx->part,
+                HIPCHK(launch_update_pq<double>(ctx->z, a0, pc, ctx->q, 0.0, n, ctx->cfg.a_min, first, ks, ctx->part,
                                                 ctx->stream));
             }
             first = false;
-            TRY(fetch_sum(ctx, v));
-            const double pq = v[0];
-            const double alpha = rz / pq;
-            HIPCHK(launch_update_ur(stream ? nullptr : ctx->u, ctx->r, pc, ctx->q, alpha, r32, n3, ctx->part,
+            HIPCHK(reduce_finalize(ctx->part, sums, ks + KS_PQ, ctx->stream));
+            HIPCHK(launch_update_ur(stream ? nullptr : ctx->u, ctx->r, pc, ctx->q, 0.0, r32, n3, ks, ctx->part,
                                     ctx->stream));
             due = stream;
-            alpha_due = alpha;
-            TRY(fetch_sum(ctx, v));
-            const double rn = std::sqrt(v[0]);
-            if (!std::isfinite(rn) || !std::isfinite(alpha)) break;
+            HIPCHK(reduce_finalize(ctx->part, sums, ks + KS_RR, ctx->stream));
+            TRY(fetch_krylov(ctx, v));
+            const double rn = std::sqrt(v[KS_RR]);
+            if (!std::isfinite(rn) || !std::isfinite(v[KS_ALPHA])) break;
             if (fixed > 0 ? cycles >= fixed : rn <= tol * bn) {
                 status = RECON_OK;
                 break;
@@ -508,12 +521,10 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             ++cycles;
             if (mixed) HIPCHK(launch_dots_zr_zq<float>(ctx->L32.u[0], ctx->r, ctx->q, n3, ctx->part, ctx->stream));
             else HIPCHK(launch_dots_zr_zq<double>(ctx->z, ctx->r, ctx->q, n3, ctx->part, ctx->stream));
-            TRY(fetch_sum(ctx, v));
-            beta = -alpha * v[1] / rz;
-            rz = v[0];
+            HIPCHK(reduce_finalize(ctx->part, sums, ks + KS_RZ, ctx->stream));
         }
-        if (due && mixed) HIPCHK(launch_axpy(ctx->u, f32(pc), alpha_due, n3, ctx->stream));
-        else if (due) HIPCHK(launch_axpy(ctx->u, pc, alpha_due, n3, ctx->stream));
+        if (due && mixed) HIPCHK(launch_axpy(ctx->u, f32(pc), 0.0, n3, ctx->stream, ks + KS_ALPHA));
+        else if (due) HIPCHK(launch_axpy(ctx->u, pc, 0.0, n3, ctx->stream, ks + KS_ALPHA));
     }
     // mean-free solution, then the true residual
     HIPCHK(launch_sum(ctx->u, n3, ctx->part, ctx->stream));
@@ -1053,25 +1064,23 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void
         const void *po = first ? (const void *)q : p_old;  // not read when first; any array other than p_new
         if (p_dtype == 1)
             HIPCHK(launch_direction25((const float *)z, (const float *)po, (float *)p_new, a, q, beta, n,
-                                                    ctx->cfg.a_min, first != 0, u, alpha_u, ctx->part, ctx->stream));
+                                      ctx->cfg.a_min, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
         else if (z_dtype == 0)
-            HIPCHK(launch_direction25((const double *)z, (const double *)po, (double *)p_new, a, q,
-                                                      beta, n, ctx->cfg.a_min, first != 0, u, alpha_u, ctx->part,
-                                                      ctx->stream));
+            HIPCHK(launch_direction25((const double *)z, (const double *)po, (double *)p_new, a, q, beta, n,
+                                      ctx->cfg.a_min, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
         else
-            HIPCHK(launch_direction25((const float *)z, (const double *)po, (double *)p_new, a, q,
-                                                     beta, n, ctx->cfg.a_min, first != 0, u, alpha_u, ctx->part,
-                                                     ctx->stream));
+            HIPCHK(launch_direction25((const float *)z, (const double *)po, (double *)p_new, a, q, beta, n,
+                                      ctx->cfg.a_min, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
     } else {
         double *pn = (double *)p_new;
         if (u) HIPCHK(launch_axpy(u, (const double *)p_old, alpha_u, n3, ctx->stream));
         if (!first) HIPCHK(launch_copy(pn, (const double *)p_old, n3, ctx->stream));
         if (z_dtype == 0)
             HIPCHK(launch_update_pq<double>((const double *)z, a, pn, q, beta, n, ctx->cfg.a_min, first != 0,
-                                            ctx->part, ctx->stream));
+                                            nullptr, ctx->part, ctx->stream));
         else
             HIPCHK(launch_update_pq<float>((const float *)z, a, pn, q, beta, n, ctx->cfg.a_min, first != 0,
-                                           ctx->part, ctx->stream));
+                                           nullptr, ctx->part, ctx->stream));
     }
     return fetch_sum(ctx, pq);
 }

@@ -368,19 +368,21 @@ hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0
 }
 
 template <typename X>
-__global__ void k_axpy(double *__restrict__ y, const X *__restrict__ x, double alpha, long n3)
+__global__ void k_axpy(double *__restrict__ y, const X *__restrict__ x, double alpha, long n3,
+                       const double *__restrict__ alpha_dev)
 {
+    if (alpha_dev) alpha = *alpha_dev;
     for (long p = blockIdx.x * 256L + threadIdx.x; p < n3; p += 256L * gridDim.x) y[p] += alpha * (double)x[p];
 }
 
 template <typename X>
-hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s)
+hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s, const double *alpha_dev)
 {
-    k_axpy<X><<<flat_blocks(n3), 256, 0, s>>>(y, x, alpha, n3);
+    k_axpy<X><<<flat_blocks(n3), 256, 0, s>>>(y, x, alpha, n3, alpha_dev);
     return hipGetLastError();
 }
-template hipError_t launch_axpy<double>(double *, const double *, double, long, hipStream_t);
-template hipError_t launch_axpy<float>(double *, const float *, double, long, hipStream_t);
+template hipError_t launch_axpy<double>(double *, const double *, double, long, hipStream_t, const double *);
+template hipError_t launch_axpy<float>(double *, const float *, double, long, hipStream_t, const double *);
 
 // y += sign * (*c) * scale
 __global__ void k_add_scalar(double *__restrict__ y, const double *c, double sign, double scale, long n3)
@@ -788,8 +790,10 @@ hipError_t launch_dots_zr_zq(const Z *z, const double *r, const double *q, long 
 
 // p = z + beta p (first: p = z)
 template <typename Z>
-__global__ void k_update_p(const Z *__restrict__ z, double *__restrict__ pv, double beta, int first, long n3)
+__global__ void k_update_p(const Z *__restrict__ z, double *__restrict__ pv, double beta, int first, long n3,
+                           const double *__restrict__ ks)
 {
+    if (ks && !first) beta = -ks[KS_ALPHA] * ks[KS_ZQ] / ks[KS_RZ_OLD];
     for (long p = blockIdx.x * 256L + threadIdx.x; p < n3; p += 256L * gridDim.x)
         pv[p] = first ? (double)z[p] : (double)z[p] + beta * pv[p];
 }
@@ -822,10 +826,10 @@ __global__ void k_apply_dot(const double *__restrict__ pv, const double *__restr
 
 template <typename Z>
 hipError_t launch_update_pq(const Z *z, const double *a, double *pv, double *q, double beta, int n, double a_min,
-                            bool first, Part &p, hipStream_t s)
+                            bool first, const double *ks, Part &p, hipStream_t s)
 {
     const long n3 = (long)n * n * n;
-    k_update_p<Z><<<flat_blocks(n3), 256, 0, s>>>(z, pv, beta, first ? 1 : 0, n3);
+    k_update_p<Z><<<flat_blocks(n3), 256, 0, s>>>(z, pv, beta, first ? 1 : 0, n3, ks);
     Shape3 sh = shape3(n);
     k_apply_dot<<<sh.grid, sh.block, 0, s>>>(pv, a, q, n, sh.ipb, a_min, p.part);
     p.blocks = rows_of(sh);
@@ -835,8 +839,18 @@ hipError_t launch_update_pq(const Z *z, const double *a, double *pv, double *q, 
 
 template <bool U>
 __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, const double *__restrict__ pv,
-                            const double *__restrict__ q, double alpha, float *__restrict__ r32, long n3, double *part)
+                            const double *__restrict__ q, double alpha, float *__restrict__ r32, long n3, double *part,
+                            double *ks)
 {
+    if (ks) {
+        const double rz = ks[KS_RZ];
+        alpha = rz / ks[KS_PQ];
+        // only this kernel's other lanes read ks, and only KS_RZ and KS_PQ
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ks[KS_ALPHA] = alpha;
+            ks[KS_RZ_OLD] = rz;
+        }
+    }
     double v[1] = {0.0};
     for (long p = blockIdx.x * 256L + threadIdx.x; p < n3; p += 256L * gridDim.x) {
         if (U) u[p] += alpha * pv[p];
@@ -849,11 +863,11 @@ __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, cons
 }
 
 hipError_t launch_update_ur(double *u, double *r, const double *pv, const double *q, double alpha, float *r32, long n3,
-                            Part &p, hipStream_t s)
+                            double *ks, Part &p, hipStream_t s)
 {
     int nb = flat_blocks(n3);
-    if (u) k_update_ur<true><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part);
-    else k_update_ur<false><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part);
+    if (u) k_update_ur<true><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part, ks);
+    else k_update_ur<false><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part, ks);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -883,7 +897,7 @@ hipError_t launch_add_correction(double *u, const Z *z, long n3, hipStream_t s)
     template hipError_t launch_coarse_solve<T>(T *, const T *, const T *, int, T, T, int, hipStream_t);            \
     template hipError_t launch_dots_zr_zq<T>(const T *, const double *, const double *, long, Part &, hipStream_t); \
     template hipError_t launch_update_pq<T>(const T *, const double *, double *, double *, double, int, double,     \
-                                            bool, Part &, hipStream_t);                                           \
+                                            bool, const double *, Part &, hipStream_t);                           \
     template hipError_t launch_add_correction<T>(double *, const T *, long, hipStream_t);                        \
 
 RECON_INSTANTIATE(double)

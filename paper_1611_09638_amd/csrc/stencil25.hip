@@ -59,8 +59,16 @@ template <typename T, typename Z, int MODE, int TJ, int NT, int TK = 64, int FIR
 __global__ void __launch_bounds__(NT)
     k_flux25(const P *__restrict__ xin, const Z *__restrict__ zg, const T *__restrict__ ag,
              const T *__restrict__ bg, T *__restrict__ out, float *__restrict__ out32, P *__restrict__ pout, int n,
-             int ci, T scale, T a_min, T beta, double *part, double *__restrict__ ug, double alpha_u)
+             int ci, T scale, T a_min, T beta, double *part, double *__restrict__ ug, double alpha_u,
+             const double *__restrict__ ks)
 {
+    if constexpr (MODE == S25_DIRECTION && !FIRST) {
+        // the step sizes of the conjugate-gradient loop, formed on the device
+        if (ks) {
+            beta = -ks[KS_ALPHA] * ks[KS_ZQ] / ks[KS_RZ_OLD];
+            alpha_u = ks[KS_ALPHA];
+        }
+    }
     static_assert(!UPD || (MODE == S25_DIRECTION && !FIRST), "the deferred update needs p_old");
     static_assert(MODE == S25_DIRECTION || sizeof(P) == sizeof(T), "P differs from T only for directions");
     using F = S25<TJ, NT, TK>;
@@ -286,7 +294,8 @@ hipError_t launch_residual25(const T *u, const T *a, const T *b, T *r, int n, T 
     if (!s25_fits<C>(n)) return hipErrorInvalidValue;
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     k_flux25<T, T, S25_RESID, C::TJ, C::NT, C::TK, 0, 0, T><<<nb, C::NT, 0, s>>>(u, nullptr, a, b, r, nullptr, nullptr, n, ci,
-                                                                       scale, a_min, (T)0, nullptr, nullptr, 0.0);
+                                                                       scale, a_min, (T)0, nullptr, nullptr, 0.0,
+                                                                       nullptr);
     return hipGetLastError();
 }
 
@@ -298,7 +307,7 @@ hipError_t launch_residual_norm25(const double *u, const double *a, const double
     const int ci = s25_chunk<C>(n), nb = s25_blocks<C>(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
     k_flux25<double, double, S25_RESNORM, C::TJ, C::NT, C::TK, 0, 0, double><<<nb, C::NT, 0, s>>>(
-        u, nullptr, a, b, r, r32, nullptr, n, ci, 1.0, a_min, 0.0, p.part, nullptr, 0.0);
+        u, nullptr, a, b, r, r32, nullptr, n, ci, 1.0, a_min, 0.0, p.part, nullptr, 0.0, nullptr);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -306,7 +315,8 @@ hipError_t launch_residual_norm25(const double *u, const double *a, const double
 
 template <typename Z, typename P>
 hipError_t launch_direction25(const Z *z, const P *p_old, P *p_new, const double *a, double *q, double beta, int n,
-                              double a_min, bool first, double *u, double alpha_u, Part &p, hipStream_t s)
+                              double a_min, bool first, double *u, double alpha_u, const double *ks, Part &p,
+                              hipStream_t s)
 {
     using C = S25Launch<double, S25_DIRECTION>;
     const void *po = p_old;
@@ -316,13 +326,13 @@ hipError_t launch_direction25(const Z *z, const P *p_old, P *p_new, const double
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
     if (first)
         k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 1, 0, P><<<nb, C::NT, 0, s>>>(
-            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0);
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0, nullptr);
     else if (u)
         k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0, 1, P><<<nb, C::NT, 0, s>>>(
-            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, u, alpha_u);
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, u, alpha_u, ks);
     else
         k_flux25<double, Z, S25_DIRECTION, C::TJ, C::NT, C::TK, 0, 0, P><<<nb, C::NT, 0, s>>>(
-            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0);
+            p_old, z, a, nullptr, q, nullptr, p_new, n, ci, 1.0, a_min, beta, p.part, nullptr, 0.0, ks);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -335,13 +345,13 @@ template hipError_t launch_residual25<float>(const float *, const float *, const
 template hipError_t launch_residual25<double>(const double *, const double *, const double *, double *, int, double,
                                               double, hipStream_t);
 template hipError_t launch_direction25<float, double>(const float *, const double *, double *, const double *,
-                                                      double *, double, int, double, bool, double *, double, Part &,
-                                                      hipStream_t);
+                                                      double *, double, int, double, bool, double *, double,
+                                                      const double *, Part &, hipStream_t);
 template hipError_t launch_direction25<float, float>(const float *, const float *, float *, const double *, double *,
-                                                     double, int, double, bool, double *, double, Part &,
-                                                     hipStream_t);
+                                                     double, int, double, bool, double *, double, const double *,
+                                                     Part &, hipStream_t);
 template hipError_t launch_direction25<double, double>(const double *, const double *, double *, const double *,
-                                                       double *, double, int, double, bool, double *, double, Part &,
-                                                       hipStream_t);
+                                                       double *, double, int, double, bool, double *, double,
+                                                       const double *, Part &, hipStream_t);
 
 }  // namespace recon
