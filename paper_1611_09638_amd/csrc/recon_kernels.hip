@@ -661,24 +661,44 @@ __global__ void __launch_bounds__(1024) k_coarse_solve(T *__restrict__ ug, const
     __syncthreads();
     for (int p = t; p < n3; p += blockDim.x) b[p] -= mb;
     __syncthreads();
+    // Each thread keeps its nodes' neighbour offsets, face coefficients, their
+    // sum and b in registers: only u changes between passes.  The arithmetic
+    // per relaxation is unchanged (faces in the order +i, -i, +j, -j, +k, -k).
+    constexpr int NPT = 4096 / 1024;
+    int q[NPT][6], col[NPT];
+    T cf[NPT][6], den[NPT], bv[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int p = t + r * 1024;
+        const int pp = p < n3 ? p : 0;
+        const int i = pp / (n * n), j = (pp / n) % n, k = pp % n;
+        col[r] = p < n3 ? ((i + j + k) & 1) : -1;
+        q[r][0] = (wrapc(i + 1, n) * n + j) * n + k;
+        q[r][1] = (wrapc(i - 1, n) * n + j) * n + k;
+        q[r][2] = (i * n + wrapc(j + 1, n)) * n + k;
+        q[r][3] = (i * n + wrapc(j - 1, n)) * n + k;
+        q[r][4] = (i * n + j) * n + wrapc(k + 1, n);
+        q[r][5] = (i * n + j) * n + wrapc(k - 1, n);
+        const T an = a[pp];
+        T d = 0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            cf[r][f] = facec(an, a[q[r][f]], a_min);
+            d += cf[r][f];
+        }
+        den[r] = d;
+        bv[r] = b[pp];
+    }
     const int passes = 2 * pairs + 1;
     for (int ps = 0; ps < passes; ++ps) {
         const int colour = ps & 1;
-        for (int p = t; p < n3; p += blockDim.x) {
-            const int i = p / (n * n), j = (p / n) % n, k = p % n;
-            if (((i + j + k) & 1) != colour) continue;
-            const int q[6] = {(wrapc(i + 1, n) * n + j) * n + k, (wrapc(i - 1, n) * n + j) * n + k,
-                              (i * n + wrapc(j + 1, n)) * n + k, (i * n + wrapc(j - 1, n)) * n + k,
-                              (i * n + j) * n + wrapc(k + 1, n), (i * n + j) * n + wrapc(k - 1, n)};
-            const T an = a[p];
-            T num = 0, den = 0;
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                const T c = facec(an, a[q[f]], a_min);
-                num += c * u[q[f]];
-                den += c;
-            }
-            u[p] = (num - b[p] * inv_scale) / den;
+        for (int r = 0; r < NPT; ++r) {
+            if (col[r] != colour) continue;
+            T num = 0;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) num += cf[r][f] * u[q[r][f]];
+            u[t + r * 1024] = (num - bv[r] * inv_scale) / den[r];
         }
         __syncthreads();
     }
