@@ -59,6 +59,7 @@ class OrcConfig(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("record_tape", ctypes.c_int), ("solver", ctypes.c_int), ("warm_start", ctypes.c_int),
+        ("mass_update", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
         ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
         ("a_min", ctypes.c_double),
@@ -97,6 +98,7 @@ class Config:
     record_tape: int = 0
     solver: int = 0  # 0: V-cycle-preconditioned CG, 1: plain V-cycle iteration
     warm_start: int = 1  # start each linear solve from the previous outer step's solution
+    mass_update: int = 0  # 1: carry M by the exact mass change of App. A instead of re-gathering it
     tol: float = 1e-10
     outer_tol: float = 0.0
     xi_m: float = 0.1
@@ -148,6 +150,8 @@ def lib():
             "orc_count_not_pd": (ctypes.c_long, [d, i]),
             "orc_max_shift": (dbl, [d, i]),
             "orc_choose_step": (i, [d, d, i, ctypes.POINTER(OrcConfig), d]),
+            "orc_choose_step_mass": (i, [d, d, d, d, i, ctypes.POINTER(OrcConfig), d]),
+            "orc_full_operator": (None, [d, d, d, i, d]),
             "orc_delta_r": (None, [d, i, d]),
             "orc_solve": (i, [d, i, dbl, ctypes.POINTER(OrcConfig), d, d, ctypes.POINTER(OrcStats)]),
             "orc_lambda_min": (dbl, [d]),
@@ -303,13 +307,27 @@ def max_shift(f) -> float:
     return lib().orc_max_shift(_p(f), f.shape[0])
 
 
-def choose_step(phi, dphi, cfg: Config | None = None):
+def choose_step(phi, dphi, cfg: Config | None = None, M=None, D=None):
+    """(j, alpha) of the step control; with M and D also M + alpha D > 0."""
     cfg = cfg or Config()
     phi, dphi = _f64(phi), _f64(dphi)
     alpha = ctypes.c_double(0.0)
     c = cfg.c()
-    j = lib().orc_choose_step(_p(phi), _p(dphi), phi.shape[0], ctypes.byref(c), ctypes.byref(alpha))
+    if M is None:
+        j = lib().orc_choose_step(_p(phi), _p(dphi), phi.shape[0], ctypes.byref(c), ctypes.byref(alpha))
+    else:
+        M, D = _f64(M), _f64(D)
+        j = lib().orc_choose_step_mass(_p(phi), _p(dphi), _p(M), _p(D), phi.shape[0], ctypes.byref(c),
+                                       ctypes.byref(alpha))
     return j, (alpha.value if j >= 0 else None)
+
+
+def full_operator(phi, M, f) -> np.ndarray:
+    """div(M e^-1 grad f) with e = I + Hess phi: the exact mass change of App. A."""
+    phi, M, f = _f64(phi), _f64(M), _f64(f)
+    out = np.empty_like(f)
+    lib().orc_full_operator(_p(phi), _p(M), _p(f), phi.shape[0], _p(out))
+    return out
 
 
 def delta_r(phi) -> np.ndarray:

@@ -41,6 +41,10 @@
  *     tol ||b||_2; u made mean-free at the end.
  *   - step: alpha = 2^-j, first j with I + Hess(phi + alpha dphi) positive
  *     definite at every node (Sylvester) and max |alpha D_c dphi| <= s_max.
+ *   - optional mass update of App. A (mass_update = 1): M is carried from step
+ *     to step as M' = M + alpha L_full[dphi], with L_full f = div(M e^-1 grad f)
+ *     (Eq. elliptic_diff) discretised in flux form (below), and the step must
+ *     also keep M' > 0 at every node.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -66,6 +70,7 @@ typedef struct {
     int record_tape;
     int solver;
     int warm_start;
+    int mass_update; /* 0: M from the CIC gather each step; 1: M += alpha L_full[dphi] */
     double tol;
     double outer_tol;
     double xi_m, v_m;
@@ -213,6 +218,73 @@ void orc_triad_at(const double *phi, int n, int i, int j, int k, double *e9)
     double e[3][3];
     triad(phi, n, i, j, k, e);
     memcpy(e9, e, sizeof(e));
+}
+
+/* Inverse of a 3x3 matrix by cofactors (transposed cofactors over det). */
+static void inverse3(const double e[3][3], double inv[3][3])
+{
+    double d = det3(e);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            int r0 = (b + 1) % 3, r1 = (b + 2) % 3, c0 = (a + 1) % 3, c1 = (a + 2) % 3;
+            /* cofactor of element (b, a) */
+            inv[a][b] = (e[r0][c0] * e[r1][c1] - e[r0][c1] * e[r1][c0]) / d;
+        }
+}
+
+/* The operator of the exact mass change (App. A, Eq. elliptic_diff):
+ *   out = d_mu ( K^{mu nu} d_nu f ),  K = M e^{-1},  e = I + Hess phi,
+ * where M is the mass per curvilinear cell (rho sqrt g) of the current mesh.
+ * Flux form on the periodic lattice, so that the sum of out is zero:
+ *   diagonal: sum_mu [ (K^{mumu}_n + K^{mumu}_{n+mu})/2 (f_{n+mu} - f_n)
+ *                    - (K^{mumu}_{n-mu} + K^{mumu}_n)/2 (f_n - f_{n-mu}) ]
+ *   cross:    sum_{mu != nu} [ K^{munu}_{n+mu} (f_{n+mu+nu} - f_{n+mu-nu})
+ *                            - K^{munu}_{n-mu} (f_{n-mu+nu} - f_{n-mu-nu}) ] / 4
+ * (central differences of the flux K^{munu} d_nu f in direction mu).  At
+ * phi = 0 it is the operator of the solve without the a_min floor. */
+void orc_full_operator(const double *phi, const double *M, const double *f, int n, double *out)
+{
+    long N3 = cube(n);
+    double *K = (double *)malloc(sizeof(double) * 9 * N3);
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                long p = at(n, i, j, k);
+                double e[3][3], inv[3][3];
+                triad(phi, n, i, j, k, e);
+                inverse3(e, inv);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) K[9 * p + 3 * a + b] = M[p] * inv[a][b];
+            }
+    int d[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                long p = at(n, i, j, k);
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    long up = at(n, i + d[a][0], j + d[a][1], k + d[a][2]);
+                    long dn = at(n, i - d[a][0], j - d[a][1], k - d[a][2]);
+                    double kup = 0.5 * (K[9 * p + 4 * a] + K[9 * up + 4 * a]);
+                    double kdn = 0.5 * (K[9 * dn + 4 * a] + K[9 * p + 4 * a]);
+                    s += kup * (f[up] - f[p]) - kdn * (f[p] - f[dn]);
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        if (a == b) continue;
+                        long up = at(n, i + d[a][0], j + d[a][1], k + d[a][2]);
+                        long dn = at(n, i - d[a][0], j - d[a][1], k - d[a][2]);
+                        double fu = f[at(n, i + d[a][0] + d[b][0], j + d[a][1] + d[b][1], k + d[a][2] + d[b][2])] -
+                                    f[at(n, i + d[a][0] - d[b][0], j + d[a][1] - d[b][1], k + d[a][2] - d[b][2])];
+                        double fd = f[at(n, i - d[a][0] + d[b][0], j - d[a][1] + d[b][1], k - d[a][2] + d[b][2])] -
+                                    f[at(n, i - d[a][0] - d[b][0], j - d[a][1] - d[b][1], k - d[a][2] - d[b][2])];
+                        s += 0.25 * (K[9 * up + 3 * a + b] * fu - K[9 * dn + 3 * a + b] * fd);
+                    }
+                out[p] = s;
+            }
+    free(K);
 }
 
 /* Central-difference gradient of phi: the displacement x - xi at a node. */
@@ -729,9 +801,11 @@ double orc_max_shift(const double *f, int n)
 }
 
 /* First alpha = 2^-j (j = 0..max_halvings) for which phi + alpha dphi keeps the
- * map positive definite everywhere and no node moves more than s_max cells.
+ * map positive definite everywhere and no node moves more than s_max cells;
+ * with M and D given (the mass update), also M + alpha D > 0 at every node.
  * Returns j, or -1 when every trial fails. */
-int orc_choose_step(const double *phi, const double *dphi, int n, const orc_config *cfg, double *alpha_out)
+int orc_choose_step_mass(const double *phi, const double *dphi, const double *M, const double *D, int n,
+                         const orc_config *cfg, double *alpha_out)
 {
     long N3 = cube(n);
     double *trial = (double *)malloc(sizeof(double) * N3);
@@ -740,6 +814,12 @@ int orc_choose_step(const double *phi, const double *dphi, int n, const orc_conf
     for (int j = 0; j <= cfg->max_halvings; ++j) {
         double alpha = ldexp(1.0, -j);
         if (alpha * shift > cfg->s_max) continue;
+        if (M && D) {
+            int positive = 1;
+            for (long p = 0; p < N3; ++p)
+                if (!(M[p] + alpha * D[p] > 0.0)) positive = 0;
+            if (!positive) continue;
+        }
         for (long p = 0; p < N3; ++p) trial[p] = phi[p] + alpha * dphi[p];
         if (orc_is_pd(trial, n)) {
             found = j;
@@ -749,6 +829,11 @@ int orc_choose_step(const double *phi, const double *dphi, int n, const orc_conf
     }
     free(trial);
     return found;
+}
+
+int orc_choose_step(const double *phi, const double *dphi, int n, const orc_config *cfg, double *alpha_out)
+{
+    return orc_choose_step_mass(phi, dphi, NULL, NULL, n, cfg, alpha_out);
 }
 
 /* -------------------------------------------------------- the outer iteration */
@@ -765,6 +850,7 @@ void orc_config_default(orc_config *c)
     c->record_tape = 0;
     c->solver = 0;
     c->warm_start = 1;
+    c->mass_update = 0;
     c->tol = 1e-10;
     c->outer_tol = 0.0;
     c->xi_m = 0.1;
@@ -835,6 +921,7 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
     if (!rho || n <= 0 || box <= 0 || !cfg || cfg->tol <= 0) return ORC_E_ARG;
     if (orc_num_levels(n, cfg->coarse_n) < 1) return ORC_E_ARG;
     if (cfg->max_outer > ORC_MAX_STEPS) return ORC_E_ARG;
+    if (cfg->mass_update && cfg->record_tape) return ORC_E_ARG; /* no reverse mode for the mass update */
     long N3 = cube(n);
     double *m = (double *)malloc(sizeof(double) * N3);
     double *phi = (double *)calloc(N3, sizeof(double));
@@ -842,6 +929,7 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
     double *b = (double *)malloc(sizeof(double) * N3);
     double *u = (double *)malloc(sizeof(double) * N3);
     double *dphi = (double *)malloc(sizeof(double) * N3);
+    double *D = cfg->mass_update ? (double *)malloc(sizeof(double) * N3) : NULL;
     orc_stats local;
     if (!st) st = &local;
     memset(st, 0, sizeof(*st));
@@ -850,7 +938,9 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
     int status = orc_normalize(rho, n, m);
     if (status == ORC_OK) {
         for (int it = 0; it < cfg->max_outer; ++it) {
-            orc_meshmass(phi, m, n, M);
+            /* the CIC gather each step, or (mass update) only at phi = 0, where it
+             * gives M = m, after which M is carried by the update below */
+            if (!cfg->mass_update || it == 0) orc_meshmass(phi, m, n, M);
             double rho_bar = field_mean(M, n);
             double ss = 0.0;
             {
@@ -875,11 +965,15 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
             st->vcycles[it] = cyc;
             st->vcycles_total += cyc;
             orc_smooth(u, n, cfg->smooth_center, dphi);
+            /* mass update: the exact change per unit step on the current mesh */
+            if (cfg->mass_update) orc_full_operator(phi, M, dphi, n, D);
             double alpha = 0.0;
-            if (orc_choose_step(phi, dphi, n, cfg, &alpha) < 0) {
+            if (orc_choose_step_mass(phi, dphi, D ? M : NULL, D, n, cfg, &alpha) < 0) {
                 status = ORC_E_NOT_PD;
                 break;
             }
+            if (D)
+                for (long p = 0; p < N3; ++p) M[p] += alpha * D[p];
             for (long p = 0; p < N3; ++p) phi[p] += alpha * dphi[p];
             st->alpha[it] = alpha;
             st->outer_steps = it + 1;
@@ -892,8 +986,9 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
         }
     }
     if (status == ORC_OK && st->outer_steps == cfg->max_outer) {
-        /* mass deviation left after the last step */
-        orc_meshmass(phi, m, n, M);
+        /* mass deviation left after the last step (the carried M under the
+         * mass update) */
+        if (!cfg->mass_update) orc_meshmass(phi, m, n, M);
         double rho_bar = field_mean(M, n);
         for (long p = 0; p < N3; ++p) b[p] = rho_bar - M[p];
         st->rms_sigma[cfg->max_outer] = sqrt(field_dot(b, b, n) / (double)N3);
@@ -920,6 +1015,7 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
     free(b);
     free(u);
     free(dphi);
+    free(D);
     return status;
 }
 
