@@ -66,6 +66,11 @@ typedef struct recon_config {
     int solver;         /* RECON_SOLVER_PCG or RECON_SOLVER_VCYCLE                         */
     int warm_start;     /* 1: start each outer step's solve from the previous solution when its
                            residual is below ||b|| (else from 0) (1)                       */
+    int mass_update;    /* 0: the mass per curvilinear cell M is gathered by CIC on the deformed
+                           mesh every step; 1: it is gathered once and then carried by the
+                           paper's update M' = M + alpha div(M e^-1 grad dphi) (App. A, Eq.
+                           elliptic_diff), and steps must also keep M' > 0.  No reverse mode:
+                           record_tape must be 0 (0)                                        */
     int fixed_cycles;   /* > 0: every linear solve runs exactly this many V-cycles, ignoring tol
                            (makes the forward a smooth map for finite differences) (0)      */
     int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
@@ -245,9 +250,16 @@ int recon_stage_choose_step(recon_ctx *ctx, const double *phi, const double *dph
  * FP64; counts: host, ntrial doubles.  variant 1 gathers the 19-point
  * neighbourhood per node, 2 streams planes through LDS (n a multiple of 64,
  * else RECON_E_ARG), 0 picks what recon_stage_choose_step uses; all variants
- * give the same counts. */
+ * give the same counts.  M and D (device n^3 FP64, both or neither): the mass
+ * update's test, a node also counts where M + 2^-(j0+t) D > 0 fails. */
 int recon_stage_pd_count(recon_ctx *ctx, const double *phi, const double *dphi, int j0, int ntrial, int variant,
-                         double *counts);
+                         double *counts, const double *M, const double *D);
+
+/* The exact change of the mass per curvilinear cell per unit step (App. A, Eq.
+ * elliptic_diff applied to f): out = div(M e^-1 grad f) with e = I + Hess phi,
+ * in flux form (it sums to zero).  phi, M, f, out: device n^3 FP64; out must
+ * not alias the inputs.  Uses library-owned scratch fields of the context. */
+int recon_stage_mass_change(recon_ctx *ctx, const double *phi, const double *M, const double *f, double *out);
 
 /* delta = -laplacian phi (7-point, Eq. rec). */
 int recon_stage_delta_r(recon_ctx *ctx, const double *phi, double *delta);

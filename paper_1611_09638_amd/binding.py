@@ -29,7 +29,8 @@ class CConfig(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
-        ("warm_start", ctypes.c_int), ("fixed_cycles", ctypes.c_int), ("record_tape", ctypes.c_int),
+        ("warm_start", ctypes.c_int), ("mass_update", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
+        ("record_tape", ctypes.c_int),
         ("tape_fp32", ctypes.c_int), ("profile", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
         ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
@@ -71,6 +72,7 @@ class Config:
     precision: int = FP64
     solver: int = SOLVER_PCG
     warm_start: int = 1
+    mass_update: int = 0
     fixed_cycles: int = 0
     record_tape: int = 0
     tape_fp32: int = 0
@@ -136,8 +138,9 @@ def lib():
         "recon_stage_vcycle": (i, [vp, vp, vp, vp, i]),
         "recon_stage_mg_solve": (i, [vp, vp, vp, d, vp, pi, pd]),
         "recon_stage_choose_step": (i, [vp, vp, vp, pd]),
-        "recon_stage_pd_count": (i, [vp, vp, vp, i, i, i, pd]),
+        "recon_stage_pd_count": (i, [vp, vp, vp, i, i, i, pd, vp, vp]),
         "recon_stage_delta_r": (i, [vp, vp, vp]),
+        "recon_stage_mass_change": (i, [vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -346,11 +349,19 @@ class Recon:
                                                   ctypes.byref(alpha)))
         return alpha.value
 
-    def pd_count(self, phi, dphi, j0, ntrial=4, variant=0):
+    def pd_count(self, phi, dphi, j0, ntrial=4, variant=0, M=None, D=None):
         counts = (ctypes.c_double * ntrial)()
         self._check(lib().recon_stage_pd_count(self._ctx, _ptr(phi, torch.float64), _ptr(dphi, torch.float64),
-                                               int(j0), int(ntrial), int(variant), counts))
+                                               int(j0), int(ntrial), int(variant), counts,
+                                               _ptr(M, torch.float64), _ptr(D, torch.float64)))
         return [int(c) for c in counts]
+
+    def mass_change(self, phi, M, f):
+        """div(M e^-1 grad f), e = I + Hess phi: the exact mass change of a step."""
+        out = self._field()
+        self._check(lib().recon_stage_mass_change(self._ctx, _ptr(phi, torch.float64), _ptr(M, torch.float64),
+                                                  _ptr(f, torch.float64), _ptr(out)))
+        return out
 
     def delta_r(self, phi):
         d = self._field()

@@ -52,12 +52,21 @@ hipError_t launch_source(const double *phi, const double *M, double rho_bar, dou
 hipError_t launch_smooth(const double *f, double *out, int n, double c0, double sub, hipStream_t s);
 // partial K=1 (max): max_a |D_c f|
 hipError_t launch_max_shift(const double *f, int n, Part &p, hipStream_t s);
-// partial K=ntrial (sum): nodes where I + Hess(phi + 2^-j dphi) is not PD, j = j0..j0+ntrial-1
+// partial K=ntrial (sum): nodes where I + Hess(phi + 2^-j dphi) is not PD, j = j0..j0+ntrial-1;
+// with M and D non-null a node also fails where M + 2^-j D > 0 does not hold
 hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p,
-                            hipStream_t s);
+                            hipStream_t s, const double *M = nullptr, const double *D = nullptr);
 // same counts from planes streamed through LDS; n a multiple of 64
 bool pd25_supported(int n);
-hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s);
+hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s,
+                       const double *M = nullptr, const double *D = nullptr);
+// The exact mass change of a step (massupdate.hip): out = div(K grad f) with
+// K = M (I + Hess phi)^{-1}, its six components stored in K's fields.
+struct MassTensor {
+    double *xx, *yy, *zz, *xy, *xz, *yz;
+};
+hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
+                              double *out, int n, hipStream_t s);
 // y += alpha x, X = double or float; with alpha_dev != null alpha is read there
 template <typename X>
 hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s,

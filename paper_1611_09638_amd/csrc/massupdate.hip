@@ -1,0 +1,88 @@
+// The paper's own mass update (App. A): after a step, the mass per curvilinear
+// cell changes by the operator of Eq. elliptic_diff applied to the increment,
+//   D = d_mu ( K^{mu nu} d_nu f ),  K = M e^{-1},  e = I + Hess phi,
+// taken on the mesh before the step (M is rho sqrt g there).  Flux form on
+// the periodic lattice, so that D sums to zero and the update conserves mass:
+//   diagonal: sum_mu [ (K^{mumu}_n + K^{mumu}_{n+mu})/2 (f_{n+mu} - f_n)
+//                    - (K^{mumu}_{n-mu} + K^{mumu}_n)/2 (f_n - f_{n-mu}) ]
+//   cross:    sum_{mu != nu} [ K^{munu}_{n+mu} (f_{n+mu+nu} - f_{n+mu-nu})
+//                            - K^{munu}_{n-mu} (f_{n-mu+nu} - f_{n-mu-nu}) ] / 4
+// Two passes: K at every node (six fields, since e is symmetric), then the
+// 19-point application.  Both run once per outer step, so they gather from
+// L2 rather than stream through LDS.
+
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace recon {
+
+namespace {
+
+// K = M e^{-1} from the transposed cofactors of the symmetric triad.
+__global__ void k_mass_tensor(const double *__restrict__ phi, const double *__restrict__ M, MassTensor K, int n,
+                              int ipb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (k >= n || j >= n) return;
+    const int i0 = blockIdx.z * ipb, i1 = min(n, i0 + ipb);
+    for (int i = i0; i < i1; ++i) {
+        Stencil19 s;
+        load19(phi, i, j, k, n, s);
+        const Sym3 e = triad19(s);
+        const double w = M[lin(i, j, k, n)] / det_sym(e);
+        const size_t p = lin(i, j, k, n);
+        K.xx[p] = w * (e.yy * e.zz - e.yz * e.yz);
+        K.yy[p] = w * (e.xx * e.zz - e.xz * e.xz);
+        K.zz[p] = w * (e.xx * e.yy - e.xy * e.xy);
+        K.xy[p] = w * (e.xz * e.yz - e.xy * e.zz);
+        K.xz[p] = w * (e.xy * e.yz - e.xz * e.yy);
+        K.yz[p] = w * (e.xy * e.xz - e.xx * e.yz);
+    }
+}
+
+__global__ void k_mass_change(MassTensor K, const double *__restrict__ f, double *__restrict__ out, int n, int ipb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (k >= n || j >= n) return;
+    const int jp = wrapc(j + 1, n), jm = wrapc(j - 1, n), kp = wrapc(k + 1, n), km = wrapc(k - 1, n);
+    const int i0 = blockIdx.z * ipb, i1 = min(n, i0 + ipb);
+    for (int i = i0; i < i1; ++i) {
+        const int ip = wrapc(i + 1, n), im = wrapc(i - 1, n);
+        Stencil19 s;
+        load19(f, i, j, k, n, s);
+        const size_t c = lin(i, j, k, n);
+        const size_t xp = lin(ip, j, k, n), xm = lin(im, j, k, n);
+        const size_t yp = lin(i, jp, k, n), ym = lin(i, jm, k, n);
+        const size_t zp = lin(i, j, kp, n), zm = lin(i, j, km, n);
+        double acc = 0.0;
+        // diagonal fluxes, directions x, y, z
+        acc += 0.5 * (K.xx[c] + K.xx[xp]) * (s.xp - s.c) - 0.5 * (K.xx[xm] + K.xx[c]) * (s.c - s.xm);
+        acc += 0.5 * (K.yy[c] + K.yy[yp]) * (s.yp - s.c) - 0.5 * (K.yy[ym] + K.yy[c]) * (s.c - s.ym);
+        acc += 0.5 * (K.zz[c] + K.zz[zp]) * (s.zp - s.c) - 0.5 * (K.zz[zm] + K.zz[c]) * (s.c - s.zm);
+        // cross fluxes: direction mu of the difference, nu of the gradient
+        acc += 0.25 * (K.xy[xp] * (s.xpyp - s.xpym) - K.xy[xm] * (s.xmyp - s.xmym));  // mu = x, nu = y
+        acc += 0.25 * (K.xz[xp] * (s.xpzp - s.xpzm) - K.xz[xm] * (s.xmzp - s.xmzm));  // mu = x, nu = z
+        acc += 0.25 * (K.xy[yp] * (s.xpyp - s.xmyp) - K.xy[ym] * (s.xpym - s.xmym));  // mu = y, nu = x
+        acc += 0.25 * (K.yz[yp] * (s.ypzp - s.ypzm) - K.yz[ym] * (s.ymzp - s.ymzm));  // mu = y, nu = z
+        acc += 0.25 * (K.xz[zp] * (s.xpzp - s.xmzp) - K.xz[zm] * (s.xpzm - s.xmzm));  // mu = z, nu = x
+        acc += 0.25 * (K.yz[zp] * (s.ypzp - s.ymzp) - K.yz[zm] * (s.ypzm - s.ymzm));  // mu = z, nu = y
+        out[c] = acc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
+                              double *out, int n, hipStream_t s)
+{
+    Shape3 sh = shape3(n);
+    k_mass_tensor<<<sh.grid, sh.block, 0, s>>>(phi, M, K, n, sh.ipb);
+    k_mass_change<<<sh.grid, sh.block, 0, s>>>(K, f, out, n, sh.ipb);
+    return hipGetLastError();
+}
+
+}  // namespace recon

@@ -1,7 +1,8 @@
 // Step-size trials of the moving mesh (Sec. II: the map x = xi + grad phi
 // must stay positive definite; App. A: small steps): for NTR consecutive
 // alpha = 2^-j, count the nodes where I + Hess(phi + alpha dphi) fails
-// Sylvester's criterion (e11 > 0, e11 e22 - e12^2 > 0, det > 0).
+// Sylvester's criterion (e11 > 0, e11 e22 - e12^2 > 0, det > 0), or, under the
+// mass update of App. A, where the updated mass M + alpha D is not positive.
 //
 // The compact Hessian reads a 19-point neighbourhood of two fields.  Here a
 // workgroup owns a TJ x TK tile and a chunk of i-planes; planes of phi and
@@ -36,7 +37,8 @@ struct PdTile {
 
 template <int NTR, int TJ, int TK, int NT>
 __global__ void __launch_bounds__(NT) k_pd25(const double *__restrict__ phi, const double *__restrict__ dphi, int n,
-                                            int ci, int j0, double *part)
+                                            int ci, int j0, double *part, const double *__restrict__ massM,
+                                            const double *__restrict__ massD)
 {
     using F = PdTile<TJ, TK, NT>;
     static_assert(TJ * TK % NT == 0, "every thread owns whole rounds of the tile");
@@ -61,11 +63,12 @@ __global__ void __launch_bounds__(NT) k_pd25(const double *__restrict__ phi, con
         offL[r] = q < PLANE ? wrapc(jb - 1 + row, n) * n + wrapc(kb - 1 + col, n) : 0;
         dstL[r] = q < PLANE ? q : PLANE;
     }
-    int oN[RS];
+    int oN[RS], gN[RS];
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
         const int q = tid + r * NT;
         oN[r] = (q / TK + 1) * W + (q % TK + 1);
+        gN[r] = (jb + q / TK) * n + (kb + q % TK);
     }
 
     double rp[2][LU], rd[2][LU];
@@ -96,6 +99,12 @@ __global__ void __launch_bounds__(NT) k_pd25(const double *__restrict__ phi, con
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
             const int c = oN[r];
+            // the mass update's positivity test: M + alpha D > 0
+            double mv = 1.0, dv = 0.0;
+            if (massM) {
+                mv = massM[(size_t)p * n2 + gN[r]];
+                dv = massD[(size_t)p * n2 + gN[r]];
+            }
             Stencil19 a, d;
             a.c = Pc[c]; d.c = Dc[c];
             a.xp = Pp[c]; d.xp = Dp[c];
@@ -141,7 +150,7 @@ __global__ void __launch_bounds__(NT) k_pd25(const double *__restrict__ phi, con
                 s.ymzm = a.ymzm + al * d.ymzm;
                 const Sym3 e = triad19(s);
                 const double m2 = e.xx * e.yy - e.xy * e.xy;
-                const bool ok = e.xx > 0.0 && m2 > 0.0 && det_sym(e) > 0.0;
+                const bool ok = e.xx > 0.0 && m2 > 0.0 && det_sym(e) > 0.0 && mv + al * dv > 0.0;
                 cnt[m] += ok ? 0.0 : 1.0;
             }
         }
@@ -182,17 +191,19 @@ bool pd25_supported(int n)
     return n >= kPdTK && n % kPdTK == 0 && n % kPdTJ == 0;
 }
 
-hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s)
+hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s,
+                       const double *M, const double *D)
 {
+    if ((M == nullptr) != (D == nullptr)) return hipErrorInvalidValue;
     if (!pd25_supported(n) || (ntrial != 1 && ntrial != 4)) return hipErrorInvalidValue;
     int ci = n;
     while (ci % 4 == 0 && (n / kPdTK) * (n / kPdTJ) * (n / ci) < kPdMinBlocks) ci /= 2;  // ci stays even
     const int nb = (n / kPdTK) * (n / kPdTJ) * (n / ci);
     if ((long)nb * ntrial > kPartCap) return hipErrorInvalidValue;
     if (ntrial == 1)
-        k_pd25<1, kPdTJ, kPdTK, kPdNT><<<nb, kPdNT, 0, s>>>(phi, dphi, n, ci, j0, p.part);
+        k_pd25<1, kPdTJ, kPdTK, kPdNT><<<nb, kPdNT, 0, s>>>(phi, dphi, n, ci, j0, p.part, M, D);
     else
-        k_pd25<4, kPdTJ, kPdTK, kPdNT><<<nb, kPdNT, 0, s>>>(phi, dphi, n, ci, j0, p.part);
+        k_pd25<4, kPdTJ, kPdTK, kPdNT><<<nb, kPdNT, 0, s>>>(phi, dphi, n, ci, j0, p.part, M, D);
     p.blocks = nb;
     p.k = ntrial;
     return hipGetLastError();

@@ -76,6 +76,7 @@ bool config_ok(const recon_config *c)
     return c && c->max_outer >= 0 && c->max_outer <= RECON_MAX_STEPS && c->n_pre >= 0 && c->n_post >= 0 &&
            c->n_pre <= 16 && c->n_post <= 16 && c->coarse_sweeps >= 0 && c->max_vcycles >= 1 &&
            c->max_halvings >= 0 && c->max_halvings <= 60 && c->fixed_cycles >= 0 && (c->warm_start == 0 || c->warm_start == 1) &&
+           (c->mass_update == 0 || c->mass_update == 1) && !(c->mass_update && c->record_tape) &&
            (c->tape_fp32 == 0 || c->tape_fp32 == 1) && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
            (c->solver == RECON_SOLVER_PCG || c->solver == RECON_SOLVER_VCYCLE) && c->tol > 0 && c->outer_tol >= 0 &&
            c->xi_m >= 0 && c->v_m > 0 && c->smooth_center >= 0 && c->smooth_center <= 1 && c->s_max > 0 &&
@@ -545,15 +546,18 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
 // ------------------------------------------------------------ step control
 
 // Failing-node counts of `ntrial` step trials from 2^-j0; variant 1 gathers
-// per node, 2 streams planes through LDS, 0 takes 2 where it applies.
-hipError_t pd_trials(recon_ctx *ctx, const double *phi, const double *dphi, int j0, int ntrial, int variant)
+// per node, 2 streams planes through LDS, 0 takes 2 where it applies.  With M
+// and D (mass update) a node also fails where M + alpha D > 0 does not hold.
+hipError_t pd_trials(recon_ctx *ctx, const double *phi, const double *dphi, int j0, int ntrial, int variant,
+                     const double *M = nullptr, const double *D = nullptr)
 {
     if (variant == 0) variant = pd25_supported(ctx->n) ? 2 : 1;
-    if (variant == 2) return launch_pd25(phi, dphi, ctx->n, j0, ntrial, ctx->part, ctx->stream);
-    return launch_pd_trials(phi, dphi, ctx->n, j0, ntrial, ctx->part, ctx->stream);
+    if (variant == 2) return launch_pd25(phi, dphi, ctx->n, j0, ntrial, ctx->part, ctx->stream, M, D);
+    return launch_pd_trials(phi, dphi, ctx->n, j0, ntrial, ctx->part, ctx->stream, M, D);
 }
 
-int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha_out)
+int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha_out,
+                const double *M = nullptr, const double *D = nullptr)
 {
     static const int opmax[1] = {RED_MAX};
     double v[8];
@@ -565,7 +569,7 @@ int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *a
     while (j0 <= ctx->cfg.max_halvings && std::ldexp(1.0, -j0) * shift > ctx->cfg.s_max) ++j0;
     // four halvings per launch, from the largest step the shift bound allows
     for (int j = j0, batch = 4; j <= ctx->cfg.max_halvings; j += batch) {
-        HIPCHK(pd_trials(ctx, phi, dphi, j, batch, 0));
+        HIPCHK(pd_trials(ctx, phi, dphi, j, batch, 0, M, D));
         TRY(fetch_sum(ctx, v));
         for (int t = 0; t < batch && j + t <= ctx->cfg.max_halvings; ++t) {
             if (v[t] == 0.0) {
@@ -574,7 +578,8 @@ int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *a
             }
         }
     }
-    return fail(ctx, RECON_E_NOT_PD, "no step 2^-j, j <= %d, keeps the map positive definite", ctx->cfg.max_halvings);
+    return fail(ctx, RECON_E_NOT_PD, "no step 2^-j, j <= %d, keeps the map positive definite%s",
+                ctx->cfg.max_halvings, M ? " and the mass positive" : "");
 }
 
 // ------------------------------------------------------------ forward
@@ -593,11 +598,13 @@ int normalize(recon_ctx *ctx, const double *rho, double *m, double *mean_out)
     return RECON_OK;
 }
 
-// rho_bar = mean(M) and rms(Sigma) for the current phi (M recomputed).
-int mass_state(recon_ctx *ctx, double *rho_bar, double *rms, double *mean_t)
+// rho_bar = mean(M), rms(Sigma) and the source for the current phi; M is
+// gathered on the deformed mesh when `gather`, else (mass update) kept.
+int mass_state(recon_ctx *ctx, double *rho_bar, double *rms, double *mean_t, bool gather = true)
 {
     double v[2];
-    HIPCHK(launch_meshmass(ctx->phi, ctx->m, ctx->M, ctx->n, ctx->part, ctx->stream));
+    if (gather) HIPCHK(launch_meshmass(ctx->phi, ctx->m, ctx->M, ctx->n, ctx->part, ctx->stream));
+    else HIPCHK(launch_sum(ctx->M, ctx->n3, ctx->part, ctx->stream));
     TRY(fetch_sum(ctx, v));
     *rho_bar = v[0] / (double)ctx->n3;
     HIPCHK(launch_source(ctx->phi, ctx->M, *rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part,
@@ -622,10 +629,17 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
     HIPCHK(launch_zero(ctx->phi, n3 * 8, ctx->stream));
     ctx->tape_valid = 0;
     ctx->tape_steps = 0;
+    // Mass update: after the first gather (at phi = 0, where it gives M = m) M
+    // is carried by M += alpha D.  D goes into m's field, which is not read
+    // again in that mode, and K into six fields idle between the solve and
+    // the next step's source.
+    const bool carry = c.mass_update != 0;
+    double *D = ctx->m;
+    const MassTensor K{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q};
     int it = 0;
     for (; it < c.max_outer; ++it) {
         double rho_bar, rms, mean_t;
-        TRY(mass_state(ctx, &rho_bar, &rms, &mean_t));
+        TRY(mass_state(ctx, &rho_bar, &rms, &mean_t, !carry || it == 0));
         st->rms_sigma[it] = rms;
         st->kappa[it] = rho_bar;
         if (!std::isfinite(rms)) return fail(ctx, RECON_E_NO_CONVERGENCE, "non-finite mass deviation");
@@ -639,8 +653,10 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         st->vcycles_total += cyc;
         st->rel_residual[it] = rel;
         HIPCHK(launch_smooth(ctx->u, ctx->dphi, ctx->n, c.smooth_center, 0.0, ctx->stream));
+        if (carry) HIPCHK(launch_mass_change(ctx->phi, ctx->M, ctx->dphi, K, D, ctx->n, ctx->stream));
         double alpha = 0.0;
-        TRY(choose_step(ctx, ctx->phi, ctx->dphi, &alpha));
+        TRY(choose_step(ctx, ctx->phi, ctx->dphi, &alpha, carry ? ctx->M : nullptr, carry ? D : nullptr));
+        if (carry) HIPCHK(launch_axpy(ctx->M, D, alpha, n3, ctx->stream));
         HIPCHK(launch_axpy(ctx->phi, ctx->dphi, alpha, n3, ctx->stream));
         st->alpha[it] = alpha;
         st->outer_steps = it + 1;
@@ -656,7 +672,7 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
     }
     if (it == c.max_outer) {
         double rho_bar, rms, mean_t;
-        TRY(mass_state(ctx, &rho_bar, &rms, &mean_t));
+        TRY(mass_state(ctx, &rho_bar, &rms, &mean_t, !carry));
         st->rms_sigma[it] = rms;
         st->kappa[it] = rho_bar;
     }
@@ -769,6 +785,7 @@ int recon_config_default(recon_config *c)
     c->precision = RECON_FP64;
     c->solver = RECON_SOLVER_PCG;
     c->warm_start = 1;
+    c->mass_update = 0;
     c->fixed_cycles = 0;
     c->record_tape = 0;
     c->tape_fp32 = 0;
@@ -1219,18 +1236,28 @@ int recon_stage_choose_step(recon_ctx *ctx, const double *phi, const double *dph
 }
 
 int recon_stage_pd_count(recon_ctx *ctx, const double *phi, const double *dphi, int j0, int ntrial, int variant,
-                         double *counts)
+                         double *counts, const double *M, const double *D)
 {
     TRY(check_ctx(ctx));
     if (!phi || !dphi || !counts || j0 < 0 || j0 > 1000 || (ntrial != 1 && ntrial != 4) || variant < 0 ||
-        variant > 2)
+        variant > 2 || (M == nullptr) != (D == nullptr))
         return fail(ctx, RECON_E_ARG, "bad arguments");
     if (variant == 2 && !pd25_supported(ctx->n))
         return fail(ctx, RECON_E_ARG, "the streaming step trials need an edge that is a multiple of 64");
     double v[8];
-    HIPCHK(pd_trials(ctx, phi, dphi, j0, ntrial, variant));
+    HIPCHK(pd_trials(ctx, phi, dphi, j0, ntrial, variant, M, D));
     TRY(fetch_sum(ctx, v));
     for (int t = 0; t < ntrial; ++t) counts[t] = v[t];
+    return RECON_OK;
+}
+
+int recon_stage_mass_change(recon_ctx *ctx, const double *phi, const double *M, const double *f, double *out)
+{
+    TRY(check_ctx(ctx));
+    if (!phi || !M || !f || !out) return fail(ctx, RECON_E_ARG, "null array");
+    const MassTensor K{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q};
+    HIPCHK(launch_mass_change(phi, M, f, K, out, ctx->n, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }
 

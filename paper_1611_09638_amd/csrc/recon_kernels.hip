@@ -307,11 +307,12 @@ hipError_t launch_max_shift(const double *f, int n, Part &p, hipStream_t s)
 }
 
 // Count nodes where I + Hess(phi + 2^-j dphi) fails Sylvester's criterion
-// (e11 > 0, e11 e22 - e12^2 > 0, det > 0) for NT consecutive j.  The trial
-// potential is formed per stencil point exactly as phi + alpha * dphi.
+// (e11 > 0, e11 e22 - e12^2 > 0, det > 0) for NT consecutive j, or (mass update,
+// Mm and Dm given) where Mm + 2^-j Dm > 0 fails.  The trial potential is formed
+// per stencil point exactly as phi + alpha * dphi.
 template <int NT>
 __global__ void k_pd_trials(const double *__restrict__ phi, const double *__restrict__ dphi, int n, int ipb, int j0,
-                            double *part)
+                            double *part, const double *__restrict__ Mm, const double *__restrict__ Dm)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -324,6 +325,8 @@ __global__ void k_pd_trials(const double *__restrict__ phi, const double *__rest
             Stencil19 a, d;
             load19(phi, i, j, k, n, a);
             load19(dphi, i, j, k, n, d);
+            // the mass update's positivity test: M + alpha D > 0
+            const double mv = Mm ? Mm[lin(i, j, k, n)] : 1.0, dv = Mm ? Dm[lin(i, j, k, n)] : 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const double al = ldexp(1.0, -(j0 + t));
@@ -349,7 +352,7 @@ __global__ void k_pd_trials(const double *__restrict__ phi, const double *__rest
                 s.ymzm = a.ymzm + al * d.ymzm;
                 const Sym3 e = triad19(s);
                 const double m2 = e.xx * e.yy - e.xy * e.xy;
-                const bool ok = e.xx > 0.0 && m2 > 0.0 && det_sym(e) > 0.0;
+                const bool ok = e.xx > 0.0 && m2 > 0.0 && det_sym(e) > 0.0 && mv + al * dv > 0.0;
                 v[t] += ok ? 0.0 : 1.0;
             }
         }
@@ -357,11 +360,13 @@ __global__ void k_pd_trials(const double *__restrict__ phi, const double *__rest
     block_reduce_store<NT, RED_SUM>(v, part, block_row());
 }
 
-hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s)
+hipError_t launch_pd_trials(const double *phi, const double *dphi, int n, int j0, int ntrial, Part &p, hipStream_t s,
+                            const double *M, const double *D)
 {
+    if ((M == nullptr) != (D == nullptr)) return hipErrorInvalidValue;
     Shape3 sh = shape3(n);
-    if (ntrial == 1) k_pd_trials<1><<<sh.grid, sh.block, 0, s>>>(phi, dphi, n, sh.ipb, j0, p.part);
-    else k_pd_trials<4><<<sh.grid, sh.block, 0, s>>>(phi, dphi, n, sh.ipb, j0, p.part);
+    if (ntrial == 1) k_pd_trials<1><<<sh.grid, sh.block, 0, s>>>(phi, dphi, n, sh.ipb, j0, p.part, M, D);
+    else k_pd_trials<4><<<sh.grid, sh.block, 0, s>>>(phi, dphi, n, sh.ipb, j0, p.part, M, D);
     p.blocks = rows_of(sh);
     p.k = ntrial == 1 ? 1 : 4;
     return hipGetLastError();
