@@ -128,6 +128,60 @@ def stream_ceilings(torch, dev, reps=10):
     return out
 
 
+def mass_update_bench(torch, binding, inputs, args):
+    """Mixed solves of lognormal512_mild with M gathered by CIC every step and
+    with the paper's mass update, and the time of the update's two kernels
+    (K = M e^-1: read phi, M, write six fields; the 19-point application: read
+    the six fields and f, write the change): 64 + 64 algorithmic B/node."""
+    name = "lognormal512_mild"
+    w = inputs.WORKLOADS[name]
+    n, box = w["n"], w["box"]
+    rho = inputs.lognormal_density(n, box, w["sigma_g"], w["seed"])
+    dev = torch.device("cuda:0")
+    rho_d = torch.from_numpy(rho).to(dev)
+    out = {"workload": name, "n": n, "box": box, "sigma_g": w["sigma_g"], "precision": "mixed", "steps": args.steps}
+    res = {}
+    for mode in (0, 1):
+        rec = binding.Recon(n, binding.Config(precision=binding.MIXED, mass_update=mode), device=dev)
+        for _ in range(args.warmup):
+            rec.solve(rho_d, box)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            phi, delta, st = rec.solve(rho_d, box)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        key = "mass_update" if mode else "cic_gather"
+        out[key] = {"wall_s": round(wall, 4), "vcycles_total": st["vcycles_total"], "alpha": st["alpha"],
+                    "rms_sigma_first": st["rms_sigma"][0], "rms_sigma_last": st["rms_sigma"][-1],
+                    "mean_M_last": st["kappa"][-1]}
+        res[mode] = (phi, delta)
+        log("%s: %.3f s, %d V-cycles" % (key, wall, st["vcycles_total"]))
+        if mode == 1:
+            h = box / n
+            phi_g = (phi / (h * h)).contiguous()
+            f = phi_g.clone()
+            rec.mass_change(phi_g, rho_d, f)  # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10
+            e0.record()
+            for _ in range(reps):
+                rec.mass_change(phi_g, rho_d, f)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = 128 * n ** 3 / (ms * 1e-3) / 1e9
+            out["mass_change_kernels"] = {"ms": round(ms, 3), "alg_bytes_per_node": 128, "GBps": round(gbs, 1),
+                                          "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                                          "note": "two gather passes, once per outer step"}
+        del rec
+        torch.cuda.empty_cache()
+    d0, d1 = (res[m][1].double() for m in (0, 1))
+    out["rel_l2_delta_r_update_vs_gather"] = float(torch.linalg.norm(d1 - d0) / torch.linalg.norm(d0))
+    out["corr_delta_r_update_vs_gather"] = float(torch.corrcoef(torch.stack([d0.flatten(), d1.flatten()]))[0, 1])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +193,9 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="counter run: one plain 1 GiB copy (calibration) and one fused sweep per precision at 512^3")
     ap.add_argument("--stream", action="store_true", help="only the streaming-bandwidth ceilings of this GPU")
+    ap.add_argument("--mass-update", action="store_true",
+                    help="the paper's mass update (App. A) against the per-step CIC gather on lognormal512_mild, "
+                         "mixed precision, and the bandwidth of its two kernels")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (one process per GPU; --gpus %d is not supported, "
@@ -170,6 +227,10 @@ def main():
         print(json.dumps({"probe": "copy 1 GiB + fused sweep f32 + fused sweep f64", "n": n,
                           "copy_bytes_read": n ** 3 * 8, "copy_bytes_written": n ** 3 * 8,
                           "sweep_alg_bytes_f32": 16 * n ** 3, "sweep_alg_bytes_f64": 32 * n ** 3}), flush=True)
+        return
+
+    if args.mass_update:
+        mass_update_bench(torch, binding, inputs, args)
         return
 
     w = inputs.WORKLOADS[args.workload]
