@@ -128,6 +128,52 @@ def stream_ceilings(torch, dev, reps=10):
     return out
 
 
+def quality_bench(torch, binding, inputs):
+    """Sec. III on stand-in data: Zel'dovich inputs at 256^3 (600 Mpc/h, cells of
+    2.34 Mpc/h) with the linear density -div Psi known exactly.  The cross-
+    correlation r(k) and the propagator C(k) of the nonlinear (CIC) and the
+    reconstructed density with the linear field (mixed precision), for rms
+    displacements of 1.5 and 3.5 cells; on the 3.5-cell input (where the
+    compression limiter engages) with 20 outer steps, the sweeps xi_m in (1/5,
+    1/10, 1/20) at v_m = 10 and v_m in (5, 10, 20) at xi_m = 1/10 (App. B).
+    Diagnostics on the host (numpy)."""
+    from paper_1611_09638_amd import diagnostics as dg
+    n, box = 256, 600.0
+    dev = torch.device("cuda:0")
+    out = {"quality": "Zel'dovich stand-in for Sec. III", "n": n, "box": box, "precision": "mixed", "shells": 16}
+    for rms in (1.5, 3.5):
+        psi = inputs.zeldovich_displacement(n, box, rms, 31)
+        dl = dg.linear_density(psi)
+        pos = torch.from_numpy(inputs.particles_from_displacement(psi, box)).to(dev)
+        del psi
+        runs = [("default", {})]
+        if rms == 3.5:
+            runs = [("xi_m=%g" % x, dict(xi_m=x, max_outer=20)) for x in (0.2, 0.1, 0.05)]
+            runs += [("v_m=%g" % v, dict(v_m=v, max_outer=20)) for v in (5.0, 20.0)]
+            runs += [("xi_m=0.1,10 steps", {})]
+        rec = binding.Recon(n, binding.Config(precision=binding.MIXED), device=dev)
+        nl = dg.propagator(rec.cic(pos, box).cpu().numpy() - 1.0, dl, box, 16)
+        del rec
+        block = {"k": [round(x, 4) for x in nl["k"]], "nonlinear": {"r": [round(x, 4) for x in nl["r"]],
+                                                                   "C": [round(x, 4) for x in nl["C"]]}}
+        for label, kw in runs:
+            rec = binding.Recon(n, binding.Config(precision=binding.MIXED, **kw), device=dev)
+            t0 = time.perf_counter()
+            _, dr, st = rec.solve_particles(pos, box, want_phi=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            q = dg.propagator(dr.cpu().numpy(), dl, box, 16)
+            block[label] = {"r": [round(x, 4) for x in q["r"]], "C": [round(x, 4) for x in q["C"]],
+                            "wall_s": round(wall, 3), "outer_steps": st["outer_steps"],
+                            "rms_sigma_last": st["rms_sigma"][-1], "min_lambda0": st["min_lambda0"],
+                            "alpha_last": st["alpha"][-3:]}
+            log("rms %.1f %s: %.2f s, rms(Sigma) %.3g" % (rms, label, wall, st["rms_sigma"][-1]))
+            del rec
+            torch.cuda.empty_cache()
+        out["rms_%g_cells" % rms] = block
+    print(json.dumps(out), flush=True)
+
+
 def mass_update_bench(torch, binding, inputs, args):
     """Mixed solves of lognormal512_mild with M gathered by CIC every step and
     with the paper's mass update, and the time of the update's two kernels
@@ -193,6 +239,9 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="counter run: one plain 1 GiB copy (calibration) and one fused sweep per precision at 512^3")
     ap.add_argument("--stream", action="store_true", help="only the streaming-bandwidth ceilings of this GPU")
+    ap.add_argument("--quality", action="store_true",
+                    help="the paper's quality measures (Sec. III) on Zel'dovich inputs at 256^3: r(k) and the "
+                         "propagator of the nonlinear and reconstructed fields, and the xi_m / v_m sweeps")
     ap.add_argument("--mass-update", action="store_true",
                     help="the paper's mass update (App. A) against the per-step CIC gather on lognormal512_mild, "
                          "mixed precision, and the bandwidth of its two kernels")
@@ -231,6 +280,9 @@ def main():
 
     if args.mass_update:
         mass_update_bench(torch, binding, inputs, args)
+        return
+    if args.quality:
+        quality_bench(torch, binding, inputs)
         return
 
     w = inputs.WORKLOADS[args.workload]
