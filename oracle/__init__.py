@@ -59,7 +59,7 @@ class OrcConfig(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("record_tape", ctypes.c_int), ("solver", ctypes.c_int), ("warm_start", ctypes.c_int),
-        ("mass_update", ctypes.c_int),
+        ("mass_update", ctypes.c_int), ("particle_deposit", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
         ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
         ("a_min", ctypes.c_double),
@@ -99,6 +99,7 @@ class Config:
     solver: int = 0  # 0: V-cycle-preconditioned CG, 1: plain V-cycle iteration
     warm_start: int = 1  # start each linear solve from the previous outer step's solution
     mass_update: int = 0  # 1: carry M by the exact mass change of App. A instead of re-gathering it
+    particle_deposit: int = 0  # particle input, 1: deposit at the Lagrangian positions every step
     tol: float = 1e-10
     outer_tol: float = 0.0
     xi_m: float = 0.1
@@ -152,6 +153,9 @@ def lib():
             "orc_choose_step": (i, [d, d, i, ctypes.POINTER(OrcConfig), d]),
             "orc_choose_step_mass": (i, [d, d, d, d, i, ctypes.POINTER(OrcConfig), d]),
             "orc_full_operator": (None, [d, d, d, i, d]),
+            "orc_invert_map": (i, [d, i, d, ctypes.c_long, d, i, dbl]),
+            "orc_deposit_xi": (None, [d, ctypes.c_long, i, d]),
+            "orc_solve_particles": (i, [fp, ll, i, dbl, ctypes.POINTER(OrcConfig), d, d, ctypes.POINTER(OrcStats)]),
             "orc_delta_r": (None, [d, i, d]),
             "orc_solve": (i, [d, i, dbl, ctypes.POINTER(OrcConfig), d, d, ctypes.POINTER(OrcStats)]),
             "orc_lambda_min": (dbl, [d]),
@@ -377,6 +381,43 @@ def backward(grad_delta, grad_phi, box: float, cfg: Config | None = None) -> np.
     if rc:
         raise OracleError(rc)
     return out
+
+
+def invert_map(phi, y, xi0=None, max_iter: int = 100, tol: float = 1e-12):
+    """Lagrangian positions xi (np x 3, grid units) with x(xi) = y for the
+    continuous map x = xi + trilinear(D_c phi); Newton from xi0 (default y)."""
+    phi = _f64(phi)
+    y = _f64(y)
+    xi = (y if xi0 is None else _f64(xi0)).copy()
+    rc = lib().orc_invert_map(_p(phi), phi.shape[0], _p(y), y.shape[0], _p(xi), max_iter, tol)
+    if rc:
+        raise OracleError(rc)
+    return xi
+
+
+def deposit_xi(xi, n: int) -> np.ndarray:
+    """CIC deposit of the particles at Lagrangian positions xi, n^3/np each."""
+    xi = _f64(xi)
+    M = np.empty((n, n, n))
+    lib().orc_deposit_xi(_p(xi), xi.shape[0], n, _p(M))
+    return M
+
+
+def solve_particles(pos, n: int, box: float, cfg: Config | None = None, raise_on_error: bool = True):
+    """Forward reconstruction from float32 particle positions [np, 3] in [0, box)."""
+    cfg = cfg or Config()
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    phi = np.empty((n, n, n))
+    dr = np.empty((n, n, n))
+    st = OrcStats()
+    c = cfg.c()
+    rc = lib().orc_solve_particles(pos.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), pos.shape[0], n, box,
+                                   ctypes.byref(c), _p(phi), _p(dr), ctypes.byref(st))
+    if rc and raise_on_error:
+        raise OracleError(rc)
+    out = st.to_dict()
+    out["status"] = rc
+    return phi, dr, out
 
 
 def solve(rho, box: float, cfg: Config | None = None, raise_on_error: bool = True):

@@ -41,6 +41,11 @@
  *     tol ||b||_2; u made mean-free at the end.
  *   - step: alpha = 2^-j, first j with I + Hess(phi + alpha dphi) positive
  *     definite at every node (Sylvester) and max |alpha D_c dphi| <= s_max.
+ *   - optional particle deposit (particle_deposit = 1, particle input): each
+ *     step, every particle's Lagrangian position xi_p with x(xi_p) = y_p is
+ *     found by Newton's method on the continuous map x(xi) = xi + S(xi), S the
+ *     trilinear interpolant of the node shifts D_c phi, and M is the CIC
+ *     deposit of the particles at xi_p with weight n^3 / N_p (mass exact).
  *   - optional mass update of App. A (mass_update = 1): M is carried from step
  *     to step as M' = M + alpha L_full[dphi], with L_full f = div(M e^-1 grad f)
  *     (Eq. elliptic_diff) discretised in flux form (below), and the step must
@@ -71,6 +76,8 @@ typedef struct {
     int solver;
     int warm_start;
     int mass_update; /* 0: M from the CIC gather each step; 1: M += alpha L_full[dphi] */
+    int particle_deposit; /* particle input: 0 CIC onto the grid once, then the gather;
+                             1 deposit the particles at their Lagrangian positions each step */
     double tol;
     double outer_tol;
     double xi_m, v_m;
@@ -391,6 +398,130 @@ void orc_smooth(const double *f, int n, double c0, double *out)
 }
 
 /* ------------------------------------------------ source of Eq. (elliptic) */
+
+/* --------------------------------- particles at their Lagrangian positions */
+
+/* Node shifts s_n = D_c phi_n (the displacement x_n - n), three per node. */
+static void node_shifts(const double *phi, int n, double *s)
+{
+    #pragma omp parallel for
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) displacement(phi, n, i, j, k, s + 3 * at(n, i, j, k));
+}
+
+/* The continuous map x(xi) = xi + S(xi), S the trilinear interpolant of the
+ * node shifts (periodic), at one point, with its derivative dx/dxi in the
+ * cell of xi (the derivative of the interpolant from the side floor() picks). */
+static void map_eval(const double *s, int n, const double xi[3], double x[3], double J[3][3])
+{
+    int f[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double fl = floor(xi[a]);
+        f[a] = (int)fl;
+        t[a] = xi[a] - fl;
+    }
+    for (int a = 0; a < 3; ++a) {
+        x[a] = xi[a];
+        for (int b = 0; b < 3; ++b) J[a][b] = a == b ? 1.0 : 0.0;
+    }
+    for (int c = 0; c < 8; ++c) {
+        int o[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+        double w[3], dw[3];
+        for (int a = 0; a < 3; ++a) {
+            w[a] = o[a] ? t[a] : 1.0 - t[a];
+            dw[a] = o[a] ? 1.0 : -1.0;
+        }
+        const double *sc = s + 3 * at(n, f[0] + o[0], f[1] + o[1], f[2] + o[2]);
+        double wc = w[0] * w[1] * w[2];
+        double g[3] = {dw[0] * w[1] * w[2], w[0] * dw[1] * w[2], w[0] * w[1] * dw[2]};
+        for (int b = 0; b < 3; ++b) {
+            x[b] += wc * sc[b];
+            for (int a = 0; a < 3; ++a) J[b][a] += g[a] * sc[b];
+        }
+    }
+}
+
+/* max_a |x(xi) - y| with each component taken modulo the box (nearest image). */
+static double map_residual(const double *s, int n, const double xi[3], const double y[3], double r[3], double J[3][3])
+{
+    double x[3], mx = 0.0;
+    map_eval(s, n, xi, x, J);
+    for (int a = 0; a < 3; ++a) {
+        double d = x[a] - y[a];
+        d -= n * floor(d / n + 0.5);
+        r[a] = d;
+        if (fabs(d) > mx) mx = fabs(d);
+    }
+    return mx;
+}
+
+/* Lagrangian positions of particles (the mapping x = xi + grad phi inverted):
+ * for each particle at y (grid units) find xi with x(xi) = y modulo the box by
+ * Newton steps xi -= t J^-1 (x(xi) - y), t = 1 halved (at most 30 times) while
+ * the step does not reduce max |x(xi) - y|.  xi holds the starts on entry and
+ * the solutions on exit, wrapped into [0, n).  ORC_E_NO_CONVERGENCE if a
+ * particle is not within tol after max_iter steps. */
+int orc_invert_map(const double *phi, int n, const double *y, long np, double *xi, int max_iter, double tol)
+{
+    double *s = (double *)malloc(sizeof(double) * 3 * cube(n));
+    node_shifts(phi, n, s);
+    int failed = 0;
+    #pragma omp parallel for reduction(| : failed)
+    for (long p = 0; p < np; ++p) {
+        double *q = xi + 3 * p;
+        const double *yp = y + 3 * p;
+        double r[3], J[3][3], inv[3][3];
+        double res = map_residual(s, n, q, yp, r, J);
+        int it = 0;
+        while (res > tol && it < max_iter) {
+            ++it;
+            inverse3(J, inv);
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = inv[a][0] * r[0] + inv[a][1] * r[1] + inv[a][2] * r[2];
+            double step = 1.0, trial[3], rt[3], Jt[3][3], rest = res;
+            for (int h = 0; h <= 30; ++h, step *= 0.5) {
+                for (int a = 0; a < 3; ++a) trial[a] = q[a] - step * d[a];
+                rest = map_residual(s, n, trial, yp, rt, Jt);
+                if (rest < res) break;
+            }
+            if (!(rest < res)) break; /* no descent: give up on this particle */
+            for (int a = 0; a < 3; ++a) {
+                q[a] = trial[a];
+                r[a] = rt[a];
+                for (int b = 0; b < 3; ++b) J[a][b] = Jt[a][b];
+            }
+            res = rest;
+        }
+        for (int a = 0; a < 3; ++a) q[a] -= n * floor(q[a] / n);
+        if (!(res <= tol)) failed = 1;
+    }
+    free(s);
+    return failed ? ORC_E_NO_CONVERGENCE : ORC_OK;
+}
+
+/* Mass per curvilinear cell from particles at Lagrangian positions xi (grid
+ * units, [0, n)): CIC deposit in xi-space, n^3 / np per particle (mean 1). */
+void orc_deposit_xi(const double *xi, long np, int n, double *M)
+{
+    memset(M, 0, sizeof(double) * cube(n));
+    double wp = (double)cube(n) / (double)np;
+    for (long p = 0; p < np; ++p) {
+        int f[3];
+        double t[3];
+        for (int a = 0; a < 3; ++a) {
+            double fl = floor(xi[3 * p + a]);
+            f[a] = (int)fl;
+            t[a] = xi[3 * p + a] - fl;
+        }
+        for (int c = 0; c < 8; ++c) {
+            int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+            double w = (o0 ? t[0] : 1.0 - t[0]) * (o1 ? t[1] : 1.0 - t[1]) * (o2 ? t[2] : 1.0 - t[2]);
+            M[at(n, f[0] + o0, f[1] + o1, f[2] + o2)] += wp * w;
+        }
+    }
+}
 
 /* t = Sigma + C + E at every node, Sigma = mean(M) - M (App. A).
  * Returns rho_bar = mean(M). */
@@ -851,6 +982,7 @@ void orc_config_default(orc_config *c)
     c->solver = 0;
     c->warm_start = 1;
     c->mass_update = 0;
+    c->particle_deposit = 0;
     c->tol = 1e-10;
     c->outer_tol = 0.0;
     c->xi_m = 0.1;
@@ -913,12 +1045,15 @@ void orc_tape_clear(void)
     memset(&g_tape, 0, sizeof(g_tape));
 }
 
-/* Full forward reconstruction.  phi_out in (box/n)^2 units (length^2),
- * delta_out dimensionless.  Either output may be NULL. */
-int orc_solve(const double *rho, int n, double box, const orc_config *cfg, double *phi_out, double *delta_out,
-              orc_stats *st)
+/* Full forward reconstruction, from a density grid (rho) or, with
+ * particle_deposit, from particles (pos, np: float positions in [0, box)).
+ * phi_out in (box/n)^2 units (length^2), delta_out dimensionless.  Either
+ * output may be NULL. */
+static int solve_core(const double *rho, const float *pos, long long np, int n, double box, const orc_config *cfg,
+                      double *phi_out, double *delta_out, orc_stats *st)
 {
-    if (!rho || n <= 0 || box <= 0 || !cfg || cfg->tol <= 0) return ORC_E_ARG;
+    if ((!rho && !pos) || n <= 0 || box <= 0 || !cfg || cfg->tol <= 0) return ORC_E_ARG;
+    if (pos && (np <= 0 || cfg->mass_update || cfg->record_tape)) return ORC_E_ARG;
     if (orc_num_levels(n, cfg->coarse_n) < 1) return ORC_E_ARG;
     if (cfg->max_outer > ORC_MAX_STEPS) return ORC_E_ARG;
     if (cfg->mass_update && cfg->record_tape) return ORC_E_ARG; /* no reverse mode for the mass update */
@@ -930,17 +1065,33 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
     double *u = (double *)malloc(sizeof(double) * N3);
     double *dphi = (double *)malloc(sizeof(double) * N3);
     double *D = cfg->mass_update ? (double *)malloc(sizeof(double) * N3) : NULL;
+    /* particle deposit: positions in grid units and their Lagrangian positions
+     * (at phi = 0 the map is the identity) */
+    double *y = NULL, *xi = NULL;
+    if (pos) {
+        y = (double *)malloc(sizeof(double) * 3 * np);
+        xi = (double *)malloc(sizeof(double) * 3 * np);
+        for (long long p = 0; p < 3 * np; ++p) y[p] = xi[p] = (double)pos[p] * ((double)n / box);
+    }
     orc_stats local;
     if (!st) st = &local;
     memset(st, 0, sizeof(*st));
     if (cfg->record_tape) orc_tape_clear();
 
-    int status = orc_normalize(rho, n, m);
+    int status = pos ? ORC_OK : orc_normalize(rho, n, m);
     if (status == ORC_OK) {
         for (int it = 0; it < cfg->max_outer; ++it) {
             /* the CIC gather each step, or (mass update) only at phi = 0, where it
              * gives M = m, after which M is carried by the update below */
-            if (!cfg->mass_update || it == 0) orc_meshmass(phi, m, n, M);
+            if (pos) {
+                /* the particles at their Lagrangian positions, warm-started from
+                 * the previous step's */
+                status = orc_invert_map(phi, n, y, np, xi, 100, 1e-12);
+                if (status != ORC_OK) break;
+                orc_deposit_xi(xi, np, n, M);
+            } else if (!cfg->mass_update || it == 0) {
+                orc_meshmass(phi, m, n, M);
+            }
             double rho_bar = field_mean(M, n);
             double ss = 0.0;
             {
@@ -988,7 +1139,12 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
     if (status == ORC_OK && st->outer_steps == cfg->max_outer) {
         /* mass deviation left after the last step (the carried M under the
          * mass update) */
-        if (!cfg->mass_update) orc_meshmass(phi, m, n, M);
+        if (pos) {
+            status = orc_invert_map(phi, n, y, np, xi, 100, 1e-12);
+            if (status == ORC_OK) orc_deposit_xi(xi, np, n, M);
+        } else if (!cfg->mass_update) {
+            orc_meshmass(phi, m, n, M);
+        }
         double rho_bar = field_mean(M, n);
         for (long p = 0; p < N3; ++p) b[p] = rho_bar - M[p];
         st->rms_sigma[cfg->max_outer] = sqrt(field_dot(b, b, n) / (double)N3);
@@ -1016,7 +1172,31 @@ int orc_solve(const double *rho, int n, double box, const orc_config *cfg, doubl
     free(u);
     free(dphi);
     free(D);
+    free(y);
+    free(xi);
     return status;
+}
+
+int orc_solve(const double *rho, int n, double box, const orc_config *cfg, double *phi_out, double *delta_out,
+              orc_stats *st)
+{
+    if (!rho || (cfg && cfg->particle_deposit)) return ORC_E_ARG;
+    return solve_core(rho, NULL, 0, n, box, cfg, phi_out, delta_out, st);
+}
+
+/* Forward reconstruction from particles: CIC onto the grid once, or, with
+ * particle_deposit, the particles deposited at their Lagrangian positions
+ * every step. */
+int orc_solve_particles(const float *pos, long long np, int n, double box, const orc_config *cfg, double *phi_out,
+                        double *delta_out, orc_stats *st)
+{
+    if (!pos || np <= 0 || n <= 0 || box <= 0 || !cfg) return ORC_E_ARG;
+    if (cfg->particle_deposit) return solve_core(NULL, pos, np, n, box, cfg, phi_out, delta_out, st);
+    double *rho = (double *)malloc(sizeof(double) * cube(n));
+    int rc = orc_cic_particles(pos, np, n, box, rho);
+    if (rc == ORC_OK) rc = solve_core(rho, NULL, 0, n, box, cfg, phi_out, delta_out, st);
+    free(rho);
+    return rc;
 }
 
 int orc_tape_steps(void) { return g_tape.steps; }
