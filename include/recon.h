@@ -71,6 +71,11 @@ typedef struct recon_config {
                            paper's update M' = M + alpha div(M e^-1 grad dphi) (App. A, Eq.
                            elliptic_diff), and steps must also keep M' > 0.  No reverse mode:
                            record_tape must be 0 (0)                                        */
+    int particle_deposit; /* particle input only (recon_solve_particles): 1 deposits the particles
+                           by CIC at their Lagrangian positions on the deformed mesh every step
+                           (xi_p with xi_p + grad phi(xi_p) = y_p, by Newton from the previous
+                           step's); 0 assigns them to the grid once.  Needs up to n^3
+                           particles, mass_update = 0 and record_tape = 0 (0)               */
     int fixed_cycles;   /* > 0: every linear solve runs exactly this many V-cycles, ignoring tol
                            (makes the forward a smooth map for finite differences) (0)      */
     int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
@@ -260,6 +265,20 @@ int recon_stage_pd_count(recon_ctx *ctx, const double *phi, const double *dphi, 
  * in flux form (it sums to zero).  phi, M, f, out: device n^3 FP64; out must
  * not alias the inputs.  Uses library-owned scratch fields of the context. */
 int recon_stage_mass_change(recon_ctx *ctx, const double *phi, const double *M, const double *f, double *out);
+
+/* Lagrangian positions of particles on the deformed mesh of phi (Sec. II):
+ * xi (device, 3 np FP64, in/out: the start of Newton's method on entry, the
+ * solution in grid units [0, n) on exit) with x(xi) = y, y = pos n / box
+ * (pos: device float32 np x 3 in [0, box)), where x = xi + trilinear
+ * interpolant of the node shifts D_c phi.  *failed (host) = particles not
+ * located to 1e-12 cells.  Uses library-owned scratch fields. */
+int recon_stage_invert_map(recon_ctx *ctx, const double *phi, const float *pos, long long np, double box, double *xi,
+                           double *failed);
+
+/* M (device n^3 FP64) = CIC deposit of np particles at Lagrangian positions
+ * xi (device 3 np FP64, grid units), n^3 / np each; coordinates that are not
+ * finite or beyond 1e9 cells are skipped. */
+int recon_stage_deposit_xi(recon_ctx *ctx, const double *xi, long long np, double *M);
 
 /* delta = -laplacian phi (7-point, Eq. rec). */
 int recon_stage_delta_r(recon_ctx *ctx, const double *phi, double *delta);

@@ -29,7 +29,8 @@ class CConfig(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
-        ("warm_start", ctypes.c_int), ("mass_update", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
+        ("warm_start", ctypes.c_int), ("mass_update", ctypes.c_int), ("particle_deposit", ctypes.c_int),
+        ("fixed_cycles", ctypes.c_int),
         ("record_tape", ctypes.c_int),
         ("tape_fp32", ctypes.c_int), ("profile", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
@@ -73,6 +74,7 @@ class Config:
     solver: int = SOLVER_PCG
     warm_start: int = 1
     mass_update: int = 0
+    particle_deposit: int = 0
     fixed_cycles: int = 0
     record_tape: int = 0
     tape_fp32: int = 0
@@ -141,6 +143,8 @@ def lib():
         "recon_stage_pd_count": (i, [vp, vp, vp, i, i, i, pd, vp, vp]),
         "recon_stage_delta_r": (i, [vp, vp, vp]),
         "recon_stage_mass_change": (i, [vp, vp, vp, vp, vp]),
+        "recon_stage_invert_map": (i, [vp, vp, vp, ll, d, vp, pd]),
+        "recon_stage_deposit_xi": (i, [vp, vp, ll, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -362,6 +366,22 @@ class Recon:
         self._check(lib().recon_stage_mass_change(self._ctx, _ptr(phi, torch.float64), _ptr(M, torch.float64),
                                                   _ptr(f, torch.float64), _ptr(out)))
         return out
+
+    def invert_map(self, phi, pos, box, xi0=None):
+        """(xi, failures): Lagrangian positions (np x 3, grid units) of float32
+        particles pos on the deformed mesh of phi, by Newton from xi0 (default
+        pos n / box)."""
+        xi = (pos.double() * (self.n / box)).contiguous() if xi0 is None else xi0.clone()
+        bad = ctypes.c_double()
+        self._check(lib().recon_stage_invert_map(self._ctx, _ptr(phi, torch.float64), _ptr(pos, torch.float32),
+                                                 pos.shape[0], float(box), _ptr(xi, torch.float64),
+                                                 ctypes.byref(bad)))
+        return xi, int(bad.value)
+
+    def deposit_xi(self, xi):
+        M = self._field()
+        self._check(lib().recon_stage_deposit_xi(self._ctx, _ptr(xi, torch.float64), xi.shape[0], _ptr(M)))
+        return M
 
     def delta_r(self, phi):
         d = self._field()

@@ -67,6 +67,14 @@ struct MassTensor {
 };
 hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
                               double *out, int n, hipStream_t s);
+// Particles at their Lagrangian positions (particles.hip): xi = pos n / box;
+// Newton for x(xi) = y from the xi given (node shifts of phi in sx, sy, sz;
+// partial K=1: particles not within tol); CIC of the particles at xi into M
+// (zeroed first), n^3 / np each.
+hipError_t launch_init_xi(const float *pos, long long np, int n, double box, double *xi, hipStream_t s);
+hipError_t launch_invert_map(const double *phi, const float *pos, long long np, int n, double box, double *xi,
+                             double *sx, double *sy, double *sz, int max_iter, double tol, Part &p, hipStream_t s);
+hipError_t launch_deposit_xi(const double *xi, long long np, int n, double *M, hipStream_t s);
 // y += alpha x, X = double or float; with alpha_dev != null alpha is read there
 template <typename X>
 hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s,

@@ -1,0 +1,211 @@
+// Particles deposited on the deformed mesh at their Lagrangian positions: for
+// a particle at y, the position xi with x(xi) = y under the moving-mesh map
+// x = xi + grad phi (Sec. II), taken continuous as xi + S(xi) with S the
+// trilinear interpolant of the node shifts s_n = D_c phi_n; then its mass is
+// assigned to the xi-grid by CIC.  The mass per curvilinear cell is then
+// exactly the particles' (no interpolation of an Eulerian density).
+//
+// xi is found by Newton's method, xi <- xi - t J^-1 (x(xi) - y) with J the
+// derivative of the map in the cell of xi, t = 1 halved (at most 30 times)
+// until max |x(xi) - y| (nearest periodic image) decreases; it starts from the
+// previous outer step's xi, which is close because the steps are small.
+
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace recon {
+
+namespace {
+
+// s_n = D_c phi_n, one field per component
+__global__ void k_node_shifts(const double *__restrict__ phi, double *__restrict__ sx, double *__restrict__ sy,
+                              double *__restrict__ sz, int n, int ipb)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (k >= n || j >= n) return;
+    const int jp = wrapc(j + 1, n), jm = wrapc(j - 1, n), kp = wrapc(k + 1, n), km = wrapc(k - 1, n);
+    const int i0 = blockIdx.z * ipb, i1 = min(n, i0 + ipb);
+    for (int i = i0; i < i1; ++i) {
+        const size_t c = lin(i, j, k, n);
+        sx[c] = 0.5 * (phi[lin(wrapc(i + 1, n), j, k, n)] - phi[lin(wrapc(i - 1, n), j, k, n)]);
+        sy[c] = 0.5 * (phi[lin(i, jp, k, n)] - phi[lin(i, jm, k, n)]);
+        sz[c] = 0.5 * (phi[lin(i, j, kp, n)] - phi[lin(i, j, km, n)]);
+    }
+}
+
+struct Shifts {
+    const double *x, *y, *z;
+};
+
+// x(xi) - y (nearest image) and its derivative; returns max |x(xi) - y|, or
+// +inf (r and J untouched) for a point that is not finite or absurdly far out,
+// so that no cell index is ever formed from it
+__device__ double map_residual(const Shifts &s, int n, const double xi[3], const double y[3], double r[3],
+                               double J[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!(fabs(xi[a]) < 1.0e9)) return INFINITY;
+    int f[3];
+    double t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double fl = floor(xi[a]);
+        t[a] = xi[a] - fl;
+        int fi = (int)fl % n;
+        f[a] = fi < 0 ? fi + n : fi;
+    }
+    double x[3] = {xi[0], xi[1], xi[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) J[a][b] = a == b ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+        const double w0 = o0 ? t[0] : 1.0 - t[0], w1 = o1 ? t[1] : 1.0 - t[1], w2 = o2 ? t[2] : 1.0 - t[2];
+        const double d0 = o0 ? 1.0 : -1.0, d1 = o1 ? 1.0 : -1.0, d2 = o2 ? 1.0 : -1.0;
+        const size_t q = lin(o0 ? wrapc(f[0] + 1, n) : f[0], o1 ? wrapc(f[1] + 1, n) : f[1],
+                             o2 ? wrapc(f[2] + 1, n) : f[2], n);
+        const double sc[3] = {s.x[q], s.y[q], s.z[q]};
+        const double wc = w0 * w1 * w2;
+        const double g[3] = {d0 * w1 * w2, w0 * d1 * w2, w0 * w1 * d2};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            x[b] += wc * sc[b];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) J[b][a] += g[a] * sc[b];
+        }
+    }
+    double mx = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double d = x[a] - y[a];
+        d -= n * floor(d / n + 0.5);
+        r[a] = d;
+        mx = fmax(mx, fabs(d));
+    }
+    return mx;
+}
+
+__global__ void k_init_xi(const float *__restrict__ pos, long long np, double toc, double *__restrict__ xi)
+{
+    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < 3 * np; p += 256LL * gridDim.x)
+        xi[p] = (double)pos[p] * toc;
+}
+
+__global__ void k_invert(const float *__restrict__ pos, long long np, double toc, Shifts s, int n,
+                         double *__restrict__ xi, int max_iter, double tol, double *part)
+{
+    double bad[1] = {0.0};
+    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < np; p += 256LL * gridDim.x) {
+        double y[3], q[3], r[3], J[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            y[a] = (double)pos[3 * p + a] * toc;
+            q[a] = xi[3 * p + a];
+        }
+        double res = map_residual(s, n, q, y, r, J);
+        for (int it = 0; res > tol && it < max_iter; ++it) {
+            // d = J^-1 r by the adjugate
+            const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+            const double a00 = c00, a01 = J[0][2] * J[2][1] - J[0][1] * J[2][2], a02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+            const double a10 = c01, a11 = J[0][0] * J[2][2] - J[0][2] * J[2][0], a12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+            const double a20 = c02, a21 = J[0][1] * J[2][0] - J[0][0] * J[2][1], a22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            const double d[3] = {(a00 * r[0] + a01 * r[1] + a02 * r[2]) / det,
+                                 (a10 * r[0] + a11 * r[1] + a12 * r[2]) / det,
+                                 (a20 * r[0] + a21 * r[1] + a22 * r[2]) / det};
+            double step = 1.0, trial[3], rt[3], Jt[3][3], rest = res;
+            for (int h = 0; h <= 30; ++h, step *= 0.5) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) trial[a] = q[a] - step * d[a];
+                rest = map_residual(s, n, trial, y, rt, Jt);
+                if (rest < res) break;
+            }
+            if (!(rest < res)) break;  // no descent: left as a failure
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                q[a] = trial[a];
+                r[a] = rt[a];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) J[a][b] = Jt[a][b];
+            }
+            res = rest;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xi[3 * p + a] = q[a] - n * floor(q[a] / n);
+        if (!(res <= tol)) bad[0] += 1.0;
+    }
+    block_reduce_store<1, RED_SUM>(bad, part, blockIdx.x);
+}
+
+// CIC of the particles at xi (grid units, periodic), weight wp each; a
+// particle with a coordinate that is not finite or beyond 1e9 cells is skipped
+__global__ void k_deposit_xi(const double *__restrict__ xi, long long np, int n, double wp, double *__restrict__ M)
+{
+    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < np; p += 256LL * gridDim.x) {
+        if (!(fabs(xi[3 * p]) < 1.0e9 && fabs(xi[3 * p + 1]) < 1.0e9 && fabs(xi[3 * p + 2]) < 1.0e9)) continue;
+        int f[3];
+        double t[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double x = xi[3 * p + a];
+            const double fl = floor(x);
+            t[a] = x - fl;
+            int fi = (int)fl % n;
+            f[a] = fi < 0 ? fi + n : fi;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+            const double w = (o0 ? t[0] : 1.0 - t[0]) * (o1 ? t[1] : 1.0 - t[1]) * (o2 ? t[2] : 1.0 - t[2]);
+            atomicAdd(&M[lin(o0 ? wrapc(f[0] + 1, n) : f[0], o1 ? wrapc(f[1] + 1, n) : f[1],
+                             o2 ? wrapc(f[2] + 1, n) : f[2], n)],
+                      wp * w);
+        }
+    }
+}
+
+int particle_blocks(long long np)
+{
+    long long b = (np + 255) / 256;
+    int nb = (int)(b < 8192 ? b : 8192);
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace
+
+hipError_t launch_init_xi(const float *pos, long long np, int n, double box, double *xi, hipStream_t s)
+{
+    k_init_xi<<<particle_blocks(3 * np), 256, 0, s>>>(pos, np, (double)n / box, xi);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_map(const double *phi, const float *pos, long long np, int n, double box, double *xi,
+                             double *sx, double *sy, double *sz, int max_iter, double tol, Part &p, hipStream_t s)
+{
+    Shape3 sh = shape3(n);
+    k_node_shifts<<<sh.grid, sh.block, 0, s>>>(phi, sx, sy, sz, n, sh.ipb);
+    const int nb = particle_blocks(np);
+    if (nb > kPartCap) return hipErrorInvalidValue;
+    k_invert<<<nb, 256, 0, s>>>(pos, np, (double)n / box, Shifts{sx, sy, sz}, n, xi, max_iter, tol, p.part);
+    p.blocks = nb;
+    p.k = 1;
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_xi(const double *xi, long long np, int n, double *M, hipStream_t s)
+{
+    hipError_t e = launch_zero(M, (long)n * n * n * 8, s);
+    if (e != hipSuccess) return e;
+    k_deposit_xi<<<particle_blocks(np), 256, 0, s>>>(xi, np, n, (double)n * n * n / (double)np, M);
+    return hipGetLastError();
+}
+
+}  // namespace recon

@@ -56,6 +56,7 @@ struct Layout {
     size_t lv32_a[kMaxLevels], lv32_u[kMaxLevels], lv32_b[kMaxLevels], lv32_res[kMaxLevels], lv32_tmp[kMaxLevels];
     size_t tape;
     size_t adj[8];
+    size_t xi;  // particle deposit: Lagrangian positions, 3 per particle (up to n^3 particles)
     int levels = 0;
 };
 
@@ -77,6 +78,8 @@ bool config_ok(const recon_config *c)
            c->n_pre <= 16 && c->n_post <= 16 && c->coarse_sweeps >= 0 && c->max_vcycles >= 1 &&
            c->max_halvings >= 0 && c->max_halvings <= 60 && c->fixed_cycles >= 0 && (c->warm_start == 0 || c->warm_start == 1) &&
            (c->mass_update == 0 || c->mass_update == 1) && !(c->mass_update && c->record_tape) &&
+           (c->particle_deposit == 0 || c->particle_deposit == 1) &&
+           !(c->particle_deposit && (c->record_tape || c->mass_update)) &&
            (c->tape_fp32 == 0 || c->tape_fp32 == 1) && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
            (c->solver == RECON_SOLVER_PCG || c->solver == RECON_SOLVER_VCYCLE) && c->tol > 0 && c->outer_tol >= 0 &&
            c->xi_m >= 0 && c->v_m > 0 && c->smooth_center >= 0 && c->smooth_center <= 1 && c->s_max > 0 &&
@@ -152,6 +155,7 @@ bool make_layout(int n, const recon_config *cfg, Layout &Lo)
             Lo.adj[5] = Lo.dphi;
         }
     }
+    Lo.xi = cfg->particle_deposit ? take(3 * f64) : (size_t)-1;
     Lo.total = off;
     return true;
 }
@@ -182,6 +186,11 @@ struct recon_ctx {
     double tape_alpha[RECON_MAX_STEPS];
     double input_mean = 0.0;
     double box = 0.0;
+    // particle deposit: the particles of the running solve and their
+    // Lagrangian positions (null outside such a solve)
+    const float *part_pos = nullptr;
+    long long part_np = 0;
+    double *xi = nullptr;
     double last_tol = 0.0;
     int tape_valid = 0;
     char err[512];
@@ -228,6 +237,11 @@ int fetch(recon_ctx *ctx, const int *ops, double *out)
     for (int c = 0; c < K; ++c) out[c] = ctx->host_scal[c];
     return RECON_OK;
 }
+
+// Newton's method for the particles' Lagrangian positions: at most this many
+// steps, to this max-norm residual in cells.
+constexpr int kInvertIters = 100;
+constexpr double kInvertTol = 1e-12;
 
 // The device scalars of the conjugate-gradient loop (KS_* in kernels.h) sit at
 // this offset of ctx->scal; fetch_krylov copies all of them to the host.
@@ -598,13 +612,35 @@ int normalize(recon_ctx *ctx, const double *rho, double *m, double *mean_out)
     return RECON_OK;
 }
 
+// Particle deposit: M = CIC of the particles at their Lagrangian positions for
+// the current phi, found by Newton from the previous ones; the node shifts
+// go into r, z, p (idle between solves).
+int deposit_particles(recon_ctx *ctx)
+{
+    double v[1];
+    HIPCHK(launch_invert_map(ctx->phi, ctx->part_pos, ctx->part_np, ctx->n, ctx->box, ctx->xi, ctx->r, ctx->z, ctx->p,
+                             kInvertIters, kInvertTol, ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    if (v[0] != 0.0)
+        return fail(ctx, RECON_E_NO_CONVERGENCE, "%.0f particles not located on the deformed mesh", v[0]);
+    HIPCHK(launch_deposit_xi(ctx->xi, ctx->part_np, ctx->n, ctx->M, ctx->stream));
+    return RECON_OK;
+}
+
 // rho_bar = mean(M), rms(Sigma) and the source for the current phi; M is
-// gathered on the deformed mesh when `gather`, else (mass update) kept.
+// gathered on the deformed mesh when `gather` (or, in a particle-deposit solve,
+// deposited from the particles), else (mass update) kept.
 int mass_state(recon_ctx *ctx, double *rho_bar, double *rms, double *mean_t, bool gather = true)
 {
     double v[2];
-    if (gather) HIPCHK(launch_meshmass(ctx->phi, ctx->m, ctx->M, ctx->n, ctx->part, ctx->stream));
-    else HIPCHK(launch_sum(ctx->M, ctx->n3, ctx->part, ctx->stream));
+    if (ctx->part_pos) {
+        TRY(deposit_particles(ctx));
+        HIPCHK(launch_sum(ctx->M, ctx->n3, ctx->part, ctx->stream));
+    } else if (gather) {
+        HIPCHK(launch_meshmass(ctx->phi, ctx->m, ctx->M, ctx->n, ctx->part, ctx->stream));
+    } else {
+        HIPCHK(launch_sum(ctx->M, ctx->n3, ctx->part, ctx->stream));
+    }
     TRY(fetch_sum(ctx, v));
     *rho_bar = v[0] / (double)ctx->n3;
     HIPCHK(launch_source(ctx->phi, ctx->M, *rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part,
@@ -786,6 +822,7 @@ int recon_config_default(recon_config *c)
     c->solver = RECON_SOLVER_PCG;
     c->warm_start = 1;
     c->mass_update = 0;
+    c->particle_deposit = 0;
     c->fixed_cycles = 0;
     c->record_tape = 0;
     c->tape_fp32 = 0;
@@ -839,6 +876,7 @@ int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace,
     ctx->p = wsp<double>(ctx, lo.p);
     ctx->q = wsp<double>(ctx, lo.q);
     ctx->dphi = wsp<double>(ctx, lo.dphi);
+    ctx->xi = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.xi) : nullptr;
     ctx->L64.L = ctx->L32.L = lo.levels;
     int nl = n;
     for (int l = 0; l < lo.levels; ++l, nl /= 2) {
@@ -915,6 +953,8 @@ int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double
     if (!density || n != ctx->n || !(box > 0.0) || !(tol >= 0.0))
         return fail(ctx, RECON_E_ARG, "bad argument (density %p, n %d vs %d, box %g, tol %g)", (const void *)density,
                     n, ctx->n, box, tol);
+    if (ctx->cfg.particle_deposit)
+        return fail(ctx, RECON_E_ARG, "particle_deposit needs particle input (recon_solve_particles)");
     recon_stats local;
     recon_stats *st = stats ? stats : &local;
     std::memset(st, 0, sizeof(*st));
@@ -954,7 +994,18 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
     ctx->input_mean = mean;
     ctx->box = box;
     ctx->last_tol = tol > 0.0 ? tol : ctx->cfg.tol;
-    TRY(forward(ctx, box, ctx->last_tol, phi_out, delta_r_out, st));
+    if (ctx->cfg.particle_deposit) {
+        // every step deposits the particles at their Lagrangian positions,
+        // starting from xi = y (the map is the identity at phi = 0)
+        if (np > ctx->n3) return fail(ctx, RECON_E_ARG, "the particle deposit takes at most n^3 particles");
+        ctx->part_pos = pos;
+        ctx->part_np = np;
+        HIPCHK(launch_init_xi(pos, np, ctx->n, box, ctx->xi, ctx->stream));
+    }
+    const int rc = forward(ctx, box, ctx->last_tol, phi_out, delta_r_out, st);
+    ctx->part_pos = nullptr;
+    ctx->part_np = 0;
+    TRY(rc);
     HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev1));
     float ms = 0.0f;
@@ -1257,6 +1308,28 @@ int recon_stage_mass_change(recon_ctx *ctx, const double *phi, const double *M, 
     if (!phi || !M || !f || !out) return fail(ctx, RECON_E_ARG, "null array");
     const MassTensor K{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q};
     HIPCHK(launch_mass_change(phi, M, f, K, out, ctx->n, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_invert_map(recon_ctx *ctx, const double *phi, const float *pos, long long np, double box, double *xi,
+                           double *failed)
+{
+    TRY(check_ctx(ctx));
+    if (!phi || !pos || np <= 0 || !(box > 0.0) || !xi || !failed) return fail(ctx, RECON_E_ARG, "bad arguments");
+    double v[1];
+    HIPCHK(launch_invert_map(phi, pos, np, ctx->n, box, xi, ctx->r, ctx->z, ctx->p, kInvertIters, kInvertTol,
+                             ctx->part, ctx->stream));
+    TRY(fetch_sum(ctx, v));
+    *failed = v[0];
+    return RECON_OK;
+}
+
+int recon_stage_deposit_xi(recon_ctx *ctx, const double *xi, long long np, double *M)
+{
+    TRY(check_ctx(ctx));
+    if (!xi || np <= 0 || !M) return fail(ctx, RECON_E_ARG, "bad arguments");
+    HIPCHK(launch_deposit_xi(xi, np, ctx->n, M, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }
