@@ -59,7 +59,7 @@ class OrcConfig(ctypes.Structure):
         ("max_outer", ctypes.c_int), ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("record_tape", ctypes.c_int), ("solver", ctypes.c_int), ("warm_start", ctypes.c_int),
-        ("mass_update", ctypes.c_int), ("particle_deposit", ctypes.c_int),
+        ("mass_update", ctypes.c_int), ("particle_deposit", ctypes.c_int), ("full_operator", ctypes.c_int),
         ("tol", ctypes.c_double), ("outer_tol", ctypes.c_double), ("xi_m", ctypes.c_double),
         ("v_m", ctypes.c_double), ("smooth_center", ctypes.c_double), ("s_max", ctypes.c_double),
         ("a_min", ctypes.c_double),
@@ -100,6 +100,7 @@ class Config:
     warm_start: int = 1  # start each linear solve from the previous outer step's solution
     mass_update: int = 0  # 1: carry M by the exact mass change of App. A instead of re-gathering it
     particle_deposit: int = 0  # particle input, 1: deposit at the Lagrangian positions every step
+    full_operator: int = 0  # 1: solve with div(M e^-1 grad .) instead of the x ~ xi operator
     tol: float = 1e-10
     outer_tol: float = 0.0
     xi_m: float = 0.1
@@ -147,6 +148,7 @@ def lib():
             "orc_prolong_add": (None, [d, d, i]),
             "orc_num_levels": (i, [i, i]),
             "orc_mg_solve": (i, [d, d, i, ctypes.POINTER(OrcConfig), d, d]),
+            "orc_mg_solve_full": (i, [d, d, d, i, ctypes.POINTER(OrcConfig), d, d, d]),
             "orc_is_pd": (i, [d, i]),
             "orc_count_not_pd": (ctypes.c_long, [d, i]),
             "orc_max_shift": (dbl, [d, i]),
@@ -281,6 +283,21 @@ def prolong_add(u, e) -> np.ndarray:
     e = _f64(e)
     lib().orc_prolong_add(_p(u), _p(e), u.shape[0])
     return u
+
+
+def mg_solve_full(a, phi, b, cfg: Config | None = None, u0=None):
+    """(u, cycles, rel): div(a e^-1 grad u) = b on the mesh of phi, preconditioned
+    by the x ~ xi V-cycle of a."""
+    cfg = cfg or Config()
+    a, phi, b = _f64(a), _f64(phi), _f64(b)
+    u = np.empty_like(b)
+    rel = ctypes.c_double()
+    c = cfg.c()
+    rc = lib().orc_mg_solve_full(_p(a), _p(phi), _p(b), a.shape[0], ctypes.byref(c),
+                                 None if u0 is None else _p(_f64(u0)), _p(u), ctypes.byref(rel))
+    if rc < 0:
+        raise OracleError(rc)
+    return u, rc, rel.value
 
 
 def mg_solve(a, b, cfg: Config | None = None):

@@ -41,6 +41,10 @@
  *     tol ||b||_2; u made mean-free at the end.
  *   - step: alpha = 2^-j, first j with I + Hess(phi + alpha dphi) positive
  *     definite at every node (Sylvester) and max |alpha D_c dphi| <= s_max.
+ *   - optional exact-Jacobian solve (full_operator = 1): the linear system is
+ *     div(M e^-1 grad u) = b, the operator of Eq. elliptic_diff on the current
+ *     mesh instead of the x ~ xi one, solved by the same Krylov iteration
+ *     with the x ~ xi V-cycle as preconditioner.
  *   - optional particle deposit (particle_deposit = 1, particle input): each
  *     step, every particle's Lagrangian position xi_p with x(xi_p) = y_p is
  *     found by Newton's method on the continuous map x(xi) = xi + S(xi), S the
@@ -78,6 +82,8 @@ typedef struct {
     int mass_update; /* 0: M from the CIC gather each step; 1: M += alpha L_full[dphi] */
     int particle_deposit; /* particle input: 0 CIC onto the grid once, then the gather;
                              1 deposit the particles at their Lagrangian positions each step */
+    int full_operator; /* 1: the linear solve uses div(M e^-1 grad .) (no x ~ xi), with the
+                          x ~ xi V-cycle as its preconditioner */
     double tol;
     double outer_tol;
     double xi_m, v_m;
@@ -447,6 +453,8 @@ static void map_eval(const double *s, int n, const double xi[3], double x[3], do
 static double map_residual(const double *s, int n, const double xi[3], const double y[3], double r[3], double J[3][3])
 {
     double x[3], mx = 0.0;
+    for (int a = 0; a < 3; ++a)
+        if (!(fabs(xi[a]) < 1.0e9)) return HUGE_VAL; /* not finite or absurdly far: no descent */
     map_eval(s, n, xi, x, J);
     for (int a = 0; a < 3; ++a) {
         double d = x[a] - y[a];
@@ -800,8 +808,27 @@ int orc_vcycle(const double *a0, const double *r, int n, const orc_config *cfg, 
  * solver 1: plain V-cycle iteration u += V(b - A u).
  * Returns the number of V-cycles (>= 0) or a negative error; *rel receives
  * the final true relative residual. */
-int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_config *cfg, const double *u0,
-                      double *u_out, double *rel)
+/* out = L x: the x ~ xi operator of coefficient a0, or (phi_full given) the
+ * full operator div(a0 e^-1 grad x) on the mesh of phi_full. */
+static void krylov_apply(const double *phi_full, const double *a0, const double *x, int n, double a_min, double *out)
+{
+    if (phi_full) orc_full_operator(phi_full, a0, x, n, out);
+    else orc_apply(x, a0, n, 1.0, a_min, out);
+}
+
+/* out = b - L x */
+static void krylov_residual(const double *phi_full, const double *a0, const double *b, const double *x, int n,
+                            double a_min, double *out)
+{
+    long N3 = cube(n);
+    krylov_apply(phi_full, a0, x, n, a_min, out);
+    for (long p = 0; p < N3; ++p) out[p] = b[p] - out[p];
+}
+
+/* The linear solve with the operator of krylov_apply (phi_full NULL: x ~ xi),
+ * preconditioned by the x ~ xi V-cycle of a0. */
+int orc_mg_solve_full(const double *a0, const double *phi_full, const double *b0, int n, const orc_config *cfg,
+                      const double *u0, double *u_out, double *rel)
 {
     mg_t mg;
     int rc = mg_alloc(&mg, a0, n, cfg);
@@ -819,7 +846,7 @@ int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_confi
     int cycles = 0;
     memcpy(r, b0, sizeof(double) * N3);
     if (u0 && bn > 0.0) {
-        orc_residual(u0, a0, b0, n, 1.0, cfg->a_min, z);
+        krylov_residual(phi_full, a0, b0, u0, n, cfg->a_min, z);
         if (norm2(z, n) < bn) {
             memcpy(u, u0, sizeof(double) * N3);
             memcpy(r, z, sizeof(double) * N3);
@@ -829,10 +856,10 @@ int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_confi
         status = 0;
     } else if (cfg->solver == 1) {
         for (cycles = 1; cycles <= cfg->max_vcycles; ++cycles) {
-            orc_residual(u, a0, b0, n, 1.0, cfg->a_min, r);
+            krylov_residual(phi_full, a0, b0, u, n, cfg->a_min, r);
             precondition(&mg, r, z);
             for (long i = 0; i < N3; ++i) u[i] += z[i];
-            orc_residual(u, a0, b0, n, 1.0, cfg->a_min, r);
+            krylov_residual(phi_full, a0, b0, u, n, cfg->a_min, r);
             double rn = norm2(r, n);
             if (!isfinite(rn)) break;
             if (rn <= cfg->tol * bn) {
@@ -846,7 +873,7 @@ int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_confi
         memcpy(p, z, sizeof(double) * N3);
         double rz = field_dot(r, z, n);
         while (cycles <= cfg->max_vcycles) {
-            orc_apply(p, a0, n, 1.0, cfg->a_min, q);
+            krylov_apply(phi_full, a0, p, n, cfg->a_min, q);
             double pq = field_dot(p, q, n);
             double alpha = rz / pq;
             memcpy(r_old, r, sizeof(double) * N3);
@@ -871,7 +898,7 @@ int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_confi
     }
     double mu = field_mean(u, n);
     for (long i = 0; i < N3; ++i) u_out[i] = u[i] - mu;
-    orc_residual(u_out, a0, b0, n, 1.0, cfg->a_min, r);
+    krylov_residual(phi_full, a0, b0, u_out, n, cfg->a_min, r);
     *rel = bn > 0.0 ? norm2(r, n) / bn : 0.0;
     free(u);
     free(r);
@@ -881,6 +908,12 @@ int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_confi
     free(r_old);
     mg_free(&mg);
     return status;
+}
+
+int orc_mg_solve_from(const double *a0, const double *b0, int n, const orc_config *cfg, const double *u0,
+                      double *u_out, double *rel)
+{
+    return orc_mg_solve_full(a0, NULL, b0, n, cfg, u0, u_out, rel);
 }
 
 int orc_mg_solve(const double *a0, const double *b0, int n, const orc_config *cfg, double *u_out, double *rel)
@@ -983,6 +1016,7 @@ void orc_config_default(orc_config *c)
     c->warm_start = 1;
     c->mass_update = 0;
     c->particle_deposit = 0;
+    c->full_operator = 0;
     c->tol = 1e-10;
     c->outer_tol = 0.0;
     c->xi_m = 0.1;
@@ -1107,7 +1141,8 @@ static int solve_core(const double *rho, const float *pos, long long np, int n, 
             orc_source(phi, M, n, cfg->xi_m, cfg->v_m, cfg->smooth_center, b);
             double rel = 0.0;
             /* warm start: the previous step's solution (the steps are small) */
-            int cyc = orc_mg_solve_from(M, b, n, cfg, (cfg->warm_start && it > 0) ? u : NULL, u, &rel);
+            int cyc = orc_mg_solve_full(M, cfg->full_operator ? phi : NULL, b, n, cfg,
+                                        (cfg->warm_start && it > 0) ? u : NULL, u, &rel);
             st->rel_residual[it] = rel;
             if (cyc < 0) {
                 status = cyc;
