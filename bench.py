@@ -263,6 +263,41 @@ def mass_update_bench(torch, binding, inputs, args):
     print(json.dumps(out), flush=True)
 
 
+def full_operator_bench(torch, binding, inputs, args):
+    """Mixed solves of the workload with the x ~ xi operator and with the
+    exact-Jacobian operator in the Krylov loop (full_operator = 1): wall time,
+    V-cycles and rms(Sigma) per step.  The full operator's kernels are timed
+    from a kernel trace of this run: the Krylov product q = L_K p with p.q
+    reads six K fields and p and writes q (64 algorithmic B/node), the Krylov
+    residual reads six K fields, u and b and writes r and its FP32 copy
+    (76 B/node)."""
+    name = args.workload
+    w = inputs.WORKLOADS[name]
+    n, box = w["n"], w["box"]
+    rho = inputs.lognormal_density(n, box, w["sigma_g"], w["seed"])
+    dev = torch.device("cuda:0")
+    rho_d = torch.from_numpy(rho).to(dev)
+    out = {"workload": name, "n": n, "box": box, "sigma_g": w["sigma_g"], "precision": "mixed", "steps": args.steps}
+    for mode in (0, 1):
+        rec = binding.Recon(n, binding.Config(precision=binding.MIXED, full_operator=mode), device=dev)
+        for _ in range(args.warmup):
+            rec.solve(rho_d, box)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            phi, delta, st = rec.solve(rho_d, box)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        key = "full_operator" if mode else "x_approx_xi"
+        out[key] = {"wall_s": round(wall, 4), "vcycles": st["vcycles"], "vcycles_total": st["vcycles_total"],
+                    "alpha": st["alpha"], "rms_sigma": [round(x, 5) for x in st["rms_sigma"]],
+                    "min_lambda0": st["min_lambda0"]}
+        log("%s: %.3f s, %d V-cycles, rms(Sigma) %.4f" % (key, wall, st["vcycles_total"], st["rms_sigma"][-1]))
+        del rec
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +315,8 @@ def main():
     ap.add_argument("--particle-deposit", action="store_true",
                     help="particles deposited at their Lagrangian positions every step against one CIC onto the "
                          "grid, on 512^3 Zel'dovich particles, mixed precision")
+    ap.add_argument("--full-operator", action="store_true",
+                    help="the exact-Jacobian operator in the linear solve against x ~ xi on --workload (mixed)")
     ap.add_argument("--mass-update", action="store_true",
                     help="the paper's mass update (App. A) against the per-step CIC gather on lognormal512_mild, "
                          "mixed precision, and the bandwidth of its two kernels")
@@ -318,6 +355,9 @@ def main():
 
     if args.mass_update:
         mass_update_bench(torch, binding, inputs, args)
+        return
+    if args.full_operator:
+        full_operator_bench(torch, binding, inputs, args)
         return
     if args.quality:
         quality_bench(torch, binding, inputs)

@@ -76,6 +76,11 @@ typedef struct recon_config {
                            (xi_p with xi_p + grad phi(xi_p) = y_p, by Newton from the previous
                            step's); 0 assigns them to the grid once.  Needs up to n^3
                            particles, mass_update = 0 and record_tape = 0 (0)               */
+    int full_operator;  /* 1: the linear system of each step is the exact Jacobian of the mass
+                           map, div(M e^-1 grad u) = b on the current mesh (App. A, Eq.
+                           elliptic_diff, without x ~ xi), solved by the same Krylov loop with
+                           the x ~ xi V-cycle of M as its preconditioner; 6 more FP64 fields
+                           of workspace.  No reverse mode: record_tape must be 0 (0)        */
     int fixed_cycles;   /* > 0: every linear solve runs exactly this many V-cycles, ignoring tol
                            (makes the forward a smooth map for finite differences) (0)      */
     int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
@@ -244,6 +249,15 @@ int recon_stage_vcycle(recon_ctx *ctx, const void *a, const void *r, void *z, in
 int recon_stage_mg_solve(recon_ctx *ctx, const double *a, const double *b, double tol, double *u, int *cycles,
                          double *rel_residual);
 
+/* The linear solve of the exact-Jacobian mode: div(K grad u) = b with
+ * K = a e^-1, e = I + Hess phi (App. A, Eq. elliptic_diff without x ~ xi), in
+ * the flux form of recon_stage_mass_change, by the context's Krylov loop
+ * preconditioned by its x ~ xi V-cycle of a.  a, phi, b, u: n^3 FP64 device
+ * fields of the context's edge (b mean-free, a > 0, phi with e positive
+ * definite); u receives the mean-free solution.  Needs a context made with
+ * full_operator = 1; RECON_E_NO_CONVERGENCE as recon_stage_mg_solve. */
+int recon_stage_mg_solve_full(recon_ctx *ctx, const double *a, const double *phi, const double *b, double tol,
+                              double *u, int *cycles, double *rel_residual);
 /* First alpha = 2^-j keeping I + Hess(phi + alpha dphi) positive definite
  * everywhere with max |alpha D_c dphi| <= s_max (host output); returns
  * RECON_E_NOT_PD if none of j = 0..max_halvings does. */

@@ -30,6 +30,7 @@ class CConfig(ctypes.Structure):
         ("coarse_n", ctypes.c_int), ("coarse_sweeps", ctypes.c_int), ("max_vcycles", ctypes.c_int),
         ("max_halvings", ctypes.c_int), ("precision", ctypes.c_int), ("solver", ctypes.c_int),
         ("warm_start", ctypes.c_int), ("mass_update", ctypes.c_int), ("particle_deposit", ctypes.c_int),
+        ("full_operator", ctypes.c_int),
         ("fixed_cycles", ctypes.c_int),
         ("record_tape", ctypes.c_int),
         ("tape_fp32", ctypes.c_int), ("profile", ctypes.c_int),
@@ -75,6 +76,7 @@ class Config:
     warm_start: int = 1
     mass_update: int = 0
     particle_deposit: int = 0
+    full_operator: int = 0
     fixed_cycles: int = 0
     record_tape: int = 0
     tape_fp32: int = 0
@@ -139,6 +141,7 @@ def lib():
         "recon_stage_prolong_add": (i, [vp, vp, vp, i, i, i]),
         "recon_stage_vcycle": (i, [vp, vp, vp, vp, i]),
         "recon_stage_mg_solve": (i, [vp, vp, vp, d, vp, pi, pd]),
+        "recon_stage_mg_solve_full": (i, [vp, vp, vp, vp, d, vp, pi, pd]),
         "recon_stage_choose_step": (i, [vp, vp, vp, pd]),
         "recon_stage_pd_count": (i, [vp, vp, vp, i, i, i, pd, vp, vp]),
         "recon_stage_delta_r": (i, [vp, vp, vp]),
@@ -345,6 +348,16 @@ class Recon:
         rel = ctypes.c_double()
         self._check(lib().recon_stage_mg_solve(self._ctx, _ptr(a, torch.float64), _ptr(b, torch.float64),
                                                float(tol), _ptr(u), ctypes.byref(cyc), ctypes.byref(rel)))
+        return u, cyc.value, rel.value
+
+    def mg_solve_full(self, a, phi, b, tol=1e-10):
+        """div(a e^-1 grad u) = b on the mesh of phi (needs full_operator=1)."""
+        u = self._field()
+        cyc = ctypes.c_int()
+        rel = ctypes.c_double()
+        self._check(lib().recon_stage_mg_solve_full(self._ctx, _ptr(a, torch.float64), _ptr(phi, torch.float64),
+                                                    _ptr(b, torch.float64), float(tol), _ptr(u),
+                                                    ctypes.byref(cyc), ctypes.byref(rel)))
         return u, cyc.value, rel.value
 
     def choose_step(self, phi, dphi):

@@ -67,6 +67,13 @@ struct MassTensor {
 };
 hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
                               double *out, int n, hipStream_t s);
+// K = M e^-1 at every node; out = L_K f; q = L_K p with partial K=1 sum p.q;
+// r = b - L_K u (optional FP32 copy r32) with partial K=1 sum r^2
+hipError_t launch_mass_tensor(const double *phi, const double *M, const MassTensor &K, int n, hipStream_t s);
+hipError_t launch_full_apply(const MassTensor &K, const double *f, double *out, int n, hipStream_t s);
+hipError_t launch_full_apply_dot(const MassTensor &K, const double *pv, double *q, int n, Part &p, hipStream_t s);
+hipError_t launch_full_residual_norm(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
+                                     int n, Part &p, hipStream_t s);
 // Particles at their Lagrangian positions (particles.hip): xi = pos n / box;
 // Newton for x(xi) = y from the xi given (node shifts of phi in sx, sy, sz;
 // partial K=1: particles not within tol); CIC of the particles at xi into M
@@ -150,6 +157,10 @@ hipError_t launch_residual_norm(const double *u, const double *a, const double *
 // partials K=2: sum z*r, sum z*q (q may be null -> 0).  Z = double or float
 template <typename Z>
 hipError_t launch_dots_zr_zq(const Z *z, const double *r, const double *q, long n3, Part &p, hipStream_t s);
+// p = z + beta p (first: p = z); with ks != null and not first,
+// beta = -ks[KS_ALPHA] ks[KS_ZQ] / ks[KS_RZ_OLD]
+template <typename Z>
+hipError_t launch_update_p(const Z *z, double *pv, double beta, long n3, bool first, const double *ks, hipStream_t s);
 // p = z + beta p; q = A z + beta q (first: p = z, q = A z); partial K=1: sum p*q
 // beta from ks as for launch_direction25 when ks != null
 template <typename Z>

@@ -8,8 +8,9 @@
 //   cross:    sum_{mu != nu} [ K^{munu}_{n+mu} (f_{n+mu+nu} - f_{n+mu-nu})
 //                            - K^{munu}_{n-mu} (f_{n-mu+nu} - f_{n-mu-nu}) ] / 4
 // Two passes: K at every node (six fields, since e is symmetric), then the
-// 19-point application.  Both run once per outer step, so they gather from
-// L2 rather than stream through LDS.
+// 19-point application.  The same application, with a dot product or as a
+// residual, is the operator of the exact-Jacobian linear solve, where it runs
+// once per Krylov iteration; it gathers from L2.
 
 #include <hip/hip_runtime.h>
 
@@ -43,45 +44,107 @@ __global__ void k_mass_tensor(const double *__restrict__ phi, const double *__re
     }
 }
 
-__global__ void k_mass_change(MassTensor K, const double *__restrict__ f, double *__restrict__ out, int n, int ipb)
+// L_K f at one node, in the flux form above; fc receives f at the node
+__device__ inline double full_node(const MassTensor &K, const double *__restrict__ f, int i, int j, int k, int n,
+                                   double &fc)
+{
+    const int ip = wrapc(i + 1, n), im = wrapc(i - 1, n);
+    const int jp = wrapc(j + 1, n), jm = wrapc(j - 1, n), kp = wrapc(k + 1, n), km = wrapc(k - 1, n);
+    Stencil19 s;
+    load19(f, i, j, k, n, s);
+    fc = s.c;
+    const size_t c = lin(i, j, k, n);
+    const size_t xp = lin(ip, j, k, n), xm = lin(im, j, k, n);
+    const size_t yp = lin(i, jp, k, n), ym = lin(i, jm, k, n);
+    const size_t zp = lin(i, j, kp, n), zm = lin(i, j, km, n);
+    double acc = 0.0;
+    // diagonal fluxes, directions x, y, z
+    acc += 0.5 * (K.xx[c] + K.xx[xp]) * (s.xp - s.c) - 0.5 * (K.xx[xm] + K.xx[c]) * (s.c - s.xm);
+    acc += 0.5 * (K.yy[c] + K.yy[yp]) * (s.yp - s.c) - 0.5 * (K.yy[ym] + K.yy[c]) * (s.c - s.ym);
+    acc += 0.5 * (K.zz[c] + K.zz[zp]) * (s.zp - s.c) - 0.5 * (K.zz[zm] + K.zz[c]) * (s.c - s.zm);
+    // cross fluxes: direction mu of the difference, nu of the gradient
+    acc += 0.25 * (K.xy[xp] * (s.xpyp - s.xpym) - K.xy[xm] * (s.xmyp - s.xmym));  // mu = x, nu = y
+    acc += 0.25 * (K.xz[xp] * (s.xpzp - s.xpzm) - K.xz[xm] * (s.xmzp - s.xmzm));  // mu = x, nu = z
+    acc += 0.25 * (K.xy[yp] * (s.xpyp - s.xmyp) - K.xy[ym] * (s.xpym - s.xmym));  // mu = y, nu = x
+    acc += 0.25 * (K.yz[yp] * (s.ypzp - s.ypzm) - K.yz[ym] * (s.ymzp - s.ymzm));  // mu = y, nu = z
+    acc += 0.25 * (K.xz[zp] * (s.xpzp - s.xmzp) - K.xz[zm] * (s.xpzm - s.xmzm));  // mu = z, nu = x
+    acc += 0.25 * (K.yz[zp] * (s.ypzp - s.ymzp) - K.yz[zm] * (s.ypzm - s.ymzm));  // mu = z, nu = y
+    return acc;
+}
+
+enum FullMode { FULL_APPLY = 0, FULL_DOT = 1, FULL_RESID = 2 };
+
+// FULL_APPLY: out = L_K f.  FULL_DOT: out = L_K f with sum f (L_K f) (the
+// conjugate-gradient product q = A p with p.q).  FULL_RESID: out = b - L_K f
+// with sum out^2 and an optional FP32 copy (the Krylov residual).
+template <int MODE>
+__global__ void k_full_apply(MassTensor K, const double *__restrict__ f, const double *__restrict__ b,
+                             double *__restrict__ out, float *__restrict__ out32, int n, int ipb, double *part)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (k >= n || j >= n) return;
-    const int jp = wrapc(j + 1, n), jm = wrapc(j - 1, n), kp = wrapc(k + 1, n), km = wrapc(k - 1, n);
-    const int i0 = blockIdx.z * ipb, i1 = min(n, i0 + ipb);
-    for (int i = i0; i < i1; ++i) {
-        const int ip = wrapc(i + 1, n), im = wrapc(i - 1, n);
-        Stencil19 s;
-        load19(f, i, j, k, n, s);
-        const size_t c = lin(i, j, k, n);
-        const size_t xp = lin(ip, j, k, n), xm = lin(im, j, k, n);
-        const size_t yp = lin(i, jp, k, n), ym = lin(i, jm, k, n);
-        const size_t zp = lin(i, j, kp, n), zm = lin(i, j, km, n);
-        double acc = 0.0;
-        // diagonal fluxes, directions x, y, z
-        acc += 0.5 * (K.xx[c] + K.xx[xp]) * (s.xp - s.c) - 0.5 * (K.xx[xm] + K.xx[c]) * (s.c - s.xm);
-        acc += 0.5 * (K.yy[c] + K.yy[yp]) * (s.yp - s.c) - 0.5 * (K.yy[ym] + K.yy[c]) * (s.c - s.ym);
-        acc += 0.5 * (K.zz[c] + K.zz[zp]) * (s.zp - s.c) - 0.5 * (K.zz[zm] + K.zz[c]) * (s.c - s.zm);
-        // cross fluxes: direction mu of the difference, nu of the gradient
-        acc += 0.25 * (K.xy[xp] * (s.xpyp - s.xpym) - K.xy[xm] * (s.xmyp - s.xmym));  // mu = x, nu = y
-        acc += 0.25 * (K.xz[xp] * (s.xpzp - s.xpzm) - K.xz[xm] * (s.xmzp - s.xmzm));  // mu = x, nu = z
-        acc += 0.25 * (K.xy[yp] * (s.xpyp - s.xmyp) - K.xy[ym] * (s.xpym - s.xmym));  // mu = y, nu = x
-        acc += 0.25 * (K.yz[yp] * (s.ypzp - s.ypzm) - K.yz[ym] * (s.ymzp - s.ymzm));  // mu = y, nu = z
-        acc += 0.25 * (K.xz[zp] * (s.xpzp - s.xmzp) - K.xz[zm] * (s.xpzm - s.xmzm));  // mu = z, nu = x
-        acc += 0.25 * (K.yz[zp] * (s.ypzp - s.ymzp) - K.yz[zm] * (s.ypzm - s.ymzm));  // mu = z, nu = y
-        out[c] = acc;
+    double v[1] = {0.0};
+    if (k < n && j < n) {
+        const int i0 = blockIdx.z * ipb, i1 = min(n, i0 + ipb);
+        for (int i = i0; i < i1; ++i) {
+            const size_t c = lin(i, j, k, n);
+            double fc;
+            const double acc = full_node(K, f, i, j, k, n, fc);
+            if (MODE == FULL_RESID) {
+                const double rv = b[c] - acc;
+                out[c] = rv;
+                if (out32) out32[c] = (float)rv;
+                v[0] += rv * rv;
+            } else {
+                out[c] = acc;
+                if (MODE == FULL_DOT) v[0] += fc * acc;
+            }
+        }
     }
+    if (MODE != FULL_APPLY) block_reduce_store<1, RED_SUM>(v, part, block_row());
 }
 
 }  // namespace
 
-hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
-                              double *out, int n, hipStream_t s)
+hipError_t launch_mass_tensor(const double *phi, const double *M, const MassTensor &K, int n, hipStream_t s)
 {
     Shape3 sh = shape3(n);
     k_mass_tensor<<<sh.grid, sh.block, 0, s>>>(phi, M, K, n, sh.ipb);
-    k_mass_change<<<sh.grid, sh.block, 0, s>>>(K, f, out, n, sh.ipb);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_apply(const MassTensor &K, const double *f, double *out, int n, hipStream_t s)
+{
+    Shape3 sh = shape3(n);
+    k_full_apply<FULL_APPLY><<<sh.grid, sh.block, 0, s>>>(K, f, nullptr, out, nullptr, n, sh.ipb, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
+                              double *out, int n, hipStream_t s)
+{
+    hipError_t e = launch_mass_tensor(phi, M, K, n, s);
+    return e != hipSuccess ? e : launch_full_apply(K, f, out, n, s);
+}
+
+hipError_t launch_full_apply_dot(const MassTensor &K, const double *pv, double *q, int n, Part &p, hipStream_t s)
+{
+    Shape3 sh = shape3(n);
+    if (rows_of(sh) > kPartCap) return hipErrorInvalidValue;
+    k_full_apply<FULL_DOT><<<sh.grid, sh.block, 0, s>>>(K, pv, nullptr, q, nullptr, n, sh.ipb, p.part);
+    p.blocks = rows_of(sh);
+    p.k = 1;
+    return hipGetLastError();
+}
+
+hipError_t launch_full_residual_norm(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
+                                     int n, Part &p, hipStream_t s)
+{
+    Shape3 sh = shape3(n);
+    if (rows_of(sh) > kPartCap) return hipErrorInvalidValue;
+    k_full_apply<FULL_RESID><<<sh.grid, sh.block, 0, s>>>(K, u, b, r, r32, n, sh.ipb, p.part);
+    p.blocks = rows_of(sh);
+    p.k = 1;
     return hipGetLastError();
 }
 

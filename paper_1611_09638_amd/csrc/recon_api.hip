@@ -57,6 +57,7 @@ struct Layout {
     size_t tape;
     size_t adj[8];
     size_t xi;  // particle deposit: Lagrangian positions, 3 per particle (up to n^3 particles)
+    size_t K;   // exact-Jacobian solve: K = M e^-1, 6 fields
     int levels = 0;
 };
 
@@ -80,6 +81,7 @@ bool config_ok(const recon_config *c)
            (c->mass_update == 0 || c->mass_update == 1) && !(c->mass_update && c->record_tape) &&
            (c->particle_deposit == 0 || c->particle_deposit == 1) &&
            !(c->particle_deposit && (c->record_tape || c->mass_update)) &&
+           (c->full_operator == 0 || c->full_operator == 1) && !(c->full_operator && c->record_tape) &&
            (c->tape_fp32 == 0 || c->tape_fp32 == 1) && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
            (c->solver == RECON_SOLVER_PCG || c->solver == RECON_SOLVER_VCYCLE) && c->tol > 0 && c->outer_tol >= 0 &&
            c->xi_m >= 0 && c->v_m > 0 && c->smooth_center >= 0 && c->smooth_center <= 1 && c->s_max > 0 &&
@@ -156,6 +158,7 @@ bool make_layout(int n, const recon_config *cfg, Layout &Lo)
         }
     }
     Lo.xi = cfg->particle_deposit ? take(3 * f64) : (size_t)-1;
+    Lo.K = cfg->full_operator ? take(6 * f64) : (size_t)-1;
     Lo.total = off;
     return true;
 }
@@ -191,6 +194,8 @@ struct recon_ctx {
     const float *part_pos = nullptr;
     long long part_np = 0;
     double *xi = nullptr;
+    // exact-Jacobian solve: K = M e^-1 of the current step (six fields)
+    MassTensor Kf{};
     double last_tol = 0.0;
     int tape_valid = 0;
     char err[512];
@@ -358,8 +363,10 @@ hipError_t prolong_level(T *u, const T *e, int n, hipStream_t s, int variant = 0
 
 // r = b - A u on the fine level in FP64, its squared norm, and optionally r
 // in FP32 (the mixed preconditioner's input).
-hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const double *b, double *r, float *r32)
+hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const double *b, double *r, float *r32,
+                         const MassTensor *Kf = nullptr)
 {
+    if (Kf) return launch_full_residual_norm(*Kf, u, b, r, r32, ctx->n, ctx->part, ctx->stream);
     if (use_stream<double>(ctx->n))
         return launch_residual_norm25(u, a, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
     return launch_residual_norm(u, a, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
@@ -433,8 +440,11 @@ int precondition(recon_ctx *ctx)
 // Solve A(a0) u = b (b mean-free) into ctx->u; hierarchy must be built.  With
 // warm set, ctx->u holds the previous solution and is kept as the starting
 // guess when ||b - A u|| < ||b||; otherwise the solve starts from u = 0.
+// With Kf the operator is L_K = div(K grad .) instead (the exact Jacobian of
+// the mass map, K = M e^-1 filled by the caller), still preconditioned by the
+// x ~ xi V-cycle of a0.
 int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int *cycles_out, double *rel_out,
-             bool warm = false)
+             bool warm = false, const MassTensor *Kf = nullptr)
 {
     const int n = ctx->n;
     const long n3 = ctx->n3;
@@ -446,14 +456,14 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
     const double bn = std::sqrt(v[0]);
     bool started = false;
     if (warm && bn > 0.0) {
-        HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32));
+        HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32, Kf));
         TRY(fetch_sum(ctx, v));
         started = std::sqrt(v[0]) < bn;
     }
     if (!started) {
         // u = 0, so the residual kernel gives r = b
         HIPCHK(launch_zero(ctx->u, n3 * 8, ctx->stream));
-        HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32));
+        HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32, Kf));
     }
     int cycles = 0;
     int status = RECON_E_NO_CONVERGENCE;
@@ -467,7 +477,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             TRY(precondition(ctx));
             if (mixed) HIPCHK(launch_add_correction<float>(ctx->u, ctx->L32.u[0], n3, ctx->stream));
             else HIPCHK(launch_add_correction<double>(ctx->u, ctx->z, n3, ctx->stream));
-            HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32));
+            HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32, Kf));
             TRY(fetch_sum(ctx, v));
             const double rn = std::sqrt(v[0]);
             if (!std::isfinite(rn)) break;
@@ -496,7 +506,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         // stored in FP32 when the preconditioner is FP32.  The solution update
         // u += alpha p of one step is deferred into the next direction pass there
         // (it reads p anyway), and applied after the loop for the last step.
-        const bool stream = use_stream<double>(n);
+        const bool stream = use_stream<double>(n) && !Kf;
         double *pc = ctx->p, *pn = ctx->t;
         auto f32 = [](double *x) { return reinterpret_cast<float *>(x); };
         bool due = false;
@@ -511,6 +521,10 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
                                               ctx->part, ctx->stream));
                 due = false;
                 std::swap(pc, pn);
+            } else if (Kf) {
+                if (mixed) HIPCHK(launch_update_p<float>(ctx->L32.u[0], pc, 0.0, n3, first, ks, ctx->stream));
+                else HIPCHK(launch_update_p<double>(ctx->z, pc, 0.0, n3, first, ks, ctx->stream));
+                HIPCHK(launch_full_apply_dot(*Kf, pc, ctx->q, n, ctx->part, ctx->stream));
             } else if (mixed) {
                 HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, pc, ctx->q, 0.0, n, ctx->cfg.a_min, first, ks,
                                                ctx->part, ctx->stream));
@@ -546,7 +560,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
     TRY(fetch_sum(ctx, v));
     HIPCHK(launch_fill(ctx->scal + 16, 1, v[0] / (double)n3, ctx->stream));
     HIPCHK(launch_add_scalar(ctx->u, ctx->scal + 16, -1.0, 1.0, n3, ctx->stream));
-    HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, nullptr));
+    HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, nullptr, Kf));
     TRY(fetch_sum(ctx, v));
     const double rel = bn > 0.0 ? std::sqrt(v[0]) / bn : 0.0;
     if (cycles_out) *cycles_out = cycles;
@@ -669,9 +683,12 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
     // is carried by M += alpha D.  D goes into m's field, which is not read
     // again in that mode, and K into six fields idle between the solve and
     // the next step's source.
+    // With the exact-Jacobian solve, K = M e^-1 of the step sits in its own
+    // fields, and the mass update reuses it (same mesh, same M).
     const bool carry = c.mass_update != 0;
+    const bool full = c.full_operator != 0;
     double *D = ctx->m;
-    const MassTensor K{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q};
+    const MassTensor K = full ? ctx->Kf : MassTensor{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q};
     int it = 0;
     for (; it < c.max_outer; ++it) {
         double rho_bar, rms, mean_t;
@@ -682,14 +699,16 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         if (rms <= c.outer_tol) break;
         HIPCHK(launch_smooth(ctx->t, ctx->b, ctx->n, c.smooth_center, mean_t, ctx->stream));
         TRY(build_hierarchy(ctx, ctx->M));
+        if (full) HIPCHK(launch_mass_tensor(ctx->phi, ctx->M, K, ctx->n, ctx->stream));
         int cyc = 0;
         double rel = 0.0;
-        TRY(mg_solve(ctx, ctx->M, ctx->b, tol, &cyc, &rel, c.warm_start && it > 0));
+        TRY(mg_solve(ctx, ctx->M, ctx->b, tol, &cyc, &rel, c.warm_start && it > 0, full ? &K : nullptr));
         st->vcycles[it] = cyc;
         st->vcycles_total += cyc;
         st->rel_residual[it] = rel;
         HIPCHK(launch_smooth(ctx->u, ctx->dphi, ctx->n, c.smooth_center, 0.0, ctx->stream));
-        if (carry) HIPCHK(launch_mass_change(ctx->phi, ctx->M, ctx->dphi, K, D, ctx->n, ctx->stream));
+        if (carry && full) HIPCHK(launch_full_apply(K, ctx->dphi, D, ctx->n, ctx->stream));
+        else if (carry) HIPCHK(launch_mass_change(ctx->phi, ctx->M, ctx->dphi, K, D, ctx->n, ctx->stream));
         double alpha = 0.0;
         TRY(choose_step(ctx, ctx->phi, ctx->dphi, &alpha, carry ? ctx->M : nullptr, carry ? D : nullptr));
         if (carry) HIPCHK(launch_axpy(ctx->M, D, alpha, n3, ctx->stream));
@@ -823,6 +842,7 @@ int recon_config_default(recon_config *c)
     c->warm_start = 1;
     c->mass_update = 0;
     c->particle_deposit = 0;
+    c->full_operator = 0;
     c->fixed_cycles = 0;
     c->record_tape = 0;
     c->tape_fp32 = 0;
@@ -877,6 +897,10 @@ int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace,
     ctx->q = wsp<double>(ctx, lo.q);
     ctx->dphi = wsp<double>(ctx, lo.dphi);
     ctx->xi = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.xi) : nullptr;
+    if (ctx->cfg.full_operator) {
+        double *k0 = wsp<double>(ctx, lo.K);
+        ctx->Kf = MassTensor{k0, k0 + ctx->n3, k0 + 2 * ctx->n3, k0 + 3 * ctx->n3, k0 + 4 * ctx->n3, k0 + 5 * ctx->n3};
+    }
     ctx->L64.L = ctx->L32.L = lo.levels;
     int nl = n;
     for (int l = 0; l < lo.levels; ++l, nl /= 2) {
@@ -1274,6 +1298,21 @@ int recon_stage_mg_solve(recon_ctx *ctx, const double *a, const double *b, doubl
     HIPCHK(launch_copy(ctx->M, a, ctx->n3, ctx->stream));
     TRY(build_hierarchy(ctx, ctx->M));
     TRY(mg_solve(ctx, ctx->M, b, tol, cycles, rel_residual));
+    HIPCHK(launch_copy(u, ctx->u, ctx->n3, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
+int recon_stage_mg_solve_full(recon_ctx *ctx, const double *a, const double *phi, const double *b, double tol,
+                              double *u, int *cycles, double *rel_residual)
+{
+    TRY(check_ctx(ctx));
+    if (!a || !phi || !b || !u || !(tol > 0.0)) return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
+    HIPCHK(launch_copy(ctx->M, a, ctx->n3, ctx->stream));
+    TRY(build_hierarchy(ctx, ctx->M));
+    HIPCHK(launch_mass_tensor(phi, ctx->M, ctx->Kf, ctx->n, ctx->stream));
+    TRY(mg_solve(ctx, ctx->M, b, tol, cycles, rel_residual, false, &ctx->Kf));
     HIPCHK(launch_copy(u, ctx->u, ctx->n3, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;

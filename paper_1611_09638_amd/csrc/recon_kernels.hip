@@ -862,6 +862,13 @@ hipError_t launch_update_pq(const Z *z, const double *a, double *pv, double *q, 
     return hipGetLastError();
 }
 
+template <typename Z>
+hipError_t launch_update_p(const Z *z, double *pv, double beta, long n3, bool first, const double *ks, hipStream_t s)
+{
+    k_update_p<Z><<<flat_blocks(n3), 256, 0, s>>>(z, pv, beta, first ? 1 : 0, n3, ks);
+    return hipGetLastError();
+}
+
 template <bool U>
 __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, const double *__restrict__ pv,
                             const double *__restrict__ q, double alpha, float *__restrict__ r32, long n3, double *part,
@@ -923,6 +930,7 @@ hipError_t launch_add_correction(double *u, const Z *z, long n3, hipStream_t s)
     template hipError_t launch_dots_zr_zq<T>(const T *, const double *, const double *, long, Part &, hipStream_t); \
     template hipError_t launch_update_pq<T>(const T *, const double *, double *, double *, double, int, double,     \
                                             bool, const double *, Part &, hipStream_t);                           \
+    template hipError_t launch_update_p<T>(const T *, double *, double, long, bool, const double *, hipStream_t);  \
     template hipError_t launch_add_correction<T>(double *, const T *, long, hipStream_t);                        \
 
 RECON_INSTANTIATE(double)
