@@ -165,6 +165,8 @@ def lib():
             "orc_triad_at": (None, [d, i, i, i, i, d]),
             "orc_tape_steps": (i, []),
             "orc_backward": (i, [d, d, dbl, ctypes.POINTER(OrcConfig), d]),
+            "orc_backward_particles": (i, [d, d, dbl, ctypes.POINTER(OrcConfig), d]),
+            "orc_tape_particles": (ctypes.c_long, []),
             "orc_eig_min_vec": (None, [d, d, d]),
             "orc_tape_clear": (None, []),
         }
@@ -395,6 +397,24 @@ def backward(grad_delta, grad_phi, box: float, cfg: Config | None = None) -> np.
     out = np.empty_like(gd)
     c = cfg.c()
     rc = lib().orc_backward(_p(gd), None if gp is None else _p(gp), box, ctypes.byref(c), _p(out))
+    if rc:
+        raise OracleError(rc)
+    return out
+
+
+def backward_particles(grad_delta, grad_phi, box: float, cfg: Config | None = None) -> np.ndarray:
+    """dL/d(positions) [np, 3] for the last solve_particles run with
+    particle_deposit=1 and record_tape=1 (the adjoint through the inversion
+    of the map and the xi-space deposit)."""
+    cfg = cfg or Config()
+    gd = _f64(grad_delta)
+    gp = None if grad_phi is None else _f64(grad_phi)
+    npart = lib().orc_tape_particles()
+    if npart <= 0:
+        raise OracleError(-5)
+    out = np.empty((npart, 3))
+    c = cfg.c()
+    rc = lib().orc_backward_particles(_p(gd), None if gp is None else _p(gp), box, ctypes.byref(c), _p(out))
     if rc:
         raise OracleError(rc)
     return out

@@ -1068,6 +1068,8 @@ typedef struct {
     double alpha[ORC_MAX_STEPS];
     double *m;   /* normalised input density */
     double mean; /* mean of the raw input density */
+    double *y;   /* particle deposit: the particle positions in grid units (3 per particle) */
+    long np;
 } orc_tape;
 
 static orc_tape g_tape;
@@ -1076,6 +1078,7 @@ void orc_tape_clear(void)
 {
     for (int s = 0; s < g_tape.steps; ++s) free(g_tape.u[s]);
     free(g_tape.m);
+    free(g_tape.y);
     memset(&g_tape, 0, sizeof(g_tape));
 }
 
@@ -1087,7 +1090,7 @@ static int solve_core(const double *rho, const float *pos, long long np, int n, 
                       double *phi_out, double *delta_out, orc_stats *st)
 {
     if ((!rho && !pos) || n <= 0 || box <= 0 || !cfg || cfg->tol <= 0) return ORC_E_ARG;
-    if (pos && (np <= 0 || cfg->mass_update || cfg->record_tape)) return ORC_E_ARG;
+    if (pos && (np <= 0 || cfg->mass_update)) return ORC_E_ARG;
     if (orc_num_levels(n, cfg->coarse_n) < 1) return ORC_E_ARG;
     if (cfg->max_outer > ORC_MAX_STEPS) return ORC_E_ARG;
     if (cfg->mass_update && cfg->record_tape) return ORC_E_ARG; /* no reverse mode for the mass update */
@@ -1193,9 +1196,15 @@ static int solve_core(const double *rho, const float *pos, long long np, int n, 
             for (long p = 0; p < N3; ++p) phi_out[p] = phi[p] * h * h;
         if (cfg->record_tape) {
             g_tape.n = n;
-            g_tape.m = m;
-            g_tape.mean = field_mean(rho, n);
-            m = NULL;
+            if (pos) {
+                g_tape.y = y;
+                g_tape.np = (long)np;
+                y = NULL;
+            } else {
+                g_tape.m = m;
+                g_tape.mean = field_mean(rho, n);
+                m = NULL;
+            }
         }
     } else if (cfg->record_tape) {
         orc_tape_clear();
@@ -1247,6 +1256,9 @@ int orc_tape_steps(void) { return g_tape.steps; }
  * the linear solve differentiated as exact: for u = A^+ b with A symmetric,
  * lambda = A^+ ubar gives bbar = lambda and, per face f of coefficient
  * c_f = max(a_min, (M_n + M_nb)/2), cbar_f = (lambda_nb - lambda_n)(u_nb - u_n).
+ * With particles deposited at their Lagrangian positions, M = CIC_xi(xi) with
+ * xi = X^-1(y; D_c phi) instead, and the gradient is taken with respect to
+ * the particle positions y (deposit_adjoint).
  * ====================================================================== */
 
 /* Smallest eigenvalue and its unit eigenvector, cyclic Jacobi with the
@@ -1337,13 +1349,62 @@ static void hess_transpose_add(const double *hb, int n, double *phibar)
             }
 }
 
-/* Gradient of the loss L(delta_r, phi_out) with respect to the input density
- * of the last recorded orc_solve.  grad_delta = dL/d delta_r, grad_phi =
- * dL/d phi_out (may be NULL).  box as in the forward. */
-int orc_backward(const double *grad_delta, const double *grad_phi, double box, const orc_config *cfg,
-                 double *grad_rho)
+/* Adjoint of the particle deposit M = orc_deposit_xi(xi) with xi = X^-1(y; s)
+ * on the mesh of node shifts s = D_c phi.  The deposit gives
+ *   xibar_p = wp sum_c Mbar(q_c) grad W_c(xi_p),
+ * and the implicit function theorem on x(xi; s) = y (x = xi + sum_c W_c(xi) s_c)
+ * turns it into lam_p = J^-T xibar_p with J = dx/dxi, so that
+ *   ybar_p += lam_p,  sbar(q_c) -= W_c(xi_p) lam_p  (each component). */
+static void deposit_adjoint(const double *s, int n, const double *xi, long np, const double *Mbar, double *sbar,
+                            double *ybar)
 {
-    if (!g_tape.m || g_tape.steps < 0 || !grad_delta || !grad_rho) return ORC_E_NO_TAPE;
+    const double wp = (double)cube(n) / (double)np;
+    for (long p = 0; p < np; ++p) {
+        const double *q = xi + 3 * p;
+        int f[3];
+        double t[3];
+        for (int a = 0; a < 3; ++a) {
+            double fl = floor(q[a]);
+            f[a] = (int)fl;
+            t[a] = q[a] - fl;
+        }
+        double xib[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 8; ++c) {
+            int o[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+            double w[3], dw[3];
+            for (int a = 0; a < 3; ++a) {
+                w[a] = o[a] ? t[a] : 1.0 - t[a];
+                dw[a] = o[a] ? 1.0 : -1.0;
+            }
+            double mb = wp * Mbar[at(n, f[0] + o[0], f[1] + o[1], f[2] + o[2])];
+            xib[0] += mb * dw[0] * w[1] * w[2];
+            xib[1] += mb * w[0] * dw[1] * w[2];
+            xib[2] += mb * w[0] * w[1] * dw[2];
+        }
+        double x[3], J[3][3], inv[3][3], lam[3];
+        map_eval(s, n, q, x, J);
+        inverse3(J, inv);
+        for (int a = 0; a < 3; ++a) {
+            lam[a] = inv[0][a] * xib[0] + inv[1][a] * xib[1] + inv[2][a] * xib[2];
+            ybar[3 * p + a] += lam[a];
+        }
+        for (int c = 0; c < 8; ++c) {
+            int o[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+            double wc = (o[0] ? t[0] : 1.0 - t[0]) * (o[1] ? t[1] : 1.0 - t[1]) * (o[2] ? t[2] : 1.0 - t[2]);
+            double *sb = sbar + 3 * at(n, f[0] + o[0], f[1] + o[1], f[2] + o[2]);
+            for (int a = 0; a < 3; ++a) sb[a] -= wc * lam[a];
+        }
+    }
+}
+
+/* Gradient of the loss L(delta_r, phi_out) with respect to the input of the
+ * last recorded forward: the density of orc_solve (grad_rho, n^3), or the
+ * particle positions of orc_solve_particles with particle_deposit (grad_pos,
+ * np x 3, in the units of the positions).  grad_delta = dL/d delta_r,
+ * grad_phi = dL/d phi_out (may be NULL).  box as in the forward. */
+static int backward_core(const double *grad_delta, const double *grad_phi, double box, const orc_config *cfg,
+                         double *grad_rho, double *grad_pos)
+{
     const int n = g_tape.n, K = g_tape.steps;
     const long N3 = cube(n);
     const double h = box / n;
@@ -1359,12 +1420,22 @@ int orc_backward(const double *grad_delta, const double *grad_phi, double box, c
     double *hb = (double *)malloc(sizeof(double) * N3 * 9);
     double *xb = (double *)malloc(sizeof(double) * N3 * 3);
     int status = ORC_OK;
+    const long np = g_tape.np;
+    double *xis = grad_pos ? (double *)malloc(sizeof(double) * 3 * np * (K > 0 ? K : 1)) : NULL;
+    double *ybar = grad_pos ? (double *)calloc(3 * np, sizeof(double)) : NULL;
 
-    /* replay the potentials phi_0 .. phi_K exactly as the forward formed them */
+    /* replay the potentials phi_0 .. phi_K exactly as the forward formed them,
+     * and (particles) the Lagrangian positions of each step by the forward's
+     * own sequence of warm-started inversions */
     memset(phis, 0, sizeof(double) * N3);
     for (int s = 0; s < K; ++s) {
         orc_smooth(g_tape.u[s], n, cfg->smooth_center, tmp);
         for (long p = 0; p < N3; ++p) phis[(s + 1) * N3 + p] = phis[s * N3 + p] + g_tape.alpha[s] * tmp[p];
+    }
+    for (int s = 0; s < K && grad_pos && status == ORC_OK; ++s) {
+        double *xi = xis + (size_t)3 * np * s;
+        memcpy(xi, s ? xi - 3 * np : g_tape.y, sizeof(double) * 3 * np);
+        status = orc_invert_map(phis + (size_t)s * N3, n, g_tape.y, np, xi, 100, 1e-12);
     }
     /* output: delta_r = -L7 phi_K (L7 symmetric), phi_out = h^2 phi_K */
     orc_delta_r(grad_delta, n, phibar);
@@ -1374,7 +1445,8 @@ int orc_backward(const double *grad_delta, const double *grad_phi, double box, c
     for (int s = K - 1; s >= 0 && status == ORC_OK; --s) {
         const double *phi = phis + s * N3;
         const double *u = g_tape.u[s];
-        orc_meshmass(phi, g_tape.m, n, M);
+        if (grad_pos) orc_deposit_xi(xis + (size_t)3 * np * s, np, n, M);
+        else orc_meshmass(phi, g_tape.m, n, M);
         double rho_bar = field_mean(M, n);
         /* phi_{s+1} = phi_s + alpha S u  ->  ubar = alpha S phibar */
         orc_smooth(phibar, n, cfg->smooth_center, ubar);
@@ -1430,9 +1502,18 @@ int orc_backward(const double *grad_delta, const double *grad_phi, double box, c
                 }
         double msb = sum_sigbar / (double)N3;
         for (long p = 0; p < N3; ++p) Mbar[p] += msb;
+        /* particles: M from the deposit at xi = X^-1(y; D_c phi); xbar holds
+         * the adjoint of the node shifts D_c phi */
+        if (grad_pos) {
+            double *sh = (double *)malloc(sizeof(double) * 3 * N3);
+            node_shifts(phi, n, sh);
+            memset(xb, 0, sizeof(double) * N3 * 3);
+            deposit_adjoint(sh, n, xis + (size_t)3 * np * s, np, Mbar, xb, ybar);
+            free(sh);
+        }
         /* M = det(e) * rho~(x):  gbar = Mbar rho~,  xbar = Mbar det(e) grad rho~,
          * mbar += Mbar det(e) W(x - j)  (the transposed CIC deposit) */
-        for (int i = 0; i < n; ++i)
+        for (int i = 0; i < n && !grad_pos; ++i)
             for (int j = 0; j < n; ++j)
                 for (int k = 0; k < n; ++k) {
                     long c = at(n, i, j, k);
@@ -1488,11 +1569,16 @@ int orc_backward(const double *grad_delta, const double *grad_phi, double box, c
                     phibar[at(n, i, j, k - 1)] -= 0.5 * xb[c * 3 + 2];
                 }
     }
-    if (status == ORC_OK) {
+    if (status == ORC_OK && grad_pos) {
+        /* y = pos n / box */
+        for (long p = 0; p < 3 * np; ++p) grad_pos[p] = ybar[p] * ((double)n / box);
+    } else if (status == ORC_OK) {
         /* m = rho / mean(rho):  rhobar = (mbar - mean(mbar m)) / mean(rho) */
         double mm = field_dot(mbar, g_tape.m, n) / (double)N3;
         for (long p = 0; p < N3; ++p) grad_rho[p] = (mbar[p] - mm) / g_tape.mean;
     }
+    free(xis);
+    free(ybar);
     free(phis);
     free(tmp);
     free(phibar);
@@ -1506,3 +1592,21 @@ int orc_backward(const double *grad_delta, const double *grad_phi, double box, c
     free(xb);
     return status;
 }
+
+int orc_backward(const double *grad_delta, const double *grad_phi, double box, const orc_config *cfg,
+                 double *grad_rho)
+{
+    if (!g_tape.m || g_tape.steps < 0 || !grad_delta || !grad_rho) return ORC_E_NO_TAPE;
+    return backward_core(grad_delta, grad_phi, box, cfg, grad_rho, NULL);
+}
+
+/* dL/d pos for the last orc_solve_particles run with particle_deposit and
+ * record_tape (np x 3, FP64). */
+int orc_backward_particles(const double *grad_delta, const double *grad_phi, double box, const orc_config *cfg,
+                           double *grad_pos)
+{
+    if (!g_tape.y || g_tape.steps < 0 || !grad_delta || !grad_pos) return ORC_E_NO_TAPE;
+    return backward_core(grad_delta, grad_phi, box, cfg, NULL, grad_pos);
+}
+
+long orc_tape_particles(void) { return g_tape.y ? g_tape.np : 0; }

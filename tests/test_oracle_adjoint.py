@@ -104,3 +104,74 @@ def test_backward_needs_a_tape(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.backward(np.zeros((8, 8, 8)), None, 10.0)
     assert e.value.code == -5
+
+
+# ------------------- particles deposited at their Lagrangian positions
+
+PBOX = 32.0  # positions below 32: a shift of 2^-10 is exact in float32
+
+
+def particle_fd(orc, pos, base, gd, gp, idx, a, eps=2.0 ** -10):
+    pp, pm = pos.copy(), pos.copy()
+    pp[idx, a] += np.float32(eps)
+    pm[idx, a] -= np.float32(eps)
+    step = (float(pp[idx, a]) - float(pm[idx, a])) / 2
+    php, dp, sp = orc.solve_particles(pp, N, PBOX, orc.Config(**base))
+    phm, dm, sm = orc.solve_particles(pm, N, PBOX, orc.Config(**base))
+    fd = np.vdot(gd, dp - dm) / (2 * step)
+    if gp is not None:
+        fd += np.vdot(gp, php - phm) / (2 * step)
+    return fd, sp["alpha"], sm["alpha"]
+
+
+@pytest.mark.parametrize("rms,seed", [(0.8, 1), (1.4, 2)])
+def test_particle_adjoint_against_finite_differences(orc, rms, seed):
+    """dL/d(position) through the inversion of the map and the xi-space
+    deposit, for single particle coordinates, with the step sizes unchanged."""
+    pos = inputs.zeldovich_particles(N, PBOX, rms, seed)
+    base = dict(max_outer=3, tol=1e-13, max_vcycles=200, particle_deposit=1)
+    rng = np.random.default_rng(20 + seed)
+    gd = rng.normal(size=(N, N, N))
+    gp = rng.normal(size=(N, N, N)) * 1e-3
+    _, _, st = orc.solve_particles(pos, N, PBOX, orc.Config(record_tape=1, **base))
+    g = orc.backward_particles(gd, gp, PBOX, orc.Config(**base))
+    assert g.shape == pos.shape
+    scale = np.abs(g).max()
+    for idx in rng.choice(len(pos), 5, replace=False):
+        for a in range(3):
+            fd, ap, am = particle_fd(orc, pos, base, gd, gp, idx, a)
+            assert ap == st["alpha"] == am
+            assert abs(fd - g[idx, a]) <= 1e-5 * max(abs(fd), 0.05 * scale), (idx, a, fd, g[idx, a])
+
+
+def test_particle_adjoint_directional_derivative(orc):
+    """<dL/dpos, v> for a random direction v moving every particle, against
+    central differences of the forward.  The CIC weights have a kink where a
+    Lagrangian position crosses a cell face, and a crossing costs an error of
+    the size of that particle's whole term; the amplitude (2^-18 of a box of
+    32, about 2e-6 cells, so that most coordinates move by one or two float32
+    units) keeps every particle inside its cells, and the sum over all
+    particles must agree to rounding."""
+    pos = inputs.zeldovich_particles(N, PBOX, 1.0, 3)
+    base = dict(max_outer=3, tol=1e-13, max_vcycles=200, particle_deposit=1)
+    rng = np.random.default_rng(31)
+    gd = rng.normal(size=(N, N, N))
+    _, _, st = orc.solve_particles(pos, N, PBOX, orc.Config(record_tape=1, **base))
+    g = orc.backward_particles(gd, None, PBOX, orc.Config(**base))
+    for seed in (1, 2):
+        v = np.random.default_rng(seed).normal(size=pos.shape) * 2.0 ** -18
+        pp = (pos + v).astype(np.float32)
+        pm = (pos - v).astype(np.float32)
+        _, dp, sp = orc.solve_particles(pp, N, PBOX, orc.Config(**base))
+        _, dm, sm = orc.solve_particles(pm, N, PBOX, orc.Config(**base))
+        assert sp["alpha"] == st["alpha"] == sm["alpha"]
+        fd = np.vdot(gd, dp - dm)
+        an = np.vdot(g, pp.astype(np.float64) - pm.astype(np.float64))
+        assert abs(fd - an) <= 1e-6 * abs(fd)
+
+
+def test_particle_backward_needs_a_particle_tape(orc):
+    rho = inputs.lognormal_density(N, BOX, 0.5, 1)
+    orc.solve(rho, BOX, orc.Config(record_tape=1, max_outer=1))
+    with pytest.raises(orc.OracleError):
+        orc.backward_particles(np.zeros((N, N, N)), None, PBOX)
