@@ -75,7 +75,8 @@ typedef struct recon_config {
                            by CIC at their Lagrangian positions on the deformed mesh every step
                            (xi_p with xi_p + grad phi(xi_p) = y_p, by Newton from the previous
                            step's); 0 assigns them to the grid once.  Needs up to n^3
-                           particles, mass_update = 0 and record_tape = 0 (0)               */
+                           particles and mass_update = 0; reverse mode through
+                           recon_backward_particles (0)                                     */
     int full_operator;  /* 1: the linear system of each step is the exact Jacobian of the mass
                            map, div(M e^-1 grad u) = b on the current mesh (App. A, Eq.
                            elliptic_diff, without x ~ xi), solved by the same Krylov loop with
@@ -156,6 +157,18 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
  * sizes, limiter branches) are held fixed; each linear solve is
  * differentiated as exact.  Returns RECON_E_NO_TAPE without a recorded tape. */
 int recon_backward(recon_ctx *ctx, const double *grad_delta_r, const double *grad_phi, double *grad_density);
+
+/* Reverse mode of a recorded recon_solve_particles with particle_deposit = 1:
+ * dL/d pos (grad_pos: np x 3 FP64 device array, in the units of pos) given
+ * dL/d delta_r and (optionally) dL/d phi_out.  pos and np must be the
+ * particles of the recorded forward (device, float32, unchanged).  Each
+ * step's Lagrangian positions are recomputed by Newton from the later step's
+ * (reverse order); the gradient runs through the inversion of the map
+ * (J^-T per particle) and the xi-space CIC, with the step sizes and limiter
+ * branches of the forward held fixed.  RECON_E_NO_TAPE without a tape,
+ * RECON_E_ARG for a density tape or other particles. */
+int recon_backward_particles(recon_ctx *ctx, const float *pos, long long np, const double *grad_delta_r,
+                             const double *grad_phi, double *grad_pos);
 
 /* Release the context (not the workspace, which the caller owns). */
 void recon_destroy(recon_ctx *ctx);
@@ -248,6 +261,25 @@ int recon_stage_vcycle(recon_ctx *ctx, const void *a, const void *r, void *z, in
  * returned mean-free.  *cycles and *rel_residual are host outputs. */
 int recon_stage_mg_solve(recon_ctx *ctx, const double *a, const double *b, double tol, double *u, int *cycles,
                          double *rel_residual);
+
+/* The Krylov residual of the exact-Jacobian mode: K = M e^-1 from phi (into
+ * the context's K fields), r = b - div(K grad u) in the flux form of
+ * recon_stage_mass_change, r32 (FP32, may be NULL) a copy of r, *rr (host)
+ * <- r.r.  All FP64 n^3 device fields except r32; r distinct from u and b.
+ * variant 1: per-node gathers; 2: one streaming pass (edges that are
+ * multiples of 64); 0: the solve's choice.  Needs full_operator = 1. */
+int recon_stage_full_residual(recon_ctx *ctx, const double *phi, const double *M, const double *u, const double *b,
+                              double *r, float *r32, double *rr, int variant);
+
+/* One Krylov direction of the exact-Jacobian mode: K = M e^-1 from phi, then
+ * as recon_stage_direction with the operator div(K grad .) in place of A:
+ * p_new = z or z + beta p_old, q = div(K grad p_new), *pq <- p_new.q, and
+ * u += alpha_u p_old when u is not NULL; same dtypes, aliasing rules and
+ * variants (2: one streaming pass, edges that are multiples of 64).  Needs
+ * full_operator = 1. */
+int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *M, const void *z, int z_dtype,
+                               const void *p_old, double beta, int first, void *p_new, double *q, double *pq,
+                               int variant, double *u, double alpha_u, int p_dtype);
 
 /* The linear solve of the exact-Jacobian mode: div(K grad u) = b with
  * K = a e^-1, e = I + Hess phi (App. A, Eq. elliptic_diff without x ~ xi), in

@@ -124,6 +124,7 @@ def lib():
         "recon_solve": (i, [vp, vp, i, d, d, vp, vp, ps]),
         "recon_solve_particles": (i, [vp, vp, ll, d, d, vp, vp, ps]),
         "recon_backward": (i, [vp, vp, vp, vp]),
+        "recon_backward_particles": (i, [vp, vp, ll, vp, vp, vp]),
         "recon_destroy": (None, [vp]),
         "recon_strerror": (ctypes.c_char_p, [i]),
         "recon_last_error": (ctypes.c_char_p, [vp]),
@@ -135,6 +136,8 @@ def lib():
         "recon_stage_apply": (i, [vp, vp, vp, i, d, vp]),
         "recon_stage_residual": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
         "recon_stage_direction": (i, [vp, vp, i, vp, vp, d, i, vp, vp, pd, i, vp, d, i]),
+        "recon_stage_full_residual": (i, [vp, vp, vp, vp, vp, vp, vp, pd, i]),
+        "recon_stage_full_direction": (i, [vp, vp, vp, vp, i, vp, d, i, vp, vp, pd, i, vp, d, i]),
         "recon_stage_rbgs": (i, [vp, vp, vp, vp, i, d, i, i, i]),
         "recon_stage_restrict": (i, [vp, vp, i, vp, i, i]),
         "recon_stage_residual_restrict": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
@@ -250,6 +253,16 @@ class Recon:
                                          _ptr(grad_phi, torch.float64), _ptr(out)))
         return out
 
+    def backward_particles(self, pos: torch.Tensor, grad_delta_r: torch.Tensor,
+                           grad_phi: torch.Tensor | None = None) -> torch.Tensor:
+        """dL/d(positions) [np, 3] (FP64) of the last recorded particle-deposit
+        solve; pos must be the particles of that solve."""
+        out = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=self.device)
+        self._check(lib().recon_backward_particles(self._ctx, _ptr(pos, torch.float32), pos.shape[0],
+                                                   _ptr(grad_delta_r, torch.float64), _ptr(grad_phi, torch.float64),
+                                                   _ptr(out)))
+        return out
+
     # ------------------------------------------------------------ stage calls
     def normalize(self, rho):
         m = self._field()
@@ -307,6 +320,33 @@ class Recon:
                                                 _ptr(p_new, p_dtype), _ptr(q), ctypes.byref(pq), variant,
                                                 None if u is None else _ptr(u, torch.float64), float(alpha_u),
                                                 1 if p_dtype == torch.float32 else 0))
+        return p_new, q, pq.value
+
+    def full_residual(self, phi, M, u, b, variant=0, fp32_copy=False):
+        """(r, r32, r.r): r = b - div(M e^-1 grad u) on the mesh of phi
+        (needs full_operator=1); r32 is None unless fp32_copy."""
+        r = self._field()
+        r32 = self._field(torch.float32) if fp32_copy else None
+        rr = ctypes.c_double()
+        self._check(lib().recon_stage_full_residual(self._ctx, _ptr(phi, torch.float64), _ptr(M, torch.float64),
+                                                    _ptr(u, torch.float64), _ptr(b, torch.float64), _ptr(r),
+                                                    None if r32 is None else _ptr(r32, torch.float32),
+                                                    ctypes.byref(rr), variant))
+        return r, r32, rr.value
+
+    def full_direction(self, phi, M, z, p_old, beta, first=False, variant=0, u=None, alpha_u=0.0,
+                       p_dtype=torch.float64):
+        """As direction() with the operator div(M e^-1 grad .) on the mesh of phi."""
+        p_new = self._field(p_dtype)
+        q = self._field()
+        pq = ctypes.c_double()
+        self._check(lib().recon_stage_full_direction(self._ctx, _ptr(phi, torch.float64), _ptr(M, torch.float64),
+                                                     _ptr(z, z.dtype), self._dt(z),
+                                                     None if p_old is None else _ptr(p_old, p_dtype),
+                                                     float(beta), 1 if first else 0, _ptr(p_new, p_dtype), _ptr(q),
+                                                     ctypes.byref(pq), variant,
+                                                     None if u is None else _ptr(u, torch.float64), float(alpha_u),
+                                                     1 if p_dtype == torch.float32 else 0))
         return p_new, q, pq.value
 
     def rbgs(self, u, a, b, scale=1.0, first=0, variant=0):

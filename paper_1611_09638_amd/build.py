@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librecon.so")
-SOURCES = ["recon_kernels.hip", "rbgs_fused.hip", "stencil25.hip", "transfer25.hip", "resrestrict25.hip", "pdcheck25.hip", "massupdate.hip", "particles.hip", "recon_adjoint.hip", "recon_api.hip"]
+SOURCES = ["recon_kernels.hip", "rbgs_fused.hip", "stencil25.hip", "transfer25.hip", "resrestrict25.hip", "pdcheck25.hip", "massupdate.hip", "fullop25.hip", "particles.hip", "recon_adjoint.hip", "recon_api.hip"]
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC_FLAGS = [

@@ -182,6 +182,36 @@ __device__ __forceinline__ void load19(const double *__restrict__ f, int i, int 
     s.ymzm = f[lin(i, jm, km, n)];
 }
 
+// The coefficients K = M e^-1 that the flux form of div(K grad f) reads around
+// one node: each diagonal component at the node and its two neighbours along
+// its own axis, each off-diagonal one at the four face neighbours across which
+// it couples.
+struct FluxK {
+    double xx_c, xx_p, xx_m, yy_c, yy_p, yy_m, zz_c, zz_p, zz_m;
+    double xy_xp, xy_xm, xy_yp, xy_ym, xz_xp, xz_xm, xz_zp, xz_zm, yz_yp, yz_ym, yz_zp, yz_zm;
+};
+
+// div(K grad f) at a node in flux form on the periodic lattice: diagonal
+// fluxes with face-averaged coefficients, cross fluxes as central differences
+// of K^{mu nu} d_nu f taken at the two neighbours along mu (sums to zero over
+// the lattice; at K = a I it is the x ~ xi operator without the face floor).
+__device__ __forceinline__ double full_flux(const Stencil19 &s, const FluxK &K)
+{
+    double acc = 0.0;
+    // diagonal fluxes, directions x, y, z
+    acc += 0.5 * (K.xx_c + K.xx_p) * (s.xp - s.c) - 0.5 * (K.xx_m + K.xx_c) * (s.c - s.xm);
+    acc += 0.5 * (K.yy_c + K.yy_p) * (s.yp - s.c) - 0.5 * (K.yy_m + K.yy_c) * (s.c - s.ym);
+    acc += 0.5 * (K.zz_c + K.zz_p) * (s.zp - s.c) - 0.5 * (K.zz_m + K.zz_c) * (s.c - s.zm);
+    // cross fluxes: direction mu of the difference, nu of the gradient
+    acc += 0.25 * (K.xy_xp * (s.xpyp - s.xpym) - K.xy_xm * (s.xmyp - s.xmym));  // mu = x, nu = y
+    acc += 0.25 * (K.xz_xp * (s.xpzp - s.xpzm) - K.xz_xm * (s.xmzp - s.xmzm));  // mu = x, nu = z
+    acc += 0.25 * (K.xy_yp * (s.xpyp - s.xmyp) - K.xy_ym * (s.xpym - s.xmym));  // mu = y, nu = x
+    acc += 0.25 * (K.yz_yp * (s.ypzp - s.ypzm) - K.yz_ym * (s.ymzp - s.ymzm));  // mu = y, nu = z
+    acc += 0.25 * (K.xz_zp * (s.xpzp - s.xmzp) - K.xz_zm * (s.xpzm - s.xmzm));  // mu = z, nu = x
+    acc += 0.25 * (K.yz_zp * (s.ypzp - s.ymzp) - K.yz_zm * (s.ypzm - s.ymzm));  // mu = z, nu = y
+    return acc;
+}
+
 // e = I + compact Hessian of the 19-point neighbourhood.
 __device__ __forceinline__ Sym3 triad19(const Stencil19 &s)
 {

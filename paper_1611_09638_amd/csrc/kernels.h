@@ -74,6 +74,18 @@ hipError_t launch_full_apply(const MassTensor &K, const double *f, double *out, 
 hipError_t launch_full_apply_dot(const MassTensor &K, const double *pv, double *q, int n, Part &p, hipStream_t s);
 hipError_t launch_full_residual_norm(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
                                      int n, Part &p, hipStream_t s);
+// Streaming forms of the last two (fullop25.hip; edges that are multiples of
+// 64): the residual with its norm, and the Krylov direction p_new = z + beta
+// p_old (first: z; beta from ks as in launch_direction25; rounded to P) fused
+// with q = L_K p_new and partial K=1 sum p_new.q, and with u += alpha_u p_old
+// when u != null (not first).  p_new must not alias p_old, u or q.
+bool full25_supported(int n);
+hipError_t launch_full_residual_norm25(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
+                                       int n, Part &p, hipStream_t s);
+template <typename Z, typename P>
+hipError_t launch_full_direction25(const Z *z, const P *p_old, P *p_new, const MassTensor &K, double *q, double beta,
+                                   int n, bool first, double *u, double alpha_u, const double *ks, Part &p,
+                                   hipStream_t s);
 // Particles at their Lagrangian positions (particles.hip): xi = pos n / box;
 // Newton for x(xi) = y from the xi given (node shifts of phi in sx, sy, sz;
 // partial K=1: particles not within tol); CIC of the particles at xi into M
@@ -82,6 +94,13 @@ hipError_t launch_init_xi(const float *pos, long long np, int n, double box, dou
 hipError_t launch_invert_map(const double *phi, const float *pos, long long np, int n, double box, double *xi,
                              double *sx, double *sy, double *sz, int max_iter, double tol, Part &p, hipStream_t s);
 hipError_t launch_deposit_xi(const double *xi, long long np, int n, double *M, hipStream_t s);
+// s = D_c phi into three fields; the adjoint of the deposit at the Lagrangian
+// positions xi (node shifts s of the same phi): gpos (3 per particle) +=
+// gscale lam, sbar (three fields, x then y then z) -= W lam with atomics
+hipError_t launch_node_shifts(const double *phi, double *sx, double *sy, double *sz, int n, hipStream_t s);
+hipError_t launch_deposit_adj(const double *xi, long long np, int n, const double *sx, const double *sy,
+                              const double *sz, const double *Mbar, double *sbar, double *gpos, double gscale,
+                              hipStream_t s);
 // y += alpha x, X = double or float; with alpha_dev != null alpha is read there
 template <typename X>
 hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s,

@@ -57,19 +57,10 @@ __device__ inline double full_node(const MassTensor &K, const double *__restrict
     const size_t xp = lin(ip, j, k, n), xm = lin(im, j, k, n);
     const size_t yp = lin(i, jp, k, n), ym = lin(i, jm, k, n);
     const size_t zp = lin(i, j, kp, n), zm = lin(i, j, km, n);
-    double acc = 0.0;
-    // diagonal fluxes, directions x, y, z
-    acc += 0.5 * (K.xx[c] + K.xx[xp]) * (s.xp - s.c) - 0.5 * (K.xx[xm] + K.xx[c]) * (s.c - s.xm);
-    acc += 0.5 * (K.yy[c] + K.yy[yp]) * (s.yp - s.c) - 0.5 * (K.yy[ym] + K.yy[c]) * (s.c - s.ym);
-    acc += 0.5 * (K.zz[c] + K.zz[zp]) * (s.zp - s.c) - 0.5 * (K.zz[zm] + K.zz[c]) * (s.c - s.zm);
-    // cross fluxes: direction mu of the difference, nu of the gradient
-    acc += 0.25 * (K.xy[xp] * (s.xpyp - s.xpym) - K.xy[xm] * (s.xmyp - s.xmym));  // mu = x, nu = y
-    acc += 0.25 * (K.xz[xp] * (s.xpzp - s.xpzm) - K.xz[xm] * (s.xmzp - s.xmzm));  // mu = x, nu = z
-    acc += 0.25 * (K.xy[yp] * (s.xpyp - s.xmyp) - K.xy[ym] * (s.xpym - s.xmym));  // mu = y, nu = x
-    acc += 0.25 * (K.yz[yp] * (s.ypzp - s.ypzm) - K.yz[ym] * (s.ymzp - s.ymzm));  // mu = y, nu = z
-    acc += 0.25 * (K.xz[zp] * (s.xpzp - s.xmzp) - K.xz[zm] * (s.xpzm - s.xmzm));  // mu = z, nu = x
-    acc += 0.25 * (K.yz[zp] * (s.ypzp - s.ymzp) - K.yz[zm] * (s.ypzm - s.ymzm));  // mu = z, nu = y
-    return acc;
+    const FluxK q{K.xx[c],  K.xx[xp], K.xx[xm], K.yy[c],  K.yy[yp], K.yy[ym], K.zz[c],
+                  K.zz[zp], K.zz[zm], K.xy[xp], K.xy[xm], K.xy[yp], K.xy[ym], K.xz[xp],
+                  K.xz[xm], K.xz[zp], K.xz[zm], K.yz[yp], K.yz[ym], K.yz[zp], K.yz[zm]};
+    return full_flux(s, q);
 }
 
 enum FullMode { FULL_APPLY = 0, FULL_DOT = 1, FULL_RESID = 2 };

@@ -172,6 +172,71 @@ __global__ void k_deposit_xi(const double *__restrict__ xi, long long np, int n,
     }
 }
 
+// Adjoint of the deposit at xi = X^-1(y; s) (s = D_c phi): per particle,
+//   xibar = wp sum_c Mbar(q_c) grad W_c(xi),  lam = J^-T xibar,
+// with J = dx/dxi in the cell of xi (implicit function theorem on
+// x(xi; s) = y); then gpos += gscale lam (the particle's own entry) and
+// sbar(q_c) -= W_c(xi) lam, component by component, with FP64 atomics.
+__global__ void k_deposit_adj(const double *__restrict__ xi, long long np, Shifts s, int n, double wp,
+                              const double *__restrict__ Mbar, double *__restrict__ sbx, double *__restrict__ sby,
+                              double *__restrict__ sbz, double *__restrict__ gpos, double gscale)
+{
+    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < np; p += 256LL * gridDim.x) {
+        if (!(fabs(xi[3 * p]) < 1.0e9 && fabs(xi[3 * p + 1]) < 1.0e9 && fabs(xi[3 * p + 2]) < 1.0e9)) continue;
+        int f[3];
+        double t[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double x = xi[3 * p + a];
+            const double fl = floor(x);
+            t[a] = x - fl;
+            int fi = (int)fl % n;
+            f[a] = fi < 0 ? fi + n : fi;
+        }
+        double xb[3] = {0.0, 0.0, 0.0};
+        double J[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+        size_t q[8];
+        double wc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+            const double w0 = o0 ? t[0] : 1.0 - t[0], w1 = o1 ? t[1] : 1.0 - t[1], w2 = o2 ? t[2] : 1.0 - t[2];
+            const double d0 = o0 ? 1.0 : -1.0, d1 = o1 ? 1.0 : -1.0, d2 = o2 ? 1.0 : -1.0;
+            q[c] = lin(o0 ? wrapc(f[0] + 1, n) : f[0], o1 ? wrapc(f[1] + 1, n) : f[1], o2 ? wrapc(f[2] + 1, n) : f[2],
+                       n);
+            wc[c] = w0 * w1 * w2;
+            const double g[3] = {d0 * w1 * w2, w0 * d1 * w2, w0 * w1 * d2};
+            const double mb = wp * Mbar[q[c]];
+            const double sc[3] = {s.x[q[c]], s.y[q[c]], s.z[q[c]]};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xb[a] += mb * g[a];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) J[b][a] += g[a] * sc[b];
+            }
+        }
+        // lam = J^-T xibar by the adjugate: (J^-1)_{ba} = adj_{ba} / det
+        const double a00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], a01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
+                     a02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        const double a10 = J[1][2] * J[2][0] - J[1][0] * J[2][2], a11 = J[0][0] * J[2][2] - J[0][2] * J[2][0],
+                     a12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        const double a20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], a21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
+                     a22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * a00 + J[0][1] * a10 + J[0][2] * a20;
+        const double lam[3] = {(a00 * xb[0] + a10 * xb[1] + a20 * xb[2]) / det,
+                               (a01 * xb[0] + a11 * xb[1] + a21 * xb[2]) / det,
+                               (a02 * xb[0] + a12 * xb[1] + a22 * xb[2]) / det};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gpos[3 * p + a] += gscale * lam[a];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            atomicAdd(&sbx[q[c]], -wc[c] * lam[0]);
+            atomicAdd(&sby[q[c]], -wc[c] * lam[1]);
+            atomicAdd(&sbz[q[c]], -wc[c] * lam[2]);
+        }
+    }
+}
+
 int particle_blocks(long long np)
 {
     long long b = (np + 255) / 256;
@@ -205,6 +270,23 @@ hipError_t launch_deposit_xi(const double *xi, long long np, int n, double *M, h
     hipError_t e = launch_zero(M, (long)n * n * n * 8, s);
     if (e != hipSuccess) return e;
     k_deposit_xi<<<particle_blocks(np), 256, 0, s>>>(xi, np, n, (double)n * n * n / (double)np, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_shifts(const double *phi, double *sx, double *sy, double *sz, int n, hipStream_t s)
+{
+    Shape3 sh = shape3(n);
+    k_node_shifts<<<sh.grid, sh.block, 0, s>>>(phi, sx, sy, sz, n, sh.ipb);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_adj(const double *xi, long long np, int n, const double *sx, const double *sy,
+                              const double *sz, const double *Mbar, double *sbar, double *gpos, double gscale,
+                              hipStream_t s)
+{
+    const size_t n3 = (size_t)n * n * n;
+    k_deposit_adj<<<particle_blocks(np), 256, 0, s>>>(xi, np, Shifts{sx, sy, sz}, n, (double)n3 / (double)np, Mbar,
+                                                      sbar, sbar + n3, sbar + 2 * n3, gpos, gscale);
     return hipGetLastError();
 }
 

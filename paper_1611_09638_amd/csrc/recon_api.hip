@@ -80,7 +80,7 @@ bool config_ok(const recon_config *c)
            c->max_halvings >= 0 && c->max_halvings <= 60 && c->fixed_cycles >= 0 && (c->warm_start == 0 || c->warm_start == 1) &&
            (c->mass_update == 0 || c->mass_update == 1) && !(c->mass_update && c->record_tape) &&
            (c->particle_deposit == 0 || c->particle_deposit == 1) &&
-           !(c->particle_deposit && (c->record_tape || c->mass_update)) &&
+           !(c->particle_deposit && c->mass_update) &&
            (c->full_operator == 0 || c->full_operator == 1) && !(c->full_operator && c->record_tape) &&
            (c->tape_fp32 == 0 || c->tape_fp32 == 1) && (c->precision == RECON_FP64 || c->precision == RECON_MIXED) &&
            (c->solver == RECON_SOLVER_PCG || c->solver == RECON_SOLVER_VCYCLE) && c->tol > 0 && c->outer_tol >= 0 &&
@@ -198,6 +198,7 @@ struct recon_ctx {
     MassTensor Kf{};
     double last_tol = 0.0;
     int tape_valid = 0;
+    long long tape_np = 0;  // particles of a recorded particle-deposit forward (0: density input)
     char err[512];
 };
 
@@ -366,6 +367,8 @@ hipError_t prolong_level(T *u, const T *e, int n, hipStream_t s, int variant = 0
 hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const double *b, double *r, float *r32,
                          const MassTensor *Kf = nullptr)
 {
+    if (Kf && use_stream<double>(ctx->n) && full25_supported(ctx->n))
+        return launch_full_residual_norm25(*Kf, u, b, r, r32, ctx->n, ctx->part, ctx->stream);
     if (Kf) return launch_full_residual_norm(*Kf, u, b, r, r32, ctx->n, ctx->part, ctx->stream);
     if (use_stream<double>(ctx->n))
         return launch_residual_norm25(u, a, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
@@ -506,12 +509,22 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         // stored in FP32 when the preconditioner is FP32.  The solution update
         // u += alpha p of one step is deferred into the next direction pass there
         // (it reads p anyway), and applied after the loop for the last step.
-        const bool stream = use_stream<double>(n) && !Kf;
+        const bool stream = use_stream<double>(n) && (!Kf || full25_supported(n));
         double *pc = ctx->p, *pn = ctx->t;
         auto f32 = [](double *x) { return reinterpret_cast<float *>(x); };
         bool due = false;
         while (true) {
-            if (stream) {
+            if (stream && Kf) {
+                double *ud = due ? ctx->u : nullptr;
+                if (mixed)
+                    HIPCHK(launch_full_direction25(ctx->L32.u[0], f32(pc), f32(pn), *Kf, ctx->q, 0.0, n, first, ud,
+                                                   0.0, ks, ctx->part, ctx->stream));
+                else
+                    HIPCHK(launch_full_direction25(ctx->z, pc, pn, *Kf, ctx->q, 0.0, n, first, ud, 0.0, ks,
+                                                   ctx->part, ctx->stream));
+                due = false;
+                std::swap(pc, pn);
+            } else if (stream) {
                 double *ud = due ? ctx->u : nullptr;
                 if (mixed)
                     HIPCHK(launch_direction25(ctx->L32.u[0], f32(pc), f32(pn), a0, ctx->q, 0.0, n, ctx->cfg.a_min,
@@ -679,6 +692,7 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
     HIPCHK(launch_zero(ctx->phi, n3 * 8, ctx->stream));
     ctx->tape_valid = 0;
     ctx->tape_steps = 0;
+    ctx->tape_np = 0;
     // Mass update: after the first gather (at phi = 0, where it gives M = m) M
     // is carried by M += alpha D.  D goes into m's field, which is not read
     // again in that mode, and K into six fields idle between the solve and
@@ -739,14 +753,21 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
     st->min_det = v[0];
     st->min_lambda0 = v[1];
     st->max_delta_r = -v[2];
-    if (c.record_tape) ctx->tape_valid = 1;
+    if (c.record_tape) {
+        ctx->tape_valid = 1;
+        ctx->tape_np = ctx->part_pos ? ctx->part_np : 0;
+    }
     return RECON_OK;
 }
 
 // Reverse sweep over the tape (transposes of the forward maps, in reverse
 // order); the discrete decisions of the forward are held fixed and each
 // linear solve is differentiated as exact.
-int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad)
+// pos, gpos (particle-deposit tapes): the particles of the forward and the
+// gradient with respect to their positions (3 per particle); else grad is
+// the gradient with respect to the input density.
+int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad, const float *pos = nullptr,
+             double *gpos = nullptr)
 {
     const recon_config &c = ctx->cfg;
     const int n = ctx->n;
@@ -769,8 +790,10 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad)
                    : nullptr;
     };
 
+    const long long np = ctx->tape_np;
     HIPCHK(launch_out_adj(gd, gp, h * h, phibar, n, ctx->stream));
     HIPCHK(launch_zero(mbar, n3 * 8, ctx->stream));
+    if (gpos) HIPCHK(launch_zero(gpos, np * 3 * 8, ctx->stream));
     for (int s = ctx->tape_steps - 1; s >= 0; --s) {
         // phi_s, rebuilt from the increments exactly as the forward built it
         HIPCHK(launch_zero(phi, n3 * 8, ctx->stream));
@@ -780,7 +803,19 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad)
             HIPCHK(launch_smooth(u_q, ctx->dphi, n, c.smooth_center, 0.0, ctx->stream));
             HIPCHK(launch_axpy(phi, ctx->dphi, ctx->tape_alpha[q], n3, ctx->stream));
         }
-        HIPCHK(launch_meshmass(phi, ctx->m, ctx->M, n, ctx->part, ctx->stream));
+        if (gpos) {
+            // the step's Lagrangian positions, warm-started from the later
+            // step's (ctx->xi holds those of the final mesh after the forward)
+            HIPCHK(launch_invert_map(phi, pos, np, n, ctx->box, ctx->xi, ctx->r, ctx->z, ctx->p, kInvertIters,
+                                     kInvertTol, ctx->part, ctx->stream));
+            TRY(fetch_sum(ctx, v));
+            if (v[0] != 0.0)
+                return fail(ctx, RECON_E_NO_CONVERGENCE, "%.0f particles not located on the mesh of step %d", v[0], s);
+            HIPCHK(launch_deposit_xi(ctx->xi, np, n, ctx->M, ctx->stream));
+            HIPCHK(launch_sum(ctx->M, n3, ctx->part, ctx->stream));
+        } else {
+            HIPCHK(launch_meshmass(phi, ctx->m, ctx->M, n, ctx->part, ctx->stream));
+        }
         TRY(fetch_sum(ctx, v));
         const double rho_bar = v[0] / (double)n3;
         // phi_{s+1} = phi_s + alpha S u:  ubar = alpha S phibar, made mean-free
@@ -807,9 +842,22 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad)
         TRY(fetch_sum(ctx, v));
         HIPCHK(launch_fill(ctx->scal + 16, 1, v[0] / (double)n3, ctx->stream));
         HIPCHK(launch_add_scalar(Mbar, ctx->scal + 16, 1.0, 1.0, n3, ctx->stream));
-        // M = det(e) rho~(x), then phibar through e and x
-        HIPCHK(launch_meshmass_adj(phi, ctx->m, Mbar, hb, xb, mbar, n, ctx->stream));
+        if (gpos) {
+            // M = CIC(xi), xi = X^-1(y; D_c phi): xb <- adjoint of the node
+            // shifts (their fields t, m, mbar are idle here in this mode)
+            HIPCHK(launch_zero(xb, 3 * n3 * 8, ctx->stream));
+            HIPCHK(launch_node_shifts(phi, ctx->t, ctx->m, mbar, n, ctx->stream));
+            HIPCHK(launch_deposit_adj(ctx->xi, np, n, ctx->t, ctx->m, mbar, Mbar, xb, gpos, (double)n / ctx->box,
+                                      ctx->stream));
+        } else {
+            // M = det(e) rho~(x), then phibar through e and x
+            HIPCHK(launch_meshmass_adj(phi, ctx->m, Mbar, hb, xb, mbar, n, ctx->stream));
+        }
         HIPCHK(launch_phibar_update(hb, xb, phibar, n, ctx->stream));
+    }
+    if (gpos) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return RECON_OK;
     }
     // m = rho / mean(rho)
     HIPCHK(launch_dot(mbar, ctx->m, n3, ctx->part, ctx->stream));
@@ -1046,7 +1094,23 @@ int recon_backward(recon_ctx *ctx, const double *grad_delta_r, const double *gra
     if (!ctx->cfg.record_tape || !ctx->tape_valid)
         return fail(ctx, RECON_E_NO_TAPE, "no forward with record_tape has completed on this context");
     if (!grad_delta_r || !grad_density) return fail(ctx, RECON_E_ARG, "null gradient array");
+    if (ctx->tape_np > 0)
+        return fail(ctx, RECON_E_ARG, "the recorded forward deposited particles: use recon_backward_particles");
     return backward(ctx, grad_delta_r, grad_phi, grad_density);
+}
+
+int recon_backward_particles(recon_ctx *ctx, const float *pos, long long np, const double *grad_delta_r,
+                             const double *grad_phi, double *grad_pos)
+{
+    TRY(check_ctx(ctx));
+    ctx->err[0] = 0;
+    if (!ctx->cfg.record_tape || !ctx->tape_valid)
+        return fail(ctx, RECON_E_NO_TAPE, "no forward with record_tape has completed on this context");
+    if (ctx->tape_np <= 0)
+        return fail(ctx, RECON_E_ARG, "the recorded forward did not deposit particles: use recon_backward");
+    if (!pos || np != ctx->tape_np || !grad_delta_r || !grad_pos)
+        return fail(ctx, RECON_E_ARG, "the particles must be those of the recorded forward");
+    return backward(ctx, grad_delta_r, grad_phi, nullptr, pos, grad_pos);
 }
 
 // ------------------------------------------------------------- stage calls
@@ -1173,6 +1237,66 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void
         else
             HIPCHK(launch_update_pq<float>((const float *)z, a, pn, q, beta, n, ctx->cfg.a_min, first != 0,
                                            nullptr, ctx->part, ctx->stream));
+    }
+    return fetch_sum(ctx, pq);
+}
+
+int recon_stage_full_residual(recon_ctx *ctx, const double *phi, const double *M, const double *u, const double *b,
+                              double *r, float *r32, double *rr, int variant)
+{
+    TRY(check_ctx(ctx));
+    const int n = ctx->n;
+    if (!phi || !M || !u || !b || !r || !rr || variant < 0 || variant > 2 || r == u || r == b)
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
+    const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
+    if (stream && !full25_supported(n))
+        return fail(ctx, RECON_E_ARG, "the streaming full operator needs an edge that is a multiple of 64");
+    HIPCHK(launch_mass_tensor(phi, M, ctx->Kf, n, ctx->stream));
+    if (stream) HIPCHK(launch_full_residual_norm25(ctx->Kf, u, b, r, r32, n, ctx->part, ctx->stream));
+    else HIPCHK(launch_full_residual_norm(ctx->Kf, u, b, r, r32, n, ctx->part, ctx->stream));
+    return fetch_sum(ctx, rr);
+}
+
+int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *M, const void *z, int z_dtype,
+                               const void *p_old, double beta, int first, void *p_new, double *q, double *pq,
+                               int variant, double *u, double alpha_u, int p_dtype)
+{
+    TRY(check_ctx(ctx));
+    const int n = ctx->n;
+    const long n3 = ctx->n3;
+    if (!phi || !M || !z || !p_new || !q || !pq || (!first && !p_old) || (z_dtype != 0 && z_dtype != 1) ||
+        variant < 0 || variant > 2 || (p_old && p_old == p_new) || (void *)q == p_new ||
+        (p_dtype != 0 && p_dtype != 1) ||
+        (u && (first || (const void *)u == p_old || (void *)u == p_new || u == q || (const void *)u == z)))
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
+    const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
+    if (stream && !full25_supported(n))
+        return fail(ctx, RECON_E_ARG, "the streaming full operator needs an edge that is a multiple of 64");
+    if (p_dtype == 1 && (!stream || z_dtype != 1))
+        return fail(ctx, RECON_E_ARG, "FP32 directions need an FP32 z and the streaming kernel");
+    HIPCHK(launch_mass_tensor(phi, M, ctx->Kf, n, ctx->stream));
+    if (stream) {
+        const void *po = first ? (const void *)q : p_old;  // not read when first; any array other than p_new
+        if (p_dtype == 1)
+            HIPCHK(launch_full_direction25((const float *)z, (const float *)po, (float *)p_new, ctx->Kf, q, beta, n,
+                                           first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
+        else if (z_dtype == 0)
+            HIPCHK(launch_full_direction25((const double *)z, (const double *)po, (double *)p_new, ctx->Kf, q, beta,
+                                           n, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
+        else
+            HIPCHK(launch_full_direction25((const float *)z, (const double *)po, (double *)p_new, ctx->Kf, q, beta,
+                                           n, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
+    } else {
+        double *pn = (double *)p_new;
+        if (u) HIPCHK(launch_axpy(u, (const double *)p_old, alpha_u, n3, ctx->stream));
+        if (!first) HIPCHK(launch_copy(pn, (const double *)p_old, n3, ctx->stream));
+        if (z_dtype == 0)
+            HIPCHK(launch_update_p<double>((const double *)z, pn, beta, n3, first != 0, nullptr, ctx->stream));
+        else
+            HIPCHK(launch_update_p<float>((const float *)z, pn, beta, n3, first != 0, nullptr, ctx->stream));
+        HIPCHK(launch_full_apply_dot(ctx->Kf, pn, q, n, ctx->part, ctx->stream));
     }
     return fetch_sum(ctx, pq);
 }

@@ -115,6 +115,84 @@ def test_full_operator_improves_on_x_approx_xi(torch_cuda):
     assert st1["rms_sigma"][-1] < st0["rms_sigma"][-1]
 
 
+@pytest.mark.parametrize("n", [64, 128])
+def test_full_residual_variants(torch_cuda, orc, n):
+    """r = b - L_K u with r.r and its FP32 copy: the per-node gather and the
+    streaming pass (several tiles and i-chunks, periodic wrap) against the
+    oracle's operator."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rec = binding.Recon(n, binding.Config(full_operator=1))
+    a, phi, b = solve_inputs(n, 960 + n)
+    u = np.random.default_rng(970 + n).normal(size=(n, n, n))
+    ref = b - orc.full_operator(phi, a, u)
+    args = [dev(torch, x) for x in (phi, a, u, b)]
+    for variant in (1, 2):
+        r, r32, rr = rec.full_residual(*args, variant=variant, fp32_copy=True)
+        r = host(r)
+        assert rel(r, ref) < 1e-13
+        assert abs(rr - (r * r).sum()) < 1e-12 * rr
+        assert np.array_equal(host(r32), r.astype(np.float32))
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_full_direction_variants(torch_cuda, orc, n):
+    """p_new = z + beta p_old, q = L_K p_new, p_new.q, and the deferred
+    u += alpha_u p_old: both variants against the oracle's operator, FP64
+    and FP32 directions."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rec = binding.Recon(n, binding.Config(full_operator=1))
+    a, phi, _ = solve_inputs(n, 980 + n)
+    rng = np.random.default_rng(990 + n)
+    z, p_old, u = (rng.normal(size=(n, n, n)) for _ in range(3))
+    beta, alpha_u = 0.37, -0.81
+    dphi, da = dev(torch, phi), dev(torch, a)
+    for variant in (1, 2):
+        # first step: p = z
+        pn, q, pq = rec.full_direction(dphi, da, dev(torch, z), None, 0.0, first=True, variant=variant)
+        assert np.array_equal(host(pn), z)
+        q = host(q)
+        assert rel(q, orc.full_operator(phi, a, z)) < 1e-13
+        assert abs(pq - (z * q).sum()) < 1e-11 * abs(pq)
+        # later step with the deferred solution update
+        ud = dev(torch, u)
+        pn, q, pq = rec.full_direction(dphi, da, dev(torch, z), dev(torch, p_old), beta, variant=variant,
+                                       u=ud, alpha_u=alpha_u)
+        pn, q = host(pn), host(q)
+        assert rel(pn, z + beta * p_old) < 1e-15
+        assert rel(q, orc.full_operator(phi, a, pn)) < 1e-13
+        assert abs(pq - (pn * q).sum()) < 1e-11 * abs(pq)
+        assert rel(host(ud), u + alpha_u * p_old) < 1e-15
+    # FP32 z and directions (streaming only): p_new rounded as formed, q of the rounded values
+    z32, p32 = z.astype(np.float32), p_old.astype(np.float32)
+    pn, q, pq = rec.full_direction(dphi, da, dev(torch, z32), dev(torch, p32), beta, variant=2,
+                                   p_dtype=torch.float32)
+    pn, q = host(pn), host(q)
+    assert pn.dtype == np.float32
+    want = (z32.astype(np.float64) + beta * p32.astype(np.float64)).astype(np.float32)
+    assert np.abs(pn.astype(np.float64) - want).max() <= 1.2e-7 * np.abs(want).max()
+    assert rel(q, orc.full_operator(phi, a, pn.astype(np.float64))) < 1e-13
+
+
+def test_full_solve_streaming_256(torch_cuda, orc):
+    """At 256^3 the solve runs the streaming kernels: its solution satisfies the
+    oracle's full operator equation to the solve's tolerance."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 256
+    a, phi, b = solve_inputs(n, 1000)
+    assert orc.is_pd(phi)
+    tol = 1e-10
+    for precision in (0, 1):
+        rec = binding.Recon(n, binding.Config(precision=precision, full_operator=1))
+        u, cyc, r = rec.mg_solve_full(dev(torch, a), dev(torch, phi), dev(torch, b), tol=tol)
+        u = host(u)
+        assert r <= tol and cyc < 40
+        assert rel(orc.full_operator(phi, a, u), b) <= 1.5 * tol
+        del rec
+
+
 def test_full_operator_config_errors(torch_cuda):
     torch = torch_cuda
     from paper_1611_09638_amd import binding
@@ -124,3 +202,9 @@ def test_full_operator_config_errors(torch_cuda):
     f = torch.ones((32, 32, 32), dtype=torch.float64, device="cuda")
     with pytest.raises(binding.ReconError):
         rec.mg_solve_full(f, f, f)
+    with pytest.raises(binding.ReconError):
+        rec.full_residual(f, f, f, f)
+    rec = binding.Recon(48, binding.Config(coarse_n=6, full_operator=1))
+    g = torch.ones((48, 48, 48), dtype=torch.float64, device="cuda")
+    with pytest.raises(binding.ReconError):  # streaming needs multiples of 64
+        rec.full_residual(g, g, g, g, variant=2)

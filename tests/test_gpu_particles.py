@@ -94,6 +94,65 @@ def test_particle_deposit_needs_particles(torch_cuda):
     rec = binding.Recon(32, binding.Config(particle_deposit=1))
     with pytest.raises(binding.ReconError):
         rec.solve(torch.ones((32, 32, 32), dtype=torch.float64, device="cuda"), 250.0)
-    for bad in (dict(record_tape=1), dict(mass_update=1)):
-        with pytest.raises(binding.ReconError):
-            binding.Recon(32, binding.Config(particle_deposit=1, **bad))
+    with pytest.raises(binding.ReconError):
+        binding.Recon(32, binding.Config(particle_deposit=1, mass_update=1))
+
+
+PCASES = [
+    # n, box, rms displacement (cells), seed, precision, every k-th particle, extra config
+    (16, 32.0, 1.0, 3, 0, 1, {}),
+    (32, 250.0, 1.2, 5, 0, 1, {}),
+    (32, 250.0, 1.2, 5, 1, 1, {}),
+    (32, 250.0, 1.0, 6, 0, 3, {}),
+    (48, 375.0, 1.0, 7, 1, 1, {"coarse_n": 6}),
+]
+
+
+@pytest.mark.parametrize("case", PCASES, ids=["16", "32", "32-mixed", "32-subsampled", "48-mixed"])
+def test_particle_gradient_matches_oracle(torch_cuda, orc, case):
+    """dL/d(positions) of a recorded particle-deposit forward, through the C
+    ABI, against the oracle's reverse mode (itself pinned to finite
+    differences)."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box, rms, seed, prec, every, extra = case
+    pos = np.ascontiguousarray(inputs.zeldovich_particles(n, box, rms, seed)[::every])
+    base = dict(max_outer=3, tol=1e-13, max_vcycles=300, particle_deposit=1, **extra)
+    rng = np.random.default_rng(seed)
+    gd = rng.normal(size=(n, n, n))
+    gp = rng.normal(size=(n, n, n)) * 1e-3
+    _, _, st_o = orc.solve_particles(pos, n, box, orc.Config(record_tape=1, **base))
+    g_o = orc.backward_particles(gd, gp, box, orc.Config(**base))
+    rec = binding.Recon(n, binding.Config(record_tape=1, precision=prec, **base))
+    pd = dev(torch, pos)
+    _, _, st = rec.solve_particles(pd, box)
+    assert st["alpha"] == st_o["alpha"]
+    g = rec.backward_particles(pd, dev(torch, gd), dev(torch, gp)).cpu().numpy()
+    assert g.shape == pos.shape
+    assert rel(g, g_o) < 1e-8, rel(g, g_o)
+    # a second backward of the same tape gives the same gradient: its Newton
+    # inversions start from other positions (the first step's, left by the
+    # first backward) and stop within 1e-12 cells, and the atomic sums run in
+    # another order
+    g2 = rec.backward_particles(pd, dev(torch, gd), dev(torch, gp)).cpu().numpy()
+    assert rel(g2, g) < 1e-10
+
+
+def test_particle_backward_errors(torch_cuda):
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 16, 32.0
+    pos = dev(torch, inputs.zeldovich_particles(n, box, 1.0, 3))
+    g = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    rec = binding.Recon(n, binding.Config(record_tape=1, particle_deposit=1, max_outer=2))
+    with pytest.raises(binding.ReconError):  # no tape yet
+        rec.backward_particles(pos, g)
+    rec.solve_particles(pos, box)
+    with pytest.raises(binding.ReconError):  # a particle tape has no density gradient
+        rec.backward(g)
+    with pytest.raises(binding.ReconError):  # other particles
+        rec.backward_particles(pos[:-1].contiguous(), g)
+    dens = binding.Recon(n, binding.Config(record_tape=1, max_outer=2))
+    dens.solve(1.0 + 0.1 * torch.rand((n, n, n), dtype=torch.float64, device="cuda"), box)
+    with pytest.raises(binding.ReconError):  # a density tape has no particle gradient
+        dens.backward_particles(pos, g)
