@@ -80,8 +80,9 @@ typedef struct recon_config {
     int full_operator;  /* 1: the linear system of each step is the exact Jacobian of the mass
                            map, div(M e^-1 grad u) = b on the current mesh (App. A, Eq.
                            elliptic_diff, without x ~ xi), solved by the same Krylov loop with
-                           the x ~ xi V-cycle of M as its preconditioner; 6 more FP64 fields
-                           of workspace.  No reverse mode: record_tape must be 0 (0)        */
+                           an x ~ xi V-cycle as its preconditioner, whose coefficient is the
+                           mean diagonal (K^xx + K^yy + K^zz) / 3 of K = M e^-1; 7 more FP64
+                           fields of workspace.  No reverse mode: record_tape must be 0 (0) */
     int fixed_cycles;   /* > 0: every linear solve runs exactly this many V-cycles, ignoring tol
                            (makes the forward a smooth map for finite differences) (0)      */
     int record_tape;    /* 1: keep every (u_i, alpha_i) so recon_backward can run          */
@@ -284,7 +285,7 @@ int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *
 /* The linear solve of the exact-Jacobian mode: div(K grad u) = b with
  * K = a e^-1, e = I + Hess phi (App. A, Eq. elliptic_diff without x ~ xi), in
  * the flux form of recon_stage_mass_change, by the context's Krylov loop
- * preconditioned by its x ~ xi V-cycle of a.  a, phi, b, u: n^3 FP64 device
+ * preconditioned by its x ~ xi V-cycle of the mean diagonal of K.  a, phi, b, u: n^3 FP64 device
  * fields of the context's edge (b mean-free, a > 0, phi with e positive
  * definite); u receives the mean-free solution.  Needs a context made with
  * full_operator = 1; RECON_E_NO_CONVERGENCE as recon_stage_mg_solve. */

@@ -44,7 +44,8 @@
  *   - optional exact-Jacobian solve (full_operator = 1): the linear system is
  *     div(M e^-1 grad u) = b, the operator of Eq. elliptic_diff on the current
  *     mesh instead of the x ~ xi one, solved by the same Krylov iteration
- *     with the x ~ xi V-cycle as preconditioner.
+ *     with an x ~ xi V-cycle as preconditioner, whose coefficient is the
+ *     mean diagonal (K^xx + K^yy + K^zz) / 3 of K = M e^-1.
  *   - optional particle deposit (particle_deposit = 1, particle input): each
  *     step, every particle's Lagrangian position xi_p with x(xi_p) = y_p is
  *     found by Newton's method on the continuous map x(xi) = xi + S(xi), S the
@@ -82,8 +83,9 @@ typedef struct {
     int mass_update; /* 0: M from the CIC gather each step; 1: M += alpha L_full[dphi] */
     int particle_deposit; /* particle input: 0 CIC onto the grid once, then the gather;
                              1 deposit the particles at their Lagrangian positions each step */
-    int full_operator; /* 1: the linear solve uses div(M e^-1 grad .) (no x ~ xi), with the
-                          x ~ xi V-cycle as its preconditioner */
+    int full_operator; /* 1: the linear solve uses div(M e^-1 grad .) (no x ~ xi), with an
+                          x ~ xi V-cycle (coefficient: mean diagonal of M e^-1) as its
+                          preconditioner */
     double tol;
     double outer_tol;
     double xi_m, v_m;
@@ -826,14 +828,32 @@ static void krylov_residual(const double *phi_full, const double *a0, const doub
 }
 
 /* The linear solve with the operator of krylov_apply (phi_full NULL: x ~ xi),
- * preconditioned by the x ~ xi V-cycle of a0. */
+ * preconditioned by one V-cycle of the x ~ xi operator whose coefficient is
+ * a0 (phi_full NULL) or the mean diagonal (K^xx + K^yy + K^zz) / 3 of
+ * K = a0 e^-1 (the scalar coefficient closest to the deformed operator's
+ * diagonal; it is a0 at phi = 0). */
 int orc_mg_solve_full(const double *a0, const double *phi_full, const double *b0, int n, const orc_config *cfg,
                       const double *u0, double *u_out, double *rel)
 {
     mg_t mg;
-    int rc = mg_alloc(&mg, a0, n, cfg);
-    if (rc) return rc;
     long N3 = cube(n);
+    double *ap = NULL;
+    if (phi_full) {
+        ap = (double *)malloc(sizeof(double) * N3);
+        #pragma omp parallel for
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                for (int k = 0; k < n; ++k) {
+                    long p = at(n, i, j, k);
+                    double e[3][3], inv[3][3];
+                    triad(phi_full, n, i, j, k, e);
+                    inverse3(e, inv);
+                    ap[p] = (a0[p] * inv[0][0] + a0[p] * inv[1][1] + a0[p] * inv[2][2]) / 3.0;
+                }
+    }
+    int rc = mg_alloc(&mg, ap ? ap : a0, n, cfg);
+    free(ap);
+    if (rc) return rc;
     double *u = (double *)calloc(N3, sizeof(double));
     double *r = (double *)malloc(sizeof(double) * N3);
     double *z = (double *)malloc(sizeof(double) * N3);

@@ -459,3 +459,27 @@ class Reconstruct(torch.autograd.Function):
             if g_delta is None else g_delta.contiguous()
         grad = ctx.recon.backward(g_delta, None if g_phi is None else g_phi.contiguous())
         return grad, None, None
+
+
+class ReconstructParticles(torch.autograd.Function):
+    """(delta_r, phi) = ReconstructParticles.apply(pos, recon, box) for float32
+    particle positions [np, 3] deposited at their Lagrangian positions; the
+    backward calls ``recon_backward_particles`` and returns dL/d(pos) in
+    FP64, cast to the dtype of pos.  ``recon`` must be a context created with
+    ``particle_deposit=1`` and ``record_tape=1``."""
+
+    @staticmethod
+    def forward(ctx, pos, recon: Recon, box: float):
+        pos = pos.contiguous()
+        phi, delta, _ = recon.solve_particles(pos, box)
+        ctx.recon = recon
+        ctx.save_for_backward(pos)
+        return delta, phi
+
+    @staticmethod
+    def backward(ctx, g_delta, g_phi):
+        (pos,) = ctx.saved_tensors
+        g_delta = torch.zeros((ctx.recon.n,) * 3, dtype=torch.float64, device=ctx.recon.device) \
+            if g_delta is None else g_delta.contiguous()
+        grad = ctx.recon.backward_particles(pos, g_delta, None if g_phi is None else g_phi.contiguous())
+        return grad.to(pos.dtype), None, None

@@ -64,6 +64,7 @@ hipError_t launch_pd25(const double *phi, const double *dphi, int n, int j0, int
 // K = M (I + Hess phi)^{-1}, its six components stored in K's fields.
 struct MassTensor {
     double *xx, *yy, *zz, *xy, *xz, *yz;
+    double *tr;  // optional: the mean diagonal (xx + yy + zz) / 3
 };
 hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
                               double *out, int n, hipStream_t s);

@@ -21,7 +21,9 @@ namespace recon {
 
 namespace {
 
-// K = M e^{-1} from the transposed cofactors of the symmetric triad.
+// K = M e^{-1} from the transposed cofactors of the symmetric triad, and
+// optionally its mean diagonal (the coefficient of the exact-Jacobian solve's
+// x ~ xi preconditioner).
 __global__ void k_mass_tensor(const double *__restrict__ phi, const double *__restrict__ M, MassTensor K, int n,
                               int ipb)
 {
@@ -41,6 +43,7 @@ __global__ void k_mass_tensor(const double *__restrict__ phi, const double *__re
         K.xy[p] = w * (e.xz * e.yz - e.xy * e.zz);
         K.xz[p] = w * (e.xy * e.yz - e.xz * e.yy);
         K.yz[p] = w * (e.xy * e.xz - e.xx * e.yz);
+        if (K.tr) K.tr[p] = (K.xx[p] + K.yy[p] + K.zz[p]) / 3.0;
     }
 }
 

@@ -57,7 +57,7 @@ struct Layout {
     size_t tape;
     size_t adj[8];
     size_t xi;  // particle deposit: Lagrangian positions, 3 per particle (up to n^3 particles)
-    size_t K;   // exact-Jacobian solve: K = M e^-1, 6 fields
+    size_t K;   // exact-Jacobian solve: K = M e^-1, 6 fields, and its mean diagonal
     int levels = 0;
 };
 
@@ -158,7 +158,7 @@ bool make_layout(int n, const recon_config *cfg, Layout &Lo)
         }
     }
     Lo.xi = cfg->particle_deposit ? take(3 * f64) : (size_t)-1;
-    Lo.K = cfg->full_operator ? take(6 * f64) : (size_t)-1;
+    Lo.K = cfg->full_operator ? take(7 * f64) : (size_t)-1;
     Lo.total = off;
     return true;
 }
@@ -445,7 +445,8 @@ int precondition(recon_ctx *ctx)
 // guess when ||b - A u|| < ||b||; otherwise the solve starts from u = 0.
 // With Kf the operator is L_K = div(K grad .) instead (the exact Jacobian of
 // the mass map, K = M e^-1 filled by the caller), still preconditioned by the
-// x ~ xi V-cycle of a0.
+// x ~ xi V-cycle of the built hierarchy (the caller builds it on K's mean
+// diagonal).
 int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int *cycles_out, double *rel_out,
              bool warm = false, const MassTensor *Kf = nullptr)
 {
@@ -702,7 +703,7 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
     const bool carry = c.mass_update != 0;
     const bool full = c.full_operator != 0;
     double *D = ctx->m;
-    const MassTensor K = full ? ctx->Kf : MassTensor{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q};
+    const MassTensor K = full ? ctx->Kf : MassTensor{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q, nullptr};
     int it = 0;
     for (; it < c.max_outer; ++it) {
         double rho_bar, rms, mean_t;
@@ -712,8 +713,10 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         if (!std::isfinite(rms)) return fail(ctx, RECON_E_NO_CONVERGENCE, "non-finite mass deviation");
         if (rms <= c.outer_tol) break;
         HIPCHK(launch_smooth(ctx->t, ctx->b, ctx->n, c.smooth_center, mean_t, ctx->stream));
-        TRY(build_hierarchy(ctx, ctx->M));
+        // the exact-Jacobian solve preconditions with the x ~ xi V-cycle of
+        // the mean diagonal of K = M e^-1
         if (full) HIPCHK(launch_mass_tensor(ctx->phi, ctx->M, K, ctx->n, ctx->stream));
+        TRY(build_hierarchy(ctx, full ? K.tr : ctx->M));
         int cyc = 0;
         double rel = 0.0;
         TRY(mg_solve(ctx, ctx->M, ctx->b, tol, &cyc, &rel, c.warm_start && it > 0, full ? &K : nullptr));
@@ -947,7 +950,13 @@ int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace,
     ctx->xi = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.xi) : nullptr;
     if (ctx->cfg.full_operator) {
         double *k0 = wsp<double>(ctx, lo.K);
-        ctx->Kf = MassTensor{k0, k0 + ctx->n3, k0 + 2 * ctx->n3, k0 + 3 * ctx->n3, k0 + 4 * ctx->n3, k0 + 5 * ctx->n3};
+        ctx->Kf = MassTensor{k0,
+                             k0 + ctx->n3,
+                             k0 + 2 * ctx->n3,
+                             k0 + 3 * ctx->n3,
+                             k0 + 4 * ctx->n3,
+                             k0 + 5 * ctx->n3,
+                             k0 + 6 * ctx->n3};
     }
     ctx->L64.L = ctx->L32.L = lo.levels;
     int nl = n;
@@ -1434,9 +1443,9 @@ int recon_stage_mg_solve_full(recon_ctx *ctx, const double *a, const double *phi
     if (!a || !phi || !b || !u || !(tol > 0.0)) return fail(ctx, RECON_E_ARG, "bad arguments");
     if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
     HIPCHK(launch_copy(ctx->M, a, ctx->n3, ctx->stream));
-    TRY(build_hierarchy(ctx, ctx->M));
     HIPCHK(launch_mass_tensor(phi, ctx->M, ctx->Kf, ctx->n, ctx->stream));
-    TRY(mg_solve(ctx, ctx->M, b, tol, cycles, rel_residual, false, &ctx->Kf));
+    TRY(build_hierarchy(ctx, ctx->Kf.tr));
+    TRY(mg_solve(ctx, ctx->Kf.tr, b, tol, cycles, rel_residual, false, &ctx->Kf));
     HIPCHK(launch_copy(u, ctx->u, ctx->n3, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
@@ -1469,7 +1478,7 @@ int recon_stage_mass_change(recon_ctx *ctx, const double *phi, const double *M, 
 {
     TRY(check_ctx(ctx));
     if (!phi || !M || !f || !out) return fail(ctx, RECON_E_ARG, "null array");
-    const MassTensor K{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q};
+    const MassTensor K{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q, nullptr};
     HIPCHK(launch_mass_change(phi, M, f, K, out, ctx->n, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;

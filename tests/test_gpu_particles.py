@@ -156,3 +156,20 @@ def test_particle_backward_errors(torch_cuda):
     dens.solve(1.0 + 0.1 * torch.rand((n, n, n), dtype=torch.float64, device="cuda"), box)
     with pytest.raises(binding.ReconError):  # a density tape has no particle gradient
         dens.backward_particles(pos, g)
+
+
+def test_autograd_function_for_particles(torch_cuda):
+    """ReconstructParticles.apply: the gradient reaching pos through autograd
+    is recon_backward_particles's."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 16, 32.0
+    pos = dev(torch, inputs.zeldovich_particles(n, box, 1.0, 3)).requires_grad_(True)
+    rec = binding.Recon(n, binding.Config(record_tape=1, particle_deposit=1, max_outer=3, tol=1e-13))
+    w = torch.from_numpy(np.random.default_rng(4).normal(size=(n, n, n))).cuda()
+    delta, phi = binding.ReconstructParticles.apply(pos, rec, box)
+    loss = (w * delta).sum() + 1e-3 * (w * phi).sum()
+    loss.backward()
+    g_ref = rec.backward_particles(pos.detach(), w, 1e-3 * w)
+    assert pos.grad.dtype == torch.float32
+    assert torch.allclose(pos.grad.double(), g_ref, rtol=1e-6, atol=1e-7 * float(g_ref.abs().max()))
