@@ -166,6 +166,7 @@ def lib():
             "orc_tape_steps": (i, []),
             "orc_backward": (i, [d, d, dbl, ctypes.POINTER(OrcConfig), d]),
             "orc_backward_particles": (i, [d, d, dbl, ctypes.POINTER(OrcConfig), d]),
+            "orc_full_operator_at": (None, [d, d, d, i, ctypes.POINTER(ctypes.c_long), ctypes.c_long, d]),
             "orc_tape_particles": (ctypes.c_long, []),
             "orc_eig_min_vec": (None, [d, d, d]),
             "orc_tape_clear": (None, []),
@@ -363,6 +364,16 @@ def delta_r(phi) -> np.ndarray:
 def lambda_min(e) -> float:
     e = np.ascontiguousarray(e, dtype=np.float64).reshape(9)
     return lib().orc_lambda_min(_p(e))
+
+
+def full_operator_at(phi, M, f, idx) -> np.ndarray:
+    """full_operator(phi, M, f).ravel()[idx], formed at the listed nodes only."""
+    phi, M, f = _f64(phi), _f64(M), _f64(f)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(len(idx))
+    lib().orc_full_operator_at(_p(phi), _p(M), _p(f), phi.shape[0],
+                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(idx), _p(out))
+    return out
 
 
 def triad_at(phi, i, j, k) -> np.ndarray:

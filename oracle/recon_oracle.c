@@ -302,6 +302,55 @@ void orc_full_operator(const double *phi, const double *M, const double *f, int 
     free(K);
 }
 
+/* orc_full_operator at the listed nodes only (flat indices idx[0..count)),
+ * with K = M e^-1 formed at each node where it is needed: for checks of
+ * large grids at sampled nodes.  Same arithmetic as orc_full_operator. */
+static void k_at(const double *phi, const double *M, int n, int i, int j, int k, double K[9])
+{
+    double e[3][3], inv[3][3];
+    long p = at(n, i, j, k);
+    triad(phi, n, i, j, k, e);
+    inverse3(e, inv);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) K[3 * a + b] = M[p] * inv[a][b];
+}
+
+void orc_full_operator_at(const double *phi, const double *M, const double *f, int n, const long *idx, long count,
+                          double *out)
+{
+    int d[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    #pragma omp parallel for
+    for (long c = 0; c < count; ++c) {
+        long q = idx[c];
+        int i = (int)(q / ((long)n * n)), j = (int)((q / n) % n), k = (int)(q % n);
+        long p = at(n, i, j, k);
+        double Kc[9], Kup[3][9], Kdn[3][9];
+        k_at(phi, M, n, i, j, k, Kc);
+        for (int a = 0; a < 3; ++a) {
+            k_at(phi, M, n, i + d[a][0], j + d[a][1], k + d[a][2], Kup[a]);
+            k_at(phi, M, n, i - d[a][0], j - d[a][1], k - d[a][2], Kdn[a]);
+        }
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            long up = at(n, i + d[a][0], j + d[a][1], k + d[a][2]);
+            long dn = at(n, i - d[a][0], j - d[a][1], k - d[a][2]);
+            double kup = 0.5 * (Kc[4 * a] + Kup[a][4 * a]);
+            double kdn = 0.5 * (Kdn[a][4 * a] + Kc[4 * a]);
+            s += kup * (f[up] - f[p]) - kdn * (f[p] - f[dn]);
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                if (a == b) continue;
+                double fu = f[at(n, i + d[a][0] + d[b][0], j + d[a][1] + d[b][1], k + d[a][2] + d[b][2])] -
+                            f[at(n, i + d[a][0] - d[b][0], j + d[a][1] - d[b][1], k + d[a][2] - d[b][2])];
+                double fd = f[at(n, i - d[a][0] + d[b][0], j - d[a][1] + d[b][1], k - d[a][2] + d[b][2])] -
+                            f[at(n, i - d[a][0] - d[b][0], j - d[a][1] - d[b][1], k - d[a][2] - d[b][2])];
+                s += 0.25 * (Kup[a][3 * a + b] * fu - Kdn[a][3 * a + b] * fd);
+            }
+        out[c] = s;
+    }
+}
+
 /* Central-difference gradient of phi: the displacement x - xi at a node. */
 static void displacement(const double *phi, int n, int i, int j, int k, double s[3])
 {

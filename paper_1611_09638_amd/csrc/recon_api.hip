@@ -1258,7 +1258,7 @@ int recon_stage_full_residual(recon_ctx *ctx, const double *phi, const double *M
     if (!phi || !M || !u || !b || !r || !rr || variant < 0 || variant > 2 || r == u || r == b)
         return fail(ctx, RECON_E_ARG, "bad arguments");
     if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
-    const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
+    const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n) && full25_supported(n));
     if (stream && !full25_supported(n))
         return fail(ctx, RECON_E_ARG, "the streaming full operator needs an edge that is a multiple of 64");
     HIPCHK(launch_mass_tensor(phi, M, ctx->Kf, n, ctx->stream));
@@ -1280,7 +1280,7 @@ int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *
         (u && (first || (const void *)u == p_old || (void *)u == p_new || u == q || (const void *)u == z)))
         return fail(ctx, RECON_E_ARG, "bad arguments");
     if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
-    const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
+    const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n) && full25_supported(n));
     if (stream && !full25_supported(n))
         return fail(ctx, RECON_E_ARG, "the streaming full operator needs an edge that is a multiple of 64");
     if (p_dtype == 1 && (!stream || z_dtype != 1))

@@ -103,6 +103,23 @@ def test_full_operator_reconstruction_against_oracle(torch_cuda, n, sigma, mass_
         assert st["vcycles"] == st_o["vcycles"]
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_full_operator_with_plain_vcycle_iteration(torch_cuda, orc, precision):
+    """solver = V-cycle iteration u += V(b - L_K u) on the exact Jacobian."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 32, 500.0
+    rho = inputs.lognormal_density(n, box, 1.0, 7)
+    phi_o, dr_o, st_o = orc.solve(rho, box, orc.Config(full_operator=1, solver=1, max_vcycles=300))
+    rec = binding.Recon(n, binding.Config(precision=precision, full_operator=1, solver=1, max_vcycles=300))
+    phi, dr, st = rec.solve(dev(torch, rho), box)
+    assert st["alpha"] == st_o["alpha"]
+    assert rel(host(phi), phi_o) < 1e-6
+    assert rel(host(dr), dr_o) < 1e-6
+    if precision == 0:
+        assert st["vcycles"] == st_o["vcycles"]
+
+
 def test_full_operator_improves_on_x_approx_xi(torch_cuda):
     """On a 64^3 sigma_g = 1 lognormal the exact-Jacobian mode leaves less mass
     deviation after ten steps than the x ~ xi mode (both on the GPU)."""
@@ -208,3 +225,60 @@ def test_full_operator_config_errors(torch_cuda):
     g = torch.ones((48, 48, 48), dtype=torch.float64, device="cuda")
     with pytest.raises(binding.ReconError):  # streaming needs multiples of 64
         rec.full_residual(g, g, g, g, variant=2)
+
+
+def test_full_operator_kernels_at_512(torch_cuda, orc):
+    """The streaming exact-Jacobian kernels at 512^3, in the launch shape the
+    solve uses there (8 x 64 tiles, 256-plane i-chunks), against the oracle's
+    operator formed at 4096 sampled nodes (and the faces and corners of the
+    periodic box): the residual with its norm, and the direction pass in FP64
+    and with FP32 directions, with the deferred solution update."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 512
+    w = inputs.WORKLOADS["lognormal512_mild"]
+    rng = np.random.default_rng(5120)
+    M = inputs.lognormal_density(n, w["box"], w["sigma_g"], w["seed"])
+    M /= M.mean()
+    g = inputs.gaussian_field(n, w["box"], 5121)
+    phi = 0.3 * g / np.abs(g).max()
+    del g
+    idx = np.concatenate([[0, n - 1, n * n - 1, n ** 3 - 1, n ** 3 - n * n, (n // 2) * (n * n + n + 1)],
+                          rng.choice(n ** 3, 4096, replace=False)])
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED, full_operator=1))
+    dphi, dM = dev(torch, phi), dev(torch, M)
+    # residual r = b - L_K u with r.r and its FP32 copy
+    u = rng.standard_normal((n, n, n))
+    b = rng.standard_normal((n, n, n))
+    r, r32, rr = rec.full_residual(dphi, dM, dev(torch, u), dev(torch, b), variant=2, fp32_copy=True)
+    r = host(r)
+    ref = b.ravel()[idx] - orc.full_operator_at(phi, M, u, idx)
+    assert np.abs(r.ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(rr - float(np.dot(r.ravel(), r.ravel()))) <= 1e-10 * rr
+    assert np.array_equal(host(r32).ravel()[idx], r.ravel()[idx].astype(np.float32))
+    del r, r32, b
+    # FP64 direction with the deferred update
+    z = rng.standard_normal((n, n, n))
+    p_old = rng.standard_normal((n, n, n))
+    beta, alpha_u = 0.41, 0.73
+    ud = dev(torch, u)
+    pn, q, pq = rec.full_direction(dphi, dM, dev(torch, z), dev(torch, p_old), beta, variant=2, u=ud,
+                                   alpha_u=alpha_u)
+    pn, q = host(pn), host(q)
+    p_ref = z + beta * p_old
+    assert np.abs(pn - p_ref).max() <= 1e-15 * np.abs(p_ref).max()
+    ref = orc.full_operator_at(phi, M, p_ref, idx)
+    assert np.abs(q.ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(pq - float(np.dot(pn.ravel(), q.ravel()))) <= 1e-10 * abs(pq)
+    assert np.abs(host(ud).ravel()[idx] - (u + alpha_u * p_old).ravel()[idx]).max() <= 1e-15 * np.abs(u).max() * 4
+    del pn, q, ud
+    # FP32 z and directions, as the mixed solve runs them
+    z32, p32 = z.astype(np.float32), p_old.astype(np.float32)
+    del z, p_old
+    pn, q, pq = rec.full_direction(dphi, dM, dev(torch, z32), dev(torch, p32), beta, variant=2,
+                                   p_dtype=torch.float32)
+    pn = host(pn)
+    p_ref = (z32.astype(np.float64) + beta * p32.astype(np.float64)).astype(np.float32)
+    assert np.abs(pn.astype(np.float64) - p_ref).max() <= 1.2e-7 * np.abs(p_ref).max()
+    ref = orc.full_operator_at(phi, M, pn.astype(np.float64), idx)
+    assert np.abs(host(q).ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()

@@ -750,3 +750,16 @@ def test_full_operator_reconstruction_converges_further(orc):
     assert st1["rms_sigma"][10] < 0.7 * st0["rms_sigma"][10]
     assert all(a == 1.0 for a in st1["alpha"][5:])
     assert st1["min_det"] > 0 and st1["min_lambda0"] > 0
+
+
+def test_full_operator_at_sampled_nodes(orc):
+    """The sampled form of the full operator (for checks of large grids) is the
+    full form at those nodes, including the faces and corners of the box."""
+    n = 24
+    rng = np.random.default_rng(1)
+    M = np.exp(0.5 * rng.normal(size=(n, n, n))) + 0.05
+    g = inputs.gaussian_field(n, 200.0, 3)
+    phi = 0.3 * g / np.abs(g).max()
+    f = rng.normal(size=(n, n, n))
+    idx = np.concatenate([[0, n - 1, n * n - 1, n ** 3 - 1], rng.choice(n ** 3, 300, replace=False)])
+    assert np.array_equal(orc.full_operator_at(phi, M, f, idx), orc.full_operator(phi, M, f).ravel()[idx])
