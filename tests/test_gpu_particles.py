@@ -30,6 +30,10 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
+def host(t):
+    return t.detach().cpu().numpy()
+
+
 def periodic_gap(a, b, n):
     d = a - b
     return np.abs(d - n * np.round(d / n)).max()
@@ -173,3 +177,33 @@ def test_autograd_function_for_particles(torch_cuda):
     g_ref = rec.backward_particles(pos.detach(), w, 1e-3 * w)
     assert pos.grad.dtype == torch.float32
     assert torch.allclose(pos.grad.double(), g_ref, rtol=1e-6, atol=1e-7 * float(g_ref.abs().max()))
+
+
+def test_inversion_and_deposit_at_512(torch_cuda, orc):
+    """134M Zel'dovich particles at 512^3 (rms displacement 1.5 cells) on a
+    deformed mesh, in the launch shape of the solve: every particle located
+    (cold start from its Eulerian position), the Lagrangian positions against
+    the oracle's own inversion, and the xi-space deposit against the oracle's
+    deposit of its own positions."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 512, 1000.0
+    pos = inputs.zeldovich_particles(n, box, 1.5, 5130)
+    g = inputs.gaussian_field(n, box, 5131)
+    phi = 0.4 * g / np.abs(g).max()
+    del g
+    assert orc.is_pd(phi)
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED, particle_deposit=1))
+    xi, bad = rec.invert_map(dev(torch, phi), dev(torch, pos), box)
+    assert bad == 0
+    M = host(rec.deposit_xi(xi))
+    xi = host(xi)
+    del rec
+    y = pos.astype(np.float64) * (n / box)
+    del pos
+    xi_o = orc.invert_map(phi, y)
+    assert periodic_gap(xi, xi_o, n) < 1e-9
+    del xi, y
+    M_o = orc.deposit_xi(xi_o, n)
+    assert rel(M, M_o) < 1e-12
+    assert abs(M.sum() - n ** 3) < 1e-9 * n ** 3 and M.min() >= 0.0
