@@ -1,6 +1,7 @@
 """The oracle built with AddressSanitizer and UBSan (every report fatal) runs
-a small forward solve, its reverse mode and the stage routines cleanly, in a
-child process on the CPU (the ASan runtime has to be preloaded there)."""
+small forward solves in every mode, both reverse modes and the stage routines
+cleanly, in a child process on the CPU (the ASan runtime has to be preloaded
+there)."""
 import os
 import subprocess
 import sys
@@ -27,7 +28,19 @@ a = oracle.normalize(rho)
 r = np.random.default_rng(2).normal(size=rho.shape)
 r -= r.mean()
 z = oracle.vcycle(a, r)
-print("ok", st["outer_steps"], st2["outer_steps"], float(np.linalg.norm(g)), float(np.linalg.norm(z)))
+# particles at their Lagrangian positions, with the exact-Jacobian solve and
+# the mass update, and the reverse mode of the particle deposit
+pos = inputs.zeldovich_particles(16, 32.0, 1.0, 3)
+pcfg = dict(max_outer=2, tol=1e-12, particle_deposit=1)
+oracle.solve_particles(pos, 16, 32.0, oracle.Config(record_tape=1, **pcfg))
+gp = oracle.backward_particles(np.random.default_rng(3).normal(size=(16, 16, 16)), None, 32.0,
+                               oracle.Config(**pcfg))
+oracle.solve_particles(pos, 16, 32.0, oracle.Config(max_outer=2, particle_deposit=1, full_operator=1))
+oracle.solve(rho, 125.0, oracle.Config(max_outer=2, mass_update=1, full_operator=1))
+idx = np.array([0, 7, 4095])
+fo = oracle.full_operator_at(phi / (125.0 / 16) ** 2, a, r, idx)
+print("ok", st["outer_steps"], st2["outer_steps"], float(np.linalg.norm(g)), float(np.linalg.norm(z)),
+      float(np.linalg.norm(gp)), float(np.linalg.norm(fo)))
 """ % ROOT
 
 
