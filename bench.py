@@ -171,7 +171,10 @@ def quality_bench(torch, binding, inputs):
     displacements of 1.5 and 3.5 cells; on the 3.5-cell input (where the
     compression limiter engages) with 20 outer steps, the sweeps xi_m in (1/5,
     1/10, 1/20) at v_m = 10 and v_m in (5, 10, 20) at xi_m = 1/10 (App. B).
-    Diagnostics on the host (numpy)."""
+    The library's options are compared on the same inputs: the exact-Jacobian
+    solve, the particles deposited at their Lagrangian positions (alone and
+    with the exact Jacobian) and the paper's mass update.  Diagnostics on the
+    host (numpy)."""
     from paper_1611_09638_amd import diagnostics as dg
     n, box = 256, 600.0
     dev = torch.device("cuda:0")
@@ -181,11 +184,15 @@ def quality_bench(torch, binding, inputs):
         dl = dg.linear_density(psi)
         pos = torch.from_numpy(inputs.particles_from_displacement(psi, box)).to(dev)
         del psi
-        runs = [("default", {})]
+        runs = [("default", {}), ("exact Jacobian", dict(full_operator=1)),
+                ("particle deposit", dict(particle_deposit=1)),
+                ("particle deposit + exact Jacobian", dict(particle_deposit=1, full_operator=1)),
+                ("mass update", dict(mass_update=1))]
         if rms == 3.5:
             runs = [("xi_m=%g" % x, dict(xi_m=x, max_outer=20)) for x in (0.2, 0.1, 0.05)]
             runs += [("v_m=%g" % v, dict(v_m=v, max_outer=20)) for v in (5.0, 20.0)]
-            runs += [("xi_m=0.1,10 steps", {})]
+            runs += [("xi_m=0.1,10 steps", {}), ("exact Jacobian, 20 steps", dict(full_operator=1, max_outer=20)),
+                     ("particle deposit, 20 steps", dict(particle_deposit=1, max_outer=20))]
         rec = binding.Recon(n, binding.Config(precision=binding.MIXED), device=dev)
         nl = dg.propagator(rec.cic(pos, box).cpu().numpy() - 1.0, dl, box, 16)
         del rec
@@ -194,7 +201,14 @@ def quality_bench(torch, binding, inputs):
         for label, kw in runs:
             rec = binding.Recon(n, binding.Config(precision=binding.MIXED, **kw), device=dev)
             t0 = time.perf_counter()
-            _, dr, st = rec.solve_particles(pos, box, want_phi=False)
+            try:
+                _, dr, st = rec.solve_particles(pos, box, want_phi=False)
+            except binding.ReconError as e:
+                block[label] = {"error": str(e)}
+                log("rms %.1f %s: %s" % (rms, label, e))
+                del rec
+                torch.cuda.empty_cache()
+                continue
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             q = dg.propagator(dr.cpu().numpy(), dl, box, 16)
