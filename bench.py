@@ -10,8 +10,10 @@ and both are compared (rel. L2 of phi and delta_r).  The finest-level
 red-black Gauss-Seidel smoother is timed live with hipEvents inside the
 library (cfg.profile) to give its achieved HBM bandwidth.
 
-Prints one JSON line.  --gpus N > 1 is not supported (one GPU per process;
-the multi-GPU decomposition is described in the design doc).
+Prints one JSON line.  --gpus N > 1 is not supported: the library runs one
+GPU per process, and a split of the grid into i-slabs over several GPUs
+(one-plane halo exchanges per sweep, scalar all-reduces per Krylov step) is
+not built.
 """
 import argparse
 import json
@@ -336,8 +338,8 @@ def main():
                          "mixed precision, and the bandwidth of its two kernels")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU (one process per GPU; --gpus %d is not supported, "
-              "see DESIGN.md for the multi-GPU decomposition)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on exactly one GPU (one process per GPU); --gpus %d is not supported: "
+              "the multi-GPU slab decomposition is not built" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -13,7 +13,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
-    # packed FP32 instructions off (build notes)
+    # no packed FP32 instructions: hipcc would otherwise form them from scalar
+    # and float2 code, and the kernels are kept on plain FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
