@@ -134,7 +134,8 @@ def particle_bench(torch, binding, inputs, args):
     """512^3 Zel'dovich particles (1000 Mpc/h, rms displacement 1.5 cells, seed
     5), mixed precision: particles assigned to the grid once (the default) and
     deposited at their Lagrangian positions every step; wall time, steps, and
-    the correlation of the two delta_r."""
+    the correlation of the two delta_r; then the reverse mode of the latter
+    (forward with a tape, and the gradient with respect to the positions)."""
     n, box = 512, 1000.0
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -162,6 +163,23 @@ def particle_bench(torch, binding, inputs, args):
         del rec
         torch.cuda.empty_cache()
     out["corr_delta_r"] = float(torch.corrcoef(torch.stack([res[0].flatten(), res[1].flatten()]))[0, 1])
+    # reverse mode of the deposit-each-step solve: dL/d(positions) for a
+    # random linear loss on delta_r, with an FP64 tape
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED, particle_deposit=1, record_tape=1), device=dev)
+    gd = torch.randn((n, n, n), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(7))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec.solve_particles(pos, box, want_phi=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = rec.backward_particles(pos, gd)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["reverse_mode"] = {"forward_with_tape_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+                           "grad_rms": float(g.pow(2).mean().sqrt()), "grad_finite": bool(torch.isfinite(g).all())}
+    log("particle reverse mode: forward %.3f s, backward %.3f s" % (t1 - t0, t2 - t1))
+    del rec, g
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
