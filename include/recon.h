@@ -79,7 +79,8 @@ typedef struct recon_config {
                            recon_backward_particles (0)                                     */
     int full_operator;  /* 1: the linear system of each step is the exact Jacobian of the mass
                            map, div(M e^-1 grad u) = b on the current mesh (App. A, Eq.
-                           elliptic_diff, without x ~ xi), solved by the same Krylov loop with
+                           elliptic_diff, without x ~ xi; diagonal face coefficients floored at
+                           a_min as in the x ~ xi operator), solved by the same Krylov loop with
                            an x ~ xi V-cycle as its preconditioner, whose coefficient is the
                            mean diagonal (K^xx + K^yy + K^zz) / 3 of K = M e^-1; 7 more FP64
                            fields of workspace.  No reverse mode: record_tape must be 0 (0) */
@@ -265,7 +266,8 @@ int recon_stage_mg_solve(recon_ctx *ctx, const double *a, const double *b, doubl
 
 /* The Krylov residual of the exact-Jacobian mode: K = M e^-1 from phi (into
  * the context's K fields), r = b - div(K grad u) in the flux form of
- * recon_stage_mass_change, r32 (FP32, may be NULL) a copy of r, *rr (host)
+ * recon_stage_mass_change with the diagonal face coefficients floored at the
+ * config's a_min, r32 (FP32, may be NULL) a copy of r, *rr (host)
  * <- r.r.  All FP64 n^3 device fields except r32; r distinct from u and b.
  * variant 1: per-node gathers; 2: one streaming pass (edges that are
  * multiples of 64); 0: the solve's choice.  Needs full_operator = 1. */
@@ -273,7 +275,8 @@ int recon_stage_full_residual(recon_ctx *ctx, const double *phi, const double *M
                               double *r, float *r32, double *rr, int variant);
 
 /* One Krylov direction of the exact-Jacobian mode: K = M e^-1 from phi, then
- * as recon_stage_direction with the operator div(K grad .) in place of A:
+ * as recon_stage_direction with the operator div(K grad .) (diagonal face
+ * coefficients floored at a_min) in place of A:
  * p_new = z or z + beta p_old, q = div(K grad p_new), *pq <- p_new.q, and
  * u += alpha_u p_old when u is not NULL; same dtypes, aliasing rules and
  * variants (2: one streaming pass, edges that are multiples of 64).  Needs
@@ -284,13 +287,15 @@ int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *
 
 /* The linear solve of the exact-Jacobian mode: div(K grad u) = b with
  * K = a e^-1, e = I + Hess phi (App. A, Eq. elliptic_diff without x ~ xi), in
- * the flux form of recon_stage_mass_change, by the context's Krylov loop
- * preconditioned by its x ~ xi V-cycle of the mean diagonal of K.  a, phi, b, u: n^3 FP64 device
- * fields of the context's edge (b mean-free, a > 0, phi with e positive
- * definite); u receives the mean-free solution.  Needs a context made with
- * full_operator = 1; RECON_E_NO_CONVERGENCE as recon_stage_mg_solve. */
+ * the flux form of recon_stage_mass_change with the diagonal face
+ * coefficients floored at a_min, by the context's Krylov loop preconditioned
+ * by its x ~ xi V-cycle of the mean diagonal of K.  a, phi, b, u: n^3 FP64
+ * device fields of the context's edge (b mean-free, a > 0, phi with e
+ * positive definite); u receives the mean-free solution.  Needs a context
+ * made with full_operator = 1; RECON_E_NO_CONVERGENCE as recon_stage_mg_solve. */
 int recon_stage_mg_solve_full(recon_ctx *ctx, const double *a, const double *phi, const double *b, double tol,
                               double *u, int *cycles, double *rel_residual);
+
 /* First alpha = 2^-j keeping I + Hess(phi + alpha dphi) positive definite
  * everywhere with max |alpha D_c dphi| <= s_max (host output); returns
  * RECON_E_NOT_PD if none of j = 0..max_halvings does. */

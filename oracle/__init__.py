@@ -155,6 +155,7 @@ def lib():
             "orc_choose_step": (i, [d, d, i, ctypes.POINTER(OrcConfig), d]),
             "orc_choose_step_mass": (i, [d, d, d, d, i, ctypes.POINTER(OrcConfig), d]),
             "orc_full_operator": (None, [d, d, d, i, d]),
+            "orc_full_operator_floor": (None, [d, d, d, i, dbl, d]),
             "orc_invert_map": (i, [d, i, d, ctypes.c_long, d, i, dbl]),
             "orc_deposit_xi": (None, [d, ctypes.c_long, i, d]),
             "orc_solve_particles": (i, [fp, ll, i, dbl, ctypes.POINTER(OrcConfig), d, d, ctypes.POINTER(OrcStats)]),
@@ -166,7 +167,7 @@ def lib():
             "orc_tape_steps": (i, []),
             "orc_backward": (i, [d, d, dbl, ctypes.POINTER(OrcConfig), d]),
             "orc_backward_particles": (i, [d, d, dbl, ctypes.POINTER(OrcConfig), d]),
-            "orc_full_operator_at": (None, [d, d, d, i, ctypes.POINTER(ctypes.c_long), ctypes.c_long, d]),
+            "orc_full_operator_at": (None, [d, d, d, i, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dbl, d]),
             "orc_tape_particles": (ctypes.c_long, []),
             "orc_eig_min_vec": (None, [d, d, d]),
             "orc_tape_clear": (None, []),
@@ -346,11 +347,16 @@ def choose_step(phi, dphi, cfg: Config | None = None, M=None, D=None):
     return j, (alpha.value if j >= 0 else None)
 
 
-def full_operator(phi, M, f) -> np.ndarray:
-    """div(M e^-1 grad f) with e = I + Hess phi: the exact mass change of App. A."""
+def full_operator(phi, M, f, a_min: float = 0.0) -> np.ndarray:
+    """div(M e^-1 grad f) with e = I + Hess phi: the exact mass change of App. A
+    (a_min = 0), or the exact-Jacobian solve's operator, whose diagonal face
+    coefficients are floored at a_min (a_min > 0)."""
     phi, M, f = _f64(phi), _f64(M), _f64(f)
     out = np.empty_like(f)
-    lib().orc_full_operator(_p(phi), _p(M), _p(f), phi.shape[0], _p(out))
+    if a_min > 0.0:
+        lib().orc_full_operator_floor(_p(phi), _p(M), _p(f), phi.shape[0], float(a_min), _p(out))
+    else:
+        lib().orc_full_operator(_p(phi), _p(M), _p(f), phi.shape[0], _p(out))
     return out
 
 
@@ -366,13 +372,13 @@ def lambda_min(e) -> float:
     return lib().orc_lambda_min(_p(e))
 
 
-def full_operator_at(phi, M, f, idx) -> np.ndarray:
-    """full_operator(phi, M, f).ravel()[idx], formed at the listed nodes only."""
+def full_operator_at(phi, M, f, idx, a_min: float = 0.0) -> np.ndarray:
+    """full_operator(phi, M, f, a_min).ravel()[idx], formed at the listed nodes only."""
     phi, M, f = _f64(phi), _f64(M), _f64(f)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     out = np.empty(len(idx))
     lib().orc_full_operator_at(_p(phi), _p(M), _p(f), phi.shape[0],
-                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(idx), _p(out))
+                               idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), len(idx), float(a_min), _p(out))
     return out
 
 

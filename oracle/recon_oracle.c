@@ -43,7 +43,8 @@
  *     definite at every node (Sylvester) and max |alpha D_c dphi| <= s_max.
  *   - optional exact-Jacobian solve (full_operator = 1): the linear system is
  *     div(M e^-1 grad u) = b, the operator of Eq. elliptic_diff on the current
- *     mesh instead of the x ~ xi one, solved by the same Krylov iteration
+ *     mesh instead of the x ~ xi one (diagonal face coefficients floored at
+ *     a_min like the x ~ xi operator's), solved by the same Krylov iteration
  *     with an x ~ xi V-cycle as preconditioner, whose coefficient is the
  *     mean diagonal (K^xx + K^yy + K^zz) / 3 of K = M e^-1.
  *   - optional particle deposit (particle_deposit = 1, particle input): each
@@ -256,8 +257,12 @@ static void inverse3(const double e[3][3], double inv[3][3])
  *   cross:    sum_{mu != nu} [ K^{munu}_{n+mu} (f_{n+mu+nu} - f_{n+mu-nu})
  *                            - K^{munu}_{n-mu} (f_{n-mu+nu} - f_{n-mu-nu}) ] / 4
  * (central differences of the flux K^{munu} d_nu f in direction mu).  At
- * phi = 0 it is the operator of the solve without the a_min floor. */
-void orc_full_operator(const double *phi, const double *M, const double *f, int n, double *out)
+ * phi = 0 it is the operator of the solve without the a_min floor.
+ * orc_full_operator_floor with a_min > 0 floors the diagonal face
+ * coefficients at a_min as the x ~ xi operator does (the operator of the
+ * exact-Jacobian solve, equal to the x ~ xi one at phi = 0); the mass update
+ * uses the unfloored form (a_min = 0), the exact change. */
+void orc_full_operator_floor(const double *phi, const double *M, const double *f, int n, double a_min, double *out)
 {
     long N3 = cube(n);
     double *K = (double *)malloc(sizeof(double) * 9 * N3);
@@ -284,6 +289,10 @@ void orc_full_operator(const double *phi, const double *M, const double *f, int 
                     long dn = at(n, i - d[a][0], j - d[a][1], k - d[a][2]);
                     double kup = 0.5 * (K[9 * p + 4 * a] + K[9 * up + 4 * a]);
                     double kdn = 0.5 * (K[9 * dn + 4 * a] + K[9 * p + 4 * a]);
+                    if (a_min > 0.0) {
+                        kup = fmax(a_min, kup);
+                        kdn = fmax(a_min, kdn);
+                    }
                     s += kup * (f[up] - f[p]) - kdn * (f[p] - f[dn]);
                 }
                 for (int a = 0; a < 3; ++a)
@@ -302,6 +311,11 @@ void orc_full_operator(const double *phi, const double *M, const double *f, int 
     free(K);
 }
 
+void orc_full_operator(const double *phi, const double *M, const double *f, int n, double *out)
+{
+    orc_full_operator_floor(phi, M, f, n, 0.0, out);
+}
+
 /* orc_full_operator at the listed nodes only (flat indices idx[0..count)),
  * with K = M e^-1 formed at each node where it is needed: for checks of
  * large grids at sampled nodes.  Same arithmetic as orc_full_operator. */
@@ -316,7 +330,7 @@ static void k_at(const double *phi, const double *M, int n, int i, int j, int k,
 }
 
 void orc_full_operator_at(const double *phi, const double *M, const double *f, int n, const long *idx, long count,
-                          double *out)
+                          double a_min, double *out)
 {
     int d[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     #pragma omp parallel for
@@ -336,6 +350,10 @@ void orc_full_operator_at(const double *phi, const double *M, const double *f, i
             long dn = at(n, i - d[a][0], j - d[a][1], k - d[a][2]);
             double kup = 0.5 * (Kc[4 * a] + Kup[a][4 * a]);
             double kdn = 0.5 * (Kdn[a][4 * a] + Kc[4 * a]);
+            if (a_min > 0.0) {
+                kup = fmax(a_min, kup);
+                kdn = fmax(a_min, kdn);
+            }
             s += kup * (f[up] - f[p]) - kdn * (f[p] - f[dn]);
         }
         for (int a = 0; a < 3; ++a)
@@ -860,10 +878,11 @@ int orc_vcycle(const double *a0, const double *r, int n, const orc_config *cfg, 
  * Returns the number of V-cycles (>= 0) or a negative error; *rel receives
  * the final true relative residual. */
 /* out = L x: the x ~ xi operator of coefficient a0, or (phi_full given) the
- * full operator div(a0 e^-1 grad x) on the mesh of phi_full. */
+ * full operator div(a0 e^-1 grad x) on the mesh of phi_full, its diagonal
+ * face coefficients floored at a_min like the x ~ xi operator's. */
 static void krylov_apply(const double *phi_full, const double *a0, const double *x, int n, double a_min, double *out)
 {
-    if (phi_full) orc_full_operator(phi_full, a0, x, n, out);
+    if (phi_full) orc_full_operator_floor(phi_full, a0, x, n, a_min, out);
     else orc_apply(x, a0, n, 1.0, a_min, out);
 }
 

@@ -192,16 +192,23 @@ struct FluxK {
 };
 
 // div(K grad f) at a node in flux form on the periodic lattice: diagonal
-// fluxes with face-averaged coefficients, cross fluxes as central differences
-// of K^{mu nu} d_nu f taken at the two neighbours along mu (sums to zero over
-// the lattice; at K = a I it is the x ~ xi operator without the face floor).
-__device__ __forceinline__ double full_flux(const Stencil19 &s, const FluxK &K)
+// fluxes with face-averaged coefficients (floored at a_min when a_min > 0,
+// as the x ~ xi operator's), cross fluxes as central differences of
+// K^{mu nu} d_nu f taken at the two neighbours along mu (sums to zero over
+// the lattice; at K = a I it is the x ~ xi operator, with its floor when
+// a_min > 0).
+__device__ __forceinline__ double face_floor(double k, double a_min) { return a_min > 0.0 ? fmax(a_min, k) : k; }
+
+__device__ __forceinline__ double full_flux(const Stencil19 &s, const FluxK &K, double a_min)
 {
     double acc = 0.0;
     // diagonal fluxes, directions x, y, z
-    acc += 0.5 * (K.xx_c + K.xx_p) * (s.xp - s.c) - 0.5 * (K.xx_m + K.xx_c) * (s.c - s.xm);
-    acc += 0.5 * (K.yy_c + K.yy_p) * (s.yp - s.c) - 0.5 * (K.yy_m + K.yy_c) * (s.c - s.ym);
-    acc += 0.5 * (K.zz_c + K.zz_p) * (s.zp - s.c) - 0.5 * (K.zz_m + K.zz_c) * (s.c - s.zm);
+    acc += face_floor(0.5 * (K.xx_c + K.xx_p), a_min) * (s.xp - s.c) -
+           face_floor(0.5 * (K.xx_m + K.xx_c), a_min) * (s.c - s.xm);
+    acc += face_floor(0.5 * (K.yy_c + K.yy_p), a_min) * (s.yp - s.c) -
+           face_floor(0.5 * (K.yy_m + K.yy_c), a_min) * (s.c - s.ym);
+    acc += face_floor(0.5 * (K.zz_c + K.zz_p), a_min) * (s.zp - s.c) -
+           face_floor(0.5 * (K.zz_m + K.zz_c), a_min) * (s.c - s.zm);
     // cross fluxes: direction mu of the difference, nu of the gradient
     acc += 0.25 * (K.xy_xp * (s.xpyp - s.xpym) - K.xy_xm * (s.xmyp - s.xmym));  // mu = x, nu = y
     acc += 0.25 * (K.xz_xp * (s.xpzp - s.xpzm) - K.xz_xm * (s.xmzp - s.xmzm));  // mu = x, nu = z

@@ -53,7 +53,7 @@ template <typename Z, typename P, int MODE, int TJ, int TK, int NT, int FIRST = 
 __global__ void __launch_bounds__(NT)
     k_full25(const P *__restrict__ xin, const Z *__restrict__ zg, const double *__restrict__ bg, MassTensor K,
              double *__restrict__ out, float *__restrict__ out32, P *__restrict__ pout, int n, int ci, double beta,
-             double *part, double *__restrict__ ug, double alpha_u, const double *__restrict__ ks)
+             double a_min, double *part, double *__restrict__ ug, double alpha_u, const double *__restrict__ ks)
 {
     if constexpr (MODE == F25_DIRECTION && !FIRST) {
         if (ks) {
@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(NT)
             const FluxK q{qxx1[r],     qxx2[r],     qxx0[r],     Syy[c],      Syy[c + W],  Syy[c - W], Szz[c],
                           Szz[c + 1],  Szz[c - 1],  qxyp[r],     qxym[r],     Sxy[c + W],  Sxy[c - W], qxzp[r],
                           qxzm[r],     Sxz[c + 1],  Sxz[c - 1],  Syz[c + W],  Syz[c - W],  Syz[c + 1], Syz[c - 1]};
-            const double acc = full_flux(s, q);
+            const double acc = full_flux(s, q, a_min);
             const size_t g = base + gN[r];
             if constexpr (MODE == F25_RESNORM) {
                 const double rv = cb[r] - acc;
@@ -279,14 +279,14 @@ int f25_blocks(int n, int ci) { return (n / F25Launch::TK) * (n / F25Launch::TJ)
 bool full25_supported(int n) { return f25_fits(n); }
 
 hipError_t launch_full_residual_norm25(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
-                                       int n, Part &p, hipStream_t s)
+                                       int n, double a_min, Part &p, hipStream_t s)
 {
     using C = F25Launch;
     if (!f25_fits(n)) return hipErrorInvalidValue;
     const int ci = f25_chunk(n), nb = f25_blocks(n, ci);
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
     k_full25<double, double, F25_RESNORM, C::TJ, C::TK, C::NT><<<nb, C::NT, 0, s>>>(
-        u, nullptr, b, K, r, r32, nullptr, n, ci, 0.0, p.part, nullptr, 0.0, nullptr);
+        u, nullptr, b, K, r, r32, nullptr, n, ci, 0.0, a_min, p.part, nullptr, 0.0, nullptr);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -294,8 +294,8 @@ hipError_t launch_full_residual_norm25(const MassTensor &K, const double *u, con
 
 template <typename Z, typename P>
 hipError_t launch_full_direction25(const Z *z, const P *p_old, P *p_new, const MassTensor &K, double *q, double beta,
-                                   int n, bool first, double *u, double alpha_u, const double *ks, Part &p,
-                                   hipStream_t s)
+                                   int n, double a_min, bool first, double *u, double alpha_u, const double *ks,
+                                   Part &p, hipStream_t s)
 {
     using C = F25Launch;
     const void *po = p_old;
@@ -305,26 +305,26 @@ hipError_t launch_full_direction25(const Z *z, const P *p_old, P *p_new, const M
     if ((long)nb > kPartCap) return hipErrorInvalidValue;
     if (first)
         k_full25<Z, P, F25_DIRECTION, C::TJ, C::TK, C::NT, 1, 0><<<nb, C::NT, 0, s>>>(
-            p_old, z, nullptr, K, q, nullptr, p_new, n, ci, beta, p.part, nullptr, 0.0, nullptr);
+            p_old, z, nullptr, K, q, nullptr, p_new, n, ci, beta, a_min, p.part, nullptr, 0.0, nullptr);
     else if (u)
         k_full25<Z, P, F25_DIRECTION, C::TJ, C::TK, C::NT, 0, 1><<<nb, C::NT, 0, s>>>(
-            p_old, z, nullptr, K, q, nullptr, p_new, n, ci, beta, p.part, u, alpha_u, ks);
+            p_old, z, nullptr, K, q, nullptr, p_new, n, ci, beta, a_min, p.part, u, alpha_u, ks);
     else
         k_full25<Z, P, F25_DIRECTION, C::TJ, C::TK, C::NT, 0, 0><<<nb, C::NT, 0, s>>>(
-            p_old, z, nullptr, K, q, nullptr, p_new, n, ci, beta, p.part, nullptr, 0.0, ks);
+            p_old, z, nullptr, K, q, nullptr, p_new, n, ci, beta, a_min, p.part, nullptr, 0.0, ks);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
 }
 
 template hipError_t launch_full_direction25<float, float>(const float *, const float *, float *, const MassTensor &,
-                                                          double *, double, int, bool, double *, double,
+                                                          double *, double, int, double, bool, double *, double,
                                                           const double *, Part &, hipStream_t);
 template hipError_t launch_full_direction25<float, double>(const float *, const double *, double *,
-                                                           const MassTensor &, double *, double, int, bool, double *,
+                                                           const MassTensor &, double *, double, int, double, bool, double *,
                                                            double, const double *, Part &, hipStream_t);
 template hipError_t launch_full_direction25<double, double>(const double *, const double *, double *,
-                                                            const MassTensor &, double *, double, int, bool, double *,
+                                                            const MassTensor &, double *, double, int, double, bool, double *,
                                                             double, const double *, Part &, hipStream_t);
 
 }  // namespace recon

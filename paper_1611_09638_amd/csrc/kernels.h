@@ -68,13 +68,16 @@ struct MassTensor {
 };
 hipError_t launch_mass_change(const double *phi, const double *M, const double *f, const MassTensor &K,
                               double *out, int n, hipStream_t s);
-// K = M e^-1 at every node; out = L_K f; q = L_K p with partial K=1 sum p.q;
-// r = b - L_K u (optional FP32 copy r32) with partial K=1 sum r^2
+// K = M e^-1 at every node; out = L_K f (the exact mass change: no floor);
+// q = L_K p with partial K=1 sum p.q; r = b - L_K u (optional FP32 copy r32)
+// with partial K=1 sum r^2.  a_min > 0 floors the diagonal face coefficients
+// (the exact-Jacobian solve's operator).
 hipError_t launch_mass_tensor(const double *phi, const double *M, const MassTensor &K, int n, hipStream_t s);
 hipError_t launch_full_apply(const MassTensor &K, const double *f, double *out, int n, hipStream_t s);
-hipError_t launch_full_apply_dot(const MassTensor &K, const double *pv, double *q, int n, Part &p, hipStream_t s);
+hipError_t launch_full_apply_dot(const MassTensor &K, const double *pv, double *q, int n, double a_min, Part &p,
+                                 hipStream_t s);
 hipError_t launch_full_residual_norm(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
-                                     int n, Part &p, hipStream_t s);
+                                     int n, double a_min, Part &p, hipStream_t s);
 // Streaming forms of the last two (fullop25.hip; edges that are multiples of
 // 64): the residual with its norm, and the Krylov direction p_new = z + beta
 // p_old (first: z; beta from ks as in launch_direction25; rounded to P) fused
@@ -82,11 +85,11 @@ hipError_t launch_full_residual_norm(const MassTensor &K, const double *u, const
 // when u != null (not first).  p_new must not alias p_old, u or q.
 bool full25_supported(int n);
 hipError_t launch_full_residual_norm25(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
-                                       int n, Part &p, hipStream_t s);
+                                       int n, double a_min, Part &p, hipStream_t s);
 template <typename Z, typename P>
 hipError_t launch_full_direction25(const Z *z, const P *p_old, P *p_new, const MassTensor &K, double *q, double beta,
-                                   int n, bool first, double *u, double alpha_u, const double *ks, Part &p,
-                                   hipStream_t s);
+                                   int n, double a_min, bool first, double *u, double alpha_u, const double *ks,
+                                   Part &p, hipStream_t s);
 // Particles at their Lagrangian positions (particles.hip): xi = pos n / box;
 // Newton for x(xi) = y from the xi given (node shifts of phi in sx, sy, sz;
 // partial K=1: particles not within tol); CIC of the particles at xi into M

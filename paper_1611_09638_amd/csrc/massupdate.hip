@@ -49,7 +49,7 @@ __global__ void k_mass_tensor(const double *__restrict__ phi, const double *__re
 
 // L_K f at one node, in the flux form above; fc receives f at the node
 __device__ inline double full_node(const MassTensor &K, const double *__restrict__ f, int i, int j, int k, int n,
-                                   double &fc)
+                                   double a_min, double &fc)
 {
     const int ip = wrapc(i + 1, n), im = wrapc(i - 1, n);
     const int jp = wrapc(j + 1, n), jm = wrapc(j - 1, n), kp = wrapc(k + 1, n), km = wrapc(k - 1, n);
@@ -63,7 +63,7 @@ __device__ inline double full_node(const MassTensor &K, const double *__restrict
     const FluxK q{K.xx[c],  K.xx[xp], K.xx[xm], K.yy[c],  K.yy[yp], K.yy[ym], K.zz[c],
                   K.zz[zp], K.zz[zm], K.xy[xp], K.xy[xm], K.xy[yp], K.xy[ym], K.xz[xp],
                   K.xz[xm], K.xz[zp], K.xz[zm], K.yz[yp], K.yz[ym], K.yz[zp], K.yz[zm]};
-    return full_flux(s, q);
+    return full_flux(s, q, a_min);
 }
 
 enum FullMode { FULL_APPLY = 0, FULL_DOT = 1, FULL_RESID = 2 };
@@ -73,7 +73,8 @@ enum FullMode { FULL_APPLY = 0, FULL_DOT = 1, FULL_RESID = 2 };
 // with sum out^2 and an optional FP32 copy (the Krylov residual).
 template <int MODE>
 __global__ void k_full_apply(MassTensor K, const double *__restrict__ f, const double *__restrict__ b,
-                             double *__restrict__ out, float *__restrict__ out32, int n, int ipb, double *part)
+                             double *__restrict__ out, float *__restrict__ out32, int n, int ipb, double a_min,
+                             double *part)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -83,7 +84,7 @@ __global__ void k_full_apply(MassTensor K, const double *__restrict__ f, const d
         for (int i = i0; i < i1; ++i) {
             const size_t c = lin(i, j, k, n);
             double fc;
-            const double acc = full_node(K, f, i, j, k, n, fc);
+            const double acc = full_node(K, f, i, j, k, n, a_min, fc);
             if (MODE == FULL_RESID) {
                 const double rv = b[c] - acc;
                 out[c] = rv;
@@ -110,7 +111,7 @@ hipError_t launch_mass_tensor(const double *phi, const double *M, const MassTens
 hipError_t launch_full_apply(const MassTensor &K, const double *f, double *out, int n, hipStream_t s)
 {
     Shape3 sh = shape3(n);
-    k_full_apply<FULL_APPLY><<<sh.grid, sh.block, 0, s>>>(K, f, nullptr, out, nullptr, n, sh.ipb, nullptr);
+    k_full_apply<FULL_APPLY><<<sh.grid, sh.block, 0, s>>>(K, f, nullptr, out, nullptr, n, sh.ipb, 0.0, nullptr);
     return hipGetLastError();
 }
 
@@ -121,22 +122,23 @@ hipError_t launch_mass_change(const double *phi, const double *M, const double *
     return e != hipSuccess ? e : launch_full_apply(K, f, out, n, s);
 }
 
-hipError_t launch_full_apply_dot(const MassTensor &K, const double *pv, double *q, int n, Part &p, hipStream_t s)
+hipError_t launch_full_apply_dot(const MassTensor &K, const double *pv, double *q, int n, double a_min, Part &p,
+                                 hipStream_t s)
 {
     Shape3 sh = shape3(n);
     if (rows_of(sh) > kPartCap) return hipErrorInvalidValue;
-    k_full_apply<FULL_DOT><<<sh.grid, sh.block, 0, s>>>(K, pv, nullptr, q, nullptr, n, sh.ipb, p.part);
+    k_full_apply<FULL_DOT><<<sh.grid, sh.block, 0, s>>>(K, pv, nullptr, q, nullptr, n, sh.ipb, a_min, p.part);
     p.blocks = rows_of(sh);
     p.k = 1;
     return hipGetLastError();
 }
 
 hipError_t launch_full_residual_norm(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
-                                     int n, Part &p, hipStream_t s)
+                                     int n, double a_min, Part &p, hipStream_t s)
 {
     Shape3 sh = shape3(n);
     if (rows_of(sh) > kPartCap) return hipErrorInvalidValue;
-    k_full_apply<FULL_RESID><<<sh.grid, sh.block, 0, s>>>(K, u, b, r, r32, n, sh.ipb, p.part);
+    k_full_apply<FULL_RESID><<<sh.grid, sh.block, 0, s>>>(K, u, b, r, r32, n, sh.ipb, a_min, p.part);
     p.blocks = rows_of(sh);
     p.k = 1;
     return hipGetLastError();

@@ -368,8 +368,8 @@ hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const
                          const MassTensor *Kf = nullptr)
 {
     if (Kf && use_stream<double>(ctx->n) && full25_supported(ctx->n))
-        return launch_full_residual_norm25(*Kf, u, b, r, r32, ctx->n, ctx->part, ctx->stream);
-    if (Kf) return launch_full_residual_norm(*Kf, u, b, r, r32, ctx->n, ctx->part, ctx->stream);
+        return launch_full_residual_norm25(*Kf, u, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
+    if (Kf) return launch_full_residual_norm(*Kf, u, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
     if (use_stream<double>(ctx->n))
         return launch_residual_norm25(u, a, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
     return launch_residual_norm(u, a, b, r, r32, ctx->n, ctx->cfg.a_min, ctx->part, ctx->stream);
@@ -518,11 +518,11 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             if (stream && Kf) {
                 double *ud = due ? ctx->u : nullptr;
                 if (mixed)
-                    HIPCHK(launch_full_direction25(ctx->L32.u[0], f32(pc), f32(pn), *Kf, ctx->q, 0.0, n, first, ud,
-                                                   0.0, ks, ctx->part, ctx->stream));
+                    HIPCHK(launch_full_direction25(ctx->L32.u[0], f32(pc), f32(pn), *Kf, ctx->q, 0.0, n,
+                                                   ctx->cfg.a_min, first, ud, 0.0, ks, ctx->part, ctx->stream));
                 else
-                    HIPCHK(launch_full_direction25(ctx->z, pc, pn, *Kf, ctx->q, 0.0, n, first, ud, 0.0, ks,
-                                                   ctx->part, ctx->stream));
+                    HIPCHK(launch_full_direction25(ctx->z, pc, pn, *Kf, ctx->q, 0.0, n, ctx->cfg.a_min, first, ud,
+                                                   0.0, ks, ctx->part, ctx->stream));
                 due = false;
                 std::swap(pc, pn);
             } else if (stream) {
@@ -538,7 +538,7 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
             } else if (Kf) {
                 if (mixed) HIPCHK(launch_update_p<float>(ctx->L32.u[0], pc, 0.0, n3, first, ks, ctx->stream));
                 else HIPCHK(launch_update_p<double>(ctx->z, pc, 0.0, n3, first, ks, ctx->stream));
-                HIPCHK(launch_full_apply_dot(*Kf, pc, ctx->q, n, ctx->part, ctx->stream));
+                HIPCHK(launch_full_apply_dot(*Kf, pc, ctx->q, n, ctx->cfg.a_min, ctx->part, ctx->stream));
             } else if (mixed) {
                 HIPCHK(launch_update_pq<float>(ctx->L32.u[0], a0, pc, ctx->q, 0.0, n, ctx->cfg.a_min, first, ks,
                                                ctx->part, ctx->stream));
@@ -1262,8 +1262,8 @@ int recon_stage_full_residual(recon_ctx *ctx, const double *phi, const double *M
     if (stream && !full25_supported(n))
         return fail(ctx, RECON_E_ARG, "the streaming full operator needs an edge that is a multiple of 64");
     HIPCHK(launch_mass_tensor(phi, M, ctx->Kf, n, ctx->stream));
-    if (stream) HIPCHK(launch_full_residual_norm25(ctx->Kf, u, b, r, r32, n, ctx->part, ctx->stream));
-    else HIPCHK(launch_full_residual_norm(ctx->Kf, u, b, r, r32, n, ctx->part, ctx->stream));
+    if (stream) HIPCHK(launch_full_residual_norm25(ctx->Kf, u, b, r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
+    else HIPCHK(launch_full_residual_norm(ctx->Kf, u, b, r, r32, n, ctx->cfg.a_min, ctx->part, ctx->stream));
     return fetch_sum(ctx, rr);
 }
 
@@ -1290,13 +1290,13 @@ int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *
         const void *po = first ? (const void *)q : p_old;  // not read when first; any array other than p_new
         if (p_dtype == 1)
             HIPCHK(launch_full_direction25((const float *)z, (const float *)po, (float *)p_new, ctx->Kf, q, beta, n,
-                                           first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
+                                           ctx->cfg.a_min, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
         else if (z_dtype == 0)
             HIPCHK(launch_full_direction25((const double *)z, (const double *)po, (double *)p_new, ctx->Kf, q, beta,
-                                           n, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
+                                           n, ctx->cfg.a_min, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
         else
             HIPCHK(launch_full_direction25((const float *)z, (const double *)po, (double *)p_new, ctx->Kf, q, beta,
-                                           n, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
+                                           n, ctx->cfg.a_min, first != 0, u, alpha_u, nullptr, ctx->part, ctx->stream));
     } else {
         double *pn = (double *)p_new;
         if (u) HIPCHK(launch_axpy(u, (const double *)p_old, alpha_u, n3, ctx->stream));
@@ -1305,7 +1305,7 @@ int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *
             HIPCHK(launch_update_p<double>((const double *)z, pn, beta, n3, first != 0, nullptr, ctx->stream));
         else
             HIPCHK(launch_update_p<float>((const float *)z, pn, beta, n3, first != 0, nullptr, ctx->stream));
-        HIPCHK(launch_full_apply_dot(ctx->Kf, pn, q, n, ctx->part, ctx->stream));
+        HIPCHK(launch_full_apply_dot(ctx->Kf, pn, q, n, ctx->cfg.a_min, ctx->part, ctx->stream));
     }
     return fetch_sum(ctx, pq);
 }

@@ -41,6 +41,9 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
+A_MIN = 1e-3  # the default face floor, on the exact-Jacobian solve's diagonal fluxes too
+
+
 def solve_inputs(n, seed):
     rng = np.random.default_rng(seed)
     a = np.exp(0.6 * rng.normal(size=(n, n, n))) + 0.05
@@ -63,7 +66,7 @@ def test_full_solve_against_oracle(torch_cuda, orc, n, cn, precision):
     u, cyc, r = rec.mg_solve_full(dev(torch, a), dev(torch, phi), dev(torch, b), tol=tol)
     u = host(u)
     assert r <= tol
-    assert rel(orc.full_operator(phi, a, u), b) <= 2 * tol
+    assert rel(orc.full_operator(phi, a, u, A_MIN), b) <= 2 * tol
     assert abs(u.mean()) < 1e-13 * np.abs(u).max()
     assert rel(u, u_o) < 1e-8
     if precision == 0:
@@ -163,7 +166,7 @@ def test_full_residual_variants(torch_cuda, orc, n):
     rec = binding.Recon(n, binding.Config(full_operator=1))
     a, phi, b = solve_inputs(n, 960 + n)
     u = np.random.default_rng(970 + n).normal(size=(n, n, n))
-    ref = b - orc.full_operator(phi, a, u)
+    ref = b - orc.full_operator(phi, a, u, A_MIN)
     args = [dev(torch, x) for x in (phi, a, u, b)]
     for variant in (1, 2):
         r, r32, rr = rec.full_residual(*args, variant=variant, fp32_copy=True)
@@ -191,7 +194,7 @@ def test_full_direction_variants(torch_cuda, orc, n):
         pn, q, pq = rec.full_direction(dphi, da, dev(torch, z), None, 0.0, first=True, variant=variant)
         assert np.array_equal(host(pn), z)
         q = host(q)
-        assert rel(q, orc.full_operator(phi, a, z)) < 1e-13
+        assert rel(q, orc.full_operator(phi, a, z, A_MIN)) < 1e-13
         assert abs(pq - (z * q).sum()) < 1e-11 * abs(pq)
         # later step with the deferred solution update
         ud = dev(torch, u)
@@ -199,7 +202,7 @@ def test_full_direction_variants(torch_cuda, orc, n):
                                        u=ud, alpha_u=alpha_u)
         pn, q = host(pn), host(q)
         assert rel(pn, z + beta * p_old) < 1e-15
-        assert rel(q, orc.full_operator(phi, a, pn)) < 1e-13
+        assert rel(q, orc.full_operator(phi, a, pn, A_MIN)) < 1e-13
         assert abs(pq - (pn * q).sum()) < 1e-11 * abs(pq)
         assert rel(host(ud), u + alpha_u * p_old) < 1e-15
     # FP32 z and directions (streaming only): p_new rounded as formed, q of the rounded values
@@ -210,7 +213,7 @@ def test_full_direction_variants(torch_cuda, orc, n):
     assert pn.dtype == np.float32
     want = (z32.astype(np.float64) + beta * p32.astype(np.float64)).astype(np.float32)
     assert np.abs(pn.astype(np.float64) - want).max() <= 1.2e-7 * np.abs(want).max()
-    assert rel(q, orc.full_operator(phi, a, pn.astype(np.float64))) < 1e-13
+    assert rel(q, orc.full_operator(phi, a, pn.astype(np.float64), A_MIN)) < 1e-13
 
 
 def test_full_solve_streaming_256(torch_cuda, orc):
@@ -227,8 +230,40 @@ def test_full_solve_streaming_256(torch_cuda, orc):
         u, cyc, r = rec.mg_solve_full(dev(torch, a), dev(torch, phi), dev(torch, b), tol=tol)
         u = host(u)
         assert r <= tol and cyc < 40
-        assert rel(orc.full_operator(phi, a, u), b) <= 1.5 * tol
+        assert rel(orc.full_operator(phi, a, u, A_MIN), b) <= 1.5 * tol
         del rec
+
+
+def test_full_operator_floor_active(torch_cuda, orc):
+    """A sigma_g = 2 lognormal whose mass falls below a_min: both kernels of the
+    exact operator against the oracle's floored operator, and the first
+    solve equal to the x ~ xi one (same operator at phi = 0); full
+    reconstructions against the oracle, FP64 and mixed."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 64, 250.0
+    rho = inputs.lognormal_density(n, box, 2.0, 9)
+    M = rho / rho.mean()
+    assert M.min() < A_MIN
+    rng = np.random.default_rng(64)
+    g = inputs.gaussian_field(n, box, 65)
+    phi = 0.3 * g / np.abs(g).max()
+    u, b = rng.normal(size=(n, n, n)), rng.normal(size=(n, n, n))
+    ref = b - orc.full_operator(phi, M, u, A_MIN)
+    assert rel(ref, b - orc.full_operator(phi, M, u)) > 1e-8  # the floor is active
+    rec = binding.Recon(n, binding.Config(full_operator=1))
+    for variant in (1, 2):
+        r, _, _ = rec.full_residual(dev(torch, phi), dev(torch, M), dev(torch, u), dev(torch, b), variant=variant)
+        assert rel(host(r), ref) < 1e-13
+    for precision in (0, 1):
+        cfg = dict(max_vcycles=300, precision=precision)
+        phi_o, dr_o, st_o = orc.solve(rho, box, orc.Config(full_operator=1, max_outer=4, max_vcycles=300))
+        r1 = binding.Recon(n, binding.Config(full_operator=1, max_outer=4, **cfg))
+        ph, dr, st = r1.solve(dev(torch, rho), box)
+        assert st["alpha"] == st_o["alpha"]
+        assert rel(host(ph), phi_o) < 1e-6 and rel(host(dr), dr_o) < 1e-6
+        _, _, s0 = binding.Recon(n, binding.Config(max_outer=1, **cfg)).solve(dev(torch, rho), box)
+        assert st["vcycles"][0] == s0["vcycles"][0]
 
 
 def test_full_operator_config_errors(torch_cuda):
@@ -273,7 +308,7 @@ def test_full_operator_kernels_at_512(torch_cuda, orc):
     b = rng.standard_normal((n, n, n))
     r, r32, rr = rec.full_residual(dphi, dM, dev(torch, u), dev(torch, b), variant=2, fp32_copy=True)
     r = host(r)
-    ref = b.ravel()[idx] - orc.full_operator_at(phi, M, u, idx)
+    ref = b.ravel()[idx] - orc.full_operator_at(phi, M, u, idx, A_MIN)
     assert np.abs(r.ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
     assert abs(rr - float(np.dot(r.ravel(), r.ravel()))) <= 1e-10 * rr
     assert np.array_equal(host(r32).ravel()[idx], r.ravel()[idx].astype(np.float32))
@@ -288,7 +323,7 @@ def test_full_operator_kernels_at_512(torch_cuda, orc):
     pn, q = host(pn), host(q)
     p_ref = z + beta * p_old
     assert np.abs(pn - p_ref).max() <= 1e-15 * np.abs(p_ref).max()
-    ref = orc.full_operator_at(phi, M, p_ref, idx)
+    ref = orc.full_operator_at(phi, M, p_ref, idx, A_MIN)
     assert np.abs(q.ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
     assert abs(pq - float(np.dot(pn.ravel(), q.ravel()))) <= 1e-10 * abs(pq)
     assert np.abs(host(ud).ravel()[idx] - (u + alpha_u * p_old).ravel()[idx]).max() <= 1e-15 * np.abs(u).max() * 4
@@ -301,5 +336,5 @@ def test_full_operator_kernels_at_512(torch_cuda, orc):
     pn = host(pn)
     p_ref = (z32.astype(np.float64) + beta * p32.astype(np.float64)).astype(np.float32)
     assert np.abs(pn.astype(np.float64) - p_ref).max() <= 1.2e-7 * np.abs(p_ref).max()
-    ref = orc.full_operator_at(phi, M, pn.astype(np.float64), idx)
+    ref = orc.full_operator_at(phi, M, pn.astype(np.float64), idx, A_MIN)
     assert np.abs(host(q).ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()

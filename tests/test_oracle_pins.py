@@ -733,7 +733,7 @@ def test_full_operator_solve(orc):
     cfg = orc.Config(coarse_n=4, tol=1e-12)
     u, cyc, r = orc.mg_solve_full(M, phi, b, cfg)
     assert cyc > 0 and r <= 1e-12
-    assert rel(orc.full_operator(phi, M, u), b) <= 1e-12
+    assert rel(orc.full_operator(phi, M, u, 1e-3), b) <= 1e-12
     assert abs(u.mean()) < 1e-14 * np.abs(u).max()
     u0, _, _ = orc.mg_solve_full(M, np.zeros_like(phi), b, cfg)
     u1, _, _ = orc.mg_solve(M, b, cfg)
@@ -763,3 +763,33 @@ def test_full_operator_at_sampled_nodes(orc):
     f = rng.normal(size=(n, n, n))
     idx = np.concatenate([[0, n - 1, n * n - 1, n ** 3 - 1], rng.choice(n ** 3, 300, replace=False)])
     assert np.array_equal(orc.full_operator_at(phi, M, f, idx), orc.full_operator(phi, M, f).ravel()[idx])
+
+
+def test_full_operator_floor_reduces_to_the_x_approx_xi_operator(orc):
+    """With the diagonal face coefficients floored at a_min (the exact-Jacobian
+    solve's operator), the full operator at phi = 0 is the x ~ xi operator
+    with its floor, also where the mass falls below a_min; without the floor
+    it differs there.  The floor leaves the flux form's zero sum intact."""
+    n = 16
+    rho = inputs.lognormal_density(n, 125.0, 2.0, 9)
+    M = rho / rho.mean()
+    assert M.min() < 1e-3
+    f = np.random.default_rng(4).normal(size=M.shape)
+    zero = np.zeros_like(M)
+    ref = orc.apply(f, M)
+    assert rel(orc.full_operator(zero, M, f, 1e-3), ref) < 1e-14
+    assert rel(orc.full_operator(zero, M, f), ref) > 1e-6
+    g = inputs.gaussian_field(n, 125.0, 5)
+    phi = 0.3 * g / np.abs(g).max()
+    out = orc.full_operator(phi, M, f, 1e-3)
+    assert abs(out.sum()) < 1e-12 * np.abs(out).sum()
+    # the solve at phi = 0 is the x ~ xi solve, and so is a first outer step
+    b = np.random.default_rng(5).normal(size=M.shape)
+    b -= b.mean()
+    u0, _, _ = orc.mg_solve_full(M, zero, b, orc.Config(coarse_n=4, tol=1e-12))
+    u1, _, _ = orc.mg_solve(M, b, orc.Config(coarse_n=4, tol=1e-12))
+    assert rel(u0, u1) < 1e-9
+    phi0, _, st0 = orc.solve(rho, 125.0, orc.Config(max_outer=1, max_vcycles=300))
+    phi1, _, st1 = orc.solve(rho, 125.0, orc.Config(max_outer=1, max_vcycles=300, full_operator=1))
+    assert st0["alpha"] == st1["alpha"] and st0["vcycles"] == st1["vcycles"]
+    assert rel(phi1, phi0) < 1e-9
