@@ -118,15 +118,18 @@ def test_error_paths(torch_cuda):
         rec.solve(good.float(), 10.0)
 
 
-def test_repeat_solves_are_bitwise_identical(torch_cuda):
-    """The forward uses no atomics and fixed-order reductions."""
+@pytest.mark.parametrize("n,opts", [(32, {}), (32, {"full_operator": 1}), (32, {"mass_update": 1}),
+                                    (256, {"full_operator": 1})],
+                         ids=["default", "exact-jacobian", "mass-update", "exact-jacobian-256-streaming"])
+def test_repeat_solves_are_bitwise_identical(torch_cuda, n, opts):
+    """The forward uses no atomics and fixed-order reductions, in every mode
+    that does not deposit particles (the particle deposit sums with atomics)."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
-    n = 32
-    rho = torch.from_numpy(inputs.lognormal_density(n, 250.0, 1.5, 9)).cuda()
-    rec = binding.Recon(n, binding.Config(max_outer=3, precision=1))
-    phi1, d1, _ = rec.solve(rho, 250.0)
-    phi2, d2, _ = rec.solve(rho, 250.0)
+    rho = torch.from_numpy(inputs.lognormal_density(n, 250.0 * n / 32, 0.5 if opts else 1.5, 9)).cuda()
+    rec = binding.Recon(n, binding.Config(max_outer=3, precision=1, **opts))
+    phi1, d1, _ = rec.solve(rho, 250.0 * n / 32)
+    phi2, d2, _ = rec.solve(rho, 250.0 * n / 32)
     assert bool((phi1 == phi2).all()) and bool((d1 == d2).all())
 
 
