@@ -245,9 +245,10 @@ def quality_bench(torch, binding, inputs):
 
 def mass_update_bench(torch, binding, inputs, args):
     """Mixed solves of lognormal512_mild with M gathered by CIC every step and
-    with the paper's mass update, and the time of the update's two kernels
-    (K = M e^-1: read phi, M, write six fields; the 19-point application: read
-    the six fields and f, write the change): 64 + 64 algorithmic B/node."""
+    with the paper's mass update, and the time of the update's two passes
+    (K = M e^-1: read phi, M, write six fields; the streaming 19-point
+    application: read the six fields and f, write the change): 64 + 64
+    algorithmic B/node."""
     name = "lognormal512_mild"
     w = inputs.WORKLOADS[name]
     n, box = w["n"], w["box"]
@@ -288,7 +289,7 @@ def mass_update_bench(torch, binding, inputs, args):
             gbs = 128 * n ** 3 / (ms * 1e-3) / 1e9
             out["mass_change_kernels"] = {"ms": round(ms, 3), "alg_bytes_per_node": 128, "GBps": round(gbs, 1),
                                           "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-                                          "note": "two gather passes, once per outer step"}
+                                          "note": "K = M e^-1 (gather) and the streaming 19-point application, once per outer step"}
         del rec
         torch.cuda.empty_cache()
     d0, d1 = (res[m][1].double() for m in (0, 1))

@@ -24,7 +24,7 @@ namespace recon {
 
 namespace {
 
-enum { F25_RESNORM = 0, F25_DIRECTION = 1 };
+enum { F25_RESNORM = 0, F25_DIRECTION = 1, F25_APPLY = 2 };
 
 template <int TJ, int TK, int NT>
 struct F25 {
@@ -46,6 +46,7 @@ __device__ __forceinline__ void lds_barrier()
 // MODE F25_RESNORM:   out = b - L_K x, out32 = (float) out, sum out^2   (x = xin, P = double)
 // MODE F25_DIRECTION: x = first ? z : z + beta xin (rounded to P, written to pout),
 //                     out = L_K x, sum x out
+// MODE F25_APPLY:     out = L_K x (x = xin, P = double; no reduction)
 // FIRST: the first Krylov step (p = z, p_old not read).  UPD (not FIRST):
 // also ug += alpha_u xin, the previous step's solution update.  With ks,
 // beta and alpha_u come from the device scalars of the Krylov loop.
@@ -62,7 +63,7 @@ __global__ void __launch_bounds__(NT)
         }
     }
     static_assert(!UPD || (MODE == F25_DIRECTION && !FIRST), "the deferred update needs p_old");
-    static_assert(MODE == F25_DIRECTION || sizeof(P) == 8, "the residual's operand is FP64");
+    static_assert(MODE == F25_DIRECTION || sizeof(P) == 8, "the residual's and the product's operand is FP64");
     using F = F25<TJ, TK, NT>;
     static_assert(TJ * TK % NT == 0, "every thread owns whole rounds of the tile");
     constexpr int W = F::W, PLANE = F::PLANE, LU = F::LU, RS = F::RS, SL = F::SL;
@@ -220,6 +221,8 @@ __global__ void __launch_bounds__(NT)
                 out[g] = rv;
                 if (out32) out32[g] = (float)rv;
                 v += rv * rv;
+            } else if constexpr (MODE == F25_APPLY) {
+                out[g] = acc;
             } else {
                 pout[g] = (P)s.c;
                 out[g] = acc;
@@ -251,8 +254,10 @@ __global__ void __launch_bounds__(NT)
         lds_barrier();
         fetch(p + 1);
     }
-    double vv[1] = {v};
-    block_reduce_store<1, RED_SUM>(vv, part, blockIdx.x);
+    if constexpr (MODE != F25_APPLY) {
+        double vv[1] = {v};
+        block_reduce_store<1, RED_SUM>(vv, part, blockIdx.x);
+    }
 }
 
 // 8 x 64 tiles, 256 threads: 14 LDS slots of 10 x 66 doubles (74 KB, two
@@ -289,6 +294,16 @@ hipError_t launch_full_residual_norm25(const MassTensor &K, const double *u, con
         u, nullptr, b, K, r, r32, nullptr, n, ci, 0.0, a_min, p.part, nullptr, 0.0, nullptr);
     p.blocks = nb;
     p.k = 1;
+    return hipGetLastError();
+}
+
+hipError_t launch_full_apply25(const MassTensor &K, const double *f, double *out, int n, double a_min, hipStream_t s)
+{
+    using C = F25Launch;
+    if (!f25_fits(n) || out == f) return hipErrorInvalidValue;
+    const int ci = f25_chunk(n), nb = f25_blocks(n, ci);
+    k_full25<double, double, F25_APPLY, C::TJ, C::TK, C::NT><<<nb, C::NT, 0, s>>>(
+        f, nullptr, nullptr, K, out, nullptr, nullptr, n, ci, 0.0, a_min, nullptr, nullptr, 0.0, nullptr);
     return hipGetLastError();
 }
 

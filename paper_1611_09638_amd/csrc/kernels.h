@@ -84,6 +84,8 @@ hipError_t launch_full_residual_norm(const MassTensor &K, const double *u, const
 // with q = L_K p_new and partial K=1 sum p_new.q, and with u += alpha_u p_old
 // when u != null (not first).  p_new must not alias p_old, u or q.
 bool full25_supported(int n);
+// out = L_K f in one streaming pass (out distinct from f)
+hipError_t launch_full_apply25(const MassTensor &K, const double *f, double *out, int n, double a_min, hipStream_t s);
 hipError_t launch_full_residual_norm25(const MassTensor &K, const double *u, const double *b, double *r, float *r32,
                                        int n, double a_min, Part &p, hipStream_t s);
 template <typename Z, typename P>

@@ -110,6 +110,8 @@ hipError_t launch_mass_tensor(const double *phi, const double *M, const MassTens
 
 hipError_t launch_full_apply(const MassTensor &K, const double *f, double *out, int n, hipStream_t s)
 {
+    // the exact mass change: no floor; one streaming pass where it applies
+    if (n >= 256 && full25_supported(n) && out != f) return launch_full_apply25(K, f, out, n, 0.0, s);
     Shape3 sh = shape3(n);
     k_full_apply<FULL_APPLY><<<sh.grid, sh.block, 0, s>>>(K, f, nullptr, out, nullptr, n, sh.ipb, 0.0, nullptr);
     return hipGetLastError();

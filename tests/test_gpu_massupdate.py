@@ -39,10 +39,11 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("n,cn", [(32, 8), (48, 6), (64, 8)])
+@pytest.mark.parametrize("n,cn", [(32, 8), (48, 6), (64, 8), (256, 8)])
 def test_mass_change_operator(torch_cuda, orc, n, cn):
     """Per node against the oracle (summation order differs: rounding only),
-    zero sum, and the solve's operator at phi = 0."""
+    zero sum, and the solve's operator at phi = 0 (256^3: the streaming
+    pass)."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
     rec = binding.Recon(n, binding.Config(coarse_n=cn))
