@@ -281,6 +281,11 @@ def test_full_operator_config_errors(torch_cuda):
     g = torch.ones((48, 48, 48), dtype=torch.float64, device="cuda")
     with pytest.raises(binding.ReconError):  # streaming needs multiples of 64
         rec.full_residual(g, g, g, g, variant=2)
+    z32 = torch.ones((48, 48, 48), dtype=torch.float32, device="cuda")
+    with pytest.raises(binding.ReconError):  # FP32 directions need the streaming kernel
+        rec.full_direction(g, g, z32, z32, 0.5, variant=1, p_dtype=torch.float32)
+    with pytest.raises(binding.ReconError):  # u may not alias p_old or z
+        rec.full_direction(g, g, g, g, 0.5, variant=1, u=g)
 
 
 def test_full_operator_kernels_at_512(torch_cuda, orc):

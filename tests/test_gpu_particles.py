@@ -156,6 +156,10 @@ def test_particle_backward_errors(torch_cuda):
         rec.backward(g)
     with pytest.raises(binding.ReconError):  # other particles
         rec.backward_particles(pos[:-1].contiguous(), g)
+    # the deposit keeps Lagrangian positions for at most n^3 particles
+    many = torch.cat([pos, pos[:1]]).contiguous()
+    with pytest.raises(binding.ReconError):
+        binding.Recon(n, binding.Config(particle_deposit=1, max_outer=1)).solve_particles(many, box)
     dens = binding.Recon(n, binding.Config(record_tape=1, max_outer=2))
     dens.solve(1.0 + 0.1 * torch.rand((n, n, n), dtype=torch.float64, device="cuda"), box)
     with pytest.raises(binding.ReconError):  # a density tape has no particle gradient
