@@ -109,10 +109,12 @@ PCASES = [
     (32, 250.0, 1.2, 5, 1, 1, {}),
     (32, 250.0, 1.0, 6, 0, 3, {}),
     (48, 375.0, 1.0, 7, 1, 1, {"coarse_n": 6}),
+    # FP32 tape: the backward linearises about phi rebuilt from the rounded u_i
+    (32, 250.0, 1.2, 5, 1, 1, {"tape_fp32": 1}),
 ]
 
 
-@pytest.mark.parametrize("case", PCASES, ids=["16", "32", "32-mixed", "32-subsampled", "48-mixed"])
+@pytest.mark.parametrize("case", PCASES, ids=["16", "32", "32-mixed", "32-subsampled", "48-mixed", "32-fp32-tape"])
 def test_particle_gradient_matches_oracle(torch_cuda, orc, case):
     """dL/d(positions) of a recorded particle-deposit forward, through the C
     ABI, against the oracle's reverse mode (itself pinned to finite
@@ -121,19 +123,21 @@ def test_particle_gradient_matches_oracle(torch_cuda, orc, case):
     from paper_1611_09638_amd import binding
     n, box, rms, seed, prec, every, extra = case
     pos = np.ascontiguousarray(inputs.zeldovich_particles(n, box, rms, seed)[::every])
+    extra = dict(extra)
+    tape32 = extra.pop("tape_fp32", 0)
     base = dict(max_outer=3, tol=1e-13, max_vcycles=300, particle_deposit=1, **extra)
     rng = np.random.default_rng(seed)
     gd = rng.normal(size=(n, n, n))
     gp = rng.normal(size=(n, n, n)) * 1e-3
     _, _, st_o = orc.solve_particles(pos, n, box, orc.Config(record_tape=1, **base))
     g_o = orc.backward_particles(gd, gp, box, orc.Config(**base))
-    rec = binding.Recon(n, binding.Config(record_tape=1, precision=prec, **base))
+    rec = binding.Recon(n, binding.Config(record_tape=1, tape_fp32=tape32, precision=prec, **base))
     pd = dev(torch, pos)
     _, _, st = rec.solve_particles(pd, box)
     assert st["alpha"] == st_o["alpha"]
     g = rec.backward_particles(pd, dev(torch, gd), dev(torch, gp)).cpu().numpy()
     assert g.shape == pos.shape
-    assert rel(g, g_o) < 1e-8, rel(g, g_o)
+    assert rel(g, g_o) < (1e-5 if tape32 else 1e-8), rel(g, g_o)
     # a second backward of the same tape gives the same gradient: its Newton
     # inversions start from other positions (the first step's, left by the
     # first backward) and stop within 1e-12 cells, and the atomic sums run in
