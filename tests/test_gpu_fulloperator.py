@@ -292,8 +292,9 @@ def test_full_operator_kernels_at_512(torch_cuda, orc):
     """The streaming exact-Jacobian kernels at 512^3, in the launch shape the
     solve uses there (8 x 64 tiles, 256-plane i-chunks), against the oracle's
     operator formed at 4096 sampled nodes (and the faces and corners of the
-    periodic box): the residual with its norm, and the direction pass in FP64
-    and with FP32 directions, with the deferred solution update."""
+    periodic box): the residual with its norm, the direction pass in FP64
+    and with FP32 directions, with the deferred solution update, and the mass
+    update's unfloored application."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
     n = 512
@@ -343,3 +344,10 @@ def test_full_operator_kernels_at_512(torch_cuda, orc):
     assert np.abs(pn.astype(np.float64) - p_ref).max() <= 1.2e-7 * np.abs(p_ref).max()
     ref = orc.full_operator_at(phi, M, pn.astype(np.float64), idx, A_MIN)
     assert np.abs(host(q).ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
+    del pn, q
+    # the mass update's exact change (no floor), in its streaming pass
+    f = rng.standard_normal((n, n, n))
+    D = host(rec.mass_change(dphi, dM, dev(torch, f)))
+    ref = orc.full_operator_at(phi, M, f, idx)
+    assert np.abs(D.ravel()[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(D.sum()) < 1e-11 * np.abs(D).sum()
