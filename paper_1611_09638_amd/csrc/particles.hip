@@ -172,19 +172,36 @@ __global__ void k_deposit_xi(const double *__restrict__ xi, long long np, int n,
     }
 }
 
-// Adjoint of the deposit at xi = X^-1(y; s) (s = D_c phi): per particle,
-//   xibar = wp sum_c Mbar(q_c) grad W_c(xi),  lam = J^-T xibar,
-// with J = dx/dxi in the cell of xi (implicit function theorem on
-// x(xi; s) = y); then gpos += gscale lam (the particle's own entry) and
-// sbar(q_c) -= W_c(xi) lam, component by component, with FP64 atomics.
-__global__ void k_deposit_adj(const double *__restrict__ xi, long long np, Shifts s, int n, double wp,
-                              const double *__restrict__ Mbar, double *__restrict__ sbx, double *__restrict__ sby,
-                              double *__restrict__ sbz, double *__restrict__ gpos, double gscale)
+// The same deposit for n^3 particles stored in lattice order (particle
+// (i, j, k) at index (i n + j) n + k): a workgroup takes a DBI x DBJ x DBK
+// block of the lattice and sums its particles' CIC weights in an LDS window
+// of the nodes around the block (two cells below it to three above), then
+// adds the window's non-zero entries to M, one atomic each, instead of eight
+// per particle.  A particle with a corner outside the window (displaced by
+// two cells or more from its lattice site, or particles not in lattice
+// order) adds to M directly, so the result is the same sum in any case.
+constexpr int DBI = 2, DBJ = 8, DBK = 16;  // 256 particles per workgroup
+constexpr int DEI = DBI + 5, DEJ = DBJ + 5, DEK = DBK + 5;
+constexpr int DWIN = DEI * DEJ * DEK;
+
+__global__ void __launch_bounds__(256) k_deposit_block(const double *__restrict__ xi, int n, double wp,
+                                                       double *__restrict__ M)
 {
-    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < np; p += 256LL * gridDim.x) {
-        if (!(fabs(xi[3 * p]) < 1.0e9 && fabs(xi[3 * p + 1]) < 1.0e9 && fabs(xi[3 * p + 2]) < 1.0e9)) continue;
-        int f[3];
+    __shared__ double win[DWIN];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < DWIN; q += 256) win[q] = 0.0;
+    const int bk = n / DBK, bj = n / DBJ;
+    const int b = blockIdx.x;
+    const int i0 = (b / (bj * bk)) * DBI, j0 = ((b / bk) % bj) * DBJ, k0 = (b % bk) * DBK;
+    const int li = tid / (DBJ * DBK), lj = (tid / DBK) % DBJ, lk = tid % DBK;
+    const long long p = ((long long)(i0 + li) * n + (j0 + lj)) * n + (k0 + lk);
+    const int org[3] = {wrapc(i0 - 2, n), wrapc(j0 - 2, n), wrapc(k0 - 2, n)};
+    const int ext[3] = {DEI, DEJ, DEK};
+    __syncthreads();
+    if (fabs(xi[3 * p]) < 1.0e9 && fabs(xi[3 * p + 1]) < 1.0e9 && fabs(xi[3 * p + 2]) < 1.0e9) {
+        int f[3], r[3];
         double t[3];
+        bool inwin = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const double x = xi[3 * p + a];
@@ -192,48 +209,168 @@ __global__ void k_deposit_adj(const double *__restrict__ xi, long long np, Shift
             t[a] = x - fl;
             int fi = (int)fl % n;
             f[a] = fi < 0 ? fi + n : fi;
+            int ra = f[a] - org[a];
+            r[a] = ra < 0 ? ra + n : ra;  // in [0, n)
+            inwin = inwin && r[a] <= ext[a] - 2;
         }
-        double xb[3] = {0.0, 0.0, 0.0};
-        double J[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
-        size_t q[8];
-        double wc[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
-            const double w0 = o0 ? t[0] : 1.0 - t[0], w1 = o1 ? t[1] : 1.0 - t[1], w2 = o2 ? t[2] : 1.0 - t[2];
-            const double d0 = o0 ? 1.0 : -1.0, d1 = o1 ? 1.0 : -1.0, d2 = o2 ? 1.0 : -1.0;
-            q[c] = lin(o0 ? wrapc(f[0] + 1, n) : f[0], o1 ? wrapc(f[1] + 1, n) : f[1], o2 ? wrapc(f[2] + 1, n) : f[2],
-                       n);
-            wc[c] = w0 * w1 * w2;
-            const double g[3] = {d0 * w1 * w2, w0 * d1 * w2, w0 * w1 * d2};
-            const double mb = wp * Mbar[q[c]];
-            const double sc[3] = {s.x[q[c]], s.y[q[c]], s.z[q[c]]};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                xb[a] += mb * g[a];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) J[b][a] += g[a] * sc[b];
-            }
+            const double w = (o0 ? t[0] : 1.0 - t[0]) * (o1 ? t[1] : 1.0 - t[1]) * (o2 ? t[2] : 1.0 - t[2]);
+            if (inwin)
+                atomicAdd(&win[((r[0] + o0) * DEJ + (r[1] + o1)) * DEK + (r[2] + o2)], wp * w);
+            else
+                atomicAdd(&M[lin(o0 ? wrapc(f[0] + 1, n) : f[0], o1 ? wrapc(f[1] + 1, n) : f[1],
+                                 o2 ? wrapc(f[2] + 1, n) : f[2], n)],
+                          wp * w);
         }
-        // lam = J^-T xibar by the adjugate: (J^-1)_{ba} = adj_{ba} / det
-        const double a00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], a01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
-                     a02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-        const double a10 = J[1][2] * J[2][0] - J[1][0] * J[2][2], a11 = J[0][0] * J[2][2] - J[0][2] * J[2][0],
-                     a12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-        const double a20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], a21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
-                     a22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-        const double det = J[0][0] * a00 + J[0][1] * a10 + J[0][2] * a20;
-        const double lam[3] = {(a00 * xb[0] + a10 * xb[1] + a20 * xb[2]) / det,
-                               (a01 * xb[0] + a11 * xb[1] + a21 * xb[2]) / det,
-                               (a02 * xb[0] + a12 * xb[1] + a22 * xb[2]) / det};
+    }
+    __syncthreads();
+    for (int q = tid; q < DWIN; q += 256) {
+        const double v = win[q];
+        if (v != 0.0) {
+            const int wi = q / (DEJ * DEK), wj = (q / DEK) % DEJ, wk = q % DEK;
+            atomicAdd(&M[lin(wrapc(org[0] + wi, n), wrapc(org[1] + wj, n), wrapc(org[2] + wk, n), n)], v);
+        }
+    }
+}
+
+bool deposit_block_fits(long long np, int n)
+{
+    return n >= 32 && n % DBK == 0 && n % DBJ == 0 && n % DBI == 0 && np == (long long)n * n * n;
+}
+
+// Adjoint of the deposit at xi = X^-1(y; s) (s = D_c phi): per particle,
+//   xibar = wp sum_c Mbar(q_c) grad W_c(xi),  lam = J^-T xibar,
+// with J = dx/dxi in the cell of xi (implicit function theorem on
+// x(xi; s) = y); then gpos += gscale lam (the particle's own entry) and
+// sbar(q_c) -= W_c(xi) lam, component by component, with FP64 atomics.
+// One particle of the deposit's adjoint: its cell f and offsets t, the eight
+// corner nodes q and weights wc, and lam = J^-T xibar; gpos gets gscale lam.
+// Returns false (nothing done) for a position that is not finite or beyond
+// 1e9 cells.
+__device__ __forceinline__ bool deposit_adj_particle(const double *__restrict__ xi, long long p, const Shifts &s,
+                                                     int n, double wp, const double *__restrict__ Mbar,
+                                                     double *__restrict__ gpos, double gscale, int f[3],
+                                                     size_t q[8], double wc[8], double lam[3])
+{
+    if (!(fabs(xi[3 * p]) < 1.0e9 && fabs(xi[3 * p + 1]) < 1.0e9 && fabs(xi[3 * p + 2]) < 1.0e9)) return false;
+    double t[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) gpos[3 * p + a] += gscale * lam[a];
+    for (int a = 0; a < 3; ++a) {
+        const double x = xi[3 * p + a];
+        const double fl = floor(x);
+        t[a] = x - fl;
+        int fi = (int)fl % n;
+        f[a] = fi < 0 ? fi + n : fi;
+    }
+    double xb[3] = {0.0, 0.0, 0.0};
+    double J[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+        const double w0 = o0 ? t[0] : 1.0 - t[0], w1 = o1 ? t[1] : 1.0 - t[1], w2 = o2 ? t[2] : 1.0 - t[2];
+        const double d0 = o0 ? 1.0 : -1.0, d1 = o1 ? 1.0 : -1.0, d2 = o2 ? 1.0 : -1.0;
+        q[c] = lin(o0 ? wrapc(f[0] + 1, n) : f[0], o1 ? wrapc(f[1] + 1, n) : f[1], o2 ? wrapc(f[2] + 1, n) : f[2], n);
+        wc[c] = w0 * w1 * w2;
+        const double g[3] = {d0 * w1 * w2, w0 * d1 * w2, w0 * w1 * d2};
+        const double mb = wp * Mbar[q[c]];
+        const double sc[3] = {s.x[q[c]], s.y[q[c]], s.z[q[c]]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xb[a] += mb * g[a];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) J[b][a] += g[a] * sc[b];
+        }
+    }
+    // lam = J^-T xibar by the adjugate: (J^-1)_{ba} = adj_{ba} / det
+    const double a00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], a01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
+                 a02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    const double a10 = J[1][2] * J[2][0] - J[1][0] * J[2][2], a11 = J[0][0] * J[2][2] - J[0][2] * J[2][0],
+                 a12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    const double a20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], a21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
+                 a22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * a00 + J[0][1] * a10 + J[0][2] * a20;
+    lam[0] = (a00 * xb[0] + a10 * xb[1] + a20 * xb[2]) / det;
+    lam[1] = (a01 * xb[0] + a11 * xb[1] + a21 * xb[2]) / det;
+    lam[2] = (a02 * xb[0] + a12 * xb[1] + a22 * xb[2]) / det;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gpos[3 * p + a] += gscale * lam[a];
+    return true;
+}
+
+__global__ void k_deposit_adj(const double *__restrict__ xi, long long np, Shifts s, int n, double wp,
+                              const double *__restrict__ Mbar, double *__restrict__ sbx, double *__restrict__ sby,
+                              double *__restrict__ sbz, double *__restrict__ gpos, double gscale)
+{
+    for (long long p = blockIdx.x * 256LL + threadIdx.x; p < np; p += 256LL * gridDim.x) {
+        int f[3];
+        size_t q[8];
+        double wc[8], lam[3];
+        if (!deposit_adj_particle(xi, p, s, n, wp, Mbar, gpos, gscale, f, q, wc, lam)) continue;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             atomicAdd(&sbx[q[c]], -wc[c] * lam[0]);
             atomicAdd(&sby[q[c]], -wc[c] * lam[1]);
             atomicAdd(&sbz[q[c]], -wc[c] * lam[2]);
         }
+    }
+}
+
+// The same for n^3 particles in lattice order, with the scatter of sbar summed
+// in three LDS windows around the workgroup's lattice block as in
+// k_deposit_block (particles with a corner outside go straight to sbar).
+__global__ void __launch_bounds__(256) k_deposit_adj_block(const double *__restrict__ xi, Shifts s, int n,
+                                                           double wp, const double *__restrict__ Mbar,
+                                                           double *__restrict__ sbx, double *__restrict__ sby,
+                                                           double *__restrict__ sbz, double *__restrict__ gpos,
+                                                           double gscale)
+{
+    __shared__ double win[3][DWIN];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < DWIN; q += 256) win[0][q] = win[1][q] = win[2][q] = 0.0;
+    const int bk = n / DBK, bj = n / DBJ;
+    const int b = blockIdx.x;
+    const int i0 = (b / (bj * bk)) * DBI, j0 = ((b / bk) % bj) * DBJ, k0 = (b % bk) * DBK;
+    const int li = tid / (DBJ * DBK), lj = (tid / DBK) % DBJ, lk = tid % DBK;
+    const long long p = ((long long)(i0 + li) * n + (j0 + lj)) * n + (k0 + lk);
+    const int org[3] = {wrapc(i0 - 2, n), wrapc(j0 - 2, n), wrapc(k0 - 2, n)};
+    const int ext[3] = {DEI, DEJ, DEK};
+    __syncthreads();
+    int f[3];
+    size_t q[8];
+    double wc[8], lam[3];
+    if (deposit_adj_particle(xi, p, s, n, wp, Mbar, gpos, gscale, f, q, wc, lam)) {
+        int r[3];
+        bool inwin = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int ra = f[a] - org[a];
+            r[a] = ra < 0 ? ra + n : ra;  // in [0, n)
+            inwin = inwin && r[a] <= ext[a] - 2;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int o0 = (c >> 2) & 1, o1 = (c >> 1) & 1, o2 = c & 1;
+            if (inwin) {
+                const int w = ((r[0] + o0) * DEJ + (r[1] + o1)) * DEK + (r[2] + o2);
+                atomicAdd(&win[0][w], -wc[c] * lam[0]);
+                atomicAdd(&win[1][w], -wc[c] * lam[1]);
+                atomicAdd(&win[2][w], -wc[c] * lam[2]);
+            } else {
+                atomicAdd(&sbx[q[c]], -wc[c] * lam[0]);
+                atomicAdd(&sby[q[c]], -wc[c] * lam[1]);
+                atomicAdd(&sbz[q[c]], -wc[c] * lam[2]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int w = tid; w < DWIN; w += 256) {
+        const int wi = w / (DEJ * DEK), wj = (w / DEK) % DEJ, wk = w % DEK;
+        const size_t g = lin(wrapc(org[0] + wi, n), wrapc(org[1] + wj, n), wrapc(org[2] + wk, n), n);
+        if (win[0][w] != 0.0) atomicAdd(&sbx[g], win[0][w]);
+        if (win[1][w] != 0.0) atomicAdd(&sby[g], win[1][w]);
+        if (win[2][w] != 0.0) atomicAdd(&sbz[g], win[2][w]);
     }
 }
 
@@ -269,7 +406,11 @@ hipError_t launch_deposit_xi(const double *xi, long long np, int n, double *M, h
 {
     hipError_t e = launch_zero(M, (long)n * n * n * 8, s);
     if (e != hipSuccess) return e;
-    k_deposit_xi<<<particle_blocks(np), 256, 0, s>>>(xi, np, n, (double)n * n * n / (double)np, M);
+    const double wp = (double)n * n * n / (double)np;
+    if (deposit_block_fits(np, n))
+        k_deposit_block<<<(unsigned)(np / 256), 256, 0, s>>>(xi, n, wp, M);
+    else
+        k_deposit_xi<<<particle_blocks(np), 256, 0, s>>>(xi, np, n, wp, M);
     return hipGetLastError();
 }
 
@@ -285,8 +426,13 @@ hipError_t launch_deposit_adj(const double *xi, long long np, int n, const doubl
                               hipStream_t s)
 {
     const size_t n3 = (size_t)n * n * n;
-    k_deposit_adj<<<particle_blocks(np), 256, 0, s>>>(xi, np, Shifts{sx, sy, sz}, n, (double)n3 / (double)np, Mbar,
-                                                      sbar, sbar + n3, sbar + 2 * n3, gpos, gscale);
+    const double wp = (double)n3 / (double)np;
+    if (deposit_block_fits(np, n))
+        k_deposit_adj_block<<<(unsigned)(np / 256), 256, 0, s>>>(xi, Shifts{sx, sy, sz}, n, wp, Mbar, sbar,
+                                                                 sbar + n3, sbar + 2 * n3, gpos, gscale);
+    else
+        k_deposit_adj<<<particle_blocks(np), 256, 0, s>>>(xi, np, Shifts{sx, sy, sz}, n, wp, Mbar, sbar, sbar + n3,
+                                                          sbar + 2 * n3, gpos, gscale);
     return hipGetLastError();
 }
 
