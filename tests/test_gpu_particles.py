@@ -111,10 +111,12 @@ PCASES = [
     (48, 375.0, 1.0, 7, 1, 1, {"coarse_n": 6}),
     # FP32 tape: the backward linearises about phi rebuilt from the rounded u_i
     (32, 250.0, 1.2, 5, 1, 1, {"tape_fp32": 1}),
+    # n^3 particles out of lattice order: the block-summed scatters fall back to memory
+    (32, 250.0, 1.2, 5, 0, 1, {"shuffle": 1}),
 ]
 
 
-@pytest.mark.parametrize("case", PCASES, ids=["16", "32", "32-mixed", "32-subsampled", "48-mixed", "32-fp32-tape"])
+@pytest.mark.parametrize("case", PCASES, ids=["16", "32", "32-mixed", "32-subsampled", "48-mixed", "32-fp32-tape", "32-shuffled"])
 def test_particle_gradient_matches_oracle(torch_cuda, orc, case):
     """dL/d(positions) of a recorded particle-deposit forward, through the C
     ABI, against the oracle's reverse mode (itself pinned to finite
@@ -125,6 +127,8 @@ def test_particle_gradient_matches_oracle(torch_cuda, orc, case):
     pos = np.ascontiguousarray(inputs.zeldovich_particles(n, box, rms, seed)[::every])
     extra = dict(extra)
     tape32 = extra.pop("tape_fp32", 0)
+    if extra.pop("shuffle", 0):
+        pos = np.ascontiguousarray(pos[np.random.default_rng(seed).permutation(len(pos))])
     base = dict(max_outer=3, tol=1e-13, max_vcycles=300, particle_deposit=1, **extra)
     rng = np.random.default_rng(seed)
     gd = rng.normal(size=(n, n, n))
@@ -215,3 +219,23 @@ def test_inversion_and_deposit_at_512(torch_cuda, orc):
     M_o = orc.deposit_xi(xi_o, n)
     assert rel(M, M_o) < 1e-12
     assert abs(M.sum() - n ** 3) < 1e-9 * n ** 3 and M.min() >= 0.0
+
+
+def test_block_summed_deposit_any_order(torch_cuda, orc):
+    """n^3 particles: the deposit summed per lattice block in LDS gives the
+    oracle's deposit whether the particles are in lattice order (all through
+    the windows) or shuffled (mostly straight to memory)."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n, box = 32, 250.0
+    pos = inputs.zeldovich_particles(n, box, 1.2, 7)
+    g = inputs.gaussian_field(n, box, 3)
+    phi = 0.4 * g / np.abs(g).max()
+    xi = orc.invert_map(phi, pos.astype(np.float64) * (n / box))
+    M_o = orc.deposit_xi(xi, n)
+    rec = binding.Recon(n, binding.Config(particle_deposit=1))
+    perm = np.random.default_rng(11).permutation(len(xi))
+    for x in (xi, xi[perm]):
+        M = host(rec.deposit_xi(dev(torch, x)))
+        assert rel(M, M_o) < 1e-13
+        assert abs(M.sum() - n ** 3) < 1e-9 * n ** 3
