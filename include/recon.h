@@ -75,7 +75,8 @@ typedef struct recon_config {
                            by CIC at their Lagrangian positions on the deformed mesh every step
                            (xi_p with xi_p + grad phi(xi_p) = y_p, by Newton from the previous
                            step's); 0 assigns them to the grid once.  Needs up to n^3
-                           particles and mass_update = 0; reverse mode through
+                           particles and mass_update = 0; 6 more FP64 fields of workspace
+                           (positions and node shifts); reverse mode through
                            recon_backward_particles (0)                                     */
     int full_operator;  /* 1: the linear system of each step is the exact Jacobian of the mass
                            map, div(M e^-1 grad u) = b on the current mesh (App. A, Eq.
@@ -323,7 +324,10 @@ int recon_stage_mass_change(recon_ctx *ctx, const double *phi, const double *M, 
  * solution in grid units [0, n) on exit) with x(xi) = y, y = pos n / box
  * (pos: device float32 np x 3 in [0, box)), where x = xi + trilinear
  * interpolant of the node shifts D_c phi.  *failed (host) = particles not
- * located to 1e-12 cells.  Uses library-owned scratch fields. */
+ * located to 1e-12 cells.  The node shifts go into the context's workspace:
+ * its particle-deposit buffer, else three fine fields that lie back to back
+ * (RECON_E_ARG when they do not, for edges whose FP64 field is not a
+ * multiple of 256 bytes and contexts without particle_deposit). */
 int recon_stage_invert_map(recon_ctx *ctx, const double *phi, const float *pos, long long np, double box, double *xi,
                            double *failed);
 

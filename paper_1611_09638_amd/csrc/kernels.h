@@ -93,20 +93,21 @@ hipError_t launch_full_direction25(const Z *z, const P *p_old, P *p_new, const M
                                    int n, double a_min, bool first, double *u, double alpha_u, const double *ks,
                                    Part &p, hipStream_t s);
 // Particles at their Lagrangian positions (particles.hip): xi = pos n / box;
-// Newton for x(xi) = y from the xi given (node shifts of phi in sx, sy, sz;
+// Newton for x(xi) = y from the xi given (node shifts of phi into s3, 3 n^3
+// doubles;
 // partial K=1: particles not within tol); CIC of the particles at xi into M
 // (zeroed first), n^3 / np each.
 hipError_t launch_init_xi(const float *pos, long long np, int n, double box, double *xi, hipStream_t s);
 hipError_t launch_invert_map(const double *phi, const float *pos, long long np, int n, double box, double *xi,
-                             double *sx, double *sy, double *sz, int max_iter, double tol, Part &p, hipStream_t s);
+                             double *s3, int max_iter, double tol, Part &p, hipStream_t s);
 hipError_t launch_deposit_xi(const double *xi, long long np, int n, double *M, hipStream_t s);
-// s = D_c phi into three fields; the adjoint of the deposit at the Lagrangian
-// positions xi (node shifts s of the same phi): gpos (3 per particle) +=
+// s = D_c phi, three components per node side by side (3 n^3 doubles); the
+// adjoint of the deposit at the Lagrangian positions xi (node shifts s3 of the
+// same phi): gpos (3 per particle) +=
 // gscale lam, sbar (three fields, x then y then z) -= W lam with atomics
-hipError_t launch_node_shifts(const double *phi, double *sx, double *sy, double *sz, int n, hipStream_t s);
-hipError_t launch_deposit_adj(const double *xi, long long np, int n, const double *sx, const double *sy,
-                              const double *sz, const double *Mbar, double *sbar, double *gpos, double gscale,
-                              hipStream_t s);
+hipError_t launch_node_shifts(const double *phi, double *s3, int n, hipStream_t s);
+hipError_t launch_deposit_adj(const double *xi, long long np, int n, const double *s3, const double *Mbar,
+                              double *sbar, double *gpos, double gscale, hipStream_t s);
 // y += alpha x, X = double or float; with alpha_dev != null alpha is read there
 template <typename X>
 hipError_t launch_axpy(double *y, const X *x, double alpha, long n3, hipStream_t s,

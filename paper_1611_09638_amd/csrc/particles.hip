@@ -19,9 +19,9 @@ namespace recon {
 
 namespace {
 
-// s_n = D_c phi_n, one field per component
-__global__ void k_node_shifts(const double *__restrict__ phi, double *__restrict__ sx, double *__restrict__ sy,
-                              double *__restrict__ sz, int n, int ipb)
+// s_n = D_c phi_n, the three components of a node side by side (s3[3 n + a]),
+// so that one corner of a particle's cell is one cache line in the gathers
+__global__ void k_node_shifts(const double *__restrict__ phi, double *__restrict__ s3, int n, int ipb)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -30,14 +30,14 @@ __global__ void k_node_shifts(const double *__restrict__ phi, double *__restrict
     const int i0 = blockIdx.z * ipb, i1 = min(n, i0 + ipb);
     for (int i = i0; i < i1; ++i) {
         const size_t c = lin(i, j, k, n);
-        sx[c] = 0.5 * (phi[lin(wrapc(i + 1, n), j, k, n)] - phi[lin(wrapc(i - 1, n), j, k, n)]);
-        sy[c] = 0.5 * (phi[lin(i, jp, k, n)] - phi[lin(i, jm, k, n)]);
-        sz[c] = 0.5 * (phi[lin(i, j, kp, n)] - phi[lin(i, j, km, n)]);
+        s3[3 * c] = 0.5 * (phi[lin(wrapc(i + 1, n), j, k, n)] - phi[lin(wrapc(i - 1, n), j, k, n)]);
+        s3[3 * c + 1] = 0.5 * (phi[lin(i, jp, k, n)] - phi[lin(i, jm, k, n)]);
+        s3[3 * c + 2] = 0.5 * (phi[lin(i, j, kp, n)] - phi[lin(i, j, km, n)]);
     }
 }
 
 struct Shifts {
-    const double *x, *y, *z;
+    const double *s;  // node shifts, three per node
 };
 
 // x(xi) - y (nearest image) and its derivative; returns max |x(xi) - y|, or
@@ -70,7 +70,7 @@ __device__ double map_residual(const Shifts &s, int n, const double xi[3], const
         const double d0 = o0 ? 1.0 : -1.0, d1 = o1 ? 1.0 : -1.0, d2 = o2 ? 1.0 : -1.0;
         const size_t q = lin(o0 ? wrapc(f[0] + 1, n) : f[0], o1 ? wrapc(f[1] + 1, n) : f[1],
                              o2 ? wrapc(f[2] + 1, n) : f[2], n);
-        const double sc[3] = {s.x[q], s.y[q], s.z[q]};
+        const double sc[3] = {s.s[3 * q], s.s[3 * q + 1], s.s[3 * q + 2]};
         const double wc = w0 * w1 * w2;
         const double g[3] = {d0 * w1 * w2, w0 * d1 * w2, w0 * w1 * d2};
 #pragma unroll
@@ -275,7 +275,7 @@ __device__ __forceinline__ bool deposit_adj_particle(const double *__restrict__ 
         wc[c] = w0 * w1 * w2;
         const double g[3] = {d0 * w1 * w2, w0 * d1 * w2, w0 * w1 * d2};
         const double mb = wp * Mbar[q[c]];
-        const double sc[3] = {s.x[q[c]], s.y[q[c]], s.z[q[c]]};
+        const double sc[3] = {s.s[3 * q[c]], s.s[3 * q[c] + 1], s.s[3 * q[c] + 2]};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             xb[a] += mb * g[a];
@@ -390,13 +390,13 @@ hipError_t launch_init_xi(const float *pos, long long np, int n, double box, dou
 }
 
 hipError_t launch_invert_map(const double *phi, const float *pos, long long np, int n, double box, double *xi,
-                             double *sx, double *sy, double *sz, int max_iter, double tol, Part &p, hipStream_t s)
+                             double *s3, int max_iter, double tol, Part &p, hipStream_t s)
 {
     Shape3 sh = shape3(n);
-    k_node_shifts<<<sh.grid, sh.block, 0, s>>>(phi, sx, sy, sz, n, sh.ipb);
+    k_node_shifts<<<sh.grid, sh.block, 0, s>>>(phi, s3, n, sh.ipb);
     const int nb = particle_blocks(np);
     if (nb > kPartCap) return hipErrorInvalidValue;
-    k_invert<<<nb, 256, 0, s>>>(pos, np, (double)n / box, Shifts{sx, sy, sz}, n, xi, max_iter, tol, p.part);
+    k_invert<<<nb, 256, 0, s>>>(pos, np, (double)n / box, Shifts{s3}, n, xi, max_iter, tol, p.part);
     p.blocks = nb;
     p.k = 1;
     return hipGetLastError();
@@ -414,24 +414,23 @@ hipError_t launch_deposit_xi(const double *xi, long long np, int n, double *M, h
     return hipGetLastError();
 }
 
-hipError_t launch_node_shifts(const double *phi, double *sx, double *sy, double *sz, int n, hipStream_t s)
+hipError_t launch_node_shifts(const double *phi, double *s3, int n, hipStream_t s)
 {
     Shape3 sh = shape3(n);
-    k_node_shifts<<<sh.grid, sh.block, 0, s>>>(phi, sx, sy, sz, n, sh.ipb);
+    k_node_shifts<<<sh.grid, sh.block, 0, s>>>(phi, s3, n, sh.ipb);
     return hipGetLastError();
 }
 
-hipError_t launch_deposit_adj(const double *xi, long long np, int n, const double *sx, const double *sy,
-                              const double *sz, const double *Mbar, double *sbar, double *gpos, double gscale,
-                              hipStream_t s)
+hipError_t launch_deposit_adj(const double *xi, long long np, int n, const double *s3, const double *Mbar,
+                              double *sbar, double *gpos, double gscale, hipStream_t s)
 {
     const size_t n3 = (size_t)n * n * n;
     const double wp = (double)n3 / (double)np;
     if (deposit_block_fits(np, n))
-        k_deposit_adj_block<<<(unsigned)(np / 256), 256, 0, s>>>(xi, Shifts{sx, sy, sz}, n, wp, Mbar, sbar,
+        k_deposit_adj_block<<<(unsigned)(np / 256), 256, 0, s>>>(xi, Shifts{s3}, n, wp, Mbar, sbar,
                                                                  sbar + n3, sbar + 2 * n3, gpos, gscale);
     else
-        k_deposit_adj<<<particle_blocks(np), 256, 0, s>>>(xi, np, Shifts{sx, sy, sz}, n, wp, Mbar, sbar, sbar + n3,
+        k_deposit_adj<<<particle_blocks(np), 256, 0, s>>>(xi, np, Shifts{s3}, n, wp, Mbar, sbar, sbar + n3,
                                                           sbar + 2 * n3, gpos, gscale);
     return hipGetLastError();
 }

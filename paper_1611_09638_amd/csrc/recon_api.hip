@@ -57,6 +57,7 @@ struct Layout {
     size_t tape;
     size_t adj[8];
     size_t xi;  // particle deposit: Lagrangian positions, 3 per particle (up to n^3 particles)
+    size_t shifts;  // particle deposit: node shifts D_c phi, 3 per node
     size_t K;   // exact-Jacobian solve: K = M e^-1, 6 fields, and its mean diagonal
     int levels = 0;
 };
@@ -158,6 +159,7 @@ bool make_layout(int n, const recon_config *cfg, Layout &Lo)
         }
     }
     Lo.xi = cfg->particle_deposit ? take(3 * f64) : (size_t)-1;
+    Lo.shifts = cfg->particle_deposit ? take(3 * f64) : (size_t)-1;
     Lo.K = cfg->full_operator ? take(7 * f64) : (size_t)-1;
     Lo.total = off;
     return true;
@@ -194,6 +196,7 @@ struct recon_ctx {
     const float *part_pos = nullptr;
     long long part_np = 0;
     double *xi = nullptr;
+    double *shifts = nullptr;  // node shifts of the particle deposit (3 per node)
     // exact-Jacobian solve: K = M e^-1 of the current step (six fields)
     MassTensor Kf{};
     double last_tol = 0.0;
@@ -646,7 +649,7 @@ int normalize(recon_ctx *ctx, const double *rho, double *m, double *mean_out)
 int deposit_particles(recon_ctx *ctx)
 {
     double v[1];
-    HIPCHK(launch_invert_map(ctx->phi, ctx->part_pos, ctx->part_np, ctx->n, ctx->box, ctx->xi, ctx->r, ctx->z, ctx->p,
+    HIPCHK(launch_invert_map(ctx->phi, ctx->part_pos, ctx->part_np, ctx->n, ctx->box, ctx->xi, ctx->shifts,
                              kInvertIters, kInvertTol, ctx->part, ctx->stream));
     TRY(fetch_sum(ctx, v));
     if (v[0] != 0.0)
@@ -809,7 +812,7 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad, c
         if (gpos) {
             // the step's Lagrangian positions, warm-started from the later
             // step's (ctx->xi holds those of the final mesh after the forward)
-            HIPCHK(launch_invert_map(phi, pos, np, n, ctx->box, ctx->xi, ctx->r, ctx->z, ctx->p, kInvertIters,
+            HIPCHK(launch_invert_map(phi, pos, np, n, ctx->box, ctx->xi, ctx->shifts, kInvertIters,
                                      kInvertTol, ctx->part, ctx->stream));
             TRY(fetch_sum(ctx, v));
             if (v[0] != 0.0)
@@ -847,10 +850,9 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad, c
         HIPCHK(launch_add_scalar(Mbar, ctx->scal + 16, 1.0, 1.0, n3, ctx->stream));
         if (gpos) {
             // M = CIC(xi), xi = X^-1(y; D_c phi): xb <- adjoint of the node
-            // shifts (their fields t, m, mbar are idle here in this mode)
+            // shifts (still those of this step's phi, from the inversion)
             HIPCHK(launch_zero(xb, 3 * n3 * 8, ctx->stream));
-            HIPCHK(launch_node_shifts(phi, ctx->t, ctx->m, mbar, n, ctx->stream));
-            HIPCHK(launch_deposit_adj(ctx->xi, np, n, ctx->t, ctx->m, mbar, Mbar, xb, gpos, (double)n / ctx->box,
+            HIPCHK(launch_deposit_adj(ctx->xi, np, n, ctx->shifts, Mbar, xb, gpos, (double)n / ctx->box,
                                       ctx->stream));
         } else {
             // M = det(e) rho~(x), then phibar through e and x
@@ -948,6 +950,7 @@ int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace,
     ctx->q = wsp<double>(ctx, lo.q);
     ctx->dphi = wsp<double>(ctx, lo.dphi);
     ctx->xi = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.xi) : nullptr;
+    ctx->shifts = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.shifts) : nullptr;
     if (ctx->cfg.full_operator) {
         double *k0 = wsp<double>(ctx, lo.K);
         ctx->Kf = MassTensor{k0,
@@ -1489,9 +1492,13 @@ int recon_stage_invert_map(recon_ctx *ctx, const double *phi, const float *pos, 
 {
     TRY(check_ctx(ctx));
     if (!phi || !pos || np <= 0 || !(box > 0.0) || !xi || !failed) return fail(ctx, RECON_E_ARG, "bad arguments");
+    // the node shifts need 3 n^3 contiguous doubles: the particle deposit's
+    // own buffer, else r, z and p where they lie back to back
+    double *s3 = ctx->shifts;
+    if (!s3 && ctx->z == ctx->r + ctx->n3 && ctx->p == ctx->r + 2 * ctx->n3) s3 = ctx->r;
+    if (!s3) return fail(ctx, RECON_E_ARG, "no room for the node shifts: make the context with particle_deposit = 1");
     double v[1];
-    HIPCHK(launch_invert_map(phi, pos, np, ctx->n, box, xi, ctx->r, ctx->z, ctx->p, kInvertIters, kInvertTol,
-                             ctx->part, ctx->stream));
+    HIPCHK(launch_invert_map(phi, pos, np, ctx->n, box, xi, s3, kInvertIters, kInvertTol, ctx->part, ctx->stream));
     TRY(fetch_sum(ctx, v));
     *failed = v[0];
     return RECON_OK;

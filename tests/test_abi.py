@@ -79,16 +79,17 @@ def test_config_default_and_workspace_sizing(blib):
 
 def test_workspace_of_the_options_and_their_exclusions(blib):
     """The options' own fields (K = M e^-1 and its mean diagonal for the
-    exact-Jacobian solve; the Lagrangian positions, 3 per node, for the particle
-    deposit), and the combinations without a reverse mode or a meaning."""
+    exact-Jacobian solve; the Lagrangian positions and the node shifts, 3 per
+    node each, for the particle deposit), and the combinations without a
+    reverse mode or a meaning."""
     w = blib.workspace_bytes(64, blib.Config())
     f = 64 ** 3 * 8
     assert blib.workspace_bytes(64, blib.Config(full_operator=1)) == w + 7 * f
-    assert blib.workspace_bytes(64, blib.Config(particle_deposit=1)) == w + 3 * f
+    assert blib.workspace_bytes(64, blib.Config(particle_deposit=1)) == w + 6 * f  # positions and node shifts
     assert blib.workspace_bytes(64, blib.Config(mass_update=1)) == w
     assert blib.workspace_bytes(64, blib.Config(full_operator=1, mass_update=1)) == w + 7 * f
     tape = blib.workspace_bytes(64, blib.Config(record_tape=1))
-    assert blib.workspace_bytes(64, blib.Config(particle_deposit=1, record_tape=1)) == tape + 3 * f
+    assert blib.workspace_bytes(64, blib.Config(particle_deposit=1, record_tape=1)) == tape + 6 * f
     for bad in (dict(full_operator=1, record_tape=1), dict(mass_update=1, record_tape=1),
                 dict(particle_deposit=1, mass_update=1), dict(full_operator=2), dict(particle_deposit=2),
                 dict(mass_update=2)):
