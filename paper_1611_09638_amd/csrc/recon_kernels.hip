@@ -883,12 +883,33 @@ __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, cons
             ks[KS_RZ_OLD] = rz;
         }
     }
+    // two consecutive elements per thread (16-byte accesses; every field is
+    // 256-byte aligned), the last element of an odd count by thread 0
     double v[1] = {0.0};
-    for (long p = blockIdx.x * 256L + threadIdx.x; p < n3; p += 256L * gridDim.x) {
-        if (U) u[p] += alpha * pv[p];
-        const double rv = r[p] - alpha * q[p];
-        r[p] = rv;
-        if (r32) r32[p] = (float)rv;
+    const long h = n3 >> 1;
+    for (long p = blockIdx.x * 256L + threadIdx.x; p < h; p += 256L * gridDim.x) {
+        const long e = 2 * p;
+        if (U) {
+            const double2 pp = *reinterpret_cast<const double2 *>(pv + e);
+            double2 uu = *reinterpret_cast<double2 *>(u + e);
+            uu.x += alpha * pp.x;
+            uu.y += alpha * pp.y;
+            *reinterpret_cast<double2 *>(u + e) = uu;
+        }
+        const double2 rr = *reinterpret_cast<const double2 *>(r + e);
+        const double2 qq = *reinterpret_cast<const double2 *>(q + e);
+        const double r0 = rr.x - alpha * qq.x, r1 = rr.y - alpha * qq.y;
+        *reinterpret_cast<double2 *>(r + e) = make_double2(r0, r1);
+        if (r32) *reinterpret_cast<float2 *>(r32 + e) = make_float2((float)r0, (float)r1);
+        v[0] += r0 * r0;
+        v[0] += r1 * r1;
+    }
+    if ((n3 & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const long e = n3 - 1;
+        if (U) u[e] += alpha * pv[e];
+        const double rv = r[e] - alpha * q[e];
+        r[e] = rv;
+        if (r32) r32[e] = (float)rv;
         v[0] += rv * rv;
     }
     block_reduce_store<1, RED_SUM>(v, part, blockIdx.x);
@@ -897,7 +918,12 @@ __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, cons
 hipError_t launch_update_ur(double *u, double *r, const double *pv, const double *q, double alpha, float *r32, long n3,
                             double *ks, Part &p, hipStream_t s)
 {
-    int nb = flat_blocks(n3);
+    // the paired accesses need 16-byte aligned fields
+    if ((reinterpret_cast<uintptr_t>(r) | reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(u) |
+         reinterpret_cast<uintptr_t>(pv)) % 16 ||
+        reinterpret_cast<uintptr_t>(r32) % 8)
+        return hipErrorInvalidValue;
+    int nb = flat_blocks((n3 + 1) / 2);
     if (u) k_update_ur<true><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part, ks);
     else k_update_ur<false><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part, ks);
     p.blocks = nb;
