@@ -128,13 +128,16 @@ typedef struct recon_ctx recon_ctx;
 int recon_config_default(recon_config *cfg);
 
 /* Bytes of device workspace recon_init needs for an n^3 grid under cfg (host
- * call, no device work).  Returns 0 if n/cfg are invalid. */
+ * call, no device work).  Returns 0 if n/cfg are invalid, n above 1024
+ * included. */
 size_t recon_workspace_bytes(int n, const recon_config *cfg);
 
 /* Create a context for n^3 grids.  workspace: device buffer of at least
  * recon_workspace_bytes(n, cfg) bytes, 256-byte aligned, owned by the caller
  * and untouched by anyone else while the context lives.  hip_stream: a
- * hipStream_t (NULL = default stream).  n must equal coarse_n * 2^k. */
+ * hipStream_t (NULL = default stream).  n must equal coarse_n * 2^k and be at
+ * most 1024 (the largest such grid whose workspace fits one 288 GB device);
+ * anything else returns RECON_E_ARG. */
 int recon_init(recon_ctx **ctx, int n, const recon_config *cfg, void *workspace, size_t ws_bytes,
                void *hip_stream);
 

@@ -103,6 +103,11 @@ def test_init_rejects_bad_workspace_without_touching_the_device(blib):
     assert L.recon_init(ctypes.byref(ctx), 32, ctypes.byref(c), None, 0, None) == -7
     assert L.recon_init(ctypes.byref(ctx), 32, ctypes.byref(c), ctypes.c_void_p(256), 16, None) == -7
     assert L.recon_init(ctypes.byref(ctx), 33, ctypes.byref(c), ctypes.c_void_p(256), 1 << 40, None) == -1
+    # n must be coarse_n * 2^k (coarse_n = 8 by default) and at most 1024
+    for n in (0, -8, 1, 4, 10, 12, 24, 2048):
+        assert blib.workspace_bytes(n, blib.Config()) == 0, n
+        assert L.recon_init(ctypes.byref(ctx), n, ctypes.byref(c), ctypes.c_void_p(256), 1 << 62, None) == -1, n
+    assert blib.workspace_bytes(1024, blib.Config()) > 0
     assert L.recon_init(None, 32, ctypes.byref(c), ctypes.c_void_p(256), 1 << 40, None) == -1
     assert L.recon_strerror(-3).decode().startswith("no step")
     assert L.recon_last_error(None).decode() == "null context"
