@@ -182,6 +182,7 @@ struct recon_ctx {
     Levels<double> L64;
     Levels<float> L32;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_ks = nullptr;  // marks the Krylov scalars' copy to host_scal
     // cfg.profile: event pairs around each fine-level smoother sweep
     hipEvent_t *prof = nullptr;
     bool prof_zero[4096];  // the timed sweep started from u = 0 (reads a and b only)
@@ -255,13 +256,25 @@ constexpr double kInvertTol = 1e-12;
 // The device scalars of the conjugate-gradient loop (KS_* in kernels.h) sit at
 // this offset of ctx->scal; fetch_krylov copies all of them to the host.
 constexpr int kKrylovScal = 32;
+// The next V-cycle is queued ahead of the stop test while the extrapolated
+// residual norm is above this multiple of the target.
+constexpr double kAheadMargin = 8.0;
 static_assert(kKrylovScal + KS_COUNT <= kScal, "the scalar block fits");
 
-int fetch_krylov(recon_ctx *ctx, double *out)
+// In two halves, so that work queued between them overlaps the round trip:
+// the copy is enqueued with an event behind it, and the host later waits for
+// that event only.  Nothing queued in between may read host_scal.
+int fetch_krylov_begin(recon_ctx *ctx)
 {
     HIPCHK(hipMemcpyAsync(ctx->host_scal, ctx->scal + kKrylovScal, sizeof(double) * KS_COUNT,
                           hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev_ks, ctx->stream));
+    return RECON_OK;
+}
+
+int fetch_krylov_end(recon_ctx *ctx, double *out)
+{
+    HIPCHK(hipEventSynchronize(ctx->ev_ks));
     for (int c = 0; c < KS_COUNT; ++c) out[c] = ctx->host_scal[c];
     return RECON_OK;
 }
@@ -517,6 +530,8 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         double *pc = ctx->p, *pn = ctx->t;
         auto f32 = [](double *x) { return reinterpret_cast<float *>(x); };
         bool due = false;
+        // residual norms: the last one seen and the next one extrapolated
+        double rn_last = 0.0, rn_next = 0.0;
         while (true) {
             if (stream && Kf) {
                 double *ud = due ? ctx->u : nullptr;
@@ -555,7 +570,19 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
                                     ctx->stream));
             due = stream;
             HIPCHK(reduce_finalize(ctx->part, sums, ks + KS_RR, ctx->stream));
-            TRY(fetch_krylov(ctx, v));
+            // The stop test needs ||r|| on the host.  When this step cannot be
+            // the last (a fixed count not yet reached, or the residual norm
+            // extrapolated from the last two steps still well above the
+            // target), the next V-cycle is queued before the host waits, so
+            // the device does not idle through the round trip.  The V-cycle
+            // writes only z and the level scratch, never u, r or the current
+            // direction, so a wrong guess costs one V-cycle and changes no
+            // result.
+            const bool ahead =
+                cycles < max_cycles && (fixed > 0 ? cycles < fixed : rn_next > kAheadMargin * tol * bn);
+            TRY(fetch_krylov_begin(ctx));
+            if (ahead) TRY(precondition(ctx));
+            TRY(fetch_krylov_end(ctx, v));
             const double rn = std::sqrt(v[KS_RR]);
             if (!std::isfinite(rn) || !std::isfinite(v[KS_ALPHA])) break;
             if (fixed > 0 ? cycles >= fixed : rn <= tol * bn) {
@@ -563,7 +590,9 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
                 break;
             }
             if (cycles >= max_cycles) break;
-            TRY(precondition(ctx));
+            if (!ahead) TRY(precondition(ctx));
+            rn_next = rn_last > 0.0 ? rn * (rn / rn_last) : 0.0;
+            rn_last = rn;
             ++cycles;
             if (mixed) HIPCHK(launch_dots_zr_zq<float>(ctx->L32.u[0], ctx->r, ctx->q, n3, ctx->part, ctx->stream));
             else HIPCHK(launch_dots_zr_zq<double>(ctx->z, ctx->r, ctx->q, n3, ctx->part, ctx->stream));
@@ -978,7 +1007,8 @@ int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace,
     }
     if (hipHostMalloc(reinterpret_cast<void **>(&ctx->host_scal), sizeof(double) * kScal, hipHostMallocDefault) !=
             hipSuccess ||
-        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_ks, hipEventDisableTiming) != hipSuccess) {
         recon_destroy(ctx);
         return RECON_E_HIP;
     }
@@ -1004,6 +1034,7 @@ void recon_destroy(recon_ctx *ctx)
     if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->ev_ks) (void)hipEventDestroy(ctx->ev_ks);
     if (ctx->prof) {
         for (int i = 0; i < 2 * kProfPairs; ++i)
             if (ctx->prof[i]) (void)hipEventDestroy(ctx->prof[i]);
