@@ -285,6 +285,25 @@ int fetch_sum(recon_ctx *ctx, double *out)
     return fetch(ctx, ops, out);
 }
 
+// fetch_sum in two halves, as fetch_krylov_begin/_end; the end reads the
+// first sum only.
+int fetch_sum1_begin(recon_ctx *ctx)
+{
+    static const int ops[8] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM};
+    HIPCHK(reduce_finalize(ctx->part, ops, ctx->scal, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->host_scal, ctx->scal, sizeof(double) * ctx->part.k, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev_ks, ctx->stream));
+    return RECON_OK;
+}
+
+int fetch_sum1_end(recon_ctx *ctx, double *out)
+{
+    HIPCHK(hipEventSynchronize(ctx->ev_ks));
+    out[0] = ctx->host_scal[0];
+    return RECON_OK;
+}
+
 double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
 
 // ------------------------------------------------------------- multigrid
@@ -493,18 +512,28 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
     if (bn == 0.0) {
         status = RECON_OK;
     } else if (ctx->cfg.solver == RECON_SOLVER_VCYCLE) {
+        // As in the Krylov loop below, the next V-cycle is queued ahead of the
+        // stop test when this cycle cannot be the last; it writes only z and
+        // the level scratch, and u changes only in the correction after it.
+        bool queued = false;
+        double rn_last = 0.0, rn_next = 0.0;
         for (cycles = 1; cycles <= max_cycles; ++cycles) {
-            TRY(precondition(ctx));
+            if (!queued) TRY(precondition(ctx));
             if (mixed) HIPCHK(launch_add_correction<float>(ctx->u, ctx->L32.u[0], n3, ctx->stream));
             else HIPCHK(launch_add_correction<double>(ctx->u, ctx->z, n3, ctx->stream));
             HIPCHK(residual_norm(ctx, ctx->u, a0, b, ctx->r, r32, Kf));
-            TRY(fetch_sum(ctx, v));
+            queued = cycles < max_cycles && (fixed > 0 ? cycles < fixed : rn_next > kAheadMargin * tol * bn);
+            TRY(fetch_sum1_begin(ctx));
+            if (queued) TRY(precondition(ctx));
+            TRY(fetch_sum1_end(ctx, v));
             const double rn = std::sqrt(v[0]);
             if (!std::isfinite(rn)) break;
             if (fixed > 0 ? cycles >= fixed : rn <= tol * bn) {
                 status = RECON_OK;
                 break;
             }
+            rn_next = rn_last > 0.0 ? rn * (rn / rn_last) : 0.0;
+            rn_last = rn;
         }
     } else {
         // Conjugate gradients on A u = b preconditioned by one symmetric V-cycle,
