@@ -5,8 +5,8 @@ and by the benchmark's ``cpu_baseline`` leg.  The product path (the HIP library
 and its Python binding) never imports or calls anything here, and this package
 imports nothing from the product package.
 
-Thin numpy wrappers over ``librecon_oracle.so`` (plain C, see
-``recon_oracle.c`` and ``recon_oracle_adjoint.c``).
+Thin numpy wrappers over ``librecon_oracle.so`` (plain C, ``recon_oracle.c``:
+the forward method and its reverse mode).
 """
 from __future__ import annotations
 
@@ -18,7 +18,7 @@ from dataclasses import dataclass, fields
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ["recon_oracle.c", "recon_oracle_adjoint.c"]
+_SOURCES = ["recon_oracle.c"]
 _LIB_PATH = os.path.join(_HERE, "librecon_oracle.so")
 
 ORC_E = {0: "ok", -1: "E_ARG", -2: "E_INPUT", -3: "E_NOT_PD", -4: "E_NO_CONVERGENCE", -5: "E_NO_TAPE", -7: "E_NOMEM"}
@@ -28,7 +28,7 @@ MAX_STEPS = 256
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no fast-math, no FMA contraction)."""
-    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
     if not force and os.path.exists(_LIB_PATH):
         newest = max(os.path.getmtime(s) for s in srcs)
         if os.path.getmtime(_LIB_PATH) >= newest:
@@ -46,7 +46,7 @@ def build_sanitized(path: str) -> str:
     aborts) into ``path``.  Loaded instead of the normal build when the
     environment variable RECON_ORACLE_LIB names it; the process must preload
     the ASan runtime."""
-    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
     cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
            "-o", path] + srcs + ["-lm"]

@@ -517,7 +517,8 @@ int mg_solve(recon_ctx *ctx, const double *a0, const double *b, double tol, int 
         // the level scratch, and u changes only in the correction after it.
         bool queued = false;
         double rn_last = 0.0, rn_next = 0.0;
-        for (cycles = 1; cycles <= max_cycles; ++cycles) {
+        for (int c = 1; c <= max_cycles; ++c) {
+            cycles = c;
             if (!queued) TRY(precondition(ctx));
             if (mixed) HIPCHK(launch_add_correction<float>(ctx->u, ctx->L32.u[0], n3, ctx->stream));
             else HIPCHK(launch_add_correction<double>(ctx->u, ctx->z, n3, ctx->stream));
@@ -703,7 +704,7 @@ int normalize(recon_ctx *ctx, const double *rho, double *m, double *mean_out)
 
 // Particle deposit: M = CIC of the particles at their Lagrangian positions for
 // the current phi, found by Newton from the previous ones; the node shifts
-// go into r, z, p (idle between solves).
+// go into their own buffer (ctx->shifts), which the reverse mode reads.
 int deposit_particles(recon_ctx *ctx)
 {
     double v[1];
@@ -1094,6 +1095,8 @@ int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double
 {
     TRY(check_ctx(ctx));
     ctx->err[0] = 0;
+    // a failed or partial solve leaves no tape behind
+    ctx->tape_valid = 0;
     if (!density || n != ctx->n || !(box > 0.0) || !(tol >= 0.0))
         return fail(ctx, RECON_E_ARG, "bad argument (density %p, n %d vs %d, box %g, tol %g)", (const void *)density,
                     n, ctx->n, box, tol);
@@ -1124,7 +1127,10 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
 {
     TRY(check_ctx(ctx));
     ctx->err[0] = 0;
+    ctx->tape_valid = 0;
     if (!pos || np <= 0 || !(box > 0.0) || !(tol >= 0.0)) return fail(ctx, RECON_E_ARG, "bad particle arguments");
+    if (ctx->cfg.particle_deposit && np > ctx->n3)
+        return fail(ctx, RECON_E_ARG, "the particle deposit takes at most n^3 particles");
     recon_stats local;
     recon_stats *st = stats ? stats : &local;
     std::memset(st, 0, sizeof(*st));
@@ -1141,7 +1147,6 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
     if (ctx->cfg.particle_deposit) {
         // every step deposits the particles at their Lagrangian positions,
         // starting from xi = y (the map is the identity at phi = 0)
-        if (np > ctx->n3) return fail(ctx, RECON_E_ARG, "the particle deposit takes at most n^3 particles");
         ctx->part_pos = pos;
         ctx->part_np = np;
         HIPCHK(launch_init_xi(pos, np, ctx->n, box, ctx->xi, ctx->stream));

@@ -369,3 +369,25 @@ def test_choose_step_and_cic(torch_cuda, orc):
     rho_o = orc.cic_particles(pos, n, 250.0)
     assert np.abs(rho_g - rho_o).max() < 1e-12
     assert abs(rho_g.sum() - 5000) < 1e-9
+
+
+@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("amp,s_max,axis,j_exp", [
+    (20.0, 1.0, 0, 3), (20.0, 100.0, 0, 2), (20.0, 0.5, 2, 4), (0.5, 1.0, 2, 0)])
+def test_choose_step_single_mode_closed_form(torch_cuda, orc, n, amp, s_max, axis, j_exp):
+    """Step control against the closed form of a single Fourier mode (Sec. II):
+    dphi = A sin(theta x_axis), theta = 2 pi / 16 scaled to the grid, shifts
+    nodes by at most A sin(theta) and bends the triad to 1 - 4 A sin^2(theta/2)
+    at worst; the step is the first 2^-j passing both bounds.  Covers a binding
+    shift bound (j = 3, 4), a binding PD bound (j = 2) and a full step."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    theta = 2 * np.pi / 16
+    i = np.arange(n)
+    X = np.meshgrid(i, i, i, indexing="ij")
+    dphi = amp * np.sin(theta * X[axis])
+    phi = 0.3 / (4 * np.sin(theta / 2) ** 2) * np.cos(theta * X[(axis + 1) % 3])
+    rec = binding.Recon(n, binding.Config(s_max=s_max))
+    a_g = rec.choose_step(dev(torch, phi), dev(torch, dphi))
+    assert a_g == 2.0 ** -j_exp
+    assert orc.choose_step(phi, dphi, orc.Config(s_max=s_max)) == (j_exp, 2.0 ** -j_exp)

@@ -78,6 +78,108 @@ def test_count_not_pd_closed_form_and_eigenvalues(orc):
     assert orc.count_not_pd(np.zeros((n, n, n))) == 0
 
 
+# ------------------------------------------------- limiters and step control
+
+def _diagonal_triad_potential(n, c):
+    """phi = sum_a A_a cos(2 pi x_a / n) with A_a = c_a / (4 sin^2(pi/n)).  Its
+    compact Hessian is exactly diagonal (the cross differences of a sum of
+    one-axis functions vanish) with entries -c_a cos(2 pi x_a / n), so the
+    triad is diag(1 - c_a cos(2 pi x_a / n)): det and smallest eigenvalue are
+    the product and the minimum of the three closed-form entries."""
+    i = np.arange(n)
+    X = np.meshgrid(i, i, i, indexing="ij")
+    s2 = 4 * np.sin(np.pi / n) ** 2
+    phi = sum((c[a] / s2) * np.cos(2 * np.pi * X[a] / n) for a in range(3))
+    diag = [1.0 - c[a] * np.cos(2 * np.pi * X[a] / n) for a in range(3)]
+    return phi, diag
+
+
+@pytest.mark.parametrize("xi_m,v_m", [(0.1, 5.0), (0.2, 5.0), (0.1, 10.0), (0.07, 2.0)])
+def test_source_terms_limiters_closed_form(orc, xi_m, v_m):
+    """t = Sigma + C + E (App. A, Eq. elliptic and the limiter definitions):
+    Sigma = mean(M) - M, compression limiter C = 4 max(0, xi_m/lambda_0 - 1)^2
+    (the reading of the garbled printed form), expansion limiter
+    E = -2 H(sqrt g - v_m) |Sigma| with H(0) = 0.  sqrt g = det e and lambda_0
+    come from the closed-form diagonal triad, not from a stencil or an
+    eigen-solver; the limiter constants are those of App. B's sweeps."""
+    n = 16
+    c = (0.94, 0.7, 0.85)
+    phi, diag = _diagonal_triad_potential(n, c)
+    g = diag[0] * diag[1] * diag[2]
+    lam0 = np.minimum(np.minimum(diag[0], diag[1]), diag[2])
+    rng = np.random.default_rng(31)
+    M = np.exp(0.6 * rng.normal(size=(n, n, n)))
+    sigma = M.mean() - M
+    ratio = xi_m / lam0 - 1.0
+    C = np.where(ratio > 0, 4.0 * ratio ** 2, 0.0)
+    expand = g > v_m
+    E = np.where(expand, -2.0 * np.abs(sigma), 0.0)
+    assert np.abs(g - v_m).min() > 1e-6 and np.abs(lam0 - xi_m).min() > 1e-6  # no node on a switch
+    if v_m < 10.0:
+        # the expansion limiter acts on overdense and underdense nodes alike
+        assert (expand & (sigma > 0)).sum() > 20 and (expand & (sigma < 0)).sum() > 20
+    else:
+        assert not expand.any()  # det e <= 7.3 < 10 on this mesh
+    assert (C > 0).sum() >= n * n  # the i = 0 plane is compressed below xi_m
+    t, rho_bar = orc.source_terms(phi, M, xi_m, v_m)
+    assert abs(rho_bar - M.mean()) <= 1e-15 * M.mean()
+    np.testing.assert_allclose(t, sigma + C + E, rtol=0, atol=1e-11)
+    # the limiters alone: with M uniform, Sigma = 0 and E = 0, so t = C
+    t0, _ = orc.source_terms(phi, np.ones_like(M), xi_m, v_m)
+    np.testing.assert_allclose(t0, C, rtol=0, atol=1e-11)
+
+
+def _expected_step(shift, curv, s_max, max_halvings=30):
+    """First j with 2^-j shift <= s_max and 1 - 2^-j curv > 0 (Sec. II: small,
+    positive-definite steps), for a step whose largest node shift is `shift`
+    and whose triad is 1 - alpha curv at its worst node."""
+    for j in range(max_halvings + 1):
+        alpha = 2.0 ** -j
+        if alpha * shift <= s_max and 1.0 - alpha * curv > 0.0:
+            return j
+    return -1
+
+
+@pytest.mark.parametrize("amp,s_max,axis,binding", [
+    (20.0, 1.0, 0, "shift"), (20.0, 100.0, 0, "pd"), (20.0, 0.5, 2, "shift"),
+    (3.0, 1.0, 1, "shift"), (0.5, 1.0, 2, "none"), (200.0, 1.0, 1, "shift"), (20.0, 4.0, 0, "pd")])
+def test_step_bound_single_mode_closed_form(orc, amp, s_max, axis, binding):
+    """Step control (Sec. II; App. A): alpha = 2^-j is the largest power of two
+    that keeps I + Hess(phi + alpha dphi) positive definite and moves no node
+    more than s_max cells.  dphi = amp sin(theta x_axis), theta = 2 pi / n,
+    has central-difference shift amp sin(theta) cos(theta x) (largest at x = 0)
+    and compact second difference -4 sin^2(theta/2) amp sin(theta x) (most
+    negative at x = n/4); the background phi bends another axis only.  Cases
+    cover a binding shift bound, a binding PD bound and a full step."""
+    n = 16
+    theta = 2 * np.pi / n
+    i = np.arange(n)
+    X = np.meshgrid(i, i, i, indexing="ij")
+    dphi = amp * np.sin(theta * X[axis])
+    other = (axis + 1) % 3
+    phi = 0.3 / (4 * np.sin(np.pi / n) ** 2) * np.cos(theta * X[other])  # triad entry 1 - 0.3 cos > 0
+    shift = amp * np.sin(theta)
+    curv = 4 * np.sin(theta / 2) ** 2 * amp
+    j_exp = _expected_step(shift, curv, s_max)
+    j_pd = _expected_step(0.0, curv, s_max)
+    j_shift = _expected_step(shift, 0.0, s_max)
+    assert j_exp == max(j_pd, j_shift)
+    if binding == "shift":
+        assert j_shift > j_pd
+    elif binding == "pd":
+        assert j_pd > j_shift
+    else:
+        assert j_exp == 0
+    assert abs(orc.max_shift(dphi) - shift) <= 1e-13 * shift
+    cfg = orc.Config(s_max=s_max)
+    j, alpha = orc.choose_step(phi, dphi, cfg)
+    assert j == j_exp and alpha == 2.0 ** -j_exp
+    # the accepted trial is PD; for a binding PD bound the next larger one is not
+    assert orc.is_pd(phi + alpha * dphi)
+    if binding == "pd":
+        assert not orc.is_pd(phi + 2 * alpha * dphi)
+
+
 # ------------------------------------------------------------- operators
 
 def test_smoothing_operator_symbol_and_symmetry(orc):
