@@ -100,32 +100,54 @@ def oracle_samples(workload):
         return json.load(f)
 
 
-def stream_ceilings(torch, dev, reps=10):
+PROBE_LIB = os.path.join(ROOT, "paper_1611_09638_amd", "libstream_probe.so")
+PROBE_KINDS = {"read": (0, 1), "write": (1, 1), "copy": (2, 2), "three_reads_one_write": (3, 4)}
+
+
+def _probe_lib():
+    import ctypes
+    if not os.path.exists(PROBE_LIB):
+        raise RuntimeError("%s is not built (run __graft_entry__.build())" % PROBE_LIB)
+    L = ctypes.CDLL(PROBE_LIB)
+    vp = ctypes.c_void_p
+    L.stream_probe_run.restype = ctypes.c_int
+    L.stream_probe_run.argtypes = [ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_int, vp, ctypes.c_int,
+                                   vp, ctypes.POINTER(ctypes.c_float)]
+    return L
+
+
+def stream_ceilings(torch, dev, reps=5, gib=4, kinds=None, blocks=(4096, 16384, 65536, 262144)):
     """Achievable HBM bandwidth on this GPU for the access patterns of the
-    path, from torch's own streaming kernels over 1 GiB arrays (FP32): read
-    only (sum), copy (1 read, 1 write) and 3 reads + 1 write (addcmul, the
-    smoother's mix).  GB/s counted as bytes moved / kernel time."""
-    nel = (1 << 30) // 4
-    x = torch.rand(nel, device=dev)
-    y = torch.rand(nel, device=dev)
-    z = torch.rand(nel, device=dev)
-    o = torch.empty(nel, device=dev)
-    s = torch.empty((), device=dev)
-    cases = {"read": (lambda: torch.sum(x, dim=0, out=s), 1), "copy": (lambda: o.copy_(x), 2),
-             "three_reads_one_write": (lambda: torch.addcmul(x, y, z, out=o), 4)}
+    path, from the hand-written streaming probes (libstream_probe.so: 16-byte
+    accesses, every byte moved once) over arrays of `gib` GiB each (FP32),
+    far beyond the 256 MB last-level cache: read only, write only, copy
+    (1 read, 1 write) and 3 reads + 1 write (the smoother's mix).  GB/s =
+    bytes moved / mean kernel time (hipEvents); the best over grid sizes."""
+    import ctypes
+    L = _probe_lib()
+    nbytes = gib << 30
+    nel = nbytes // 4
+    arrs = [torch.ones(nel, device=dev) for _ in range(4)]
+    part = torch.empty(max(blocks), device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
     out = {}
-    for name, (fn, arrays) in cases.items():
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[name + "_GBps"] = round(arrays * (1 << 30) / (ms * 1e-3) / 1e9, 1)
-    del x, y, z, o
+    for name, (kind, arrays) in PROBE_KINDS.items():
+        if kinds and name not in kinds:
+            continue
+        best = None
+        for nb in blocks:
+            ms = ctypes.c_float(0.0)
+            rc = L.stream_probe_run(kind, arrs[0].data_ptr(), arrs[1].data_ptr(), arrs[2].data_ptr(),
+                                    arrs[3].data_ptr(), nbytes, nb, part.data_ptr(), reps, stream, ctypes.byref(ms))
+            if rc:
+                raise RuntimeError("stream probe %s failed (%d)" % (name, rc))
+            gbs = arrays * nbytes / (ms.value * 1e-3) / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, nb, ms.value)
+        out[name + "_GBps"] = round(best[0], 1)
+        out[name + "_blocks"] = best[1]
+    out["array_GiB"] = gib
+    del arrs, part
     torch.cuda.empty_cache()
     return out
 
@@ -366,7 +388,7 @@ def main():
     from paper_1611_09638_amd import binding, inputs
 
     if args.stream:
-        print(json.dumps({"stream": stream_ceilings(torch, torch.device("cuda:0"), reps=20)}), flush=True)
+        print(json.dumps({"stream": stream_ceilings(torch, torch.device("cuda:0"), reps=10)}), flush=True)
         return
 
     if args.probe:
@@ -376,15 +398,23 @@ def main():
         a = torch.rand((n, n, n), dtype=torch.float64, device=dev, generator=g) + 0.01
         u = torch.rand((n, n, n), dtype=torch.float64, device=dev, generator=g)
         b = torch.rand((n, n, n), dtype=torch.float64, device=dev, generator=g)
-        y = torch.empty_like(a)
-        y.copy_(a)  # calibration: 1 GiB read + 1 GiB written
+        # calibration: the hand-written copy probe over 4 GiB (4 GiB read +
+        # 4 GiB written per launch, far beyond the last-level cache)
+        import ctypes
+        x = torch.ones(1 << 30, device=dev)
+        y = torch.empty_like(x)
+        ms = ctypes.c_float(0.0)
+        rc = _probe_lib().stream_probe_run(2, y.data_ptr(), x.data_ptr(), None, None, 4 << 30, 8192, None, 1,
+                                           torch.cuda.current_stream(dev).cuda_stream, ctypes.byref(ms))
+        assert rc == 0
+        del x, y
         torch.cuda.synchronize()
         rec = binding.Recon(n, binding.Config(precision=binding.MIXED), device=dev)
         rec.rbgs(u.float(), a.float(), b.float(), first=1, variant=2)
         rec.rbgs(u, a, b, first=1, variant=2)
         torch.cuda.synchronize()
-        print(json.dumps({"probe": "copy 1 GiB + fused sweep f32 + fused sweep f64", "n": n,
-                          "copy_bytes_read": n ** 3 * 8, "copy_bytes_written": n ** 3 * 8,
+        print(json.dumps({"probe": "copy 4 GiB (twice: untimed + timed) + fused sweep f32 + fused sweep f64",
+                          "n": n, "copy_bytes_read": 4 << 30, "copy_bytes_written": 4 << 30,
                           "sweep_alg_bytes_f32": 16 * n ** 3, "sweep_alg_bytes_f64": 32 * n ** 3}), flush=True)
         return
 

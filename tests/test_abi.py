@@ -111,3 +111,32 @@ def test_init_rejects_bad_workspace_without_touching_the_device(blib):
     assert L.recon_init(None, 32, ctypes.byref(c), ctypes.c_void_p(256), 1 << 40, None) == -1
     assert L.recon_strerror(-3).decode().startswith("no step")
     assert L.recon_last_error(None).decode() == "null context"
+
+
+def test_stream_probe_library_exports_its_header():
+    """libstream_probe.so (the benchmark's bandwidth probes) exports what
+    include/stream_probe.h declares, and rejects bad arguments on the host
+    without launching anything."""
+    import ctypes
+    lib_path = os.path.join(ROOT, "paper_1611_09638_amd", "libstream_probe.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("probe library not built")
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "stream_probe.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(stream_probe_[a-z_0-9]+)\s*\(", src)))
+    assert names == ["stream_probe_run"]
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True, text=True, check=True)
+    exported = set(line.split()[-1] for line in out.stdout.splitlines() if line.strip())
+    assert set(names) <= exported
+    L = ctypes.CDLL(lib_path)
+    fn = L.stream_probe_run
+    vp = ctypes.c_void_p
+    fn.argtypes = [ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_int, vp, ctypes.c_int, vp,
+                   ctypes.POINTER(ctypes.c_float)]
+    ms = ctypes.c_float(0.0)
+    fake = ctypes.c_void_p(256)  # never dereferenced: every call below fails its host checks
+    assert fn(2, fake, fake, None, None, 1 << 20, 64, None, 1, None, None) == -1      # no output pointer
+    assert fn(2, fake, fake, None, None, 1 << 20, 64, None, 0, None, ctypes.byref(ms)) == -1  # no repetitions
+    assert fn(2, fake, fake, None, None, 100, 64, None, 1, None, ctypes.byref(ms)) == -1  # not 16-byte sized
+    assert fn(3, fake, fake, None, fake, 1 << 20, 64, None, 1, None, ctypes.byref(ms)) == -1  # triad needs b
+    assert fn(0, None, fake, None, None, 1 << 20, 64, None, 1, None, ctypes.byref(ms)) == -1  # read needs part
+    assert fn(7, fake, fake, fake, fake, 1 << 20, 64, fake, 1, None, ctypes.byref(ms)) == -1  # no such probe
