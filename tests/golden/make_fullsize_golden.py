@@ -1,12 +1,14 @@
 """Write <workload>_oracle_forward.json: the FP64 oracle's forward solve of a
-full-size lognormal workload (256^3 or 512^3, default configuration: 10 outer
-steps, inner tolerance 1e-10), reduced to what a GPU test can compare without
+full-size workload (256^3 or 512^3, default configuration: 10 outer steps,
+inner tolerance 1e-10), reduced to what a GPU test can compare without
 running the oracle: the step sizes, V-cycle counts and per-step rms(Sigma),
 phi and delta_r at 2048 seeded voxels, their 8^3 block means, and the L2
-norms of both fields.
+norms of both fields.  Lognormal workloads are solved from their density;
+particle workloads (Zel'dovich) from the oracle's CIC assignment of the
+particles.
 
 Calls only oracle/ and the seeded input generators.  Run from the repository
-root: python tests/golden/make_fullsize_golden.py lognormal256 [lognormal512]
+root: python tests/golden/make_fullsize_golden.py lognormal256 [lognormal512 zeldovich256]
 """
 import json
 import os
@@ -37,7 +39,10 @@ def main(names):
     for name in names:
         w = inputs.WORKLOADS[name]
         n, box = w["n"], w["box"]
-        rho = inputs.lognormal_density(n, box, w["sigma_g"], w["seed"])
+        if w["kind"] == "lognormal":
+            rho = inputs.lognormal_density(n, box, w["sigma_g"], w["seed"])
+        else:
+            rho = oracle.cic_particles(inputs.zeldovich_particles(n, box, w["rms_cells"], w["seed"]), n, box)
         cfg = oracle.Config()
         t0 = time.time()
         phi, delta, st = oracle.solve(rho, box, cfg)
@@ -45,7 +50,8 @@ def main(names):
         del rho
         vox = np.random.default_rng(VOX_SEED).choice(n ** 3, N_VOX, replace=False)
         out = {
-            "workload": name, "n": n, "box": box, "sigma_g": w["sigma_g"], "seed": w["seed"],
+            "workload": name, "n": n, "box": box, "kind": w["kind"], "sigma_g": w.get("sigma_g"),
+            "rms_cells": w.get("rms_cells"), "seed": w["seed"],
             "tol": cfg.tol, "max_outer": cfg.max_outer, "vox_seed": VOX_SEED,
             "alpha": st["alpha"], "vcycles": st["vcycles"], "rms_sigma": st["rms_sigma"],
             "voxels": [int(v) for v in vox],
@@ -54,7 +60,7 @@ def main(names):
             "phi_blocks": block_means(phi, BLOCKS).ravel().tolist(),
             "delta_r_blocks": block_means(delta, BLOCKS).ravel().tolist(),
             "phi_l2": float(np.linalg.norm(phi)), "delta_r_l2": float(np.linalg.norm(delta)),
-            "delta_r_max": float(delta.max()),
+            "delta_r_max": float(delta.max()), "min_lambda0": st["min_lambda0"], "min_det": st["min_det"],
             "oracle_seconds": round(t1 - t0, 1), "threads": int(os.environ.get("OMP_NUM_THREADS", "0")),
             "generator": "tests/golden/make_fullsize_golden.py (FP64 oracle, C + OpenMP)",
         }
