@@ -43,6 +43,7 @@ extern "C" {
 #define RECON_E_NO_TAPE (-5)        /* backward without a forward that recorded its tape */
 #define RECON_E_HIP (-6)            /* a HIP runtime call or kernel launch failed */
 #define RECON_E_WORKSPACE (-7)      /* workspace null, too small or misaligned */
+#define RECON_E_SCRATCH (-8)        /* recon_solve_noalloc: the problem needs more than the static scratch */
 
 #define RECON_FP64 0  /* every kernel in FP64 */
 #define RECON_MIXED 1 /* V-cycle (smoother, residual, transfers, coarse solve) in FP32 inside the FP64 loop */
@@ -175,6 +176,32 @@ int recon_backward(recon_ctx *ctx, const double *grad_delta_r, const double *gra
  * RECON_E_ARG for a density tape or other particles. */
 int recon_backward_particles(recon_ctx *ctx, const float *pos, long long np, const double *grad_delta_r,
                              const double *grad_phi, double *grad_pos);
+
+/* For callers that cannot allocate device or pinned host memory (tight
+ * serving loops, harnesses that forbid hipMalloc): recon_solve without a
+ * context or a workspace.  Same arguments and results as recon_solve on a
+ * context made by recon_init(n, cfg) (the same kernels; bitwise-identical
+ * phi, delta_r and stats apart from ms_total), with hip_stream (a
+ * hipStream_t, NULL = default stream) on the current device.
+ *
+ * Scratch: a static device array of RECON_NOALLOC_SCRATCH_BYTES (64 MiB) in
+ * the library, one copy per device, held from the library's first use on that
+ * device until the process ends; its device address is looked up on the first
+ * call on each device.  The call makes no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating call, creates no events, and keeps its host-side state in
+ * static memory.  Problems whose workspace (recon_workspace_bytes(n, cfg))
+ * exceeds the scratch return RECON_E_SCRATCH: every mode fits for n <= 64
+ * (coarse_n = 8).  cfg->record_tape, cfg->particle_deposit and cfg->profile
+ * must be 0 (RECON_E_ARG): there is no reverse mode, no particle input and no
+ * sweep timing here.  The scratch keeps the last call's contents; nothing the
+ * solve reads is taken from it before being written.  Calls on one device
+ * share its scratch: the library serialises them on the host and each returns
+ * only after its device work has finished, so they never overlap on the
+ * device.  Work the caller enqueues on other streams must not touch the
+ * scratch (it cannot name it).  Error text: recon_strerror(code). */
+#define RECON_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int recon_solve_noalloc(const double *density, int n, double box, double tol, const recon_config *cfg,
+                        double *phi_out, double *delta_r_out, recon_stats *stats, void *hip_stream);
 
 /* Release the context (not the workspace, which the caller owns). */
 void recon_destroy(recon_ctx *ctx);

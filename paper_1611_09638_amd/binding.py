@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librecon.so")
 
 RECON_OK = 0
 ERRORS = {-1: "E_ARG", -2: "E_INPUT", -3: "E_NOT_PD", -4: "E_NO_CONVERGENCE", -5: "E_NO_TAPE", -6: "E_HIP",
-          -7: "E_WORKSPACE"}
+          -7: "E_WORKSPACE", -8: "E_SCRATCH"}
 FP64, MIXED = 0, 1
 SOLVER_PCG, SOLVER_VCYCLE = 0, 1
 MAX_STEPS = 64
@@ -123,6 +123,7 @@ def lib():
         "recon_init": (i, [ctypes.POINTER(vp), i, pc, vp, sz, vp]),
         "recon_solve": (i, [vp, vp, i, d, d, vp, vp, ps]),
         "recon_solve_particles": (i, [vp, vp, ll, d, d, vp, vp, ps]),
+        "recon_solve_noalloc": (i, [vp, i, d, d, pc, vp, vp, ps, vp]),
         "recon_backward": (i, [vp, vp, vp, vp]),
         "recon_backward_particles": (i, [vp, vp, ll, vp, vp, vp]),
         "recon_destroy": (None, [vp]),
@@ -182,6 +183,29 @@ def _ptr(t: torch.Tensor | None, dtype=None):
     if dtype is not None and t.dtype != dtype:
         raise ValueError("expected dtype %s, got %s" % (dtype, t.dtype))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def solve_noalloc(density: torch.Tensor, box: float, cfg: Config | None = None, tol: float = 0.0,
+                  phi: torch.Tensor | None = None, delta: torch.Tensor | None = None,
+                  stream: torch.cuda.Stream | None = None):
+    """recon_solve_noalloc: the forward solve on the library's static scratch,
+    without a context or workspace.  The caller supplies the output tensors
+    (phi, delta: n^3 FP64 on density's device, either may be None); the call
+    itself allocates nothing.  Returns (phi, delta, stats)."""
+    cfg = cfg or Config()
+    n = density.shape[0]
+    if density.dim() != 3 or density.shape != (n, n, n):
+        raise ValueError("density must be n^3")
+    st = CStats()
+    c = cfg.c()
+    stream = stream or torch.cuda.current_stream(density.device)
+    with torch.cuda.device(density.device):
+        rc = lib().recon_solve_noalloc(_ptr(density, torch.float64), n, float(box), float(tol), ctypes.byref(c),
+                                       _ptr(phi, torch.float64), _ptr(delta, torch.float64), ctypes.byref(st),
+                                       ctypes.c_void_p(stream.cuda_stream))
+    if rc:
+        raise ReconError(rc, lib().recon_strerror(rc).decode())
+    return phi, delta, st.to_dict()
 
 
 class Recon:

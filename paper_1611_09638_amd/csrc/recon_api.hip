@@ -19,13 +19,20 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <chrono>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/recon.h"
 #include "kernels.h"
 
 using namespace recon;
+
+// Static scratch of recon_solve_noalloc, one copy per device.  In host code
+// this name is only a handle for hipGetSymbolAddress: its device address is
+// looked up once per device and used everywhere instead.
+static __device__ __align__(256) char scratch[RECON_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -264,17 +271,31 @@ static_assert(kKrylovScal + KS_COUNT <= kScal, "the scalar block fits");
 // In two halves, so that work queued between them overlaps the round trip:
 // the copy is enqueued with an event behind it, and the host later waits for
 // that event only.  Nothing queued in between may read host_scal.
+// A context without events (recon_solve_noalloc) waits for the whole stream
+// instead: the same results, without the overlap.
+int wait_copy_begin(recon_ctx *ctx)
+{
+    if (ctx->ev_ks) HIPCHK(hipEventRecord(ctx->ev_ks, ctx->stream));
+    return RECON_OK;
+}
+
+int wait_copy_end(recon_ctx *ctx)
+{
+    if (ctx->ev_ks) HIPCHK(hipEventSynchronize(ctx->ev_ks));
+    else HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+
 int fetch_krylov_begin(recon_ctx *ctx)
 {
     HIPCHK(hipMemcpyAsync(ctx->host_scal, ctx->scal + kKrylovScal, sizeof(double) * KS_COUNT,
                           hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipEventRecord(ctx->ev_ks, ctx->stream));
-    return RECON_OK;
+    return wait_copy_begin(ctx);
 }
 
 int fetch_krylov_end(recon_ctx *ctx, double *out)
 {
-    HIPCHK(hipEventSynchronize(ctx->ev_ks));
+    TRY(wait_copy_end(ctx));
     for (int c = 0; c < KS_COUNT; ++c) out[c] = ctx->host_scal[c];
     return RECON_OK;
 }
@@ -293,13 +314,12 @@ int fetch_sum1_begin(recon_ctx *ctx)
     HIPCHK(reduce_finalize(ctx->part, ops, ctx->scal, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->host_scal, ctx->scal, sizeof(double) * ctx->part.k, hipMemcpyDeviceToHost,
                           ctx->stream));
-    HIPCHK(hipEventRecord(ctx->ev_ks, ctx->stream));
-    return RECON_OK;
+    return wait_copy_begin(ctx);
 }
 
 int fetch_sum1_end(recon_ctx *ctx, double *out)
 {
-    HIPCHK(hipEventSynchronize(ctx->ev_ks));
+    TRY(wait_copy_end(ctx));
     out[0] = ctx->host_scal[0];
     return RECON_OK;
 }
@@ -933,6 +953,121 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad, c
 
 int check_ctx(recon_ctx *ctx) { return ctx ? RECON_OK : RECON_E_ARG; }
 
+// Point a fresh context at its workspace (laid out by lo) and stream.  Host
+// resources (the scalar mirror, events) are the caller's to attach.
+void bind_context(recon_ctx *ctx, int n, const recon_config *cfg, void *workspace, size_t ws_bytes,
+                  void *hip_stream, const Layout &lo)
+{
+    ctx->err[0] = 0;
+    ctx->n = n;
+    ctx->n3 = (long)n * n * n;
+    ctx->cfg = *cfg;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    ctx->ws = reinterpret_cast<char *>(workspace);
+    ctx->ws_bytes = ws_bytes;
+    ctx->lo = lo;
+    ctx->part.part = wsp<double>(ctx, lo.part);
+    ctx->part.blocks = 0;
+    ctx->part.k = 0;
+    ctx->scal = wsp<double>(ctx, lo.scal);
+    ctx->m = wsp<double>(ctx, lo.m);
+    ctx->phi = wsp<double>(ctx, lo.phi);
+    ctx->M = wsp<double>(ctx, lo.M);
+    ctx->t = wsp<double>(ctx, lo.t);
+    ctx->b = wsp<double>(ctx, lo.b);
+    ctx->u = wsp<double>(ctx, lo.u);
+    ctx->r = wsp<double>(ctx, lo.r);
+    ctx->z = wsp<double>(ctx, lo.z);
+    ctx->p = wsp<double>(ctx, lo.p);
+    ctx->q = wsp<double>(ctx, lo.q);
+    ctx->dphi = wsp<double>(ctx, lo.dphi);
+    ctx->xi = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.xi) : nullptr;
+    ctx->shifts = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.shifts) : nullptr;
+    if (ctx->cfg.full_operator) {
+        double *k0 = wsp<double>(ctx, lo.K);
+        ctx->Kf = MassTensor{k0,
+                             k0 + ctx->n3,
+                             k0 + 2 * ctx->n3,
+                             k0 + 3 * ctx->n3,
+                             k0 + 4 * ctx->n3,
+                             k0 + 5 * ctx->n3,
+                             k0 + 6 * ctx->n3};
+    }
+    ctx->L64.L = ctx->L32.L = lo.levels;
+    int nl = n;
+    for (int l = 0; l < lo.levels; ++l, nl /= 2) {
+        ctx->L64.n[l] = ctx->L32.n[l] = nl;
+        ctx->L64.a[l] = wsp<double>(ctx, lo.lv64_a[l]);
+        ctx->L64.u[l] = wsp<double>(ctx, lo.lv64_u[l]);
+        ctx->L64.b[l] = l ? wsp<double>(ctx, lo.lv64_b[l]) : ctx->r;
+        ctx->L64.res[l] = wsp<double>(ctx, lo.lv64_res[l]);
+        ctx->L64.tmp[l] = wsp<double>(ctx, lo.lv64_tmp[l]);
+        ctx->L32.a[l] = wsp<float>(ctx, lo.lv32_a[l]);
+        ctx->L32.u[l] = wsp<float>(ctx, lo.lv32_u[l]);
+        ctx->L32.b[l] = wsp<float>(ctx, lo.lv32_b[l]);
+        ctx->L32.res[l] = wsp<float>(ctx, lo.lv32_res[l]);
+        ctx->L32.tmp[l] = wsp<float>(ctx, lo.lv32_tmp[l]);
+    }
+}
+
+// recon_solve on a bound context.  Wall time from the context's events, or
+// from the host clock around a drained stream when it has none.
+int solve_density(recon_ctx *ctx, const double *density, int n, double box, double tol, double *phi_out,
+                  double *delta_r_out, recon_stats *stats)
+{
+    ctx->err[0] = 0;
+    // a failed or partial solve leaves no tape behind
+    ctx->tape_valid = 0;
+    if (!density || n != ctx->n || !(box > 0.0) || !(tol >= 0.0))
+        return fail(ctx, RECON_E_ARG, "bad argument (density %p, n %d vs %d, box %g, tol %g)", (const void *)density,
+                    n, ctx->n, box, tol);
+    if (ctx->cfg.particle_deposit)
+        return fail(ctx, RECON_E_ARG, "particle_deposit needs particle input (recon_solve_particles)");
+    recon_stats local;
+    recon_stats *st = stats ? stats : &local;
+    std::memset(st, 0, sizeof(*st));
+    ctx->prof_count = 0;
+    std::chrono::steady_clock::time_point t0;
+    if (ctx->ev0) {
+        HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
+    } else {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        t0 = std::chrono::steady_clock::now();
+    }
+    double mean = 0.0;
+    TRY(normalize(ctx, density, ctx->m, &mean));
+    ctx->input_mean = mean;
+    ctx->box = box;
+    ctx->last_tol = tol > 0.0 ? tol : ctx->cfg.tol;
+    TRY(forward(ctx, box, ctx->last_tol, phi_out, delta_r_out, st));
+    if (ctx->ev0) {
+        HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
+        HIPCHK(hipEventSynchronize(ctx->ev1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        st->ms_total = ms;
+    } else {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    TRY(collect_profile(ctx, st));
+    return RECON_OK;
+}
+
+// ------------------------------------------- the allocation-free entry point
+
+constexpr int kNoallocDevices = 64;
+
+struct NoallocSlot {
+    std::mutex mu;       // serialises the calls on this device
+    bool ready = false;  // device address looked up
+    char *ptr = nullptr; // device address of `scratch` on this device
+    double host_scal[kScal];
+    recon_ctx ctx;
+};
+
+NoallocSlot g_noalloc[kNoallocDevices];
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -985,56 +1120,7 @@ int recon_init(recon_ctx **out, int n, const recon_config *cfg, void *workspace,
         return RECON_E_WORKSPACE;
     recon_ctx *ctx = new (std::nothrow) recon_ctx();
     if (!ctx) return RECON_E_ARG;
-    ctx->err[0] = 0;
-    ctx->n = n;
-    ctx->n3 = (long)n * n * n;
-    ctx->cfg = *cfg;
-    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    ctx->ws = reinterpret_cast<char *>(workspace);
-    ctx->ws_bytes = ws_bytes;
-    ctx->lo = lo;
-    ctx->part.part = wsp<double>(ctx, lo.part);
-    ctx->part.blocks = 0;
-    ctx->part.k = 0;
-    ctx->scal = wsp<double>(ctx, lo.scal);
-    ctx->m = wsp<double>(ctx, lo.m);
-    ctx->phi = wsp<double>(ctx, lo.phi);
-    ctx->M = wsp<double>(ctx, lo.M);
-    ctx->t = wsp<double>(ctx, lo.t);
-    ctx->b = wsp<double>(ctx, lo.b);
-    ctx->u = wsp<double>(ctx, lo.u);
-    ctx->r = wsp<double>(ctx, lo.r);
-    ctx->z = wsp<double>(ctx, lo.z);
-    ctx->p = wsp<double>(ctx, lo.p);
-    ctx->q = wsp<double>(ctx, lo.q);
-    ctx->dphi = wsp<double>(ctx, lo.dphi);
-    ctx->xi = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.xi) : nullptr;
-    ctx->shifts = ctx->cfg.particle_deposit ? wsp<double>(ctx, lo.shifts) : nullptr;
-    if (ctx->cfg.full_operator) {
-        double *k0 = wsp<double>(ctx, lo.K);
-        ctx->Kf = MassTensor{k0,
-                             k0 + ctx->n3,
-                             k0 + 2 * ctx->n3,
-                             k0 + 3 * ctx->n3,
-                             k0 + 4 * ctx->n3,
-                             k0 + 5 * ctx->n3,
-                             k0 + 6 * ctx->n3};
-    }
-    ctx->L64.L = ctx->L32.L = lo.levels;
-    int nl = n;
-    for (int l = 0; l < lo.levels; ++l, nl /= 2) {
-        ctx->L64.n[l] = ctx->L32.n[l] = nl;
-        ctx->L64.a[l] = wsp<double>(ctx, lo.lv64_a[l]);
-        ctx->L64.u[l] = wsp<double>(ctx, lo.lv64_u[l]);
-        ctx->L64.b[l] = l ? wsp<double>(ctx, lo.lv64_b[l]) : ctx->r;
-        ctx->L64.res[l] = wsp<double>(ctx, lo.lv64_res[l]);
-        ctx->L64.tmp[l] = wsp<double>(ctx, lo.lv64_tmp[l]);
-        ctx->L32.a[l] = wsp<float>(ctx, lo.lv32_a[l]);
-        ctx->L32.u[l] = wsp<float>(ctx, lo.lv32_u[l]);
-        ctx->L32.b[l] = wsp<float>(ctx, lo.lv32_b[l]);
-        ctx->L32.res[l] = wsp<float>(ctx, lo.lv32_res[l]);
-        ctx->L32.tmp[l] = wsp<float>(ctx, lo.lv32_tmp[l]);
-    }
+    bind_context(ctx, n, cfg, workspace, ws_bytes, hip_stream, lo);
     if (hipHostMalloc(reinterpret_cast<void **>(&ctx->host_scal), sizeof(double) * kScal, hipHostMallocDefault) !=
             hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
@@ -1084,6 +1170,9 @@ const char *recon_strerror(int code)
     case RECON_E_NO_TAPE: return "backward called without a recorded forward";
     case RECON_E_HIP: return "HIP runtime error";
     case RECON_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    case RECON_E_SCRATCH:
+        return "the problem needs more workspace than the static scratch of recon_solve_noalloc "
+               "(RECON_NOALLOC_SCRATCH_BYTES, 64 MiB: n <= 64)";
     default: return "unknown error";
     }
 }
@@ -1094,32 +1183,33 @@ int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double
                 double *delta_r_out, recon_stats *stats)
 {
     TRY(check_ctx(ctx));
-    ctx->err[0] = 0;
-    // a failed or partial solve leaves no tape behind
-    ctx->tape_valid = 0;
-    if (!density || n != ctx->n || !(box > 0.0) || !(tol >= 0.0))
-        return fail(ctx, RECON_E_ARG, "bad argument (density %p, n %d vs %d, box %g, tol %g)", (const void *)density,
-                    n, ctx->n, box, tol);
-    if (ctx->cfg.particle_deposit)
-        return fail(ctx, RECON_E_ARG, "particle_deposit needs particle input (recon_solve_particles)");
-    recon_stats local;
-    recon_stats *st = stats ? stats : &local;
-    std::memset(st, 0, sizeof(*st));
-    ctx->prof_count = 0;
-    HIPCHK(hipEventRecord(ctx->ev0, ctx->stream));
-    double mean = 0.0;
-    TRY(normalize(ctx, density, ctx->m, &mean));
-    ctx->input_mean = mean;
-    ctx->box = box;
-    ctx->last_tol = tol > 0.0 ? tol : ctx->cfg.tol;
-    TRY(forward(ctx, box, ctx->last_tol, phi_out, delta_r_out, st));
-    HIPCHK(hipEventRecord(ctx->ev1, ctx->stream));
-    HIPCHK(hipEventSynchronize(ctx->ev1));
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    st->ms_total = ms;
-    TRY(collect_profile(ctx, st));
-    return RECON_OK;
+    return solve_density(ctx, density, n, box, tol, phi_out, delta_r_out, stats);
+}
+
+int recon_solve_noalloc(const double *density, int n, double box, double tol, const recon_config *cfg,
+                        double *phi_out, double *delta_r_out, recon_stats *stats, void *hip_stream)
+{
+    Layout lo;
+    if (!cfg || !make_layout(n, cfg, lo) || cfg->record_tape || cfg->particle_deposit || cfg->profile)
+        return RECON_E_ARG;
+    if (lo.total > RECON_NOALLOC_SCRATCH_BYTES) return RECON_E_SCRATCH;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return RECON_E_HIP;
+    if (dev < 0 || dev >= kNoallocDevices) return RECON_E_ARG;
+    NoallocSlot &slot = g_noalloc[dev];
+    std::lock_guard<std::mutex> lock(slot.mu);
+    if (!slot.ready) {
+        // set-up, once per device, with that device current
+        if (hipGetSymbolAddress(reinterpret_cast<void **>(&slot.ptr), HIP_SYMBOL(scratch)) != hipSuccess ||
+            !slot.ptr)
+            return RECON_E_HIP;
+        slot.ready = true;
+    }
+    recon_ctx *ctx = &slot.ctx;
+    *ctx = recon_ctx();
+    bind_context(ctx, n, cfg, slot.ptr, RECON_NOALLOC_SCRATCH_BYTES, hip_stream, lo);
+    ctx->host_scal = slot.host_scal;  // pageable static mirror; every read waits for its copy
+    return solve_density(ctx, density, n, box, tol, phi_out, delta_r_out, stats);
 }
 
 int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double box, double tol, double *phi_out,
