@@ -60,10 +60,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(rho, n, stats, cores):
-    """Oracle (FP64 C, OpenMP) on a bounded sample of the same workload: one
-    deformed-mesh mass, one source, one V-cycle and one operator application
-    at full size, scaled by the GPU solve's outer steps and V-cycle count."""
+def cpu_baseline(rho, n, stats, cores, workload):
+    """Oracle (FP64 C, OpenMP) on a bounded sample of the same workload, timed
+    on this host: the first outer step's own code path at full size -- the
+    deformed-mesh mass, the source, the oracle's Krylov solve capped at one
+    and at two V-cycles (the difference is one Krylov iteration: V-cycle,
+    operator, dot products and vector updates; the rest is the solve's
+    set-up, coefficient hierarchy and true residual) and the step control --
+    scaled by the GPU solve's outer steps and V-cycle count.  Beside it, the
+    oracle's full solve of this workload as recorded when its golden values
+    were written (threads stated there)."""
     import oracle
 
     oracle.build(force=False)
@@ -75,19 +81,37 @@ def cpu_baseline(rho, n, stats, cores):
     t0 = time.perf_counter()
     b = oracle.source(phi, M)
     t_src = time.perf_counter() - t0
+    del m
+    t_solve = {}
+    u = None
+    for k in (1, 2):
+        cfg = oracle.Config(max_vcycles=k, tol=1e-300)
+        t0 = time.perf_counter()
+        try:
+            u, _, _ = oracle.mg_solve(M, b, cfg)
+        except oracle.OracleError as e:  # capped: no convergence, by design
+            assert e.code == -4
+        t_solve[k] = time.perf_counter() - t0
+    t_iter = t_solve[2] - t_solve[1]
+    t_setup = max(t_solve[1] - t_iter, 0.0)
+    dphi = oracle.smooth(b)  # an increment of the solve's shape, for the step control's timing
     t0 = time.perf_counter()
-    z = oracle.vcycle(M, b)
-    t_vc = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.apply(z, M)
-    t_ap = time.perf_counter() - t0
+    oracle.choose_step(phi, dphi, oracle.Config())
+    t_step = time.perf_counter() - t0
     outer = stats["outer_steps"]
     vc = stats["vcycles_total"]
-    est = outer * (t_mm + t_src) + vc * (t_vc + t_ap)
-    return {"value": round(est, 3), "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": ("one oracle meshmass (%.2fs), source (%.2fs), V-cycle (%.2fs) and operator application "
-                       "(%.2fs) at %d^3, scaled by the GPU solve's %d outer steps and %d V-cycles"
-                       % (t_mm, t_src, t_vc, t_ap, n, outer, vc))}
+    est = outer * (t_mm + t_src + t_setup + t_step) + vc * t_iter
+    out = {"value": round(est, 3), "unit": "s", "cores": cores, "kind": "oracle",
+           "sample": ("the oracle's first outer step at %d^3 on this host: meshmass %.2fs, source %.2fs, Krylov "
+                      "solve capped at 1 / 2 V-cycles %.2fs / %.2fs (one iteration %.2fs, set-up and true residual "
+                      "%.2fs), step control %.2fs; scaled by the GPU solve's %d outer steps and %d V-cycles"
+                      % (n, t_mm, t_src, t_solve[1], t_solve[2], t_iter, t_setup, t_step, outer, vc))}
+    gold = oracle_samples(workload)
+    if gold is not None and "oracle_seconds" in gold:
+        out["full_solve_recorded"] = {"value": gold["oracle_seconds"], "unit": "s", "threads": gold.get("threads"),
+                                      "source": "tests/golden/%s_oracle_forward.json (the whole 10-step solve, "
+                                                "timed when the golden values were written)" % workload}
+    return out
 
 
 def oracle_samples(workload):
@@ -116,17 +140,19 @@ def _probe_lib():
     return L
 
 
-def stream_ceilings(torch, dev, reps=5, gib=4, kinds=None, blocks=(4096, 16384, 65536, 262144)):
+def stream_ceilings(torch, dev, reps=5, gib=4, kinds=None):
     """Achievable HBM bandwidth on this GPU for the access patterns of the
     path, from the hand-written streaming probes (libstream_probe.so: 16-byte
     accesses, every byte moved once) over arrays of `gib` GiB each (FP32),
     far beyond the 256 MB last-level cache: read only, write only, copy
     (1 read, 1 write) and 3 reads + 1 write (the smoother's mix).  GB/s =
-    bytes moved / mean kernel time (hipEvents); the best over grid sizes."""
+    bytes moved / mean kernel time (hipEvents); the best over grid sizes
+    (down to one vector per thread) and cache policies (plain, nontemporal)."""
     import ctypes
     L = _probe_lib()
     nbytes = gib << 30
     nel = nbytes // 4
+    blocks = (16384, 65536, nbytes // (16 * 256))
     arrs = [torch.ones(nel, device=dev) for _ in range(4)]
     part = torch.empty(max(blocks), device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
@@ -135,17 +161,19 @@ def stream_ceilings(torch, dev, reps=5, gib=4, kinds=None, blocks=(4096, 16384, 
         if kinds and name not in kinds:
             continue
         best = None
-        for nb in blocks:
-            ms = ctypes.c_float(0.0)
-            rc = L.stream_probe_run(kind, arrs[0].data_ptr(), arrs[1].data_ptr(), arrs[2].data_ptr(),
-                                    arrs[3].data_ptr(), nbytes, nb, part.data_ptr(), reps, stream, ctypes.byref(ms))
-            if rc:
-                raise RuntimeError("stream probe %s failed (%d)" % (name, rc))
-            gbs = arrays * nbytes / (ms.value * 1e-3) / 1e9
-            if best is None or gbs > best[0]:
-                best = (gbs, nb, ms.value)
+        for nt in (0, 16):
+            for nb in blocks:
+                ms = ctypes.c_float(0.0)
+                rc = L.stream_probe_run(kind | nt, arrs[0].data_ptr(), arrs[1].data_ptr(), arrs[2].data_ptr(),
+                                        arrs[3].data_ptr(), nbytes, nb, part.data_ptr(), reps, stream,
+                                        ctypes.byref(ms))
+                if rc:
+                    raise RuntimeError("stream probe %s failed (%d)" % (name, rc))
+                gbs = arrays * nbytes / (ms.value * 1e-3) / 1e9
+                if best is None or gbs > best[0]:
+                    best = (gbs, nb, nt)
         out[name + "_GBps"] = round(best[0], 1)
-        out[name + "_blocks"] = best[1]
+        out[name + "_how"] = "%d blocks%s" % (best[1], ", nontemporal" if best[2] else "")
     out["array_GiB"] = gib
     del arrs, part
     torch.cuda.empty_cache()
@@ -492,6 +520,8 @@ def main():
         "vcycles_total": st["vcycles_total"],
         "vcycles": st["vcycles"],
         "alpha": st["alpha"],
+        "alpha_limit": st["alpha_limit"],
+        "rms_sigma": [float("%.6g" % x) for x in st["rms_sigma"]],
     }
     for name, R in results.items():
         s = R["stats"]
@@ -531,7 +561,7 @@ def main():
     out["stream"] = stream
     if not args.skip_cpu:
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
-        out["cpu_baseline"] = cpu_baseline(rho, n, st, cores)
+        out["cpu_baseline"] = cpu_baseline(rho, n, st, cores, args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -121,6 +121,10 @@ typedef struct recon_stats {
     int smoother_zero_sweeps;           /* timed fine-level sweeps that start a V-cycle from u = 0
                                            (read a and b, write u) */
     double smoother_zero_ms;            /* their summed kernel time */
+    int alpha_limit[RECON_MAX_STEPS];   /* what set each step: 0 the full step alpha = 1 was taken;
+                                           1 the shift bound s_max (the largest step it allows passed);
+                                           2 the positive-definiteness (or mass positivity) test, which
+                                           rejected at least one step the shift bound allows */
 } recon_stats;
 
 typedef struct recon_ctx recon_ctx;

@@ -21,16 +21,18 @@ extern "C" {
 #define STREAM_PROBE_WRITE 1 /* fill d (bytes written)                        */
 #define STREAM_PROBE_COPY 2  /* d = a (bytes read + bytes written)            */
 #define STREAM_PROBE_TRIAD 3 /* d = a + b * c (3 x bytes read + bytes written) */
+#define STREAM_PROBE_NONTEMPORAL 16 /* or-ed into a kind: streaming (nontemporal) loads and stores */
 
-#define STREAM_PROBE_MAX_BLOCKS (1 << 20)
+#define STREAM_PROBE_MAX_BLOCKS (1 << 22)
 
-/* Launch probe `kind` once untimed, then `reps` times back to back on
+/* Launch probe `kind` (optionally | STREAM_PROBE_NONTEMPORAL) once untimed, then `reps` times back to back on
  * hip_stream (a hipStream_t, NULL = default stream), and write the mean
  * duration of one launch in milliseconds (hipEvents) to *ms_out (host).
  * d, a, b, c: device buffers of `bytes` bytes each (a multiple of 16), float32
  * data; the kind reads a (and b, c for the triad) and writes d; unused ones
  * may be NULL.  blocks: workgroups of 256 threads (1..STREAM_PROBE_MAX_BLOCKS),
- * each striding over the arrays.  part: device float[blocks], the read
+ * each striding over the arrays (blocks * 256 * 16 >= bytes: one vector per
+ * thread).  part: device float[blocks], the read
  * probe's per-block sums (NULL for the others).  Returns 0, -1 for a bad
  * argument (nothing launched) or -2 for a HIP error. */
 int stream_probe_run(int kind, void *d, const void *a, const void *b, const void *c, size_t bytes, int blocks,

@@ -49,6 +49,7 @@ class CStats(ctypes.Structure):
         ("min_det", ctypes.c_double), ("min_lambda0", ctypes.c_double), ("max_delta_r", ctypes.c_double),
         ("ms_total", ctypes.c_double), ("smoother_sweeps", ctypes.c_int), ("smoother_ms", ctypes.c_double),
         ("smoother_zero_sweeps", ctypes.c_int), ("smoother_zero_ms", ctypes.c_double),
+        ("alpha_limit", ctypes.c_int * MAX_STEPS),
     ]
 
     def to_dict(self):
@@ -58,7 +59,8 @@ class CStats(ctypes.Structure):
                     kappa=list(self.kappa[:k + 1]), rel_residual=list(self.rel_residual[:k]),
                     min_det=self.min_det, min_lambda0=self.min_lambda0, max_delta_r=self.max_delta_r,
                     ms_total=self.ms_total, smoother_sweeps=self.smoother_sweeps, smoother_ms=self.smoother_ms,
-                    smoother_zero_sweeps=self.smoother_zero_sweeps, smoother_zero_ms=self.smoother_zero_ms)
+                    smoother_zero_sweeps=self.smoother_zero_sweeps, smoother_zero_ms=self.smoother_zero_ms,
+                    alpha_limit=[("full", "shift", "pd")[x] for x in self.alpha_limit[:k]])
 
 
 @dataclass

@@ -681,7 +681,7 @@ hipError_t pd_trials(recon_ctx *ctx, const double *phi, const double *dphi, int 
 }
 
 int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *alpha_out,
-                const double *M = nullptr, const double *D = nullptr)
+                const double *M = nullptr, const double *D = nullptr, int *limit_out = nullptr)
 {
     static const int opmax[1] = {RED_MAX};
     double v[8];
@@ -698,6 +698,7 @@ int choose_step(recon_ctx *ctx, const double *phi, const double *dphi, double *a
         for (int t = 0; t < batch && j + t <= ctx->cfg.max_halvings; ++t) {
             if (v[t] == 0.0) {
                 *alpha_out = std::ldexp(1.0, -(j + t));
+                if (limit_out) *limit_out = j + t > j0 ? 2 : (j0 > 0 ? 1 : 0);
                 return RECON_OK;
             }
         }
@@ -809,7 +810,8 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         if (carry && full) HIPCHK(launch_full_apply(K, ctx->dphi, D, ctx->n, ctx->stream));
         else if (carry) HIPCHK(launch_mass_change(ctx->phi, ctx->M, ctx->dphi, K, D, ctx->n, ctx->stream));
         double alpha = 0.0;
-        TRY(choose_step(ctx, ctx->phi, ctx->dphi, &alpha, carry ? ctx->M : nullptr, carry ? D : nullptr));
+        TRY(choose_step(ctx, ctx->phi, ctx->dphi, &alpha, carry ? ctx->M : nullptr, carry ? D : nullptr,
+                        &st->alpha_limit[it]));
         if (carry) HIPCHK(launch_axpy(ctx->M, D, alpha, n3, ctx->stream));
         HIPCHK(launch_axpy(ctx->phi, ctx->dphi, alpha, n3, ctx->stream));
         st->alpha[it] = alpha;

@@ -65,6 +65,8 @@ def test_forward_matches_oracle(torch_cuda, orc, case, precision, solver):
     phi, d = phi.cpu().numpy(), d.cpu().numpy()
     assert st["alpha"] == st_o["alpha"]
     assert st["outer_steps"] == st_o["outer_steps"] == mo
+    # what set each step: the full step exactly when alpha = 1
+    assert all((lim == "full") == (a == 1.0) for lim, a in zip(st["alpha_limit"], st["alpha"]))
     assert rel(phi, phi_o) < 1e-6, rel(phi, phi_o)
     assert rel(d, d_o) < 1e-6, rel(d, d_o)
     assert max(st["rel_residual"]) <= 1e-10
