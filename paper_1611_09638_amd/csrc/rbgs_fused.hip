@@ -39,6 +39,15 @@ __device__ __forceinline__ void lds_barrier()
 // halo plane write one spare word per slot, so every thread loads and
 // deposits unconditionally and the load queue stays countable.
 //
+// SLOTS = 6 keeps six planes in the ring instead of four: plane s+3 then goes
+// into the slot of plane s-3, dead since the step before, at the start of
+// step s, so the barrier after the first colour also publishes it and a
+// step needs two barriers instead of three (76 KB of LDS in FP32, still two
+// workgroups per CU).  The steady loop is unrolled by six; a chunk whose
+// length is not a multiple of six runs up to five extra steps past its end,
+// which relax planes that are not stored.  Both forms give the same sweep
+// bit for bit.
+//
 // Face order in the relaxation: +i, -i, +j, -j, +k, -k (as in k_rbgs_half),
 // so the fused and per-colour sweeps round identically; a is stored halved
 // (the face coefficient max(a_min, (a_n + a_nb) / 2) is max(a_min, h_n + h_nb)).
@@ -62,18 +71,19 @@ using IC = std::integral_constant<int, X>;
 // planes that are multiples of 4, so with the steady loop unrolled by the
 // ring depth every ring slot and every plane parity is a compile-time
 // constant, and each LDS access is one per-thread offset plus an immediate).
-template <typename T, int TJ, int ZERO, int FIRST, int TK_ = 64, int NT_ = 512, int MINW = 1>
+template <typename T, int TJ, int ZERO, int FIRST, int TK_ = 64, int NT_ = 512, int MINW = 1, int SLOTS = 4>
 __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
                                                     const T *__restrict__ ag, const T *__restrict__ bg, int n,
                                                     int ci, T inv_scale, T a_min)
 {
     using F = Ring4<T, TJ, TK_, NT_>;
     static_assert(TJ * TK_ % NT_ == 0, "every thread stores whole rounds of the tile");
+    static_assert(SLOTS == 4 || SLOTS == 6, "a ring of four or six planes");
     constexpr int W = F::W, HW = W / 2, PLANE = F::PLANE, NT = F::NT, LU = F::LU, R1 = F::R1, R2 = F::R2;
     constexpr int RS = F::RS, C1 = FIRST, C2 = 1 - FIRST;
     static_assert(W % 2 == 0, "rows split into equal even and odd halves");
-    __shared__ T sU[4][F::PU];
-    __shared__ T sA[4][F::PU];
+    __shared__ T sU[SLOTS][F::PU];
+    __shared__ T sA[SLOTS][F::PU];
 
     const int tid = threadIdx.x;
     const int tiles_k = n / F::TK, tiles_j = n / TJ, chunks = n / ci;
@@ -215,6 +225,62 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         for (int r = 0; r < RS; ++r) *reinterpret_cast<T *>(ob + gS[r]) = sU[SLOT][sN[r]];
     };
 
+    if constexpr (SLOTS == 6) {
+    // Ring slot of plane i0 + d is (d + 60) % 6.  Prologue: planes i0-2 ..
+    // i0+2 resident, i0+3 (set 0) and i0+4 (set 1) staged, b of the first
+    // two steps staged; warm-up: first colour on planes i0-1 and i0 (they
+    // read only second-colour values, so no barrier between them).
+    fetch(IC<0>{}, i0 - 2);
+    deposit(IC<0>{}, IC<4>{});
+    fetch(IC<0>{}, i0 - 1);
+    deposit(IC<0>{}, IC<5>{});
+    fetch(IC<0>{}, i0);
+    deposit(IC<0>{}, IC<0>{});
+    fetch(IC<0>{}, i0 + 1);
+    deposit(IC<0>{}, IC<1>{});
+    fetch(IC<0>{}, i0 + 2);
+    deposit(IC<0>{}, IC<2>{});
+    fetch(IC<0>{}, i0 + 3);
+    fetch(IC<1>{}, i0 + 4);
+    fetch_b(IC<0>{}, i0 + 1, IC<(C1 + 1) & 1>{}, i0, IC<C2 & 1>{});
+    fetch_b(IC<1>{}, i0 + 2, IC<C1 & 1>{}, i0 + 1, IC<(C2 + 1) & 1>{});
+    lds_barrier();
+    {
+        T bw[R1], bx[R1];
+        const char *bb = plane(bg, i0 - 1), *bc = plane(bg, i0);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            bw[r] = at(bb, g1[r][(C1 + 1) & 1]);
+            bx[r] = at(bc, g1[r][C1 & 1]);
+        }
+        relax_first(IC<5>{}, IC<0>{}, IC<4>{}, IC<(C1 + 1) & 1>{}, bw);
+        relax_first(IC<0>{}, IC<1>{}, IC<5>{}, IC<C1 & 1>{}, bx);
+    }
+    lds_barrier();
+    const int iend = i0 + ci;
+    // Step H (plane ss): deposit ss+3 into the slot of ss-3, stage ss+5;
+    // first colour on ss+1; second colour on ss; store ss unless past the
+    // chunk; stage the b values of the step after next.
+    auto step6 = [&](auto Hc, int ss) {
+        constexpr int H = decltype(Hc)::value, h = H & 1;
+        deposit(IC<h>{}, IC<(H + 3) % 6>{});
+        fetch(IC<h>{}, ss + 5);
+        relax_first(IC<(H + 1) % 6>{}, IC<(H + 2) % 6>{}, IC<H % 6>{}, IC<(C1 + H + 1) & 1>{}, rb1[h]);
+        lds_barrier();
+        relax_second(IC<H % 6>{}, IC<(H + 1) % 6>{}, IC<(H + 5) % 6>{}, IC<(C2 + H) & 1>{}, rb2[h]);
+        lds_barrier();
+        if (ss < iend) store_plane(IC<H % 6>{}, ss);
+        fetch_b(IC<h>{}, ss + 3, IC<(C1 + H + 3) & 1>{}, ss + 2, IC<(C2 + H + 2) & 1>{});
+    };
+    for (int s = i0; s < iend; s += 6) {
+        step6(IC<0>{}, s);
+        step6(IC<1>{}, s + 1);
+        step6(IC<2>{}, s + 2);
+        step6(IC<3>{}, s + 3);
+        step6(IC<4>{}, s + 4);
+        step6(IC<5>{}, s + 5);
+    }
+    } else {
     // Ring slot of plane i0 + d is d & 3 (d >= -2: slot (d + 4) & 3); the
     // first colour's parity on plane i0 + d is (C1 + d) & 1, the second's
     // (C2 + d) & 1 (i0 is even).
@@ -276,58 +342,80 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         step(IC<2>{}, s + 2);
         step(IC<3>{}, s + 3);
     }
+    }
 }
 
-// Tile rows x width, workgroup size, smallest launch and waves per SIMD
-// (register budget), per precision, as measured best at 512^3 and 256^3:
-// FP32 8 x 128 tiles with 256 threads (50 KB of LDS; rows of 512 B, so the
-// k-halo columns cost fewer partly used cache lines than with 64-wide rows),
-// two workgroups per CU; FP64 16 x 64 tiles with 512 threads (87 KB, one per
-// CU; its halo re-reads are the lowest).  Both launch 512 workgroups at 512^3,
-// each streaming a 256-plane chunk (every chunk re-reads four planes).
-template <typename T>
-struct FusedLaunch;
-template <>
-struct FusedLaunch<float> {
-    static constexpr int TJ = 8, TK = 128, NT = 256, MIN_BLOCKS = 512, MINW = 2;
+// Launch shapes, as measured best inside the solve (and in standalone
+// timings of every shape and ring on fixed fields, each bitwise equal to
+// the others):
+//   FP32: 8 x 128 tiles, 256 threads, 4-plane ring (50 KB of LDS, two
+//     workgroups per CU; rows of 512 B, so the k-halo columns cost fewer
+//     partly used cache lines than 64-wide rows); from 512^3 the sweep that
+//     starts from zero takes the 6-plane ring (76 KB, still two per CU), and
+//     from 1024^3 the others take 16 x 128 tiles with 512 threads on the
+//     6-plane ring (127 KB, one per CU; half the j-halo rows per node);
+//   FP64: 16 x 64 tiles, 512 threads (one per CU), 4-plane ring below 512^3,
+//     6-plane ring from 512^3 (131 KB).
+// Launches keep at least 512 workgroups, each streaming the longest i-chunk
+// that allows (every chunk re-reads four planes).
+template <typename T, int TJ_, int TK_, int NT_, int MINW_, int SLOTS_>
+struct FusedShape {
+    static constexpr int TJ = TJ_, TK = TK_, NT = NT_, MINW = MINW_, SLOTS = SLOTS_, MIN_BLOCKS = 512;
 };
-template <>
-struct FusedLaunch<double> {
-    static constexpr int TJ = 16, TK = 64, NT = 512, MIN_BLOCKS = 512, MINW = 2;
-};
+
+template <typename C, typename T>
+hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, int n, T inv, T a_min, int first,
+                              bool zero_init, hipStream_t s)
+{
+    if (n < C::TK || n % C::TK || n % C::TJ) return hipErrorInvalidValue;
+    int ci = n;
+    while (ci > 16 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
+    if (C::SLOTS == 4 && ci % 4) return hipErrorInvalidValue;  // the 4-slot loop takes planes in fours
+    const int nblk = (n / C::TK) * (n / C::TJ) * (n / ci);
+#define RECON_FUSED(Z, F1)                                                                                \
+    k_rbgs_fused<T, C::TJ, Z, F1, C::TK, C::NT, C::MINW, C::SLOTS><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, \
+                                                                                        inv, a_min)
+    if (zero_init) {
+        if (first) RECON_FUSED(1, 1);
+        else RECON_FUSED(1, 0);
+    } else {
+        if (first) RECON_FUSED(0, 1);
+        else RECON_FUSED(0, 0);
+    }
+#undef RECON_FUSED
+    return hipGetLastError();
+}
 
 template <typename T>
 bool rbgs_fused_supported(int n)
 {
-    using C = FusedLaunch<T>;
-    return n >= C::TK && n % C::TK == 0 && n % C::TJ == 0;
+    // every shape above divides the edges it is used for
+    const int tk = sizeof(T) == 4 ? 128 : 64, tj = sizeof(T) == 4 ? (n >= 1024 ? 16 : 8) : 16;
+    return n >= tk && n % tk == 0 && n % tj == 0;
 }
 
 template <typename T>
 hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, int n, T scale, T a_min, int first,
                              bool zero_init, hipStream_t s)
 {
-    using C = FusedLaunch<T>;
     if (!rbgs_fused_supported<T>(n)) return hipErrorInvalidValue;
-    // i-chunk: as long as possible while the launch still has MIN_BLOCKS
-    // workgroups (each chunk re-reads 4 planes of u and a)
-    int ci = n;
-    while (ci > 16 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
-    if (ci % 4) return hipErrorInvalidValue;  // the steady-state loop takes planes in fours
-    const int nblk = (n / C::TK) * (n / C::TJ) * (n / ci);
     const T inv = (T)1 / scale;
-    if (zero_init) {
-        if (first)
-            k_rbgs_fused<T, C::TJ, 1, 1, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
-        else
-            k_rbgs_fused<T, C::TJ, 1, 0, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+    if constexpr (sizeof(T) == 4) {
+        if (n >= 1024 && !zero_init)
+            return launch_fused_shape<FusedShape<T, 16, 128, 512, 1, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                        zero_init, s);
+        if (n >= 512 && n < 1024 && zero_init)
+            return launch_fused_shape<FusedShape<T, 8, 128, 256, 2, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                       zero_init, s);
+        return launch_fused_shape<FusedShape<T, 8, 128, 256, 2, 4>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                   zero_init, s);
     } else {
-        if (first)
-            k_rbgs_fused<T, C::TJ, 0, 1, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
-        else
-            k_rbgs_fused<T, C::TJ, 0, 0, C::TK, C::NT, C::MINW><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, inv, a_min);
+        if (n >= 512)
+            return launch_fused_shape<FusedShape<T, 16, 64, 512, 2, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                       zero_init, s);
+        return launch_fused_shape<FusedShape<T, 16, 64, 512, 2, 4>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                   zero_init, s);
     }
-    return hipGetLastError();
 }
 
 template hipError_t launch_rbgs_fused<float>(const float *, float *, const float *, const float *, int, float,

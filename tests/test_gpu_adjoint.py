@@ -142,11 +142,20 @@ def test_lognormal128_filtered_power_loss(torch_cuda):
     L = sum_k exp(-k^2 R^2) |delta_r(k)|^2 with R = 10 Mpc/h: the GPU gradient
     at 64 seeded voxels against the FP64 oracle's (stored by
     tests/golden/make_lognormal128_grad.py), within 1e-4, and against central
-    finite differences of the GPU forward.  At this conditioning (coefficient
-    contrast ~1e5, ten nonlinear steps) the forward carries ~1e-10 relative
-    rounding noise, so differences with eps = 1e-6 rho scatter by up to a few
-    percent while eps = 1e-4 rho (truncation O(eps^2)) agrees to 1e-4; the
-    eps = 1e-6 check is made at 32^3 above."""
+    finite differences of the GPU forward (fields differenced before the loss).
+
+    Per voxel, the difference quotient is limited by the FP64 floor of the
+    forward, not by the adjoint: at coefficient contrast ~1e5 the true
+    residual of every linear solve stops near 4e-13 relative whatever the
+    tolerance (1e-13 .. 1e-15 measured), and a one-voxel change of eps rho
+    moves the loss by only ~eps / n^3 of itself.  The per-voxel relative error
+    falls as 1/eps (max 7e-4 / 3.5e-4 / 1.1e-4 at eps = 1e-4 / 2e-4 / 4e-4,
+    median 2e-5 .. 6e-6), so at eps = 1e-4 rho the check holds the median to
+    1e-4 and every voxel to 1e-3.  A perturbation spread over many voxels
+    moves the loss far above that floor: along a smooth bump the directional
+    derivative at eps = 1e-6 agrees to 1e-4 (measured 4e-5), and along a
+    global modulation at eps = 1e-8 to 1e-5 (measured 2e-7; at eps >= 1e-6
+    the trilinear gather's kinks, crossed by O(eps n^3) nodes, bias it)."""
     import json
     import os
     torch = torch_cuda
@@ -171,6 +180,13 @@ def test_lognormal128_filtered_power_loss(torch_cuda):
     assert np.abs(g[vox] - g_o).max() <= 1e-4 * np.abs(g_o).max()
     assert np.linalg.norm(g[vox] - g_o) <= 1e-4 * np.linalg.norm(g_o)
     assert abs(np.linalg.norm(g) - gold["grad_l2"]) <= 1e-4 * gold["grad_l2"]
+    def loss_diff(rp, rm):
+        _, dp, sp = fwd.solve(rp, box)
+        _, dm, sm = fwd.solve(rm, box)
+        assert sp["alpha"] == st["alpha"] == sm["alpha"]
+        Fp, Fm = torch.fft.fftn(dp), torch.fft.fftn(dm)
+        return float((W * ((Fp - Fm) * (Fp + Fm).conj()).real).sum())
+
     fd = []
     for flat in vox:
         idx = np.unravel_index(flat, (n, n, n))
@@ -178,14 +194,24 @@ def test_lognormal128_filtered_power_loss(torch_cuda):
         rp, rm = rho.clone(), rho.clone()
         rp[idx] += eps
         rm[idx] -= eps
-        _, dp, sp = fwd.solve(rp, box)
-        _, dm, sm = fwd.solve(rm, box)
-        assert sp["alpha"] == st["alpha"] == sm["alpha"]
-        Fp, Fm = torch.fft.fftn(dp), torch.fft.fftn(dm)
-        fd.append(float((W * ((Fp - Fm) * (Fp + Fm).conj()).real).sum()) / (2 * eps))
+        fd.append(loss_diff(rp, rm) / (2 * eps))
     fd = np.array(fd)
+    per_voxel = np.abs(g[vox] - fd) / np.abs(fd)
+    assert np.median(per_voxel) <= 1e-4 and per_voxel.max() <= 1e-3, (np.median(per_voxel), per_voxel.max())
     assert np.linalg.norm(g[vox] - fd) <= 1e-4 * np.linalg.norm(fd)
     assert np.abs(g[vox] - fd).max() <= 1e-4 * np.abs(fd).max()
+    # directional derivatives (the gradient on the whole grid)
+    g_d = torch.from_numpy(g.reshape(n, n, n)).cuda()
+    x = torch.arange(n, dtype=torch.float64, device="cuda")
+    dist = lambda c: torch.minimum((x - c) % n, (c - x) % n)  # noqa: E731
+    bump = torch.exp(-(dist(40)[:, None, None] ** 2 + dist(70)[None, :, None] ** 2
+                       + dist(90)[None, None, :] ** 2) / 8.0) * rho
+    ang = x * (2 * np.pi / n)
+    wave = torch.sin(ang[:, None, None] + 2 * ang[None, :, None] + 3 * ang[None, None, :]) * rho
+    for v, eps, bound in ((bump, 1e-6, 1e-4), (wave, 1e-8, 1e-5)):
+        adj = float((g_d * v).sum())
+        fdv = loss_diff(rho + eps * v, rho - eps * v) / (2 * eps)
+        assert abs(adj - fdv) <= bound * abs(fdv), (eps, adj, fdv)
 
 
 def test_fixed_cycles_option(torch_cuda):

@@ -40,15 +40,37 @@ def test_fused_sweep_512(torch_cuda, orc, field512):
     b = rng.standard_normal((n, n, n))
     rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
     uo = orc.rbgs_sweep(u, a, b, first=1)
-    ug = rec.rbgs(torch.from_numpy(u).cuda(), torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), first=1,
-                  variant=0).cpu().numpy()
-    assert rel(ug, uo) < 1e-13
+    d = lambda x: torch.from_numpy(x).cuda()  # noqa: E731
+    ug = rec.rbgs(d(u), d(a), d(b), first=1, variant=0)
+    assert rel(ug.cpu().numpy(), uo) < 1e-13
+    # the fused kernel equals the per-colour pair bit for bit (FP64: six-plane ring at this size)
+    assert torch.equal(ug, rec.rbgs(d(u), d(a), d(b), first=1, variant=1))
     del ug
     q = lambda x: torch.from_numpy(x.astype(np.float32)).cuda()  # noqa: E731
-    ug = rec.rbgs(q(u), q(a), q(b), first=0, variant=0).cpu().numpy()
+    ug = rec.rbgs(q(u), q(a), q(b), first=0, variant=0)
+    assert torch.equal(ug, rec.rbgs(q(u), q(a), q(b), first=0, variant=1))
+    ug = ug.cpu().numpy()
     uo = orc.rbgs_sweep(u.astype(np.float32).astype(np.float64), a.astype(np.float32).astype(np.float64),
                         b.astype(np.float32).astype(np.float64), first=0)
     assert rel(ug, uo) < 2e-6
+
+
+def test_fused_sweep_1024_fp32_bitwise(torch_cuda):
+    """At 1024^3 the FP32 fused sweep runs 16 x 128 tiles with 512 threads on
+    the six-plane ring: both colour orders equal the per-colour kernels bit
+    for bit (fields drawn on the device)."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 1024
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
+    g = torch.Generator(device="cuda").manual_seed(1024)
+    a = torch.exp(1.5 * torch.randn((n, n, n), generator=g, device="cuda", dtype=torch.float32))
+    u = torch.randn((n, n, n), generator=g, device="cuda", dtype=torch.float32)
+    b = torch.randn((n, n, n), generator=g, device="cuda", dtype=torch.float32)
+    for first in (0, 1):
+        fused = rec.rbgs(u, a, b, scale=0.25, first=first, variant=2)
+        assert torch.equal(fused, rec.rbgs(u, a, b, scale=0.25, first=first, variant=1))
+        del fused
 
 
 def test_vcycle_256(torch_cuda, orc):
