@@ -529,12 +529,19 @@ def main():
         sm = s["smoother_ms"] / max(s["smoother_sweeps"], 1)
         out["%s_s" % name] = round(R["wall_s"], 4)
         zm = s["smoother_zero_ms"] / max(s["smoother_zero_sweeps"], 1)
+        fm = s["smoother_folded_ms"] / max(s["smoother_folded_sweeps"], 1)
+        # the folded sweep also reads the coarse correction (1/8 of a field)
+        fb = nb + nb / 4 / 8
         out["%s_smoother" % name] = {"sweeps": s["smoother_sweeps"], "ms_per_sweep": round(sm, 4),
                                      "GBps": round(nb * n ** 3 / (sm * 1e-3) / 1e9, 1),
                                      "bytes_per_node": nb,
                                      "zero_start_sweeps": s["smoother_zero_sweeps"],
                                      "zero_start_ms_per_sweep": round(zm, 4),
                                      "zero_start_GBps": round(nb * 3 // 4 * n ** 3 / (zm * 1e-3) / 1e9, 1),
+                                     "folded_sweeps": s["smoother_folded_sweeps"],
+                                     "folded_ms_per_sweep": round(fm, 4),
+                                     "folded_bytes_per_node": fb,
+                                     "folded_GBps": round(fb * n ** 3 / (fm * 1e-3) / 1e9, 1),
                                      "vcycles": s["vcycles_total"]}
     gold = oracle_samples(args.workload)
     if gold is not None:

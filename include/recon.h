@@ -116,7 +116,7 @@ typedef struct recon_stats {
     double max_delta_r;                 /* max of delta_r (< 3 for a positive-definite map) */
     double ms_total;                    /* wall time of the solve on the stream (hipEvents) */
     int smoother_sweeps;                /* fine-level RB-GS sweeps timed (cfg.profile) that read
-                                           u, a and b and write u */
+                                           u, a and b and write u (the plain sweeps) */
     double smoother_ms;                 /* their summed kernel time on the stream */
     int smoother_zero_sweeps;           /* timed fine-level sweeps that start a V-cycle from u = 0
                                            (read a and b, write u) */
@@ -125,6 +125,9 @@ typedef struct recon_stats {
                                            1 the shift bound s_max (the largest step it allows passed);
                                            2 the positive-definiteness (or mass positivity) test, which
                                            rejected at least one step the shift bound allows */
+    int smoother_folded_sweeps;         /* timed fine-level sweeps with the V-cycle's coarse correction
+                                           folded in (read u, a, b and the coarse e, write u) */
+    double smoother_folded_ms;          /* their summed kernel time */
 } recon_stats;
 
 typedef struct recon_ctx recon_ctx;
@@ -290,6 +293,17 @@ int recon_stage_residual_restrict(recon_ctx *ctx, const void *u, const void *a, 
 /* u += trilinear prolongation of the (nl/2)^3 field e onto the nl^3 field u
  * (P = 8 R^T).  variant as for recon_stage_restrict. */
 int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int dtype, int variant);
+
+/* A V-cycle's coarse correction followed by its first post-smoothing sweep
+ * (App. A multigrid): u <- one fused red-black sweep (colour `first` first)
+ * of u + P e, with P the trilinear prolongation of e (edge nl/2) and the
+ * operator of coefficient a at level scale `scale`, rhs b.  variant 1: the
+ * prolongation's own pass, then the sweep; 2: the correction added as the
+ * sweep reads each plane (what the V-cycle runs).  Both give the same values.
+ * nl an even level edge that the fused sweep takes (a multiple of 128 in
+ * FP32, 64 in FP64), else RECON_E_ARG.  Uses the context's scratch field t. */
+int recon_stage_prolong_sweep(recon_ctx *ctx, void *u, const void *e, const void *a, const void *b, int nl,
+                              double scale, int first, int dtype, int variant);
 
 /* z = one symmetric V-cycle applied to r for coefficient a (fine level n). */
 int recon_stage_vcycle(recon_ctx *ctx, const void *a, const void *r, void *z, int dtype);

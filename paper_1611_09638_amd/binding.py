@@ -50,6 +50,7 @@ class CStats(ctypes.Structure):
         ("ms_total", ctypes.c_double), ("smoother_sweeps", ctypes.c_int), ("smoother_ms", ctypes.c_double),
         ("smoother_zero_sweeps", ctypes.c_int), ("smoother_zero_ms", ctypes.c_double),
         ("alpha_limit", ctypes.c_int * MAX_STEPS),
+        ("smoother_folded_sweeps", ctypes.c_int), ("smoother_folded_ms", ctypes.c_double),
     ]
 
     def to_dict(self):
@@ -60,7 +61,9 @@ class CStats(ctypes.Structure):
                     min_det=self.min_det, min_lambda0=self.min_lambda0, max_delta_r=self.max_delta_r,
                     ms_total=self.ms_total, smoother_sweeps=self.smoother_sweeps, smoother_ms=self.smoother_ms,
                     smoother_zero_sweeps=self.smoother_zero_sweeps, smoother_zero_ms=self.smoother_zero_ms,
-                    alpha_limit=[("full", "shift", "pd")[x] for x in self.alpha_limit[:k]])
+                    alpha_limit=[("full", "shift", "pd")[x] for x in self.alpha_limit[:k]],
+                    smoother_folded_sweeps=self.smoother_folded_sweeps,
+                    smoother_folded_ms=self.smoother_folded_ms)
 
 
 @dataclass
@@ -145,6 +148,7 @@ def lib():
         "recon_stage_restrict": (i, [vp, vp, i, vp, i, i]),
         "recon_stage_residual_restrict": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
         "recon_stage_prolong_add": (i, [vp, vp, vp, i, i, i]),
+        "recon_stage_prolong_sweep": (i, [vp, vp, vp, vp, vp, i, d, i, i, i]),
         "recon_stage_vcycle": (i, [vp, vp, vp, vp, i]),
         "recon_stage_mg_solve": (i, [vp, vp, vp, d, vp, pi, pd]),
         "recon_stage_mg_solve_full": (i, [vp, vp, vp, vp, d, vp, pi, pd]),
@@ -396,6 +400,15 @@ class Recon:
                                                         _ptr(b, u.dtype), u.shape[0], float(scale), _ptr(c),
                                                         self._dt(u), variant))
         return c
+
+    def prolong_sweep(self, u, e, a, b, scale=1.0, first=1, variant=2):
+        """One fused sweep of u + P e (the V-cycle's first post-smoothing
+        sweep); variant 1 prolongs in a pass of its own first."""
+        u = u.clone()
+        self._check(lib().recon_stage_prolong_sweep(self._ctx, _ptr(u, u.dtype), _ptr(e, u.dtype), _ptr(a, u.dtype),
+                                                    _ptr(b, u.dtype), u.shape[0], float(scale), first, self._dt(u),
+                                                    variant))
+        return u
 
     def prolong_add(self, u, e, variant=0):
         u = u.clone()

@@ -125,10 +125,12 @@ hipError_t launch_apply(const T *u, const T *a, T *out, int n, T scale, T a_min,
 template <typename T>
 hipError_t launch_rbgs_half(T *u, const T *a, const T *b, int n, T scale, T a_min, int colour, bool zero_init,
                             hipStream_t s, bool fine = false);
-// fused two-colour sweep, out of place: u_out = sweep(u_in); colour `first` first
+// fused two-colour sweep, out of place: u_out = sweep(u_in); colour `first`
+// first.  With e (the coarse-grid correction, edge n/2; not with zero_init):
+// u_out = sweep(u_in + P e), P the trilinear prolongation.
 template <typename T>
 hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, int n, T scale, T a_min, int first,
-                             bool zero_init, hipStream_t s);
+                             bool zero_init, hipStream_t s, const T *e = nullptr);
 template <typename T>
 bool rbgs_fused_supported(int n);
 template <typename T>

@@ -71,14 +71,34 @@ using IC = std::integral_constant<int, X>;
 // planes that are multiples of 4, so with the steady loop unrolled by the
 // ring depth every ring slot and every plane parity is a compile-time
 // constant, and each LDS access is one per-thread offset plus an immediate).
-template <typename T, int TJ, int ZERO, int FIRST, int TK_ = 64, int NT_ = 512, int MINW = 1, int SLOTS = 4>
+// PRO = 1 folds the multigrid's coarse correction into the sweep (the first
+// post-smoothing sweep of a V-cycle): every plane of u_in enters the ring as
+// u_in + P e, with P the trilinear prolongation of the coarse-grid correction
+// e (edge n/2), formed exactly as the prolongation kernels form it (weights
+// 1/2 along k, then j, then between coarse planes).  The coarse planes a
+// plane needs pass through a 4-slot LDS ring of their own ((TJ/2 + 3) x
+// (TK/2 + 3) nodes, one coarse node beyond the fine halo); the coarse plane
+// c + 1 is staged with fine plane 2c and stored with it.  u_out is then
+// exactly the sweep of the prolonged field, without the prolongation's own
+// pass over u.
+template <int TJ, int TK, int NT>
+struct CoarseTile {
+    static constexpr int CH = TJ / 2 + 3, CW = TK / 2 + 3, PLANE = CH * CW;
+    static constexpr int LU = (PLANE + NT - 1) / NT, PU = PLANE + 1;
+};
+
+template <typename T, int TJ, int ZERO, int FIRST, int TK_ = 64, int NT_ = 512, int MINW = 1, int SLOTS = 4,
+          int PRO = 0>
 __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
                                                     const T *__restrict__ ag, const T *__restrict__ bg, int n,
-                                                    int ci, T inv_scale, T a_min)
+                                                    int ci, T inv_scale, T a_min, const T *__restrict__ eg)
 {
     using F = Ring4<T, TJ, TK_, NT_>;
+    using CT = CoarseTile<TJ, TK_, NT_>;
     static_assert(TJ * TK_ % NT_ == 0, "every thread stores whole rounds of the tile");
     static_assert(SLOTS == 4 || SLOTS == 6, "a ring of four or six planes");
+    static_assert(!(PRO && ZERO), "the coarse correction is added to a sweep's input");
+    __shared__ T sE[PRO ? 4 : 1][PRO ? CT::PU : 1];
     constexpr int W = F::W, HW = W / 2, PLANE = F::PLANE, NT = F::NT, LU = F::LU, R1 = F::R1, R2 = F::R2;
     constexpr int RS = F::RS, C1 = FIRST, C2 = 1 - FIRST;
     static_assert(W % 2 == 0, "rows split into equal even and odd halves");
@@ -160,6 +180,56 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
     };
     auto at = [](const char *base, unsigned off) { return *reinterpret_cast<const T *>(base + off); };
 
+    // PRO: the coarse tile's loads (offsets into a coarse plane, LDS words)
+    // and, per halo-load slot, the coarse LDS word of its (j, k) corner with
+    // the node's parities (bit 0: k odd, bit 1: j odd)
+    constexpr int CLU = PRO ? CT::LU : 1;
+    const int nc = n >> 1;
+    const size_t cplane = (size_t)nc * nc;
+    unsigned offC[CLU];
+    int dstC[CLU], cor[PRO ? LU : 1];
+    unsigned par = 0;
+    if constexpr (PRO) {
+#pragma unroll
+        for (int r = 0; r < CLU; ++r) {
+            const int q = tid + r * NT;
+            const int row = q / CT::CW, col = q % CT::CW;
+            const int gj = (j0 >> 1) - 1 + row, gk = (k0 >> 1) - 1 + col;
+            offC[r] = q < CT::PLANE ? (unsigned)(wrapc(gj, nc) * nc + wrapc(gk, nc)) : 0u;
+            dstC[r] = q < CT::PLANE ? q : CT::PLANE;
+        }
+#pragma unroll
+        for (int r = 0; r < LU; ++r) {
+            const int q = tid + r * NT;
+            const int row = q < PLANE ? q / W : 0, col = q < PLANE ? q % W : 0;
+            cor[r] = (row >> 1) * CT::CW + (col >> 1);
+            par |= (unsigned)((col & 1) | ((row & 1) << 1)) << (2 * r);
+        }
+    }
+    T rcs[2][CLU];
+    auto coarse_load = [&](int c, T (&dst)[CLU]) {
+        const T *pl = eg + (size_t)wrapc(c, nc) * cplane;
+#pragma unroll
+        for (int r = 0; r < CLU; ++r) dst[r] = pl[offC[r]];
+    };
+    auto coarse_store = [&](int c, const T (&src)[CLU]) {
+        T *E = sE[c & 3];
+#pragma unroll
+        for (int r = 0; r < CLU; ++r) E[dstC[r]] = src[r];
+    };
+    // the coarse correction at halo-load slot r from coarse plane c: the
+    // in-plane interpolation of the prolongation kernels
+    auto inplane = [&](int c, int r) {
+        const T *E = sE[c & 3];
+        const int kod = (par >> (2 * r)) & 1, jod = (par >> (2 * r + 1)) & 1;
+        const int a00 = cor[r], a01 = a00 + kod, a10 = a00 + jod * CT::CW, a11 = a10 + kod;
+        const T v00 = E[a00], v01 = E[a01], v10 = E[a10], v11 = E[a11];
+        const T wk = (T)0.5, wj = (T)0.5;
+        const T r0 = kod ? wk * (v00 + v01) : v00;
+        const T r1 = kod ? wk * (v10 + v11) : v10;
+        return jod ? wj * (r0 + r1) : r0;
+    };
+
     T ru[2][LU], ra[2][LU];
     auto fetch = [&](auto SETc, int p) {
         constexpr int SET = decltype(SETc)::value;
@@ -169,13 +239,47 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
             ru[SET][r] = ZERO ? (T)0 : at(ub, offU[r]);
             ra[SET][r] = at(ab, offU[r]);
         }
+        // PRO: an even plane 2c brings coarse plane c + 1 along
+        if constexpr (PRO)
+            if (!(p & 1)) coarse_load((p >> 1) + 1, rcs[SET]);
     };
-    auto deposit = [&](auto SETc, auto SLOTc) {
+    // store the staged plane p (PRO: plus its coarse correction; with cw,
+    // an even plane also stores the coarse plane staged with it)
+    auto deposit = [&](auto SETc, auto SLOTc, int p = 0, bool cw = false) {
         constexpr int SET = decltype(SETc)::value, SLOT = decltype(SLOTc)::value;
+        if constexpr (PRO) {
+            const int c = p >> 1;
+            const T wi = (T)0.5;
+            if (p & 1) {
 #pragma unroll
-        for (int r = 0; r < LU; ++r) {
-            sU[SLOT][dstU[r]] = ru[SET][r];
-            sA[SLOT][dstU[r]] = (T)0.5 * ra[SET][r];
+                for (int r = 0; r < LU; ++r) {
+                    T acc = inplane(c, r);
+                    const T acc1 = inplane(c + 1, r);
+                    acc = wi * (acc + acc1);
+                    sU[SLOT][dstU[r]] = ru[SET][r] + acc;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < LU; ++r) sU[SLOT][dstU[r]] = ru[SET][r] + inplane(c, r);
+                if (cw) coarse_store(c + 1, rcs[SET]);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < LU; ++r) sU[SLOT][dstU[r]] = ru[SET][r];
+        }
+#pragma unroll
+        for (int r = 0; r < LU; ++r) sA[SLOT][dstU[r]] = (T)0.5 * ra[SET][r];
+    };
+    // PRO: the coarse planes the prologue's deposits read, c0 - 1 .. c0 + K
+    // with c0 = i0 / 2, stored before them
+    auto coarse_preload = [&](int K) {
+        if constexpr (PRO) {
+            for (int c = (i0 >> 1) - 1; c <= (i0 >> 1) + K; ++c) {
+                T tmp[CLU];
+                coarse_load(c, tmp);
+                coarse_store(c, tmp);
+            }
+            lds_barrier();
         }
     };
     // b at the first-colour nodes of plane q1 (parity P1) and at the
@@ -230,16 +334,17 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
     // i0+2 resident, i0+3 (set 0) and i0+4 (set 1) staged, b of the first
     // two steps staged; warm-up: first colour on planes i0-1 and i0 (they
     // read only second-colour values, so no barrier between them).
+    coarse_preload(2);
     fetch(IC<0>{}, i0 - 2);
-    deposit(IC<0>{}, IC<4>{});
+    deposit(IC<0>{}, IC<4>{}, i0 - 2);
     fetch(IC<0>{}, i0 - 1);
-    deposit(IC<0>{}, IC<5>{});
+    deposit(IC<0>{}, IC<5>{}, i0 - 1);
     fetch(IC<0>{}, i0);
-    deposit(IC<0>{}, IC<0>{});
+    deposit(IC<0>{}, IC<0>{}, i0);
     fetch(IC<0>{}, i0 + 1);
-    deposit(IC<0>{}, IC<1>{});
+    deposit(IC<0>{}, IC<1>{}, i0 + 1);
     fetch(IC<0>{}, i0 + 2);
-    deposit(IC<0>{}, IC<2>{});
+    deposit(IC<0>{}, IC<2>{}, i0 + 2);
     fetch(IC<0>{}, i0 + 3);
     fetch(IC<1>{}, i0 + 4);
     fetch_b(IC<0>{}, i0 + 1, IC<(C1 + 1) & 1>{}, i0, IC<C2 & 1>{});
@@ -263,7 +368,7 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
     // chunk; stage the b values of the step after next.
     auto step6 = [&](auto Hc, int ss) {
         constexpr int H = decltype(Hc)::value, h = H & 1;
-        deposit(IC<h>{}, IC<(H + 3) % 6>{});
+        deposit(IC<h>{}, IC<(H + 3) % 6>{}, ss + 3, true);
         fetch(IC<h>{}, ss + 5);
         relax_first(IC<(H + 1) % 6>{}, IC<(H + 2) % 6>{}, IC<H % 6>{}, IC<(C1 + H + 1) & 1>{}, rb1[h]);
         lds_barrier();
@@ -286,14 +391,15 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
     // (C2 + d) & 1 (i0 is even).
     // prologue: planes i0-2 .. i0+1 resident, i0+2 (set 1) and i0+3 (set 0)
     // staged, b for the first two steady steps staged
+    coarse_preload(1);
     fetch(IC<0>{}, i0 - 2);
-    deposit(IC<0>{}, IC<2>{});
+    deposit(IC<0>{}, IC<2>{}, i0 - 2);
     fetch(IC<0>{}, i0 - 1);
-    deposit(IC<0>{}, IC<3>{});
+    deposit(IC<0>{}, IC<3>{}, i0 - 1);
     fetch(IC<0>{}, i0);
-    deposit(IC<0>{}, IC<0>{});
+    deposit(IC<0>{}, IC<0>{}, i0);
     fetch(IC<0>{}, i0 + 1);
-    deposit(IC<0>{}, IC<1>{});
+    deposit(IC<0>{}, IC<1>{}, i0 + 1);
     fetch(IC<1>{}, i0 + 2);
     fetch(IC<0>{}, i0 + 3);
     fetch_b(IC<0>{}, i0 + 1, IC<(C1 + 1) & 1>{}, i0, IC<C2 & 1>{});
@@ -308,7 +414,7 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         relax_first(IC<3>{}, IC<0>{}, IC<2>{}, IC<(C1 + 1) & 1>{}, bw);
     }
     lds_barrier();
-    deposit(IC<1>{}, IC<2>{});  // plane i0+2 into the slot of plane i0-2, read last just above
+    deposit(IC<1>{}, IC<2>{}, i0 + 2, true);  // plane i0+2 into the slot of plane i0-2, read last just above
     fetch(IC<1>{}, i0 + 4);
     lds_barrier();
     {
@@ -330,7 +436,7 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         lds_barrier();
         relax_second(IC<H & 3>{}, IC<(H + 1) & 3>{}, IC<(H + 3) & 3>{}, IC<(C2 + H) & 1>{}, rb2[h]);
         lds_barrier();
-        deposit(IC<h>{}, IC<(H + 3) & 3>{});
+        deposit(IC<h>{}, IC<(H + 3) & 3>{}, ss + 3, true);
         store_plane(IC<H & 3>{}, ss);
         fetch(IC<h>{}, ss + 5);
         fetch_b(IC<h>{}, ss + 3, IC<(C1 + H + 3) & 1>{}, ss + 2, IC<(C2 + H + 2) & 1>{});
@@ -365,8 +471,9 @@ struct FusedShape {
 
 template <typename C, typename T>
 hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, int n, T inv, T a_min, int first,
-                              bool zero_init, hipStream_t s)
+                              bool zero_init, hipStream_t s, const T *e = nullptr)
 {
+    if (e && (zero_init || n % 2)) return hipErrorInvalidValue;
     if (n < C::TK || n % C::TK || n % C::TJ) return hipErrorInvalidValue;
     int ci = n;
     while (ci > 16 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
@@ -374,8 +481,14 @@ hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, i
     const int nblk = (n / C::TK) * (n / C::TJ) * (n / ci);
 #define RECON_FUSED(Z, F1)                                                                                \
     k_rbgs_fused<T, C::TJ, Z, F1, C::TK, C::NT, C::MINW, C::SLOTS><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, \
-                                                                                        inv, a_min)
-    if (zero_init) {
+                                                                                        inv, a_min, nullptr)
+#define RECON_FUSED_PRO(F1)                                                                                   \
+    k_rbgs_fused<T, C::TJ, 0, F1, C::TK, C::NT, C::MINW, C::SLOTS, 1><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, \
+                                                                                           ci, inv, a_min, e)
+    if (e) {
+        if (first) RECON_FUSED_PRO(1);
+        else RECON_FUSED_PRO(0);
+    } else if (zero_init) {
         if (first) RECON_FUSED(1, 1);
         else RECON_FUSED(1, 0);
     } else {
@@ -383,6 +496,7 @@ hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, i
         else RECON_FUSED(0, 0);
     }
 #undef RECON_FUSED
+#undef RECON_FUSED_PRO
     return hipGetLastError();
 }
 
@@ -396,32 +510,32 @@ bool rbgs_fused_supported(int n)
 
 template <typename T>
 hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, int n, T scale, T a_min, int first,
-                             bool zero_init, hipStream_t s)
+                             bool zero_init, hipStream_t s, const T *e)
 {
     if (!rbgs_fused_supported<T>(n)) return hipErrorInvalidValue;
     const T inv = (T)1 / scale;
     if constexpr (sizeof(T) == 4) {
         if (n >= 1024 && !zero_init)
             return launch_fused_shape<FusedShape<T, 16, 128, 512, 1, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
-                                                                        zero_init, s);
+                                                                        zero_init, s, e);
         if (n >= 512 && n < 1024 && zero_init)
             return launch_fused_shape<FusedShape<T, 8, 128, 256, 2, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
                                                                        zero_init, s);
         return launch_fused_shape<FusedShape<T, 8, 128, 256, 2, 4>>(u_in, u_out, a, b, n, inv, a_min, first,
-                                                                   zero_init, s);
+                                                                   zero_init, s, e);
     } else {
         if (n >= 512)
             return launch_fused_shape<FusedShape<T, 16, 64, 512, 2, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
-                                                                       zero_init, s);
+                                                                       zero_init, s, e);
         return launch_fused_shape<FusedShape<T, 16, 64, 512, 2, 4>>(u_in, u_out, a, b, n, inv, a_min, first,
-                                                                   zero_init, s);
+                                                                   zero_init, s, e);
     }
 }
 
 template hipError_t launch_rbgs_fused<float>(const float *, float *, const float *, const float *, int, float,
-                                              float, int, bool, hipStream_t);
+                                              float, int, bool, hipStream_t, const float *);
 template hipError_t launch_rbgs_fused<double>(const double *, double *, const double *, const double *, int, double,
-                                               double, int, bool, hipStream_t);
+                                               double, int, bool, hipStream_t, const double *);
 template bool rbgs_fused_supported<float>(int);
 template bool rbgs_fused_supported<double>(int);
 

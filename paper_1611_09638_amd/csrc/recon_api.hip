@@ -192,7 +192,8 @@ struct recon_ctx {
     hipEvent_t ev_ks = nullptr;  // marks the Krylov scalars' copy to host_scal
     // cfg.profile: event pairs around each fine-level smoother sweep
     hipEvent_t *prof = nullptr;
-    bool prof_zero[4096];  // the timed sweep started from u = 0 (reads a and b only)
+    unsigned char prof_zero[4096];  // 0: a plain sweep (reads u, a, b, writes u); 1: from u = 0 (reads a
+                                    // and b only); 2: with the coarse correction folded in (also reads e)
     int prof_count = 0;
     // tape of the last recorded forward
     int tape_steps = 0;
@@ -343,21 +344,22 @@ bool use_fused(int n)
 // One red-black sweep on level l: fused levels out of place between `cur` and
 // `alt` (the pointers are swapped), the others in place.
 template <typename T>
-int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, int first, bool zero_init)
+int sweep(recon_ctx *ctx, Levels<T> &S, int l, T *&cur, T *&alt, const T *rhs, int first, bool zero_init,
+          const T *coarse = nullptr)
 {
     const int n = S.n[l];
     const T sc = (T)level_scale(l), amin = (T)ctx->cfg.a_min;
     const bool timed = l == 0 && ctx->prof && ctx->prof_count < kProfPairs;
     if (timed) HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count], ctx->stream));
     if (use_fused<T>(n)) {
-        HIPCHK(launch_rbgs_fused<T>(cur, alt, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream));
+        HIPCHK(launch_rbgs_fused<T>(cur, alt, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream, coarse));
         std::swap(cur, alt);
     } else {
         HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, first, zero_init, ctx->stream, l == 0));
         HIPCHK(launch_rbgs_half<T>(cur, S.a[l], rhs, n, sc, amin, 1 - first, false, ctx->stream, l == 0));
     }
     if (timed) {
-        ctx->prof_zero[ctx->prof_count] = zero_init;
+        ctx->prof_zero[ctx->prof_count] = zero_init ? 1 : (coarse && use_fused<T>(n) ? 2 : 0);
         HIPCHK(hipEventRecord(ctx->prof[2 * ctx->prof_count++ + 1], ctx->stream));
     }
     return RECON_OK;
@@ -433,8 +435,8 @@ hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const
 // Sum the recorded fine-level sweep times (stream already synchronised).
 int collect_profile(recon_ctx *ctx, recon_stats *st)
 {
-    double ms[2] = {0.0, 0.0};
-    int count[2] = {0, 0};
+    double ms[3] = {0.0, 0.0, 0.0};
+    int count[3] = {0, 0, 0};
     for (int i = 0; i < ctx->prof_count; ++i) {
         float e = 0.0f;
         HIPCHK(hipEventElapsedTime(&e, ctx->prof[2 * i], ctx->prof[2 * i + 1]));
@@ -445,6 +447,8 @@ int collect_profile(recon_ctx *ctx, recon_stats *st)
     st->smoother_ms = ms[0];
     st->smoother_zero_sweeps = count[1];
     st->smoother_zero_ms = ms[1];
+    st->smoother_folded_sweeps = count[2];
+    st->smoother_folded_ms = ms[2];
     ctx->prof_count = 0;
     return RECON_OK;
 }
@@ -467,8 +471,12 @@ int vcycle(recon_ctx *ctx, Levels<T> &S, int l, const T *rhs, T *out)
     for (int s = 0; s < ctx->cfg.n_pre; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 0, s == 0));
     HIPCHK(coarse_rhs<T>(cur, S.a[l], rhs, S.res[l], S.b[l + 1], n, sc, amin, ctx->stream));
     TRY(vcycle<T>(ctx, S, l + 1, S.b[l + 1], S.u[l + 1]));
-    HIPCHK(prolong_level<T>(cur, S.u[l + 1], n, ctx->stream));
-    for (int s = 0; s < ctx->cfg.n_post; ++s) TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 1, false));
+    // on fused levels the coarse correction enters the first post-smoothing
+    // sweep's planes as they are read (no pass of its own over u)
+    const bool fold = ctx->cfg.n_post >= 1 && use_fused<T>(n);
+    if (!fold) HIPCHK(prolong_level<T>(cur, S.u[l + 1], n, ctx->stream));
+    for (int s = 0; s < ctx->cfg.n_post; ++s)
+        TRY(sweep<T>(ctx, S, l, cur, alt, rhs, 1, false, fold && s == 0 ? S.u[l + 1] : nullptr));
     if (cur != out) HIPCHK(hipMemcpyAsync(out, cur, n3 * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
     return RECON_OK;
 }
@@ -1508,6 +1516,40 @@ int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int 
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
+}
+
+extern "C++" {
+template <typename T>
+static int stage_prolong_sweep(recon_ctx *ctx, T *u, const T *e, const T *a, const T *b, int nl, double scale,
+                               int first, int variant)
+{
+    T *scratch = reinterpret_cast<T *>(ctx->t);  // n^3 doubles >= nl^3 values of T
+    if (variant == 1) {
+        HIPCHK(prolong_level<T>(u, e, nl, ctx->stream));
+        HIPCHK(launch_rbgs_fused<T>(u, scratch, a, b, nl, (T)scale, (T)ctx->cfg.a_min, first, false, ctx->stream));
+    } else {
+        HIPCHK(launch_rbgs_fused<T>(u, scratch, a, b, nl, (T)scale, (T)ctx->cfg.a_min, first, false, ctx->stream, e));
+    }
+    HIPCHK(hipMemcpyAsync(u, scratch, (size_t)nl * nl * nl * sizeof(T), hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RECON_OK;
+}
+}
+
+int recon_stage_prolong_sweep(recon_ctx *ctx, void *u, const void *e, const void *a, const void *b, int nl,
+                              double scale, int first, int dtype, int variant)
+{
+    TRY(check_ctx(ctx));
+    if (!u || !e || !a || !b || !level_ok(ctx, nl) || nl % 2 || (dtype != 0 && dtype != 1) ||
+        (first != 0 && first != 1) || (variant != 1 && variant != 2))
+        return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (dtype == 0 ? !rbgs_fused_supported<double>(nl) : !rbgs_fused_supported<float>(nl))
+        return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 128 (FP32) or 64 (FP64)");
+    if (dtype == 0)
+        return stage_prolong_sweep<double>(ctx, (double *)u, (const double *)e, (const double *)a, (const double *)b,
+                                           nl, scale, first, variant);
+    return stage_prolong_sweep<float>(ctx, (float *)u, (const float *)e, (const float *)a, (const float *)b, nl,
+                                      scale, first, variant);
 }
 
 int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dtype, int variant)

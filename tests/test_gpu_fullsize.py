@@ -55,6 +55,27 @@ def test_fused_sweep_512(torch_cuda, orc, field512):
     assert rel(ug, uo) < 2e-6
 
 
+def test_prolongation_folded_into_the_sweep_512(torch_cuda, field512):
+    """At the benchmark's size the first post-smoothing sweep reads u + P e
+    as it streams u (FP32: four-plane ring; FP64: six-plane ring); it equals
+    the prolongation's own pass followed by the sweep, bit for bit."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 512
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
+    g = torch.Generator(device="cuda").manual_seed(512)
+    a = torch.from_numpy(field512 / field512.mean()).cuda()
+    for dt in (torch.float64, torch.float32):
+        u = torch.randn((n, n, n), generator=g, device="cuda", dtype=dt)
+        b = torch.randn((n, n, n), generator=g, device="cuda", dtype=dt)
+        e = torch.randn((n // 2,) * 3, generator=g, device="cuda", dtype=dt)
+        ad = a.to(dt)
+        for first in (0, 1):
+            x = rec.prolong_sweep(u, e, ad, b, scale=1.0, first=first, variant=2)
+            assert torch.equal(x, rec.prolong_sweep(u, e, ad, b, scale=1.0, first=first, variant=1))
+            del x
+
+
 def test_fused_sweep_1024_fp32_bitwise(torch_cuda):
     """At 1024^3 the FP32 fused sweep runs 16 x 128 tiles with 512 threads on
     the six-plane ring: both colour orders equal the per-colour kernels bit
@@ -71,6 +92,9 @@ def test_fused_sweep_1024_fp32_bitwise(torch_cuda):
         fused = rec.rbgs(u, a, b, scale=0.25, first=first, variant=2)
         assert torch.equal(fused, rec.rbgs(u, a, b, scale=0.25, first=first, variant=1))
         del fused
+    e = torch.randn((n // 2,) * 3, generator=g, device="cuda", dtype=torch.float32)
+    folded = rec.prolong_sweep(u, e, a, b, scale=0.25, first=1, variant=2)
+    assert torch.equal(folded, rec.prolong_sweep(u, e, a, b, scale=0.25, first=1, variant=1))
 
 
 def test_vcycle_256(torch_cuda, orc):

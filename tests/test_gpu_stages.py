@@ -391,3 +391,27 @@ def test_choose_step_single_mode_closed_form(torch_cuda, orc, n, amp, s_max, axi
     a_g = rec.choose_step(dev(torch, phi), dev(torch, dphi))
     assert a_g == 2.0 ** -j_exp
     assert orc.choose_step(phi, dphi, orc.Config(s_max=s_max)) == (j_exp, 2.0 ** -j_exp)
+
+
+@pytest.mark.parametrize("first", [0, 1])
+def test_prolongation_folded_into_the_sweep(torch_cuda, orc, first):
+    """The V-cycle's coarse correction folded into its first post-smoothing
+    sweep (App. A multigrid) at 256^3, where the fused sweep runs: equal bit
+    for bit to the prolongation's own pass followed by the sweep, in FP64 and
+    FP32, and to the oracle's prolongation and sweep in FP64."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 256
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
+    rng = np.random.default_rng(900 + first)
+    a = np.exp(1.5 * rng.normal(size=(n, n, n)))
+    u, b = rng.normal(size=(2, n, n, n))
+    e = rng.normal(size=(n // 2,) * 3)
+    ug = [rec.prolong_sweep(dev(torch, u), dev(torch, e), dev(torch, a), dev(torch, b), scale=0.25, first=first,
+                            variant=v) for v in (1, 2)]
+    assert torch.equal(ug[0], ug[1])
+    uo = orc.rbgs_sweep(orc.prolong_add(u, e), a, b, scale=0.25, first=first)
+    assert rel(host(ug[1]), uo) < 1e-13
+    f = lambda x: dev(torch, x, torch.float32)  # noqa: E731
+    ug = [rec.prolong_sweep(f(u), f(e), f(a), f(b), scale=0.25, first=first, variant=v) for v in (1, 2)]
+    assert torch.equal(ug[0], ug[1])
