@@ -230,6 +230,14 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         return jod ? wj * (r0 + r1) : r0;
     };
 
+    // PRO: each halo-load slot's in-plane interpolation of the coarse plane
+    // above the last odd plane deposited (deposits run through consecutive
+    // planes, so every coarse plane is interpolated once per slot and serves
+    // the fine planes 2c - 1, 2c and 2c + 1 from registers).  The FP64 sweep
+    // on the six-plane ring recomputes them instead, which measured faster
+    // there (0.93 against 0.95 ms at 512^3; elsewhere keeping them saves 8-15%).
+    constexpr bool KEEP = PRO && !(sizeof(T) == 8 && SLOTS == 6);
+    T ic[KEEP ? LU : 1];
     T ru[2][LU], ra[2][LU];
     auto fetch = [&](auto SETc, int p) {
         constexpr int SET = decltype(SETc)::value;
@@ -243,6 +251,11 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         if constexpr (PRO)
             if (!(p & 1)) coarse_load((p >> 1) + 1, rcs[SET]);
     };
+    // the interpolation of coarse plane c at slot r, kept or recomputed
+    auto held = [&](int c, int r) {
+        if constexpr (KEEP) return ic[r];
+        else return inplane(c, r);
+    };
     // store the staged plane p (PRO: plus its coarse correction; with cw,
     // an even plane also stores the coarse plane staged with it)
     auto deposit = [&](auto SETc, auto SLOTc, int p = 0, bool cw = false) {
@@ -253,14 +266,14 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
             if (p & 1) {
 #pragma unroll
                 for (int r = 0; r < LU; ++r) {
-                    T acc = inplane(c, r);
-                    const T acc1 = inplane(c + 1, r);
-                    acc = wi * (acc + acc1);
-                    sU[SLOT][dstU[r]] = ru[SET][r] + acc;
+                    const T lo = held(c, r);
+                    const T up = inplane(c + 1, r);
+                    if constexpr (KEEP) ic[r] = up;
+                    sU[SLOT][dstU[r]] = ru[SET][r] + wi * (lo + up);
                 }
             } else {
 #pragma unroll
-                for (int r = 0; r < LU; ++r) sU[SLOT][dstU[r]] = ru[SET][r] + inplane(c, r);
+                for (int r = 0; r < LU; ++r) sU[SLOT][dstU[r]] = ru[SET][r] + held(c, r);
                 if (cw) coarse_store(c + 1, rcs[SET]);
             }
         } else {
@@ -271,7 +284,8 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         for (int r = 0; r < LU; ++r) sA[SLOT][dstU[r]] = (T)0.5 * ra[SET][r];
     };
     // PRO: the coarse planes the prologue's deposits read, c0 - 1 .. c0 + K
-    // with c0 = i0 / 2, stored before them
+    // with c0 = i0 / 2, stored before them, and (when kept) the interpolation
+    // of c0 - 1 for the first deposit (plane i0 - 2)
     auto coarse_preload = [&](int K) {
         if constexpr (PRO) {
             for (int c = (i0 >> 1) - 1; c <= (i0 >> 1) + K; ++c) {
@@ -280,6 +294,9 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
                 coarse_store(c, tmp);
             }
             lds_barrier();
+            if constexpr (KEEP)
+#pragma unroll
+                for (int r = 0; r < LU; ++r) ic[r] = inplane((i0 >> 1) - 1, r);
         }
     };
     // b at the first-colour nodes of plane q1 (parity P1) and at the
@@ -464,9 +481,12 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
 //     6-plane ring from 512^3 (131 KB).
 // Launches keep at least 512 workgroups, each streaming the longest i-chunk
 // that allows (every chunk re-reads four planes).
-template <typename T, int TJ_, int TK_, int NT_, int MINW_, int SLOTS_>
+// FOLD = 0: a shape only the zero-start sweep uses, built without the
+// folded coarse correction.
+template <typename T, int TJ_, int TK_, int NT_, int MINW_, int SLOTS_, int FOLD_ = 1>
 struct FusedShape {
     static constexpr int TJ = TJ_, TK = TK_, NT = NT_, MINW = MINW_, SLOTS = SLOTS_, MIN_BLOCKS = 512;
+    static constexpr bool FOLD = FOLD_;
 };
 
 template <typename C, typename T>
@@ -486,8 +506,12 @@ hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, i
     k_rbgs_fused<T, C::TJ, 0, F1, C::TK, C::NT, C::MINW, C::SLOTS, 1><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, \
                                                                                            ci, inv, a_min, e)
     if (e) {
-        if (first) RECON_FUSED_PRO(1);
-        else RECON_FUSED_PRO(0);
+        if constexpr (C::FOLD) {
+            if (first) RECON_FUSED_PRO(1);
+            else RECON_FUSED_PRO(0);
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else if (zero_init) {
         if (first) RECON_FUSED(1, 1);
         else RECON_FUSED(1, 0);
@@ -519,8 +543,8 @@ hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, in
             return launch_fused_shape<FusedShape<T, 16, 128, 512, 1, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
                                                                         zero_init, s, e);
         if (n >= 512 && n < 1024 && zero_init)
-            return launch_fused_shape<FusedShape<T, 8, 128, 256, 2, 6>>(u_in, u_out, a, b, n, inv, a_min, first,
-                                                                       zero_init, s);
+            return launch_fused_shape<FusedShape<T, 8, 128, 256, 2, 6, 0>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                          zero_init, s);
         return launch_fused_shape<FusedShape<T, 8, 128, 256, 2, 4>>(u_in, u_out, a, b, n, inv, a_min, first,
                                                                    zero_init, s, e);
     } else {

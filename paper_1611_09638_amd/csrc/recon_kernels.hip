@@ -25,18 +25,24 @@ __global__ void k_finalize(const double *__restrict__ part, int rows, int K, Ops
     const int t = threadIdx.x;
     for (int c = 0; c < K; ++c) {
         const int op = ops.op[c];
+        auto fold = [op](double x, double y) {
+            return op == RED_SUM ? x + y : (op == RED_MAX ? (x > y ? x : y) : (x < y ? x : y));
+        };
         double x = op == RED_SUM ? 0.0 : (op == RED_MAX ? -INFINITY : INFINITY);
-        for (int r = t; r < rows; r += 256) {
-            double y = part[(size_t)r * K + c];
-            x = op == RED_SUM ? x + y : (op == RED_MAX ? (x > y ? x : y) : (x < y ? x : y));
+        // rows t, t + 256, ... in order; eight loads in flight at a time
+        int r = t;
+        for (; r + 7 * 256 < rows; r += 8 * 256) {
+            double y[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) y[v] = part[(size_t)(r + v * 256) * K + c];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) x = fold(x, y[v]);
         }
+        for (; r < rows; r += 256) x = fold(x, part[(size_t)r * K + c]);
         sm[t] = x;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
-            if (t < w) {
-                double a = sm[t], b = sm[t + w];
-                sm[t] = op == RED_SUM ? a + b : (op == RED_MAX ? (a > b ? a : b) : (a < b ? a : b));
-            }
+            if (t < w) sm[t] = fold(sm[t], sm[t + w]);
             __syncthreads();
         }
         if (t == 0) out[c] = sm[0];
