@@ -271,7 +271,8 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void
 /* One red-black Gauss-Seidel sweep in place (colour `first` then the other;
  * red = i+j+k even) on an nl^3 level.  variant 0: the kernel the solver uses
  * on that level; 1: two per-colour launches; 2: the fused two-colour kernel
- * (nl a multiple of 128 in FP32 or of 64 in FP64, else RECON_E_ARG). */
+ * (nl a multiple of 16, else RECON_E_ARG).  All variants give the same
+ * values. */
 int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int nl, double scale, int first,
                      int dtype, int variant);
 
@@ -300,8 +301,8 @@ int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int 
  * operator of coefficient a at level scale `scale`, rhs b.  variant 1: the
  * prolongation's own pass, then the sweep; 2: the correction added as the
  * sweep reads each plane (what the V-cycle runs).  Both give the same values.
- * nl an even level edge that the fused sweep takes (a multiple of 128 in
- * FP32, 64 in FP64), else RECON_E_ARG.  Uses the context's scratch field t. */
+ * nl a level edge that the fused sweep takes (a multiple of 16), else
+ * RECON_E_ARG.  Uses the context's scratch field t. */
 int recon_stage_prolong_sweep(recon_ctx *ctx, void *u, const void *e, const void *a, const void *b, int nl,
                               double scale, int first, int dtype, int variant);
 

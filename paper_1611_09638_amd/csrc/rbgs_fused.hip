@@ -482,11 +482,15 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
 // Launches keep at least 512 workgroups, each streaming the longest i-chunk
 // that allows (every chunk re-reads four planes).
 // FOLD = 0: a shape only the zero-start sweep uses, built without the
-// folded coarse correction.
-template <typename T, int TJ_, int TK_, int NT_, int MINW_, int SLOTS_, int FOLD_ = 1>
+// folded coarse correction.  CI > 0 fixes the i-chunk length (the small
+// levels, where a launch costs more than its bytes and short chunks keep
+// every CU busy); CI = 0 takes the longest chunk that keeps MIN_BLOCKS
+// workgroups.
+template <typename T, int TJ_, int TK_, int NT_, int MINW_, int SLOTS_, int FOLD_ = 1, int CI_ = 0>
 struct FusedShape {
     static constexpr int TJ = TJ_, TK = TK_, NT = NT_, MINW = MINW_, SLOTS = SLOTS_, MIN_BLOCKS = 512;
     static constexpr bool FOLD = FOLD_;
+    static constexpr int CI = CI_;
 };
 
 template <typename C, typename T>
@@ -495,9 +499,10 @@ hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, i
 {
     if (e && (zero_init || n % 2)) return hipErrorInvalidValue;
     if (n < C::TK || n % C::TK || n % C::TJ) return hipErrorInvalidValue;
-    int ci = n;
-    while (ci > 16 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
-    if (C::SLOTS == 4 && ci % 4) return hipErrorInvalidValue;  // the 4-slot loop takes planes in fours
+    int ci = C::CI ? C::CI : n;
+    if (!C::CI)
+        while (ci > 16 && (n / C::TK) * (n / C::TJ) * (n / ci) < C::MIN_BLOCKS) ci /= 2;
+    if (n % ci || (C::SLOTS == 4 && ci % 4)) return hipErrorInvalidValue;  // the 4-slot loop takes planes in fours
     const int nblk = (n / C::TK) * (n / C::TJ) * (n / ci);
 #define RECON_FUSED(Z, F1)                                                                                \
     k_rbgs_fused<T, C::TJ, Z, F1, C::TK, C::NT, C::MINW, C::SLOTS><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, \
@@ -524,12 +529,21 @@ hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, i
     return hipGetLastError();
 }
 
+// The shapes of levels from 256^3 whose edge they divide.
+template <typename T>
+bool fused_large(int n)
+{
+    const int tk = sizeof(T) == 4 ? 128 : 64, tj = sizeof(T) == 4 ? (n >= 1024 ? 16 : 8) : 16;
+    return n >= 256 && n % tk == 0 && n % tj == 0;
+}
+
+// Every shape divides the edges it is used for: the large ones above, the
+// small ones (8 x 32 and 8 x 16 tiles, 8- and 4-plane chunks) edges that are
+// multiples of 16.
 template <typename T>
 bool rbgs_fused_supported(int n)
 {
-    // every shape above divides the edges it is used for
-    const int tk = sizeof(T) == 4 ? 128 : 64, tj = sizeof(T) == 4 ? (n >= 1024 ? 16 : 8) : 16;
-    return n >= tk && n % tk == 0 && n % tj == 0;
+    return fused_large<T>(n) || (n >= 16 && n % 16 == 0);
 }
 
 template <typename T>
@@ -538,6 +552,19 @@ hipError_t launch_rbgs_fused(const T *u_in, T *u_out, const T *a, const T *b, in
 {
     if (!rbgs_fused_supported<T>(n)) return hipErrorInvalidValue;
     const T inv = (T)1 / scale;
+    if (!fused_large<T>(n)) {
+        // levels below 256^3 (L2-resident): narrow tiles and 4- or 8-plane
+        // chunks, so that even 16^3 spreads over several workgroups
+        if (n % 32 == 0 && n >= 64) {
+            if (n >= 128)
+                return launch_fused_shape<FusedShape<T, 8, 32, 256, 2, 4, 1, 8>>(u_in, u_out, a, b, n, inv, a_min,
+                                                                                first, zero_init, s, e);
+            return launch_fused_shape<FusedShape<T, 8, 32, 256, 2, 4, 1, 4>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                            zero_init, s, e);
+        }
+        return launch_fused_shape<FusedShape<T, 8, 16, 128, 2, 4, 1, 4>>(u_in, u_out, a, b, n, inv, a_min, first,
+                                                                        zero_init, s, e);
+    }
     if constexpr (sizeof(T) == 4) {
         if (n >= 1024 && !zero_init)
             return launch_fused_shape<FusedShape<T, 16, 128, 512, 1, 6>>(u_in, u_out, a, b, n, inv, a_min, first,

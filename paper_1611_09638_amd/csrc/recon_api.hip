@@ -331,14 +331,15 @@ double level_scale(int l) { return std::ldexp(1.0, -2 * l); }
 
 constexpr int kProfPairs = 4096;  // size of recon_ctx::prof_zero
 
-// Levels of at least 256^3 whose edge is a multiple of the fused kernel's tile
-// (128 in FP32, 64 in FP64) are swept by the fused two-colour kernel; smaller
-// levels (resident in L2/MALL) by two
-// per-colour launches, which keep more workgroups busy there.
+// Every level whose edge a fused shape divides (multiples of 16) is swept by
+// the fused two-colour kernel: from 256^3 with the wide streaming tiles,
+// below with narrow tiles and short chunks, where one launch instead of two
+// per sweep is most of the gain.  Other edges (ragged hierarchies) take two
+// per-colour launches.
 template <typename T>
 bool use_fused(int n)
 {
-    return n >= 256 && rbgs_fused_supported<T>(n);
+    return rbgs_fused_supported<T>(n);
 }
 
 // One red-black sweep on level l: fused levels out of place between `cur` and
@@ -1498,7 +1499,7 @@ int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int 
         return fail(ctx, RECON_E_ARG, "bad arguments");
     const bool can_fuse = dtype == 0 ? rbgs_fused_supported<double>(nl) : rbgs_fused_supported<float>(nl);
     if (variant == 2 && !can_fuse)
-        return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 128 (FP32) or 64 (FP64)");
+        return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 16");
     const bool fused = variant == 2 || (variant == 0 && (dtype == 0 ? use_fused<double>(nl) : use_fused<float>(nl)));
     if (fused) {
         if (dtype == 0) TRY(stage_rbgs_fused<double>(ctx, (double *)u, (const double *)a, (const double *)b, nl, scale, first));
@@ -1544,7 +1545,7 @@ int recon_stage_prolong_sweep(recon_ctx *ctx, void *u, const void *e, const void
         (first != 0 && first != 1) || (variant != 1 && variant != 2))
         return fail(ctx, RECON_E_ARG, "bad arguments");
     if (dtype == 0 ? !rbgs_fused_supported<double>(nl) : !rbgs_fused_supported<float>(nl))
-        return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 128 (FP32) or 64 (FP64)");
+        return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 16");
     if (dtype == 0)
         return stage_prolong_sweep<double>(ctx, (double *)u, (const double *)e, (const double *)a, (const double *)b,
                                            nl, scale, first, variant);

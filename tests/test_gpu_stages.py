@@ -81,16 +81,17 @@ def test_normalize_meshmass_source_smooth(torch_cuda, orc, n, cn):
 @pytest.mark.parametrize("n,cn", SIZES + [(128, 8), (256, 8)])
 @pytest.mark.parametrize("first", [0, 1])
 def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
-    """Both sweep kernels (fused two-colour where n is a multiple of its tile
-    width, and per-colour) against the oracle; the two kernels round
-    identically.  At 256 the FP32 fused kernel has two tiles along k."""
+    """Both sweep kernels (fused two-colour where n is a multiple of 16, and
+    per-colour) against the oracle; the two kernels round identically.  The
+    fused kernel runs its narrow tiles with short chunks below 256 and its
+    wide streaming tiles at 256 (two tiles along k in FP32)."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
     rec = binding.Recon(n, binding.Config(coarse_n=cn))
     rng = np.random.default_rng(100 + n + first)
     a = np.exp(1.5 * rng.normal(size=(n, n, n)))
     u, b = rng.normal(size=(2, n, n, n))
-    variants = (1, 2) if n % 64 == 0 else (1,)  # fused FP64: 16 x 64 tiles
+    variants = (1, 2) if n % 16 == 0 else (1,)
     for scale in (1.0, 1.0 / 16):
         uo = orc.rbgs_sweep(u, a, b, scale=scale, first=first)
         ug = [host(rec.rbgs(dev(torch, u), dev(torch, a), dev(torch, b), scale=scale, first=first, variant=v))
@@ -99,11 +100,13 @@ def test_rbgs_sweep_fp64_and_fp32(torch_cuda, orc, n, cn, first):
             assert rel(x, uo) < 1e-13
             assert np.array_equal(x, ug[0])
     a32, u32, b32 = (x.astype(np.float32).astype(np.float64) for x in (a, u, b))
-    variants = (1, 2) if n % 128 == 0 else (1,)  # fused FP32: 8 x 128 tiles
-    if n == 64:
-        with pytest.raises(binding.ReconError):
-            rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32), dev(torch, b32, torch.float32),
-                     variant=2)
+    if n == 48:
+        # level 24 of this hierarchy is no multiple of 16
+        h = n // 2
+        for dt in (torch.float32, torch.float64):
+            with pytest.raises(binding.ReconError):
+                rec.rbgs(dev(torch, u32[:h, :h, :h], dt), dev(torch, a32[:h, :h, :h], dt),
+                         dev(torch, b32[:h, :h, :h], dt), variant=2)
     uo = orc.rbgs_sweep(u32, a32, b32, first=first)
     ug = [host(rec.rbgs(dev(torch, u32, torch.float32), dev(torch, a32, torch.float32),
                         dev(torch, b32, torch.float32), first=first, variant=v)) for v in variants]
@@ -393,17 +396,19 @@ def test_choose_step_single_mode_closed_form(torch_cuda, orc, n, amp, s_max, axi
     assert orc.choose_step(phi, dphi, orc.Config(s_max=s_max)) == (j_exp, 2.0 ** -j_exp)
 
 
+@pytest.mark.parametrize("n", [16, 32, 48, 64, 128, 256])
 @pytest.mark.parametrize("first", [0, 1])
-def test_prolongation_folded_into_the_sweep(torch_cuda, orc, first):
+def test_prolongation_folded_into_the_sweep(torch_cuda, orc, n, first):
     """The V-cycle's coarse correction folded into its first post-smoothing
-    sweep (App. A multigrid) at 256^3, where the fused sweep runs: equal bit
-    for bit to the prolongation's own pass followed by the sweep, in FP64 and
+    sweep (App. A multigrid) on every kind of level the fused sweep runs on
+    (narrow tiles with 4- and 8-plane chunks below 256, the streaming tiles at
+    256; 16 takes its correction from the 8^3 coarsest level): equal bit for
+    bit to the prolongation's own pass followed by the sweep, in FP64 and
     FP32, and to the oracle's prolongation and sweep in FP64."""
     torch = torch_cuda
     from paper_1611_09638_amd import binding
-    n = 256
-    rec = binding.Recon(n, binding.Config(precision=binding.MIXED))
-    rng = np.random.default_rng(900 + first)
+    rec = binding.Recon(n, binding.Config(precision=binding.MIXED, coarse_n=6 if n == 48 else 8))
+    rng = np.random.default_rng(900 + first + n)
     a = np.exp(1.5 * rng.normal(size=(n, n, n)))
     u, b = rng.normal(size=(2, n, n, n))
     e = rng.normal(size=(n // 2,) * 3)
