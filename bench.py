@@ -31,7 +31,8 @@ METRIC = "recon wall time + smoother HBM GB/s at 512^3, mixed vs FP64, at 1e-6 r
 
 
 # The finest-level sweep kernels (the instantiation that reads u, a and b).
-FUSED_KERNEL = {"mixed": "k_rbgs_fused<float,8,0,{0,1},128,256,2,4>", "fp64": "k_rbgs_fused<double,16,0,{0,1},64,512,2,6>"}
+FUSED_KERNEL = {"mixed": "k_rbgs_fused<float,8,0,{0,1},128,256,2,4,0,1>",
+                "fp64": "k_rbgs_fused<double,16,0,{0,1},64,512,2,6,0,1>"}
 COUNTERS = os.path.join(ROOT, "profiles", "rbgs_fused_512_counters.json")
 
 

@@ -71,6 +71,9 @@ using IC = std::integral_constant<int, X>;
 // planes that are multiples of 4, so with the steady loop unrolled by the
 // ring depth every ring slot and every plane parity is a compile-time
 // constant, and each LDS access is one per-thread offset plus an immediate).
+// NTS = 1 stores the swept planes nontemporally: on fields far larger than
+// the caches nothing reads them back soon, and keeping them out of L2 leaves
+// it to the halo rows that neighbouring tiles share (5-8% faster at 512^3).
 // PRO = 1 folds the multigrid's coarse correction into the sweep (the first
 // post-smoothing sweep of a V-cycle): every plane of u_in enters the ring as
 // u_in + P e, with P the trilinear prolongation of the coarse-grid correction
@@ -88,7 +91,7 @@ struct CoarseTile {
 };
 
 template <typename T, int TJ, int ZERO, int FIRST, int TK_ = 64, int NT_ = 512, int MINW = 1, int SLOTS = 4,
-          int PRO = 0>
+          int PRO = 0, int NTS = 0>
 __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ uin, T *__restrict__ uout,
                                                     const T *__restrict__ ag, const T *__restrict__ bg, int n,
                                                     int ci, T inv_scale, T a_min, const T *__restrict__ eg)
@@ -343,7 +346,11 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         constexpr int SLOT = decltype(SLOTc)::value;
         char *ob = reinterpret_cast<char *>(uout) + (size_t)wrapc(p, n) * plane_bytes;
 #pragma unroll
-        for (int r = 0; r < RS; ++r) *reinterpret_cast<T *>(ob + gS[r]) = sU[SLOT][sN[r]];
+        for (int r = 0; r < RS; ++r) {
+            T *dst = reinterpret_cast<T *>(ob + gS[r]);
+            if constexpr (NTS) __builtin_nontemporal_store(sU[SLOT][sN[r]], dst);
+            else *dst = sU[SLOT][sN[r]];
+        }
     };
 
     if constexpr (SLOTS == 6) {
@@ -491,6 +498,7 @@ struct FusedShape {
     static constexpr int TJ = TJ_, TK = TK_, NT = NT_, MINW = MINW_, SLOTS = SLOTS_, MIN_BLOCKS = 512;
     static constexpr bool FOLD = FOLD_;
     static constexpr int CI = CI_;
+    static constexpr int NTS = CI_ == 0;  // the streaming shapes store nontemporally
 };
 
 template <typename C, typename T>
@@ -505,11 +513,11 @@ hipError_t launch_fused_shape(const T *u_in, T *u_out, const T *a, const T *b, i
     if (n % ci || (C::SLOTS == 4 && ci % 4)) return hipErrorInvalidValue;  // the 4-slot loop takes planes in fours
     const int nblk = (n / C::TK) * (n / C::TJ) * (n / ci);
 #define RECON_FUSED(Z, F1)                                                                                \
-    k_rbgs_fused<T, C::TJ, Z, F1, C::TK, C::NT, C::MINW, C::SLOTS><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, ci, \
-                                                                                        inv, a_min, nullptr)
+    k_rbgs_fused<T, C::TJ, Z, F1, C::TK, C::NT, C::MINW, C::SLOTS, 0, C::NTS><<<nblk, C::NT, 0, s>>>(         \
+        u_in, u_out, a, b, n, ci, inv, a_min, nullptr)
 #define RECON_FUSED_PRO(F1)                                                                                   \
-    k_rbgs_fused<T, C::TJ, 0, F1, C::TK, C::NT, C::MINW, C::SLOTS, 1><<<nblk, C::NT, 0, s>>>(u_in, u_out, a, b, n, \
-                                                                                           ci, inv, a_min, e)
+    k_rbgs_fused<T, C::TJ, 0, F1, C::TK, C::NT, C::MINW, C::SLOTS, 1, C::NTS><<<nblk, C::NT, 0, s>>>(         \
+        u_in, u_out, a, b, n, ci, inv, a_min, e)
     if (e) {
         if constexpr (C::FOLD) {
             if (first) RECON_FUSED_PRO(1);

@@ -875,6 +875,13 @@ hipError_t launch_update_p(const Z *z, double *pv, double beta, long n3, bool fi
     return hipGetLastError();
 }
 
+// Vector types that the nontemporal store builtins accept.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// r and its FP32 copy are stored nontemporally: the next kernels that read
+// them stream fields far larger than the caches, and keeping the stores out
+// of L2 measured faster at 256^3 and 512^3.
 template <bool U>
 __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, const double *__restrict__ pv,
                             const double *__restrict__ q, double alpha, float *__restrict__ r32, long n3, double *part,
@@ -905,8 +912,16 @@ __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, cons
         const double2 rr = *reinterpret_cast<const double2 *>(r + e);
         const double2 qq = *reinterpret_cast<const double2 *>(q + e);
         const double r0 = rr.x - alpha * qq.x, r1 = rr.y - alpha * qq.y;
-        *reinterpret_cast<double2 *>(r + e) = make_double2(r0, r1);
-        if (r32) *reinterpret_cast<float2 *>(r32 + e) = make_float2((float)r0, (float)r1);
+        v2d rv;
+        rv.x = r0;
+        rv.y = r1;
+        __builtin_nontemporal_store(rv, reinterpret_cast<v2d *>(r + e));
+        if (r32) {
+            v2f fv;
+            fv.x = (float)r0;
+            fv.y = (float)r1;
+            __builtin_nontemporal_store(fv, reinterpret_cast<v2f *>(r32 + e));
+        }
         v[0] += r0 * r0;
         v[0] += r1 * r1;
     }
