@@ -233,16 +233,22 @@ int recon_stage_normalize(recon_ctx *ctx, const double *rho, double *m);
 /* Cloud-in-cell assignment of np particles onto the n^3 grid (particle count per node). */
 int recon_stage_cic(recon_ctx *ctx, const float *pos, long long np, double box, double *rho);
 
+/* The next three run on the context's n^3 grid.  variant 0: the kernels the
+ * solver uses at that size; 1: per-node gathers; 2: the stencil field streamed
+ * through LDS (n a multiple of 64, else RECON_E_ARG).  All variants give the
+ * same node values; sums (mean M, rms(Sigma)) may differ in rounding. */
+
 /* Mass per curvilinear cell M = det(I + Hess phi) * CIC(m)(xi + D_c phi)
  * (rho sqrt g of App. A on the current mesh); phi in grid units. */
-int recon_stage_meshmass(recon_ctx *ctx, const double *phi, const double *m, double *M);
+int recon_stage_meshmass(recon_ctx *ctx, const double *phi, const double *m, double *M, int variant);
 
 /* b = S(Sigma + C + E) - mean, Sigma = mean(M) - M, with the compression and
  * expansion limiters of App. A (Eq. elliptic).  *rms_sigma (host) <- rms(Sigma). */
-int recon_stage_source(recon_ctx *ctx, const double *phi, const double *M, double *b, double *rms_sigma);
+int recon_stage_source(recon_ctx *ctx, const double *phi, const double *M, double *b, double *rms_sigma,
+                       int variant);
 
 /* out = S f, the nearest-neighbour smoothing of App. A. */
-int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out);
+int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out, int variant);
 
 /* out = A u with A = div(a grad .) in flux form on an nl^3 level (scale 4^-l). */
 int recon_stage_apply(recon_ctx *ctx, const double *u, const double *a, int nl, double scale, double *out);

@@ -136,9 +136,9 @@ def lib():
         "recon_last_error": (ctypes.c_char_p, [vp]),
         "recon_stage_normalize": (i, [vp, vp, vp]),
         "recon_stage_cic": (i, [vp, vp, ll, d, vp]),
-        "recon_stage_meshmass": (i, [vp, vp, vp, vp]),
-        "recon_stage_source": (i, [vp, vp, vp, vp, pd]),
-        "recon_stage_smooth": (i, [vp, vp, vp]),
+        "recon_stage_meshmass": (i, [vp, vp, vp, vp, i]),
+        "recon_stage_source": (i, [vp, vp, vp, vp, pd, i]),
+        "recon_stage_smooth": (i, [vp, vp, vp, i]),
         "recon_stage_apply": (i, [vp, vp, vp, i, d, vp]),
         "recon_stage_residual": (i, [vp, vp, vp, vp, i, d, vp, i, i]),
         "recon_stage_direction": (i, [vp, vp, i, vp, vp, d, i, vp, vp, pd, i, vp, d, i]),
@@ -304,21 +304,22 @@ class Recon:
         self._check(lib().recon_stage_cic(self._ctx, _ptr(pos, torch.float32), pos.shape[0], float(box), _ptr(rho)))
         return rho
 
-    def meshmass(self, phi, m):
+    def meshmass(self, phi, m, variant=0):
         M = self._field()
-        self._check(lib().recon_stage_meshmass(self._ctx, _ptr(phi, torch.float64), _ptr(m, torch.float64), _ptr(M)))
+        self._check(lib().recon_stage_meshmass(self._ctx, _ptr(phi, torch.float64), _ptr(m, torch.float64), _ptr(M),
+                                               variant))
         return M
 
-    def source(self, phi, M):
+    def source(self, phi, M, variant=0):
         b = self._field()
         rms = ctypes.c_double()
         self._check(lib().recon_stage_source(self._ctx, _ptr(phi, torch.float64), _ptr(M, torch.float64), _ptr(b),
-                                             ctypes.byref(rms)))
+                                             ctypes.byref(rms), variant))
         return b, rms.value
 
-    def smooth(self, f):
+    def smooth(self, f, variant=0):
         out = self._field()
-        self._check(lib().recon_stage_smooth(self._ctx, _ptr(f, torch.float64), _ptr(out)))
+        self._check(lib().recon_stage_smooth(self._ctx, _ptr(f, torch.float64), _ptr(out), variant))
         return out
 
     def apply(self, u, a, scale=1.0):

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "librecon.so")
 PROBE_LIB = os.path.join(HERE, "libstream_probe.so")
 PROBE_SOURCES = ["stream_probe.hip"]
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["recon_kernels.hip", "rbgs_fused.hip", "stencil25.hip", "transfer25.hip", "resrestrict25.hip", "pdcheck25.hip", "massupdate.hip", "fullop25.hip", "particles.hip", "recon_adjoint.hip", "recon_api.hip"]
+SOURCES = ["recon_kernels.hip", "rbgs_fused.hip", "stencil25.hip", "transfer25.hip", "resrestrict25.hip", "pdcheck25.hip", "outer25.hip", "massupdate.hip", "fullop25.hip", "particles.hip", "recon_adjoint.hip", "recon_api.hip"]
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HIPCC_FLAGS = [

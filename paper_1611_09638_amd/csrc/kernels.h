@@ -50,6 +50,13 @@ hipError_t launch_source(const double *phi, const double *M, double rho_bar, dou
                          Part &p, hipStream_t s);
 // out = c0 f + (1-c0)/6 sum nb - sub
 hipError_t launch_smooth(const double *f, double *out, int n, double c0, double sub, hipStream_t s);
+// the same three passes with the stencil field streamed through LDS (outer25.hip);
+// n a multiple of 64; the same node values, the partial sums grouped per workgroup
+bool outer25_supported(int n);
+hipError_t launch_meshmass25(const double *phi, const double *m, double *M, int n, Part &p, hipStream_t s);
+hipError_t launch_source25(const double *phi, const double *M, double rho_bar, double xi_m, double v_m, double *t,
+                           int n, Part &p, hipStream_t s);
+hipError_t launch_smooth25(const double *f, double *out, int n, double c0, double sub, hipStream_t s);
 // partial K=1 (max): max_a |D_c f|
 hipError_t launch_max_shift(const double *f, int n, Part &p, hipStream_t s);
 // partial K=ntrial (sum): nodes where I + Hess(phi + 2^-j dphi) is not PD, j = j0..j0+ntrial-1;

@@ -420,6 +420,36 @@ hipError_t prolong_level(T *u, const T *e, int n, hipStream_t s, int variant = 0
     return launch_prolong_add<T>(u, e, n, s);
 }
 
+// The outer step's per-node passes (deformed-mesh mass, source, smoothing):
+// from 256^3 on edges that are multiples of 64 the stencil field streams
+// through LDS; otherwise per-node gathers.  Both give the same node values;
+// the sums are grouped differently.  variant: 0 = that choice, 1 = gather,
+// 2 = streaming.
+bool use_outer_stream(int n, int variant = 0)
+{
+    return variant == 2 || (variant == 0 && n >= 256 && outer25_supported(n));
+}
+
+hipError_t meshmass_pass(const double *phi, const double *m, double *M, int n, Part &p, hipStream_t s,
+                         int variant = 0)
+{
+    if (use_outer_stream(n, variant)) return launch_meshmass25(phi, m, M, n, p, s);
+    return launch_meshmass(phi, m, M, n, p, s);
+}
+
+hipError_t source_pass(const double *phi, const double *M, double rho_bar, double xi_m, double v_m, double *t, int n,
+                       Part &p, hipStream_t s, int variant = 0)
+{
+    if (use_outer_stream(n, variant)) return launch_source25(phi, M, rho_bar, xi_m, v_m, t, n, p, s);
+    return launch_source(phi, M, rho_bar, xi_m, v_m, t, n, p, s);
+}
+
+hipError_t smooth_pass(const double *f, double *out, int n, double c0, double sub, hipStream_t s, int variant = 0)
+{
+    if (use_outer_stream(n, variant)) return launch_smooth25(f, out, n, c0, sub, s);
+    return launch_smooth(f, out, n, c0, sub, s);
+}
+
 // r = b - A u on the fine level in FP64, its squared norm, and optionally r
 // in FP32 (the mixed preconditioner's input).
 hipError_t residual_norm(recon_ctx *ctx, const double *u, const double *a, const double *b, double *r, float *r32,
@@ -757,13 +787,13 @@ int mass_state(recon_ctx *ctx, double *rho_bar, double *rms, double *mean_t, boo
         TRY(deposit_particles(ctx));
         HIPCHK(launch_sum(ctx->M, ctx->n3, ctx->part, ctx->stream));
     } else if (gather) {
-        HIPCHK(launch_meshmass(ctx->phi, ctx->m, ctx->M, ctx->n, ctx->part, ctx->stream));
+        HIPCHK(meshmass_pass(ctx->phi, ctx->m, ctx->M, ctx->n, ctx->part, ctx->stream));
     } else {
         HIPCHK(launch_sum(ctx->M, ctx->n3, ctx->part, ctx->stream));
     }
     TRY(fetch_sum(ctx, v));
     *rho_bar = v[0] / (double)ctx->n3;
-    HIPCHK(launch_source(ctx->phi, ctx->M, *rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part,
+    HIPCHK(source_pass(ctx->phi, ctx->M, *rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part,
                          ctx->stream));
     TRY(fetch_sum(ctx, v));
     *rms = std::sqrt(v[0] / (double)ctx->n3);
@@ -804,7 +834,7 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         st->kappa[it] = rho_bar;
         if (!std::isfinite(rms)) return fail(ctx, RECON_E_NO_CONVERGENCE, "non-finite mass deviation");
         if (rms <= c.outer_tol) break;
-        HIPCHK(launch_smooth(ctx->t, ctx->b, ctx->n, c.smooth_center, mean_t, ctx->stream));
+        HIPCHK(smooth_pass(ctx->t, ctx->b, ctx->n, c.smooth_center, mean_t, ctx->stream));
         // the exact-Jacobian solve preconditions with the x ~ xi V-cycle of
         // the mean diagonal of K = M e^-1
         if (full) HIPCHK(launch_mass_tensor(ctx->phi, ctx->M, K, ctx->n, ctx->stream));
@@ -815,7 +845,7 @@ int forward(recon_ctx *ctx, double box, double tol, double *phi_out, double *del
         st->vcycles[it] = cyc;
         st->vcycles_total += cyc;
         st->rel_residual[it] = rel;
-        HIPCHK(launch_smooth(ctx->u, ctx->dphi, ctx->n, c.smooth_center, 0.0, ctx->stream));
+        HIPCHK(smooth_pass(ctx->u, ctx->dphi, ctx->n, c.smooth_center, 0.0, ctx->stream));
         if (carry && full) HIPCHK(launch_full_apply(K, ctx->dphi, D, ctx->n, ctx->stream));
         else if (carry) HIPCHK(launch_mass_change(ctx->phi, ctx->M, ctx->dphi, K, D, ctx->n, ctx->stream));
         double alpha = 0.0;
@@ -896,7 +926,7 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad, c
         for (int q = 0; q < s; ++q) {
             const double *u_q = tape_u(q);
             if (!u_q) return fail(ctx, RECON_E_HIP, "tape widening launch failed");
-            HIPCHK(launch_smooth(u_q, ctx->dphi, n, c.smooth_center, 0.0, ctx->stream));
+            HIPCHK(smooth_pass(u_q, ctx->dphi, n, c.smooth_center, 0.0, ctx->stream));
             HIPCHK(launch_axpy(phi, ctx->dphi, ctx->tape_alpha[q], n3, ctx->stream));
         }
         if (gpos) {
@@ -910,7 +940,7 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad, c
             HIPCHK(launch_deposit_xi(ctx->xi, np, n, ctx->M, ctx->stream));
             HIPCHK(launch_sum(ctx->M, n3, ctx->part, ctx->stream));
         } else {
-            HIPCHK(launch_meshmass(phi, ctx->m, ctx->M, n, ctx->part, ctx->stream));
+            HIPCHK(meshmass_pass(phi, ctx->m, ctx->M, n, ctx->part, ctx->stream));
         }
         TRY(fetch_sum(ctx, v));
         const double rho_bar = v[0] / (double)n3;
@@ -932,7 +962,7 @@ int backward(recon_ctx *ctx, const double *gd, const double *gp, double *grad, c
         // b = S t - mean:  tbar = S (lambda - mean lambda)
         HIPCHK(launch_sum(lam, n3, ctx->part, ctx->stream));
         TRY(fetch_sum(ctx, v));
-        HIPCHK(launch_smooth(lam, tbar, n, c.smooth_center, v[0] / (double)n3, ctx->stream));
+        HIPCHK(smooth_pass(lam, tbar, n, c.smooth_center, v[0] / (double)n3, ctx->stream));
         // source, then Sigma = mean(M) - M
         HIPCHK(launch_source_adj(phi, ctx->M, rho_bar, tbar, c.xi_m, c.v_m, Mbar, hb, n, ctx->part, ctx->stream));
         TRY(fetch_sum(ctx, v));
@@ -1310,36 +1340,48 @@ int recon_stage_cic(recon_ctx *ctx, const float *pos, long long np, double box, 
     return RECON_OK;
 }
 
-int recon_stage_meshmass(recon_ctx *ctx, const double *phi, const double *m, double *M)
+static int outer_variant_ok(recon_ctx *ctx, int variant)
+{
+    if (variant < 0 || variant > 2) return fail(ctx, RECON_E_ARG, "bad variant");
+    if (variant == 2 && !outer25_supported(ctx->n))
+        return fail(ctx, RECON_E_ARG, "the streaming outer-step passes need an edge that is a multiple of 64");
+    return RECON_OK;
+}
+
+int recon_stage_meshmass(recon_ctx *ctx, const double *phi, const double *m, double *M, int variant)
 {
     TRY(check_ctx(ctx));
     if (!phi || !m || !M) return fail(ctx, RECON_E_ARG, "null array");
-    HIPCHK(launch_meshmass(phi, m, M, ctx->n, ctx->part, ctx->stream));
+    TRY(outer_variant_ok(ctx, variant));
+    HIPCHK(meshmass_pass(phi, m, M, ctx->n, ctx->part, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }
 
-int recon_stage_source(recon_ctx *ctx, const double *phi, const double *M, double *b, double *rms_sigma)
+int recon_stage_source(recon_ctx *ctx, const double *phi, const double *M, double *b, double *rms_sigma, int variant)
 {
     TRY(check_ctx(ctx));
     if (!phi || !M || !b) return fail(ctx, RECON_E_ARG, "null array");
+    TRY(outer_variant_ok(ctx, variant));
     double v[2];
     HIPCHK(launch_sum(M, ctx->n3, ctx->part, ctx->stream));
     TRY(fetch_sum(ctx, v));
     const double rho_bar = v[0] / (double)ctx->n3;
-    HIPCHK(launch_source(phi, M, rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part, ctx->stream));
+    HIPCHK(source_pass(phi, M, rho_bar, ctx->cfg.xi_m, ctx->cfg.v_m, ctx->t, ctx->n, ctx->part, ctx->stream,
+                       variant));
     TRY(fetch_sum(ctx, v));
     if (rms_sigma) *rms_sigma = std::sqrt(v[0] / (double)ctx->n3);
-    HIPCHK(launch_smooth(ctx->t, b, ctx->n, ctx->cfg.smooth_center, v[1] / (double)ctx->n3, ctx->stream));
+    HIPCHK(smooth_pass(ctx->t, b, ctx->n, ctx->cfg.smooth_center, v[1] / (double)ctx->n3, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }
 
-int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out)
+int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out, int variant)
 {
     TRY(check_ctx(ctx));
     if (!f || !out) return fail(ctx, RECON_E_ARG, "null array");
-    HIPCHK(launch_smooth(f, out, ctx->n, ctx->cfg.smooth_center, 0.0, ctx->stream));
+    TRY(outer_variant_ok(ctx, variant));
+    HIPCHK(smooth_pass(f, out, ctx->n, ctx->cfg.smooth_center, 0.0, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
 }

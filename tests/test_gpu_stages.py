@@ -76,6 +76,55 @@ def test_normalize_meshmass_source_smooth(torch_cuda, orc, n, cn):
     assert rel(host(rec.smooth(dev(torch, M_o))), orc.smooth(M_o)) < 1e-15
     d_g = host(rec.delta_r(dev(torch, phi)))
     assert rel(d_g, orc.delta_r(phi)) < 1e-14
+    if n % 64 == 0:
+        _outer_variants_agree(torch, rec, phi, m, M_o)
+    else:
+        with pytest.raises(binding.ReconError):
+            rec.smooth(dev(torch, M_o), variant=2)
+
+
+def _outer_variants_agree(torch, rec, phi, m, M):
+    """The gather and LDS-streaming forms of the outer step's passes give the
+    same node values bit for bit; only sums are grouped differently."""
+    Ms = [rec.meshmass(dev(torch, phi), dev(torch, m), variant=v) for v in (1, 2)]
+    assert torch.equal(Ms[0], Ms[1])
+    src = [rec.source(dev(torch, phi), dev(torch, M), variant=v) for v in (1, 2)]
+    assert rel(host(src[0][0]), host(src[1][0])) < 1e-15
+    assert abs(src[0][1] - src[1][1]) <= 1e-14 * src[0][1]
+    sm = [rec.smooth(dev(torch, M), variant=v) for v in (1, 2)]
+    assert torch.equal(sm[0], sm[1])
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_outer_passes_streamed(torch_cuda, orc, n):
+    """The deformed-mesh mass, the limited source and the smoothing (App. A)
+    in their LDS-streaming form (the solver's from 256^3; several tiles and
+    i-chunks) against the oracle, on a strongly deformed mesh: displacements
+    of up to 13 cells and cells compressed below xi_m, where the compression
+    limiter acts.  Node values equal the gather kernels' bit for bit."""
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    rng = np.random.default_rng(700 + n)
+    x = np.arange(n) * (2 * np.pi / n)
+    X = np.meshgrid(x, x, x, indexing="ij")
+    amp = 0.93 / (2 * np.sin(3 * np.pi / n)) ** 2
+    # triad entries 1 - 0.93 cos (x), at least 0.5 (y, z): positive definite,
+    # with lambda_0 down to about 0.07 < xi_m
+    phi = amp * (np.cos(3 * X[0]) + 0.15 * np.cos(5 * X[1] + 1.0) + 0.5 * np.cos(2 * X[2] + 2.0))
+    phi += 0.002 * rng.normal(size=phi.shape)
+    m = orc.normalize(inputs.lognormal_density(n, 1000.0, 1.0, 70 + n))
+    rec = binding.Recon(n, binding.Config())
+    M_g = host(rec.meshmass(dev(torch, phi), dev(torch, m), variant=2))
+    M_o = orc.meshmass(phi, m)
+    assert rel(M_g, M_o) < 1e-13
+    t_o, _ = orc.source_terms(phi, M_o)
+    assert (t_o > M_o.mean() - M_o + 1e-3).any()  # the compression limiter acts somewhere
+    assert orc.count_not_pd(phi) == 0
+    b_g, rms_g = rec.source(dev(torch, phi), dev(torch, M_o), variant=2)
+    assert rel(host(b_g), orc.source(phi, M_o)) < 1e-11
+    assert abs(rms_g - np.sqrt(np.mean((M_o.mean() - M_o) ** 2))) < 1e-12 * rms_g
+    assert rel(host(rec.smooth(dev(torch, M_o), variant=2)), orc.smooth(M_o)) < 1e-15
+    _outer_variants_agree(torch, rec, phi, m, M_o)
 
 
 @pytest.mark.parametrize("n,cn", SIZES + [(128, 8), (256, 8)])
