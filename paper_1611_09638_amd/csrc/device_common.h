@@ -150,6 +150,19 @@ __device__ double lambda_min_sym(const Sym3 &e)
     return q + 2.0 * p * cos(ang + 2.0943951023931954923);  // + 2 pi / 3
 }
 
+// The compression limiter C = 4 max(0, xi_m / lambda_0 - 1)^2 (App. A).  It
+// vanishes wherever lambda_0 >= xi_m, that is wherever e - xi_m I is positive
+// semidefinite; where Sylvester's leading minors of e - xi_m I are all
+// positive the eigenvalue is not formed (most nodes of a mildly deformed
+// mesh, and the trigonometric closed form is the costliest step of a node).
+__device__ __forceinline__ double compression_limiter(const Sym3 &e, double xi_m)
+{
+    const Sym3 d{e.xx - xi_m, e.yy - xi_m, e.zz - xi_m, e.xy, e.xz, e.yz};
+    if (d.xx > 0.0 && d.xx * d.yy - d.xy * d.xy > 0.0 && det_sym(d) > 0.0) return 0.0;
+    const double r = xi_m / lambda_min_sym(e) - 1.0;
+    return r > 0.0 ? 4.0 * r * r : 0.0;
+}
+
 // 19-point neighbourhood of a node (centre, 6 faces, 12 edges), periodic.
 struct Stencil19 {
     double c, xp, xm, yp, ym, zp, zm;

@@ -157,10 +157,8 @@ __global__ void __launch_bounds__(NT) k_outer25(const double *__restrict__ f, in
                     A.out[g] = Mv;
                     v[0] += Mv;
                 } else {
-                    const double lam0 = lambda_min_sym(e);
                     const double sigma = A.rho_bar - A.M[g];
-                    const double rr = A.xi_m / lam0 - 1.0;
-                    const double C = rr > 0.0 ? 4.0 * rr * rr : 0.0;
+                    const double C = compression_limiter(e, A.xi_m);
                     const double E = gdet > A.v_m ? -2.0 * fabs(sigma) : 0.0;
                     const double tv = sigma + C + E;
                     A.out[g] = tv;

@@ -8,6 +8,7 @@
 // Lattice: n^3, C-order [i][j][k] (k fastest), periodic, grid units.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "device_common.h"
@@ -232,11 +233,9 @@ __global__ void k_source(const double *__restrict__ phi, const double *__restric
             load19(phi, i, j, k, n, s);
             const Sym3 e = triad19(s);
             const double g = det_sym(e);
-            const double lam0 = lambda_min_sym(e);
             const size_t p = lin(i, j, k, n);
             const double sigma = rho_bar - M[p];
-            const double r = xi_m / lam0 - 1.0;
-            const double C = r > 0.0 ? 4.0 * r * r : 0.0;
+            const double C = compression_limiter(e, xi_m);
             const double E = g > v_m ? -2.0 * fabs(sigma) : 0.0;
             const double tv = sigma + C + E;
             t[p] = tv;
@@ -897,20 +896,19 @@ __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, cons
         }
     }
     // two consecutive elements per thread (16-byte accesses; every field is
-    // 256-byte aligned), the last element of an odd count by thread 0
+    // 256-byte aligned), the last element of an odd count by thread 0.  A
+    // thread visits its pairs p, p + stride, ... in order; the loads of eight
+    // of them are issued together, which keeps the same order of the sum.
     double v[1] = {0.0};
-    const long h = n3 >> 1;
-    for (long p = blockIdx.x * 256L + threadIdx.x; p < h; p += 256L * gridDim.x) {
-        const long e = 2 * p;
+    const long h = n3 >> 1, stride = 256L * gridDim.x;
+    auto pair = [&](long e, const v2d rr, const v2d qq) {
         if (U) {
-            const double2 pp = *reinterpret_cast<const double2 *>(pv + e);
-            double2 uu = *reinterpret_cast<double2 *>(u + e);
+            const v2d pp = *reinterpret_cast<const v2d *>(pv + e);
+            v2d uu = *reinterpret_cast<v2d *>(u + e);
             uu.x += alpha * pp.x;
             uu.y += alpha * pp.y;
-            *reinterpret_cast<double2 *>(u + e) = uu;
+            *reinterpret_cast<v2d *>(u + e) = uu;
         }
-        const double2 rr = *reinterpret_cast<const double2 *>(r + e);
-        const double2 qq = *reinterpret_cast<const double2 *>(q + e);
         const double r0 = rr.x - alpha * qq.x, r1 = rr.y - alpha * qq.y;
         v2d rv;
         rv.x = r0;
@@ -924,7 +922,21 @@ __global__ void k_update_ur(double *__restrict__ u, double *__restrict__ r, cons
         }
         v[0] += r0 * r0;
         v[0] += r1 * r1;
+    };
+    constexpr int UN = 8;
+    long p = blockIdx.x * 256L + threadIdx.x;
+    for (; p + (UN - 1) * stride < h; p += UN * stride) {
+        v2d rr[UN], qq[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+            rr[k] = *reinterpret_cast<const v2d *>(r + 2 * (p + k * stride));
+            qq[k] = *reinterpret_cast<const v2d *>(q + 2 * (p + k * stride));
+        }
+#pragma unroll
+        for (int k = 0; k < UN; ++k) pair(2 * (p + k * stride), rr[k], qq[k]);
     }
+    for (; p < h; p += stride)
+        pair(2 * p, *reinterpret_cast<const v2d *>(r + 2 * p), *reinterpret_cast<const v2d *>(q + 2 * p));
     if ((n3 & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         const long e = n3 - 1;
         if (U) u[e] += alpha * pv[e];
@@ -944,7 +956,9 @@ hipError_t launch_update_ur(double *u, double *r, const double *pv, const double
          reinterpret_cast<uintptr_t>(pv)) % 16 ||
         reinterpret_cast<uintptr_t>(r32) % 8)
         return hipErrorInvalidValue;
-    int nb = flat_blocks((n3 + 1) / 2);
+    // up to 16384 workgroups (measured 755 against 813 us at 512^3 with 8192)
+    const long pairs = (n3 + 1) / 2;
+    const int nb = (int)std::min<long>((pairs + 255) / 256, 16384);
     if (u) k_update_ur<true><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part, ks);
     else k_update_ur<false><<<nb, 256, 0, s>>>(u, r, pv, q, alpha, r32, n3, p.part, ks);
     p.blocks = nb;
