@@ -24,7 +24,7 @@ __device__ __forceinline__ void lds_barrier()
 // ---------------------------------------------- fused two-colour RB-GS sweep
 //
 // u_out = one full red-black sweep of u_in (colour `first` relaxed first),
-// streaming every field through HBM once.  A workgroup owns a TJ x 64 tile of
+// streaming every field through HBM once.  A workgroup owns a TJ x TK tile of
 // (j, k) and a chunk of CI consecutive i-planes.  Planes of u_in and a enter a
 // 4-plane LDS ring with a 2-cell halo in j and k, two planes ahead of use
 // (register-staged prefetch); b is fetched straight into registers at each
@@ -486,8 +486,11 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
 //     6-plane ring (127 KB, one per CU; half the j-halo rows per node);
 //   FP64: 16 x 64 tiles, 512 threads (one per CU), 4-plane ring below 512^3,
 //     6-plane ring from 512^3 (131 KB).
-// Launches keep at least 512 workgroups, each streaming the longest i-chunk
-// that allows (every chunk re-reads four planes).
+// These launches keep at least 512 workgroups, each streaming the longest
+// i-chunk that allows (every chunk re-reads four planes), and store their
+// planes nontemporally.  Levels below 256^3 (L2-resident) take narrow tiles
+// with short chunks instead: 8 x 32 tiles of 256 threads with 8-plane chunks
+// from 128^3 and 4-plane chunks at 64^3, 8 x 16 tiles of 128 threads below.
 // FOLD = 0: a shape only the zero-start sweep uses, built without the
 // folded coarse correction.  CI > 0 fixes the i-chunk length (the small
 // levels, where a launch costs more than its bytes and short chunks keep
