@@ -37,11 +37,15 @@ struct S25 {
     static constexpr int RS = TJ * TK / NT;  // nodes per thread per plane
 };
 
+// LDS-only barrier.  The scheduling barrier keeps the compiler from moving
+// arithmetic on staged registers across it: that would make a wave wait for
+// loads issued just before the barrier instead of two planes earlier.
 __device__ __forceinline__ void lds_fence_barrier()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // MODE S25_RESID:     out = b - scale A x                    (x = xin, type T)
@@ -108,31 +112,38 @@ __global__ void __launch_bounds__(NT)
         gN[r] = (j0 + row) * n + (k0 + col);
     }
 
-    // operand value at global offset g of the plane starting at base
-    auto operand = [&](size_t g) -> T {
+    // the operand from its loaded parts: x itself, or the direction
+    // z + beta p_old (z alone on the first step)
+    auto combine = [&](Z zv, P xv) -> T {
         if constexpr (MODE == S25_DIRECTION) {
-            const T zv = (T)zg[g];
             T x;
             if constexpr (FIRST)
-                x = zv;
+                x = (T)zv;
             else
-                x = zv + beta * (T)xin[g];
+                x = (T)zv + beta * (T)xv;
             if constexpr (sizeof(P) < sizeof(T)) x = (T)(P)x;
             return x;
         } else {
-            return xin[g];
+            return xv;
         }
     };
+    constexpr bool HAS_Z = MODE == S25_DIRECTION, HAS_X = !(MODE == S25_DIRECTION && FIRST);
+    auto operand = [&](size_t g) -> T { return combine(HAS_Z ? zg[g] : Z(0), HAS_X ? xin[g] : P(0)); };
 
-    // register stage: halo plane p of x and a, and b (or u and p_old) at this
-    // thread's nodes of plane p - 2
-    T rx[2][LU], ra[2][LU], rb[2][HAS_B ? RS : 1];
-    double ru[2][UPD ? RS : 1], rq[2][UPD ? RS : 1];
+    // register stage, as loaded: halo plane p of x (or of z and p_old) and a,
+    // and b (or u and p_old) at this thread's nodes of plane p - 2.  The
+    // operand is formed when the plane is deposited, so a wave waits for
+    // these loads only there, two planes after issuing them.
+    Z rz[2][HAS_Z ? LU : 1];
+    P rx[2][HAS_X ? LU : 1], rq[2][UPD ? RS : 1];
+    T ra[2][LU], rb[2][HAS_B ? RS : 1];
+    double ru[2][UPD ? RS : 1];
     auto fetch = [&](int set, int p) {
         const size_t base = (size_t)wrapc(p, n) * n2;
 #pragma unroll
         for (int r = 0; r < LU; ++r) {
-            rx[set][r] = operand(base + offL[r]);
+            if constexpr (HAS_Z) rz[set][r] = zg[base + offL[r]];
+            if constexpr (HAS_X) rx[set][r] = xin[base + offL[r]];
             ra[set][r] = ag[base + offL[r]];
         }
         if constexpr (HAS_B) {
@@ -145,14 +156,14 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
             for (int r = 0; r < RS; ++r) {
                 ru[set][r] = ug[bb + gN[r]];
-                rq[set][r] = (double)xin[bb + gN[r]];
+                rq[set][r] = xin[bb + gN[r]];
             }
         }
     };
     auto deposit = [&](int set, int slot) {
 #pragma unroll
         for (int r = 0; r < LU; ++r) {
-            sX[slot][tid + r * NT] = rx[set][r];
+            sX[slot][tid + r * NT] = combine(HAS_Z ? rz[set][r] : Z(0), HAS_X ? rx[set][r] : P(0));
             sA[slot][tid + r * NT] = (T)0.5 * ra[set][r];
         }
     };
@@ -196,7 +207,7 @@ __global__ void __launch_bounds__(NT)
                 __builtin_nontemporal_store((P)xc, &pout[g]);
                 __builtin_nontemporal_store(acc, &out[g]);
                 v += xc * acc;
-                if constexpr (UPD) __builtin_nontemporal_store(ru[set][r] + alpha_u * rq[set][r], &ug[g]);
+                if constexpr (UPD) __builtin_nontemporal_store(ru[set][r] + alpha_u * (double)rq[set][r], &ug[g]);
             }
             xd[r] = xc;
             hd[r] = hc;
