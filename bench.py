@@ -234,6 +234,125 @@ def particle_bench(torch, binding, inputs, args):
     print(json.dumps(out), flush=True)
 
 
+# The workloads of the paper-shaped configurations: name, workload, solver
+# settings, precisions, and whether the reverse mode is timed as well.  The
+# 128^3 adjoint case uses the tolerance its oracle gradient was computed with.
+CONFIG_RUNS = [
+    ("cfg1", "zeldovich32", dict(coarse_n=8, max_outer=10), ("fp64", "mixed"), False),
+    ("cfg2", "lognormal256", {}, ("fp64", "mixed"), False),
+    ("cfg3", "lognormal512", {}, ("fp64", "mixed"), False),
+    ("cfg4", "lognormal128", dict(tol=1e-13, max_vcycles=400), ("fp64",), True),
+]
+
+
+def _loss_window(torch, n, box, dev, R=10.0):
+    """exp(-k^2 R^2) on the FFT grid: the filtered-power loss of the 128^3
+    adjoint case, whose gradient with respect to delta_r is
+    2 n^3 Re(ifftn(W fftn(delta_r)))."""
+    k = 2 * np.pi * np.fft.fftfreq(n, box / n)
+    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
+    return torch.from_numpy(np.exp(-k2 * R ** 2)).to(dev)
+
+
+def configs_bench(torch, binding, inputs, args):
+    """GPU wall time of every paper-shaped configuration that fits the
+    oracle's reach (32^3 particles, 256^3, 512^3 and 128^3 densities): the
+    median of --steps solves after --warmup, inputs resident in HBM; for the
+    128^3 case also the reverse mode over the recorded tape.  The 1024^3
+    particle case is timed by its own test (its inputs take minutes to
+    generate).  Beside each, the oracle's whole solve as recorded with its
+    golden values, and for the 32^3 case the oracle timed here, on all host
+    threads and on one."""
+    dev = torch.device("cuda:0")
+    out = {"configs": [], "steps": args.steps, "warmup": args.warmup}
+    prec = {"fp64": binding.FP64, "mixed": binding.MIXED}
+    for name, wl, extra, precs, adjoint in CONFIG_RUNS:
+        w = inputs.WORKLOADS[wl]
+        n, box = w["n"], w["box"]
+        kind, arr, _, _ = inputs.make_workload(wl)
+        x = torch.from_numpy(arr).to(dev)
+        row = {"name": name, "workload": wl, "n": n, "box": box, "input": kind, "settings": extra, "gpu": {}}
+        for pn in precs:
+            rec = binding.Recon(n, binding.Config(precision=prec[pn], record_tape=1 if adjoint else 0, **extra),
+                                device=dev)
+            solve = rec.solve_particles if kind == "particles" else rec.solve
+            for _ in range(args.warmup):
+                solve(x, box, want_phi=False)
+            walls, bw = [], []
+            gd = None
+            for _ in range(args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, d, st = solve(x, box, want_phi=False)
+                torch.cuda.synchronize()
+                walls.append(time.perf_counter() - t0)
+                if adjoint:
+                    if gd is None:
+                        gd = (2.0 * n ** 3 * torch.fft.ifftn(_loss_window(torch, n, box, dev) *
+                                                              torch.fft.fftn(d)).real).contiguous()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    rec.backward(gd)
+                    torch.cuda.synchronize()
+                    bw.append(time.perf_counter() - t0)
+            r = {"wall_s": round(float(np.median(walls)), 4), "vcycles_total": st["vcycles_total"],
+                 "outer_steps": st["outer_steps"]}
+            if adjoint:
+                r["backward_s"] = round(float(np.median(bw)), 4)
+            row["gpu"][pn] = r
+            log("%s %s %s: %s" % (name, wl, pn, r))
+            del rec
+            torch.cuda.empty_cache()
+        gold = oracle_samples(wl)
+        if gold is not None and "oracle_seconds" in gold:
+            row["oracle_recorded"] = {"seconds": gold["oracle_seconds"], "threads": gold.get("threads"),
+                                      "source": "tests/golden/%s_oracle_forward.json" % wl}
+        out["configs"].append(row)
+        del x
+    if not args.skip_cpu:
+        out["oracle_cfg1"] = configs_cpu_baseline(inputs, ("cfg1",))["cfg1"]
+    print(json.dumps(out), flush=True)
+
+
+def configs_cpu_baseline(inputs, names):
+    """The oracle (FP64 C with OpenMP) timed on this host for the named
+    configurations: its whole forward solve, and for the 128^3 adjoint case
+    the reverse mode too, on all host threads (OMP_NUM_THREADS, else every
+    core); the 32^3 case also on one thread, in a child process that sets
+    OMP_NUM_THREADS=1 before the oracle library is loaded."""
+    import subprocess
+    import oracle
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    res = {}
+    for name, wl, extra, _, adjoint in CONFIG_RUNS:
+        if name not in names:
+            continue
+        w = inputs.WORKLOADS[wl]
+        n, box = w["n"], w["box"]
+        kind, arr, _, _ = inputs.make_workload(wl)
+        rho = oracle.cic_particles(arr, n, box) if kind == "particles" else arr
+        cfg = oracle.Config(record_tape=1 if adjoint else 0, **extra)
+        t0 = time.perf_counter()
+        _, d, st = oracle.solve(rho, box, cfg)
+        r = {"threads": threads, "forward_s": round(time.perf_counter() - t0, 3), "vcycles_total": sum(st["vcycles"])}
+        if adjoint:
+            k = 2 * np.pi * np.fft.fftfreq(n, box / n)
+            k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
+            gd = 2.0 * n ** 3 * np.real(np.fft.ifftn(np.exp(-k2 * 100.0) * np.fft.fftn(d)))
+            t0 = time.perf_counter()
+            oracle.backward(gd, None, box, cfg)
+            r["backward_s"] = round(time.perf_counter() - t0, 3)
+        if name == "cfg1" and threads > 1:
+            env = dict(os.environ, OMP_NUM_THREADS="1")
+            cp = subprocess.run([sys.executable, os.path.abspath(__file__), "--configs-oracle", "cfg1"], env=env,
+                                capture_output=True, text=True, check=True)
+            r["one_thread"] = json.loads(cp.stdout.strip().splitlines()[-1])["cfg1"]
+        res[name] = r
+        log("oracle %s: %s" % (name, r))
+    return res
+
+
 def quality_bench(torch, binding, inputs):
     """Sec. III on stand-in data: Zel'dovich inputs at 256^3 (600 Mpc/h, cells of
     2.34 Mpc/h) with the linear density -div Psi known exactly.  The cross-
@@ -403,6 +522,11 @@ def main():
                          "grid, on 512^3 Zel'dovich particles, mixed precision")
     ap.add_argument("--full-operator", action="store_true",
                     help="the exact-Jacobian operator in the linear solve against x ~ xi on --workload (mixed)")
+    ap.add_argument("--configs", action="store_true",
+                    help="GPU wall time of the paper-shaped configurations (32^3 particles, 256^3, 512^3, 128^3 "
+                         "with its reverse mode) beside the oracle's recorded and measured times")
+    ap.add_argument("--configs-oracle", nargs="+", metavar="CFG",
+                    help="the oracle alone on this host's cores for the named configurations (no GPU used)")
     ap.add_argument("--mass-update", action="store_true",
                     help="the paper's mass update (App. A) against the per-step CIC gather on lognormal512_mild, "
                          "mixed precision, and the bandwidth of its two kernels")
@@ -411,6 +535,11 @@ def main():
         print("bench.py runs on exactly one GPU (one process per GPU); --gpus %d is not supported: "
               "the multi-GPU slab decomposition is not built" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.configs_oracle:
+        from paper_1611_09638_amd import inputs
+        print(json.dumps(configs_cpu_baseline(inputs, tuple(args.configs_oracle))), flush=True)
+        return
 
     import torch
 
@@ -455,6 +584,9 @@ def main():
         return
     if args.quality:
         quality_bench(torch, binding, inputs)
+        return
+    if args.configs:
+        configs_bench(torch, binding, inputs, args)
         return
     if args.particle_deposit:
         particle_bench(torch, binding, inputs, args)
