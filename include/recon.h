@@ -224,7 +224,12 @@ const char *recon_last_error(const recon_ctx *ctx);
  * on the context's stream, using its workspace for reductions and multigrid
  * levels.  The grid edge is the context's n unless stated.  dtype: 0 = FP64
  * arrays, 1 = FP32 arrays.  They exist so each kernel can be checked and
- * timed on its own.
+ * timed on its own.  An output array must not overlap an input array or
+ * another output (RECON_E_ARG), except where a function updates an array in
+ * place (u of recon_stage_rbgs, recon_stage_prolong_add and
+ * recon_stage_prolong_sweep, xi of recon_stage_invert_map); normalize and
+ * source may also write over their inputs.  Caller arrays must not lie in
+ * the context's workspace.
  * ------------------------------------------------------------------------ */
 
 /* m = rho / mean(rho) after checking rho (App. A input; Sec. III gridding). */

@@ -1323,6 +1323,16 @@ int recon_backward_particles(recon_ctx *ctx, const float *pos, long long np, con
 
 // ------------------------------------------------------------- stage calls
 
+// True when the byte ranges [p, p + np) and [q, q + nq) share a byte: an
+// output written while other lanes still read an overlapping input would
+// race, so the stage entry points reject such calls.
+static bool overlap(const void *p, size_t np, const void *q, size_t nq)
+{
+    if (!p || !q) return false;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p), b = reinterpret_cast<uintptr_t>(q);
+    return a < b + nq && b < a + np;
+}
+
 int recon_stage_normalize(recon_ctx *ctx, const double *rho, double *m)
 {
     TRY(check_ctx(ctx));
@@ -1334,6 +1344,7 @@ int recon_stage_cic(recon_ctx *ctx, const float *pos, long long np, double box, 
 {
     TRY(check_ctx(ctx));
     if (!pos || !rho || np < 0 || !(box > 0.0)) return fail(ctx, RECON_E_ARG, "bad particle arguments");
+    if (overlap(rho, ctx->n3 * 8, pos, (size_t)np * 12)) return fail(ctx, RECON_E_ARG, "rho overlaps pos");
     HIPCHK(launch_zero(rho, ctx->n3 * 8, ctx->stream));
     if (np > 0) HIPCHK(launch_cic(pos, np, ctx->n, box, rho, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1352,6 +1363,8 @@ int recon_stage_meshmass(recon_ctx *ctx, const double *phi, const double *m, dou
 {
     TRY(check_ctx(ctx));
     if (!phi || !m || !M) return fail(ctx, RECON_E_ARG, "null array");
+    const size_t F = ctx->n3 * 8;
+    if (overlap(M, F, phi, F) || overlap(M, F, m, F)) return fail(ctx, RECON_E_ARG, "M overlaps phi or m");
     TRY(outer_variant_ok(ctx, variant));
     HIPCHK(meshmass_pass(phi, m, M, ctx->n, ctx->part, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1380,6 +1393,7 @@ int recon_stage_smooth(recon_ctx *ctx, const double *f, double *out, int variant
 {
     TRY(check_ctx(ctx));
     if (!f || !out) return fail(ctx, RECON_E_ARG, "null array");
+    if (overlap(out, ctx->n3 * 8, f, ctx->n3 * 8)) return fail(ctx, RECON_E_ARG, "out overlaps f");
     TRY(outer_variant_ok(ctx, variant));
     HIPCHK(smooth_pass(f, out, ctx->n, ctx->cfg.smooth_center, 0.0, ctx->stream, variant));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1397,6 +1411,8 @@ int recon_stage_apply(recon_ctx *ctx, const double *u, const double *a, int nl, 
 {
     TRY(check_ctx(ctx));
     if (!u || !a || !out || !level_ok(ctx, nl)) return fail(ctx, RECON_E_ARG, "bad arguments");
+    const size_t L = (size_t)nl * nl * nl * 8;
+    if (overlap(out, L, u, L) || overlap(out, L, a, L)) return fail(ctx, RECON_E_ARG, "out overlaps u or a");
     HIPCHK(launch_apply<double>(u, a, out, nl, scale, ctx->cfg.a_min, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
@@ -1408,6 +1424,11 @@ int recon_stage_residual(recon_ctx *ctx, const void *u, const void *a, const voi
     TRY(check_ctx(ctx));
     if (!u || !a || !b || !r || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || variant < 0 || variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    {
+        const size_t L = (size_t)nl * nl * nl * (dtype ? 4 : 8);
+        if (overlap(r, L, u, L) || overlap(r, L, a, L) || overlap(r, L, b, L))
+            return fail(ctx, RECON_E_ARG, "r overlaps u, a or b");
+    }
     if (variant == 2 && !(dtype == 0 ? stencil25_supported<double>(nl) : stencil25_supported<float>(nl)))
         return fail(ctx, RECON_E_ARG, "the streaming residual needs an edge that is a multiple of 128");
     if (dtype == 0)
@@ -1431,6 +1452,15 @@ int recon_stage_direction(recon_ctx *ctx, const void *z, int z_dtype, const void
         variant > 2 || (p_old && p_old == p_new) || (void *)q == p_new || (p_dtype != 0 && p_dtype != 1) ||
         (u && (first || (const void *)u == p_old || (void *)u == p_new || u == q || u == a || (const void *)u == z)))
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    {
+        const size_t F = (size_t)n3 * 8, Z = (size_t)n3 * (z_dtype ? 4 : 8), P = (size_t)n3 * (p_dtype ? 4 : 8);
+        const void *po = first ? nullptr : p_old;
+        if (overlap(q, F, z, Z) || overlap(q, F, po, P) || overlap(q, F, a, F) || overlap(q, F, p_new, P) ||
+            overlap(p_new, P, z, Z) || overlap(p_new, P, po, P) || overlap(p_new, P, a, F) ||
+            (u && (overlap(u, F, z, Z) || overlap(u, F, po, P) || overlap(u, F, a, F) || overlap(u, F, p_new, P) ||
+                   overlap(u, F, q, F))))
+            return fail(ctx, RECON_E_ARG, "the outputs overlap each other or the inputs");
+    }
     const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n));
     if (stream && !stencil25_supported<double>(n))
         return fail(ctx, RECON_E_ARG, "the streaming direction update needs an edge that is a multiple of 128");
@@ -1468,6 +1498,13 @@ int recon_stage_full_residual(recon_ctx *ctx, const double *phi, const double *M
     const int n = ctx->n;
     if (!phi || !M || !u || !b || !r || !rr || variant < 0 || variant > 2 || r == u || r == b)
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    {
+        const size_t F = ctx->n3 * 8, H = ctx->n3 * 4;
+        if (overlap(r, F, phi, F) || overlap(r, F, M, F) || overlap(r, F, u, F) || overlap(r, F, b, F) ||
+            overlap(r32, H, phi, F) || overlap(r32, H, M, F) || overlap(r32, H, u, F) || overlap(r32, H, b, F) ||
+            overlap(r32, H, r, F))
+            return fail(ctx, RECON_E_ARG, "r or r32 overlaps an input or each other");
+    }
     if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
     const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n) && full25_supported(n));
     if (stream && !full25_supported(n))
@@ -1490,6 +1527,16 @@ int recon_stage_full_direction(recon_ctx *ctx, const double *phi, const double *
         (p_dtype != 0 && p_dtype != 1) ||
         (u && (first || (const void *)u == p_old || (void *)u == p_new || u == q || (const void *)u == z)))
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    {
+        const size_t F = (size_t)n3 * 8, Z = (size_t)n3 * (z_dtype ? 4 : 8), P = (size_t)n3 * (p_dtype ? 4 : 8);
+        const void *po = first ? nullptr : p_old;
+        auto hits = [&](const void *o, size_t no) {
+            return overlap(o, no, z, Z) || overlap(o, no, po, P) || overlap(o, no, phi, F) || overlap(o, no, M, F);
+        };
+        if (hits(q, F) || hits(p_new, P) || overlap(q, F, p_new, P) ||
+            (u && (hits(u, F) || overlap(u, F, p_new, P) || overlap(u, F, q, F))))
+            return fail(ctx, RECON_E_ARG, "the outputs overlap each other or the inputs");
+    }
     if (!ctx->cfg.full_operator) return fail(ctx, RECON_E_ARG, "the context was made without full_operator");
     const bool stream = variant == 2 || (variant == 0 && use_stream<double>(n) && full25_supported(n));
     if (stream && !full25_supported(n))
@@ -1539,6 +1586,10 @@ int recon_stage_rbgs(recon_ctx *ctx, void *u, const void *a, const void *b, int 
     if (!u || !a || !b || !level_ok(ctx, nl) || (dtype != 0 && dtype != 1) || (first != 0 && first != 1) ||
         variant < 0 || variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    {
+        const size_t L = (size_t)nl * nl * nl * (dtype ? 4 : 8);
+        if (overlap(u, L, a, L) || overlap(u, L, b, L)) return fail(ctx, RECON_E_ARG, "u overlaps a or b");
+    }
     const bool can_fuse = dtype == 0 ? rbgs_fused_supported<double>(nl) : rbgs_fused_supported<float>(nl);
     if (variant == 2 && !can_fuse)
         return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 16");
@@ -1586,6 +1637,11 @@ int recon_stage_prolong_sweep(recon_ctx *ctx, void *u, const void *e, const void
     if (!u || !e || !a || !b || !level_ok(ctx, nl) || nl % 2 || (dtype != 0 && dtype != 1) ||
         (first != 0 && first != 1) || (variant != 1 && variant != 2))
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    {
+        const size_t L = (size_t)nl * nl * nl * (dtype ? 4 : 8), C = L / 8;
+        if (overlap(u, L, e, C) || overlap(u, L, a, L) || overlap(u, L, b, L))
+            return fail(ctx, RECON_E_ARG, "u overlaps e, a or b");
+    }
     if (dtype == 0 ? !rbgs_fused_supported<double>(nl) : !rbgs_fused_supported<float>(nl))
         return fail(ctx, RECON_E_ARG, "the fused sweep needs an edge that is a multiple of 16");
     if (dtype == 0)
@@ -1601,6 +1657,8 @@ int recon_stage_restrict(recon_ctx *ctx, const void *f, int nl, void *c, int dty
     if (!f || !c || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1) || variant < 0 ||
         variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (overlap(c, (size_t)nl * nl * nl * (dtype ? 4 : 8) / 8, f, (size_t)nl * nl * nl * (dtype ? 4 : 8)))
+        return fail(ctx, RECON_E_ARG, "c overlaps f");
     if (variant == 2 && !(dtype == 0 ? transfer25_supported<double>(nl) : transfer25_supported<float>(nl)))
         return fail(ctx, RECON_E_ARG, "the streaming transfers need a fine edge that is a multiple of 256");
     if (dtype == 0) HIPCHK(restrict_level<double>((const double *)f, (double *)c, nl, ctx->stream, variant));
@@ -1616,6 +1674,11 @@ int recon_stage_residual_restrict(recon_ctx *ctx, const void *u, const void *a, 
     if (!u || !a || !b || !c || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1) ||
         variant < 0 || variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    {
+        const size_t L = (size_t)nl * nl * nl * (dtype ? 4 : 8), C = L / 8;
+        if (overlap(c, C, u, L) || overlap(c, C, a, L) || overlap(c, C, b, L))
+            return fail(ctx, RECON_E_ARG, "c overlaps u, a or b");
+    }
     if (variant == 2 && !(dtype == 0 ? resrestrict25_supported<double>(nl) : resrestrict25_supported<float>(nl)))
         return fail(ctx, RECON_E_ARG, "the fused residual-restriction needs a coarse edge that is a multiple of 32");
     if (dtype == 0)
@@ -1634,6 +1697,8 @@ int recon_stage_prolong_add(recon_ctx *ctx, void *u, const void *e, int nl, int 
     if (!u || !e || !level_ok(ctx, nl) || nl < 4 || (nl & 1) || (dtype != 0 && dtype != 1) || variant < 0 ||
         variant > 2)
         return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (overlap(u, (size_t)nl * nl * nl * (dtype ? 4 : 8), e, (size_t)nl * nl * nl * (dtype ? 4 : 8) / 8))
+        return fail(ctx, RECON_E_ARG, "u overlaps e");
     if (variant == 2 && !(dtype == 0 ? transfer25_supported<double>(nl) : transfer25_supported<float>(nl)))
         return fail(ctx, RECON_E_ARG, "the streaming transfers need a fine edge that is a multiple of 256");
     if (dtype == 0) HIPCHK(prolong_level<double>((double *)u, (const double *)e, nl, ctx->stream, variant));
@@ -1646,6 +1711,7 @@ int recon_stage_vcycle(recon_ctx *ctx, const void *a, const void *r, void *z, in
 {
     TRY(check_ctx(ctx));
     if (!a || !r || !z || (dtype != 0 && dtype != 1)) return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (overlap(z, ctx->n3 * (dtype ? 4 : 8), r, ctx->n3 * (dtype ? 4 : 8))) return fail(ctx, RECON_E_ARG, "z overlaps r");
     if (dtype == 1 && ctx->cfg.precision != RECON_MIXED)
         return fail(ctx, RECON_E_ARG, "FP32 V-cycle needs a context created with precision RECON_MIXED");
     const long n3 = ctx->n3;
@@ -1723,6 +1789,11 @@ int recon_stage_mass_change(recon_ctx *ctx, const double *phi, const double *M, 
 {
     TRY(check_ctx(ctx));
     if (!phi || !M || !f || !out) return fail(ctx, RECON_E_ARG, "null array");
+    {
+        const size_t F = ctx->n3 * 8;
+        if (overlap(out, F, phi, F) || overlap(out, F, M, F) || overlap(out, F, f, F))
+            return fail(ctx, RECON_E_ARG, "out overlaps phi, M or f");
+    }
     const MassTensor K{ctx->t, ctx->b, ctx->r, ctx->z, ctx->p, ctx->q, nullptr};
     HIPCHK(launch_mass_change(phi, M, f, K, out, ctx->n, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1734,6 +1805,8 @@ int recon_stage_invert_map(recon_ctx *ctx, const double *phi, const float *pos, 
 {
     TRY(check_ctx(ctx));
     if (!phi || !pos || np <= 0 || !(box > 0.0) || !xi || !failed) return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (overlap(xi, (size_t)np * 24, phi, ctx->n3 * 8) || overlap(xi, (size_t)np * 24, pos, (size_t)np * 12))
+        return fail(ctx, RECON_E_ARG, "xi overlaps phi or pos");
     // the node shifts need 3 n^3 contiguous doubles: the particle deposit's
     // own buffer, else r, z and p where they lie back to back
     double *s3 = ctx->shifts;
@@ -1750,6 +1823,7 @@ int recon_stage_deposit_xi(recon_ctx *ctx, const double *xi, long long np, doubl
 {
     TRY(check_ctx(ctx));
     if (!xi || np <= 0 || !M) return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (overlap(M, ctx->n3 * 8, xi, (size_t)np * 24)) return fail(ctx, RECON_E_ARG, "M overlaps xi");
     HIPCHK(launch_deposit_xi(xi, np, ctx->n, M, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;
@@ -1759,6 +1833,7 @@ int recon_stage_delta_r(recon_ctx *ctx, const double *phi, double *delta)
 {
     TRY(check_ctx(ctx));
     if (!phi || !delta) return fail(ctx, RECON_E_ARG, "null array");
+    if (overlap(delta, ctx->n3 * 8, phi, ctx->n3 * 8)) return fail(ctx, RECON_E_ARG, "delta overlaps phi");
     HIPCHK(launch_output(phi, delta, nullptr, 1.0, ctx->n, ctx->part, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return RECON_OK;

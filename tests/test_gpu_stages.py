@@ -469,3 +469,39 @@ def test_prolongation_folded_into_the_sweep(torch_cuda, orc, n, first):
     f = lambda x: dev(torch, x, torch.float32)  # noqa: E731
     ug = [rec.prolong_sweep(f(u), f(e), f(a), f(b), scale=0.25, first=first, variant=v) for v in (1, 2)]
     assert torch.equal(ug[0], ug[1])
+
+
+def test_stage_outputs_must_not_overlap_inputs(torch_cuda):
+    """An output that overlaps an input (whole or in part) is rejected with
+    RECON_E_ARG before anything is launched; the same calls on separate arrays
+    run."""
+    import ctypes
+    torch = torch_cuda
+    from paper_1611_09638_amd import binding
+    n = 32
+    rec = binding.Recon(n, binding.Config())
+    L, ctx = binding.lib(), rec._ctx
+    E_ARG = -1
+
+    def P(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    f = torch.rand((n, n, n), dtype=torch.float64, device="cuda") + 0.5
+    g = torch.rand((n, n, n), dtype=torch.float64, device="cuda") + 0.5
+    big = torch.rand(2 * n ** 3, dtype=torch.float64, device="cuda") + 0.5
+    half = big[n ** 3 // 2:]  # starts inside the first n^3 values of big
+    assert L.recon_stage_apply(ctx, P(f), P(g), n, 1.0, P(f)) == E_ARG
+    assert L.recon_stage_apply(ctx, P(big), P(g), n, 1.0, P(half)) == E_ARG
+    assert L.recon_stage_residual(ctx, P(f), P(g), P(f), n, 1.0, P(g), 0, 0) == E_ARG
+    assert L.recon_stage_delta_r(ctx, P(f), P(f)) == E_ARG
+    assert L.recon_stage_meshmass(ctx, P(f), P(g), P(g), 0) == E_ARG
+    assert L.recon_stage_smooth(ctx, P(half), P(big), 0) == E_ARG
+    assert L.recon_stage_restrict(ctx, P(f), n, P(f), 0, 0) == E_ARG
+    assert L.recon_stage_residual_restrict(ctx, P(f), P(g), P(f), n, 1.0, P(g), 0, 0) == E_ARG
+    assert L.recon_stage_rbgs(ctx, P(f), P(f), P(g), n, 1.0, 0, 0, 0) == E_ARG
+    assert b"overlap" in L.recon_last_error(ctx)
+    out = torch.empty_like(f)
+    assert L.recon_stage_apply(ctx, P(f), P(g), n, 1.0, P(out)) == 0
+    assert L.recon_stage_delta_r(ctx, P(f), P(out)) == 0
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
