@@ -153,8 +153,10 @@ int recon_init(recon_ctx **ctx, int n, const recon_config *cfg, void *workspace,
  * positive total (any normalisation: it is divided by its mean).  box: box
  * edge in length units; phi_out is returned in length^2 (grid-unit phi times
  * (box/n)^2), delta_r_out = -laplacian phi (dimensionless; Eq. rec).  tol > 0
- * overrides cfg->tol for this call.  Either output may be NULL.  stats may be
- * NULL.  Records the tape when cfg->record_tape is set. */
+ * overrides cfg->tol for this call.  Either output may be NULL; the two must
+ * not overlap (RECON_E_ARG), and either may be the density array, which is
+ * read before they are written.  stats may be NULL.  Records the tape when
+ * cfg->record_tape is set. */
 int recon_solve(recon_ctx *ctx, const double *density, int n, double box, double tol, double *phi_out,
                 double *delta_r_out, recon_stats *stats);
 

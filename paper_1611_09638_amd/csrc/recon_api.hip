@@ -1053,6 +1053,16 @@ void bind_context(recon_ctx *ctx, int n, const recon_config *cfg, void *workspac
 
 // recon_solve on a bound context.  Wall time from the context's events, or
 // from the host clock around a drained stream when it has none.
+// True when the byte ranges [p, p + np) and [q, q + nq) share a byte: an
+// output written while other lanes still read an overlapping input would
+// race, so the entry points reject such calls.
+static bool overlap(const void *p, size_t np, const void *q, size_t nq)
+{
+    if (!p || !q) return false;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p), b = reinterpret_cast<uintptr_t>(q);
+    return a < b + nq && b < a + np;
+}
+
 int solve_density(recon_ctx *ctx, const double *density, int n, double box, double tol, double *phi_out,
                   double *delta_r_out, recon_stats *stats)
 {
@@ -1064,6 +1074,8 @@ int solve_density(recon_ctx *ctx, const double *density, int n, double box, doub
                     n, ctx->n, box, tol);
     if (ctx->cfg.particle_deposit)
         return fail(ctx, RECON_E_ARG, "particle_deposit needs particle input (recon_solve_particles)");
+    if (overlap(phi_out, ctx->n3 * 8, delta_r_out, ctx->n3 * 8))
+        return fail(ctx, RECON_E_ARG, "phi_out overlaps delta_r_out");
     recon_stats local;
     recon_stats *st = stats ? stats : &local;
     std::memset(st, 0, sizeof(*st));
@@ -1260,6 +1272,8 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
     ctx->err[0] = 0;
     ctx->tape_valid = 0;
     if (!pos || np <= 0 || !(box > 0.0) || !(tol >= 0.0)) return fail(ctx, RECON_E_ARG, "bad particle arguments");
+    if (overlap(phi_out, ctx->n3 * 8, delta_r_out, ctx->n3 * 8))
+        return fail(ctx, RECON_E_ARG, "phi_out overlaps delta_r_out");
     if (ctx->cfg.particle_deposit && np > ctx->n3)
         return fail(ctx, RECON_E_ARG, "the particle deposit takes at most n^3 particles");
     recon_stats local;
@@ -1322,16 +1336,6 @@ int recon_backward_particles(recon_ctx *ctx, const float *pos, long long np, con
 }
 
 // ------------------------------------------------------------- stage calls
-
-// True when the byte ranges [p, p + np) and [q, q + nq) share a byte: an
-// output written while other lanes still read an overlapping input would
-// race, so the stage entry points reject such calls.
-static bool overlap(const void *p, size_t np, const void *q, size_t nq)
-{
-    if (!p || !q) return false;
-    const uintptr_t a = reinterpret_cast<uintptr_t>(p), b = reinterpret_cast<uintptr_t>(q);
-    return a < b + nq && b < a + np;
-}
 
 int recon_stage_normalize(recon_ctx *ctx, const double *rho, double *m)
 {

@@ -500,6 +500,7 @@ def test_stage_outputs_must_not_overlap_inputs(torch_cuda):
     assert L.recon_stage_residual_restrict(ctx, P(f), P(g), P(f), n, 1.0, P(g), 0, 0) == E_ARG
     assert L.recon_stage_rbgs(ctx, P(f), P(f), P(g), n, 1.0, 0, 0, 0) == E_ARG
     assert b"overlap" in L.recon_last_error(ctx)
+    assert L.recon_solve(ctx, P(g), n, 250.0, 0.0, P(f), P(f), None) == E_ARG
     out = torch.empty_like(f)
     assert L.recon_stage_apply(ctx, P(f), P(g), n, 1.0, P(out)) == 0
     assert L.recon_stage_delta_r(ctx, P(f), P(out)) == 0
