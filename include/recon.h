@@ -177,7 +177,8 @@ int recon_backward(recon_ctx *ctx, const double *grad_delta_r, const double *gra
 /* Reverse mode of a recorded recon_solve_particles with particle_deposit = 1:
  * dL/d pos (grad_pos: np x 3 FP64 device array, in the units of pos) given
  * dL/d delta_r and (optionally) dL/d phi_out.  pos and np must be the
- * particles of the recorded forward (device, float32, unchanged).  Each
+ * particles of the recorded forward (device, float32, unchanged; grad_pos
+ * must not overlap them, RECON_E_ARG).  Each
  * step's Lagrangian positions are recomputed by Newton from the later step's
  * (reverse order); the gradient runs through the inversion of the map
  * (J^-T per particle) and the xi-space CIC, with the step sizes and limiter

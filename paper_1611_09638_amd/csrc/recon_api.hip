@@ -1332,6 +1332,8 @@ int recon_backward_particles(recon_ctx *ctx, const float *pos, long long np, con
         return fail(ctx, RECON_E_ARG, "the recorded forward did not deposit particles: use recon_backward");
     if (!pos || np != ctx->tape_np || !grad_delta_r || !grad_pos)
         return fail(ctx, RECON_E_ARG, "the particles must be those of the recorded forward");
+    if (overlap(grad_pos, (size_t)np * 24, pos, (size_t)np * 12))
+        return fail(ctx, RECON_E_ARG, "grad_pos overlaps pos");
     return backward(ctx, grad_delta_r, grad_phi, nullptr, pos, grad_pos);
 }
 
