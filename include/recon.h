@@ -151,9 +151,10 @@ int recon_init(recon_ctx **ctx, int n, const recon_config *cfg, void *workspace,
 
 /* Forward reconstruction (Sec. II, App. A).  density: n^3 values >= 0 with a
  * positive total (any normalisation: it is divided by its mean).  box: box
- * edge in length units; phi_out is returned in length^2 (grid-unit phi times
- * (box/n)^2), delta_r_out = -laplacian phi (dimensionless; Eq. rec).  tol > 0
- * overrides cfg->tol for this call.  Either output may be NULL; the two must
+ * edge in length units (finite and > 0); phi_out is returned in length^2
+ * (grid-unit phi times (box/n)^2), delta_r_out = -laplacian phi
+ * (dimensionless; Eq. rec).  tol (finite, >= 0): > 0 overrides cfg->tol for
+ * this call; 0 keeps it.  Other box or tol values give RECON_E_ARG.  Either output may be NULL; the two must
  * not overlap (RECON_E_ARG), and either may be the density array, which is
  * read before they are written.  stats may be NULL.  Records the tape when
  * cfg->record_tape is set. */

@@ -1069,7 +1069,7 @@ int solve_density(recon_ctx *ctx, const double *density, int n, double box, doub
     ctx->err[0] = 0;
     // a failed or partial solve leaves no tape behind
     ctx->tape_valid = 0;
-    if (!density || n != ctx->n || !(box > 0.0) || !(tol >= 0.0))
+    if (!density || n != ctx->n || !(box > 0.0) || !std::isfinite(box) || !(tol >= 0.0) || !std::isfinite(tol))
         return fail(ctx, RECON_E_ARG, "bad argument (density %p, n %d vs %d, box %g, tol %g)", (const void *)density,
                     n, ctx->n, box, tol);
     if (ctx->cfg.particle_deposit)
@@ -1271,7 +1271,8 @@ int recon_solve_particles(recon_ctx *ctx, const float *pos, long long np, double
     TRY(check_ctx(ctx));
     ctx->err[0] = 0;
     ctx->tape_valid = 0;
-    if (!pos || np <= 0 || !(box > 0.0) || !(tol >= 0.0)) return fail(ctx, RECON_E_ARG, "bad particle arguments");
+    if (!pos || np <= 0 || !(box > 0.0) || !std::isfinite(box) || !(tol >= 0.0) || !std::isfinite(tol))
+        return fail(ctx, RECON_E_ARG, "bad particle arguments");
     if (overlap(phi_out, ctx->n3 * 8, delta_r_out, ctx->n3 * 8))
         return fail(ctx, RECON_E_ARG, "phi_out overlaps delta_r_out");
     if (ctx->cfg.particle_deposit && np > ctx->n3)
@@ -1349,7 +1350,8 @@ int recon_stage_normalize(recon_ctx *ctx, const double *rho, double *m)
 int recon_stage_cic(recon_ctx *ctx, const float *pos, long long np, double box, double *rho)
 {
     TRY(check_ctx(ctx));
-    if (!pos || !rho || np < 0 || !(box > 0.0)) return fail(ctx, RECON_E_ARG, "bad particle arguments");
+    if (!pos || !rho || np < 0 || !(box > 0.0) || !std::isfinite(box))
+        return fail(ctx, RECON_E_ARG, "bad particle arguments");
     if (overlap(rho, ctx->n3 * 8, pos, (size_t)np * 12)) return fail(ctx, RECON_E_ARG, "rho overlaps pos");
     HIPCHK(launch_zero(rho, ctx->n3 * 8, ctx->stream));
     if (np > 0) HIPCHK(launch_cic(pos, np, ctx->n, box, rho, ctx->stream));
@@ -1810,7 +1812,8 @@ int recon_stage_invert_map(recon_ctx *ctx, const double *phi, const float *pos, 
                            double *failed)
 {
     TRY(check_ctx(ctx));
-    if (!phi || !pos || np <= 0 || !(box > 0.0) || !xi || !failed) return fail(ctx, RECON_E_ARG, "bad arguments");
+    if (!phi || !pos || np <= 0 || !(box > 0.0) || !std::isfinite(box) || !xi || !failed)
+        return fail(ctx, RECON_E_ARG, "bad arguments");
     if (overlap(xi, (size_t)np * 24, phi, ctx->n3 * 8) || overlap(xi, (size_t)np * 24, pos, (size_t)np * 12))
         return fail(ctx, RECON_E_ARG, "xi overlaps phi or pos");
     // the node shifts need 3 n^3 contiguous doubles: the particle deposit's

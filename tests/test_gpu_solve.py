@@ -103,9 +103,11 @@ def test_error_paths(torch_cuda):
     with pytest.raises(binding.ReconError) as e:
         rec.solve(torch.zeros_like(good), 10.0)
     assert e.value.code == -2
-    with pytest.raises(binding.ReconError) as e:
-        rec.solve(good, -1.0)
-    assert e.value.code == -1
+    for box, tol in ((-1.0, 0.0), (float("inf"), 0.0), (float("nan"), 0.0), (10.0, float("inf")),
+                     (10.0, float("nan"))):
+        with pytest.raises(binding.ReconError) as e:
+            rec.solve(good, box, tol=tol)
+        assert e.value.code == -1
     rho = torch.from_numpy(inputs.lognormal_density(n, 125.0, 2.0, 3)).cuda()
     with pytest.raises(binding.ReconError) as e:
         binding.Recon(n, binding.Config(max_halvings=0)).solve(rho, 125.0)
