@@ -52,6 +52,10 @@ __device__ __forceinline__ void lds_barrier()
 // so the fused and per-colour sweeps round identically; a is stored halved
 // (the face coefficient max(a_min, (a_n + a_nb) / 2) is max(a_min, h_n + h_nb)).
 // ZERO: u_in is taken as 0 and not read (the first sweep from a zero guess).
+// The first colour then has only zero neighbours: its weighted sum is +0, so
+// only the face coefficients are summed, and the zero planes of u are never
+// staged in LDS (every value the second colour and the plane store read is
+// written by a relaxation first).  The result is the same bit for bit.
 template <typename T, int TJ, int TK_, int NT_>
 struct Ring4 {
     static constexpr int TK = TK_, NT = NT_;
@@ -247,7 +251,7 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         const char *ub = plane(uin, p), *ab = plane(ag, p);
 #pragma unroll
         for (int r = 0; r < LU; ++r) {
-            ru[SET][r] = ZERO ? (T)0 : at(ub, offU[r]);
+            if constexpr (!ZERO) ru[SET][r] = at(ub, offU[r]);
             ra[SET][r] = at(ab, offU[r]);
         }
         // PRO: an even plane 2c brings coarse plane c + 1 along
@@ -279,7 +283,7 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
                 for (int r = 0; r < LU; ++r) sU[SLOT][dstU[r]] = ru[SET][r] + held(c, r);
                 if (cw) coarse_store(c + 1, rcs[SET]);
             }
-        } else {
+        } else if constexpr (!ZERO) {
 #pragma unroll
             for (int r = 0; r < LU; ++r) sU[SLOT][dstU[r]] = ru[SET][r];
         }
@@ -328,12 +332,30 @@ __global__ void __launch_bounds__(NT_, MINW) k_rbgs_fused(const T *__restrict__ 
         cf = fmax(hn + sA[SC][pk - 1], a_min); num += cf * sU[SC][pk - 1]; den += cf;
         return qdiv(num - bval * inv_scale, den);
     };
+    // the same relaxation with every neighbour zero (ZERO's first colour):
+    // the weighted sum stays +0 and the face coefficients add up in order
+    auto relax_zero = [&](auto SCc, auto SUc, auto SDc, int c, int pk, T bval) {
+        constexpr int SC = decltype(SCc)::value, SU = decltype(SUc)::value, SD = decltype(SDc)::value;
+        const T hn = sA[SC][c];
+        T den = 0;
+        den += fmax(hn + sA[SU][c], a_min);
+        den += fmax(hn + sA[SD][c], a_min);
+        den += fmax(hn + sA[SC][c + W], a_min);
+        den += fmax(hn + sA[SC][c - W], a_min);
+        den += fmax(hn + sA[SC][pk], a_min);
+        den += fmax(hn + sA[SC][pk - 1], a_min);
+        const T num = 0;
+        return qdiv(num - bval * inv_scale, den);
+    };
     // first colour over the tile and its ring (reads only second-colour values)
     auto relax_first = [&](auto SCc, auto SUc, auto SDc, auto Pc, const T (&bv)[R1]) {
         constexpr int SC = decltype(SCc)::value, P = decltype(Pc)::value;
 #pragma unroll
         for (int r = 0; r < R1; ++r)
-            if (tid + r * NT < F::N1) sU[SC][c1[r][P]] = relax(SCc, SUc, SDc, c1[r][P], p1[r][P], bv[r]);
+            if (tid + r * NT < F::N1) {
+                if constexpr (ZERO) sU[SC][c1[r][P]] = relax_zero(SCc, SUc, SDc, c1[r][P], p1[r][P], bv[r]);
+                else sU[SC][c1[r][P]] = relax(SCc, SUc, SDc, c1[r][P], p1[r][P], bv[r]);
+            }
     };
     // second colour over the tile (reads only new first-colour values)
     auto relax_second = [&](auto SCc, auto SUc, auto SDc, auto Pc, const T (&bv)[R2]) {
